@@ -1,0 +1,126 @@
+"""Planted mistakes: each case copies the oracle's C source, plants one
+plausible mistake (textual replacement), compiles the copy to a temporary
+library on the CPU and checks that the pin battery rejects it.  The oracle
+itself is never modified."""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_1111_6549_amd import inputs
+from tests import helpers as H
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "gf2_oracle.c")
+
+MUTATIONS = {
+    "last_nonzero_pivot": ("{ p = i; break; }", "{ p = i; }"),
+    "add_from_pivot_column": ("(~0ULL << ((c & 63) + 1))", "(~0ULL << (c & 63))"),
+    "skip_first_row_below": ("for (int64_t i = r + 1; i < m; i++) {", "for (int64_t i = r + 2; i < m; i++) {"),
+    "skip_word_after_pivot": ("for (int64_t w = w0 + 1; w < nw; w++) row[w] ^= pr[w];",
+                              "for (int64_t w = w0 + 2; w < nw; w++) row[w] ^= pr[w];"),
+    "P_relative": ("P[r] = p;", "P[r] = p - r;"),
+    "no_compress": ("if (q == j) continue;", "continue;"),
+    "compress_includes_row_j": ("for (int64_t i = j + 1; i < m; i++) {\n            uint64_t *row = A + i * ldw;\n            setbit(row, j",
+                                "for (int64_t i = j; i < m; i++) {\n            uint64_t *row = A + i * ldw;\n            setbit(row, j"),
+    "compress_keeps_old_bit": ("setbit(row, q, 0);", ";"),
+    "rref_skips_top_row": ("for (int64_t i = 0; i < j; i++) {", "for (int64_t i = 1; i < j; i++) {"),
+    "table_lsb_first": ("if ((x >> (k - 1 - t)) & 1)", "if ((x >> t) & 1)"),
+    "no_row_swap": ("if (p != r) {                              /* swap whole rows */",
+                    "if (0) {"),
+}
+
+
+def _build_mutant(name, tmpdir):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    path = os.path.join(tmpdir, name + ".c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    so = os.path.join(tmpdir, name + ".so")
+    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", path, "-o", so])
+    lib = ctypes.CDLL(so)
+    i64, p = ctypes.c_int64, ctypes.c_void_p
+    lib.gf2o_ple.restype = i64
+    lib.gf2o_ple.argtypes = [p, i64, i64, i64, p, p]
+    lib.gf2o_rref_from_ple.argtypes = [p, i64, i64, i64, p, i64]
+    lib.gf2o_make_table.argtypes = [p, i64, i64, i64, p]
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _ple(lib, bits):
+    bits = np.asarray(bits, dtype=np.uint8)
+    m, n = bits.shape
+    A = H.pack(bits)
+    P = np.empty(m, np.int64)
+    Q = np.empty(min(m, n), np.int64)
+    r = lib.gf2o_ple(_ptr(A), m, n, A.shape[1], _ptr(P), _ptr(Q))
+    return int(r), P, Q, A
+
+
+def battery(lib):
+    """The pins of test_oracle_pins, compressed; raises AssertionError on the
+    first violated fact."""
+    g = dict(H.read_golden("perm_example.txt"))
+    mat = np.array(g["matrix"], np.uint8)
+    r, P, Q, A = _ple(lib, mat)
+    assert r == 5 and list(P) == g["P"] and np.array_equal(H.unpack(A, 5), np.eye(5, dtype=np.uint8))
+    f3 = dict(H.read_golden("fig3_m4ri.txt"))
+    piv = H.pack(np.array(f3["pivots"], np.uint8))
+    T = np.empty((8, 1), np.uint64)
+    lib.gf2o_make_table(_ptr(piv), 1, 3, 1, _ptr(T))
+    assert np.array_equal(H.unpack(T, 8), np.array(f3["table"], np.uint8))
+    for key, val in H.read_golden("postprocess_example.txt"):
+        if key == "case":
+            case = np.array(val, np.uint8)
+        else:
+            r, P, Q, A = _ple(lib, case)
+            assert list(H.unpack(A, 8)[3, :3]) == val
+    rng = np.random.default_rng(3)
+    for t in range(400):
+        m, n = rng.integers(1, 8, size=2)
+        bits = (rng.random((m, n)) < 0.5).astype(np.uint8)
+        rank, lead, rref_rows = H.brute_facts(bits)
+        r, P, Q, A = _ple(lib, bits)
+        out = H.unpack(A, n)
+        assert r == rank and list(Q[:r]) == lead
+        H.check_ple(bits, out, r, P, Q)
+        H.check_first_nonzero(out, r, P)
+        lib.gf2o_rref_from_ple(_ptr(A), m, n, A.shape[1], _ptr(Q), r)
+        assert H.row_ints(H.unpack(A, n)[:r]) == rref_rows
+    for seed, (m, n) in enumerate([(130, 140), (70, 200)]):
+        Ap = inputs.bernoulli(m, n, 50 + seed)
+        bits = H.unpack(Ap, n)
+        r, P, Q, A = _ple(lib, bits)
+        H.check_ple(bits, H.unpack(A, n), r, P, Q)
+
+
+def test_battery_accepts_oracle():
+    with tempfile.TemporaryDirectory() as d:
+        src = open(SRC).read()
+        path = os.path.join(d, "clean.c")
+        open(path, "w").write(src)
+        so = os.path.join(d, "clean.so")
+        subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", path, "-o", so])
+        lib = ctypes.CDLL(so)
+        i64, p = ctypes.c_int64, ctypes.c_void_p
+        lib.gf2o_ple.restype = i64
+        lib.gf2o_ple.argtypes = [p, i64, i64, i64, p, p]
+        lib.gf2o_rref_from_ple.argtypes = [p, i64, i64, i64, p, i64]
+        lib.gf2o_make_table.argtypes = [p, i64, i64, i64, p]
+        battery(lib)
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name):
+    with tempfile.TemporaryDirectory() as d:
+        lib = _build_mutant(name, d)
+        with pytest.raises(AssertionError):
+            battery(lib)
