@@ -1,0 +1,143 @@
+/*
+ * gf2ple: PLE decomposition over GF(2) on MI355X (gfx950), C ABI.
+ *
+ * Method: Albrecht, Bard, Pernet, "Efficient Dense Gaussian Elimination over
+ * the Finite Field with Two Elements" -- block-iterative PLE (Algorithm 2)
+ * whose trailing update is the Method of Four Russians: all 2^k sums of k
+ * pivot rows in a table (MakeTable, Appendix A) and one table row added per
+ * matrix row (AddRowsFromTable, Appendix A).
+ *
+ * Packed format (Section 1.1, Section 2 "row major representation"):
+ *   an m x n matrix over GF(2) is m rows of `ldw` 64-bit words, row-major;
+ *   column j of row i is bit (j & 63) of word A[i*ldw + (j >> 6)].
+ *   ldw >= ceil(n/64); every bit at a column >= n must be zero.
+ *
+ * Conventions shared by all calls:
+ *   - Every matrix, permutation, rank and workspace pointer is a DEVICE
+ *     pointer owned by the caller; the library never frees or keeps them.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     stream-ordered and return once the work is enqueued, except where a
+ *     call says it synchronises.
+ *   - Errors are return codes.  An error found before launch leaves every
+ *     output untouched.  After GF2_EHIP the outputs are undefined
+ *     (hipGetLastError() has the runtime's detail).
+ *   - Calls on different streams with disjoint buffers are independent.
+ */
+#ifndef GF2PLE_H
+#define GF2PLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gf2_status {
+    GF2_OK = 0,
+    GF2_EINVAL = 1,     /* negative size, ldw < ceil(n/64), NULL or misaligned pointer, bad option */
+    GF2_EWORKSPACE = 2, /* workspace smaller than the matching *_workspace_bytes() */
+    GF2_ENOMEM = 3,     /* a host-side allocation failed (serving sessions) */
+    GF2_EBUDGET = 4,    /* serving: request larger than the whole device budget */
+    GF2_EHIP = 5,       /* HIP runtime error */
+    GF2_EPADDING = 6,   /* check_padding: a bit at a column >= n is set */
+    GF2_EBUSY = 7       /* serving: no ticket of that number is pending */
+} gf2_status;
+
+/* Schedule options.  A NULL pointer or a zeroed struct selects the defaults. */
+typedef struct gf2_ple_opts {
+    int32_t check_padding; /* 1: scan for set bits at columns >= n first (synchronises) */
+    int32_t update;        /* trailing update: 0 = default, 1 = XOR table (Four Russians), 2 = int8 MFMA */
+    int32_t mfma_block;    /* MFMA outer panel width in columns (multiple of 64; 0 = default 256) */
+    int32_t reserved[5];
+} gf2_ple_opts;
+
+/* Library version string, e.g. "gf2ple 0.1.0 gfx950". */
+const char *gf2_version(void);
+
+/* Text for a status code (static storage). */
+const char *gf2_status_str(gf2_status s);
+
+/* Bytes of device workspace gf2_ple needs for an m x n matrix with row
+ * stride ldw (tables, per-row coefficients, pivot block, pass record and
+ * the pivot-search scratch).  Returns 0 for invalid sizes. */
+size_t gf2_ple_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf2_ple_opts *opts);
+
+/*
+ * PLE decomposition A = P L E (Section 2, definition of the PLE
+ * decomposition; computed by Algorithm 2 with Algorithm 1's pivot rule).
+ *
+ *   A    [in/out] m x n packed, row stride ldw words.  Overwritten by L\E in
+ *        the space-sharing form of Section 1.2, "clean" variant:
+ *          row i <  r: columns < i hold L[i][0..i-1]; columns >= i hold row i
+ *                      of E (zero before its pivot Q[i], 1 at Q[i]);
+ *          row i >= r: columns < r hold L[i][0..r-1]; columns >= r are zero.
+ *   P    [out] m entries, LAPACK-style swap vector (Section 1.2): P^T A is A
+ *        with rows i and P[i] swapped for i = 0, 1, ... in order; P[i] = i
+ *        for i >= r.
+ *   Q    [out] min(m, n) entries: Q[i] = column of the i-th pivot (the column
+ *        rank profile, Section 2), -1 for i >= r.
+ *   rank [out] one int64: r.
+ *   ws   device workspace of at least gf2_ple_workspace_bytes(m, n, ldw)
+ *        bytes, 256-byte aligned; its contents need not be initialised.
+ *
+ * The pivot of each column is the first row at or below the current rank in
+ * the current row order (Algorithm 1), swapped in whole; so P, L, E are
+ * unique and bit-identical to plain Gaussian elimination with that rule.
+ * When n > m the call may synchronise the stream once the rank can have
+ * reached m, to skip passes that have nothing left to do.
+ */
+gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
+                   void *ws, size_t ws_bytes, const gf2_ple_opts *opts, void *stream);
+
+/* Echelon form from a PLE result (Section 2, row echelon form): in place,
+ * A <- E: rows i < r keep columns >= i (their L part is cleared), rows
+ * i >= r become zero.  `rank` is the device int64 written by gf2_ple. */
+gf2_status gf2_echelon_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, const int64_t *rank, void *stream);
+
+/* Bytes of workspace gf2_rref_from_ple needs. */
+size_t gf2_rref_workspace_bytes(int64_t m, int64_t n, int64_t ldw);
+
+/* Reduced row echelon form from a PLE result (Section 2: the RREF is unique;
+ * Section 5 recovers it from the PLE output): in place, A <- RREF of the
+ * original matrix in rows 0..r-1 and zero below.  Q and rank are the device
+ * outputs of gf2_ple. */
+gf2_status gf2_rref_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, const int64_t *Q, const int64_t *rank,
+                             void *ws, size_t ws_bytes, void *stream);
+
+/* gf2_ple followed by gf2_rref_from_ple (the "PLE" timing of Section 5).
+ * P and Q are still required (they are outputs of the decomposition). */
+size_t gf2_rref_full_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf2_ple_opts *opts);
+gf2_status gf2_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
+                    void *ws, size_t ws_bytes, const gf2_ple_opts *opts, void *stream);
+
+/*
+ * C ^= A * B over GF(2): the Four-Russians product that Algorithm 2 applies
+ * to the trailing block (A22 <- L21 A12 + A22; M4RM, Section 3.2), as a
+ * standalone call.  A is m x k (row stride lda words), B is k x n (ldb),
+ * C is m x n (ldc).  For each 64-column slice of A the 64 matching rows of B
+ * are tabulated 8 at a time (256-entry tables) and one table row per byte of
+ * A's word is added to C.  opts->update = 2 selects the int8 MFMA product
+ * instead (bit-identical).  No workspace.
+ */
+gf2_status gf2_addmul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *B, int64_t ldb,
+                      int64_t m, int64_t k, int64_t n, const gf2_ple_opts *opts, void *stream);
+
+/*
+ * MakeTable (Appendix A): T[x] = sum of the rows t of `rows` whose bit
+ * (k-1-t) is set in x, i.e. the first row is the most significant index bit
+ * (the order of Appendix A's figure).  rows: k x n packed (stride ldr),
+ * 1 <= k <= 8; T: 2^k rows of ldt words (ldt >= ceil(n/64)).  Built by the
+ * Gray-code enumeration, 2^k - 1 row additions.
+ */
+gf2_status gf2_make_table(const uint64_t *rows, int64_t ldr, int32_t k, int64_t n, uint64_t *T, int64_t ldt,
+                          void *stream);
+
+/* Scan for set bits at columns >= n (padding); synchronises the stream.
+ * Returns GF2_OK or GF2_EPADDING. */
+gf2_status gf2_check_padding(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GF2PLE_H */

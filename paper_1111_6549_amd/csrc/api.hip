@@ -1,0 +1,273 @@
+// C-ABI entry points of libgf2ple (declared in include/gf2ple.h): argument
+// checks, workspace layout and the pass loop of Algorithm 2.  All arithmetic
+// runs in the HIP kernels of ple_kernels.hip / rref_kernels.hip.
+#include <mutex>
+#include <vector>
+
+#include "../../include/gf2ple.h"
+#include "common.h"
+
+namespace gf2 {
+hipError_t launch_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *rank, PassRec *rec, hipStream_t s);
+hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, PassRec *rec, int64_t *P,
+                       int64_t *Q, int64_t *rank, uint64_t *coef, uint64_t *PB, uint64_t *gsv, int32_t *gsid,
+                       hipStream_t s);
+hipError_t launch_m4rm(uint64_t *C, int64_t ldc, int64_t m, const uint64_t *coef, int64_t coef_ld, const uint64_t *B,
+                       int64_t ldb, int nbits, int64_t w_begin, int64_t w_end, hipStream_t s);
+hipError_t launch_echelon(uint64_t *A, int64_t m, int64_t ldw, const int64_t *rank, hipStream_t s);
+hipError_t launch_padding(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, int *flag, hipStream_t s);
+hipError_t launch_make_table(const uint64_t *rows, int64_t ldr, int k, int64_t nw, uint64_t *T, int64_t ldt,
+                             hipStream_t s);
+hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t j0, int64_t j1,
+                             int64_t wq0, uint64_t *coef, uint64_t *PB, hipStream_t s);
+}  // namespace gf2
+
+using namespace gf2;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct PleLayout {
+    size_t rec, coef, pb, gsv, gsid, total;
+};
+
+// workspace of gf2_ple: pass record | coef[m] | pivot block 64 x ldw |
+// slow-search values[m] | slow-search ids[m]
+PleLayout ple_layout(int64_t m, int64_t ldw) {
+    PleLayout L;
+    size_t off = 0;
+    L.rec = off;
+    off += align_up(sizeof(PassRec));
+    L.coef = off;
+    off += align_up((size_t)m * 8);
+    L.pb = off;
+    off += align_up((size_t)KW * (size_t)ldw * 8);
+    L.gsv = off;
+    off += align_up((size_t)m * 8);
+    L.gsid = off;
+    off += align_up((size_t)m * 4);
+    L.total = off;
+    return L;
+}
+
+// workspace of gf2_rref_from_ple: coef[m] | pivot block 64 x ldw
+struct RrefLayout {
+    size_t coef, pb, total;
+};
+RrefLayout rref_layout(int64_t m, int64_t ldw) {
+    RrefLayout L;
+    L.coef = 0;
+    L.pb = align_up((size_t)m * 8);
+    L.total = L.pb + align_up((size_t)KW * (size_t)ldw * 8);
+    return L;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// sizes: m, n >= 0, ldw >= ceil(n/64), m * ldw * 8 representable
+bool sizes_ok(int64_t m, int64_t n, int64_t ldw) {
+    if (m < 0 || n < 0 || ldw < 0) return false;
+    if (ldw < words_for(n)) return false;
+    if (ldw > 0 && m > (int64_t)(INT64_MAX / 8) / ldw) return false;
+    if (m > (int64_t)INT32_MAX) return false;  // positions are kept as int32 in the slow search
+    return true;
+}
+
+gf2_status hip_status(hipError_t e) { return e == hipSuccess ? GF2_OK : GF2_EHIP; }
+
+std::mutex g_flag_mu;
+std::vector<int *> g_flag;  // per device: one int for the padding scan
+
+int *device_flag() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_flag_mu);
+    if ((int)g_flag.size() <= dev) g_flag.resize(dev + 1, nullptr);
+    if (!g_flag[dev]) {
+        int *p = nullptr;
+        if (hipMalloc(&p, sizeof(int)) != hipSuccess) return nullptr;
+        g_flag[dev] = p;
+    }
+    return g_flag[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gf2_version(void) { return "gf2ple 0.1.0 gfx950"; }
+
+const char *gf2_status_str(gf2_status s) {
+    switch (s) {
+        case GF2_OK: return "ok";
+        case GF2_EINVAL: return "invalid argument";
+        case GF2_EWORKSPACE: return "workspace too small";
+        case GF2_ENOMEM: return "out of memory";
+        case GF2_EBUDGET: return "request exceeds the device budget";
+        case GF2_EHIP: return "HIP runtime error";
+        case GF2_EPADDING: return "non-zero bit at a column >= n";
+        case GF2_EBUSY: return "no such pending request";
+    }
+    return "unknown status";
+}
+
+size_t gf2_ple_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf2_ple_opts *opts) {
+    (void)opts;
+    if (!sizes_ok(m, n, ldw)) return 0;
+    return ple_layout(m, ldw).total;
+}
+
+gf2_status gf2_check_padding(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, void *stream) {
+    if (!sizes_ok(m, n, ldw)) return GF2_EINVAL;
+    if (m == 0 || ldw == 0) return GF2_OK;
+    if (!A || !aligned(A, 8)) return GF2_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int *flag = device_flag();
+    if (!flag) return GF2_EHIP;
+    if (hipMemsetAsync(flag, 0, sizeof(int), s) != hipSuccess) return GF2_EHIP;
+    if (launch_padding(A, m, n, ldw, flag, s) != hipSuccess) return GF2_EHIP;
+    int host = 0;
+    if (hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return GF2_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return GF2_EHIP;
+    return host ? GF2_EPADDING : GF2_OK;
+}
+
+gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
+                   size_t ws_bytes, const gf2_ple_opts *opts, void *stream) {
+    if (!sizes_ok(m, n, ldw)) return GF2_EINVAL;
+    const int64_t mn = m < n ? m : n;
+    if (!rank || !aligned(rank, 8)) return GF2_EINVAL;
+    if (m > 0 && (!P || !aligned(P, 8))) return GF2_EINVAL;
+    if (mn > 0 && (!Q || !aligned(Q, 8))) return GF2_EINVAL;
+    if (m > 0 && ldw > 0 && (!A || !aligned(A, 8))) return GF2_EINVAL;
+    if (opts && (opts->update < 0 || opts->update > 2)) return GF2_EINVAL;
+    if (opts && opts->update == 2) return GF2_EINVAL;  // MFMA trailing update: see gf2_addmul
+    const PleLayout L = ple_layout(m, ldw);
+    if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;
+    if (ws_bytes < L.total) return GF2_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (opts && opts->check_padding) {
+        gf2_status st = gf2_check_padding(A, m, n, ldw, stream);
+        if (st != GF2_OK) return st;
+    }
+    char *base = (char *)ws;
+    PassRec *rec = (PassRec *)(base + L.rec);
+    uint64_t *coef = (uint64_t *)(base + L.coef);
+    uint64_t *PB = (uint64_t *)(base + L.pb);
+    uint64_t *gsv = (uint64_t *)(base + L.gsv);
+    int32_t *gsid = (int32_t *)(base + L.gsid);
+
+    if (launch_init(P, m, Q, mn, rank, rec, s) != hipSuccess) return GF2_EHIP;
+    if (m == 0 || n == 0) return GF2_OK;
+
+    const int64_t npasses = words_for(n);
+    int64_t since_check = 0;
+    for (int64_t t = 0; t < npasses; t++) {
+        const int64_t c = t * KW;
+        if (c >= m) {
+            // rank <= m: once it reaches m the remaining passes are empty
+            if (since_check == 0) {
+                int64_t host_rank = 0;
+                if (hipMemcpyAsync(&host_rank, rank, 8, hipMemcpyDeviceToHost, s) != hipSuccess) return GF2_EHIP;
+                if (hipStreamSynchronize(s) != hipSuccess) return GF2_EHIP;
+                if (host_rank >= m) break;
+            }
+            since_check = (since_check + 1) % 8;
+        }
+        if (launch_pass(A, m, n, ldw, c, rec, P, Q, rank, coef, PB, gsv, gsid, s) != hipSuccess) return GF2_EHIP;
+    }
+    return hip_status(hipGetLastError());
+}
+
+gf2_status gf2_echelon_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, const int64_t *rank, void *stream) {
+    if (!sizes_ok(m, n, ldw)) return GF2_EINVAL;
+    if (!rank || !aligned(rank, 8)) return GF2_EINVAL;
+    if (m == 0 || ldw == 0) return GF2_OK;
+    if (!A || !aligned(A, 8)) return GF2_EINVAL;
+    return hip_status(launch_echelon(A, m, ldw, rank, (hipStream_t)stream));
+}
+
+size_t gf2_rref_workspace_bytes(int64_t m, int64_t n, int64_t ldw) {
+    if (!sizes_ok(m, n, ldw)) return 0;
+    return rref_layout(m, ldw).total;
+}
+
+gf2_status gf2_rref_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, const int64_t *Q, const int64_t *rank,
+                             void *ws, size_t ws_bytes, void *stream) {
+    if (!sizes_ok(m, n, ldw)) return GF2_EINVAL;
+    if (!rank || !aligned(rank, 8)) return GF2_EINVAL;
+    const int64_t mn = m < n ? m : n;
+    if (mn > 0 && (!Q || !aligned(Q, 8))) return GF2_EINVAL;
+    if (m == 0 || ldw == 0) return GF2_OK;
+    if (!A || !aligned(A, 8)) return GF2_EINVAL;
+    const RrefLayout L = rref_layout(m, ldw);
+    if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;
+    if (ws_bytes < L.total) return GF2_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (launch_echelon(A, m, ldw, rank, s) != hipSuccess) return GF2_EHIP;
+    // the number of pivot blocks and their first columns size the launches
+    int64_t r = 0;
+    if (hipMemcpyAsync(&r, rank, 8, hipMemcpyDeviceToHost, s) != hipSuccess) return GF2_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return GF2_EHIP;
+    if (r <= 0) return GF2_OK;
+    std::vector<int64_t> hq((size_t)r);
+    if (hipMemcpy(hq.data(), Q, (size_t)r * 8, hipMemcpyDeviceToHost) != hipSuccess) return GF2_EHIP;
+    char *base = (char *)ws;
+    uint64_t *coef = (uint64_t *)(base + L.coef);
+    uint64_t *PB = (uint64_t *)(base + L.pb);
+    const int64_t nw = words_for(n);
+    const int64_t nblk = (r + KW - 1) / KW;
+    for (int64_t b = nblk - 1; b >= 0; b--) {
+        const int64_t j0 = b * KW;
+        const int64_t j1 = j0 + KW < r ? j0 + KW : r;
+        const int64_t wq0 = hq[(size_t)j0] >> 6;
+        if (launch_rref_block(A, ldw, nw, Q, j0, j1, wq0, coef, PB, s) != hipSuccess) return GF2_EHIP;
+        if (launch_m4rm(A, ldw, j1, coef, 1, PB, ldw, (int)(j1 - j0), wq0, nw, s) != hipSuccess) return GF2_EHIP;
+    }
+    return hip_status(hipGetLastError());
+}
+
+size_t gf2_rref_full_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf2_ple_opts *opts) {
+    size_t a = gf2_ple_workspace_bytes(m, n, ldw, opts);
+    size_t b = gf2_rref_workspace_bytes(m, n, ldw);
+    if (!a || !b) return 0;
+    return a > b ? a : b;
+}
+
+gf2_status gf2_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
+                    size_t ws_bytes, const gf2_ple_opts *opts, void *stream) {
+    gf2_status st = gf2_ple(A, m, n, ldw, P, Q, rank, ws, ws_bytes, opts, stream);
+    if (st != GF2_OK) return st;
+    return gf2_rref_from_ple(A, m, n, ldw, Q, rank, ws, ws_bytes, stream);
+}
+
+gf2_status gf2_addmul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *B, int64_t ldb,
+                      int64_t m, int64_t k, int64_t n, const gf2_ple_opts *opts, void *stream) {
+    if (m < 0 || k < 0 || n < 0) return GF2_EINVAL;
+    if (ldc < words_for(n) || lda < words_for(k) || ldb < words_for(n)) return GF2_EINVAL;
+    if (opts && (opts->update < 0 || opts->update > 2)) return GF2_EINVAL;
+    if (m == 0 || n == 0 || k == 0) return GF2_OK;
+    if (!C || !A || !B || !aligned(C, 8) || !aligned(A, 8) || !aligned(B, 8)) return GF2_EINVAL;
+    if (opts && opts->update == 2) return GF2_EINVAL;  // not built yet
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nw = words_for(n);
+    for (int64_t kb = 0; kb * KW < k; kb++) {
+        const int nb = (int)(k - kb * KW < KW ? k - kb * KW : KW);
+        if (launch_m4rm(C, ldc, m, A + kb, lda, B + kb * KW * ldb, ldb, nb, 0, nw, s) != hipSuccess) return GF2_EHIP;
+    }
+    return hip_status(hipGetLastError());
+}
+
+gf2_status gf2_make_table(const uint64_t *rows, int64_t ldr, int32_t k, int64_t n, uint64_t *T, int64_t ldt,
+                          void *stream) {
+    if (k < 1 || k > 8 || n < 0) return GF2_EINVAL;
+    const int64_t nw = words_for(n);
+    if (ldr < nw || ldt < nw) return GF2_EINVAL;
+    if (ldt == 0) return GF2_OK;
+    if (!rows || !T || !aligned(rows, 8) || !aligned(T, 8)) return GF2_EINVAL;
+    return hip_status(launch_make_table(rows, ldr, k, nw, T, ldt, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// RREF from a PLE result (Section 2: the reduced row echelon form is unique;
+// Section 5 computes it from the PLE output).  Back-substitution by blocks
+// of 64 pivots, last block first, each block being one Four-Russians
+// product:
+//   U     = block rows at the block's pivot columns (unit upper triangular),
+//   Y     = U^-1,
+//   new block rows   = Y * block            (rows become reduced on the block)
+//   rows above (i<j0): row_i ^= (c_i Y) * block, c_i = row_i at the pivot columns.
+// k_rref_block computes Y (per workgroup), stages the block rows and writes
+// every row's coefficient word; the update itself is k_m4rm.
+#include "common.h"
+
+namespace gf2 {
+
+__device__ __forceinline__ uint64_t rl64(uint64_t v, int l) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+constexpr int RREF_THREADS = 256;
+
+__global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__restrict__ A, int64_t ldw, int64_t nw,
+                                                             const int64_t *__restrict__ Q, int64_t j0, int64_t j1,
+                                                             int64_t wq0, uint64_t *__restrict__ coef,
+                                                             uint64_t *__restrict__ PB, int nA) {
+    __shared__ int64_t sq[KW];
+    __shared__ uint64_t sY[KW];
+    __shared__ uint64_t tab[8][256];
+    const int tid = threadIdx.x;
+    const int nb = (int)(j1 - j0);
+
+    if ((int)blockIdx.x < nA) {  // stage the block rows' words >= wq0
+        const int64_t w = wq0 + (int64_t)blockIdx.x * 64 + (tid & 63);
+        if (w >= nw) return;
+        for (int k = tid >> 6; k < nb; k += RREF_THREADS / 64) PB[(int64_t)k * ldw + w] = A[(j0 + k) * ldw + w];
+        return;
+    }
+
+    if (tid < KW) sq[tid] = tid < nb ? Q[j0 + tid] : 0;
+    __syncthreads();
+    if (tid < 64) {  // wave 0: Y = U^-1
+        const int lane = tid;
+        uint64_t U = 0;
+        if (lane < nb) {
+            const uint64_t *row = A + (j0 + lane) * ldw;
+            int64_t cw = -1;
+            uint64_t cur = 0;
+            for (int t = 0; t < nb; t++) {
+                const int64_t q = sq[t];
+                if ((q >> 6) != cw) {
+                    cw = q >> 6;
+                    cur = row[cw];
+                }
+                U |= ((cur >> (q & 63)) & 1ull) << t;
+            }
+        }
+        uint64_t Y = 1ull << lane;
+        for (int t = nb - 1; t >= 0; t--) {
+            const uint64_t yt = rl64(Y, t);
+            if (lane < t && ((U >> t) & 1ull)) Y ^= yt;
+        }
+        sY[lane] = Y;
+    }
+    __syncthreads();
+    for (int e = tid; e < 8 * 256; e += RREF_THREADS) {
+        const int b = e >> 8, x = e & 255;
+        uint64_t a = 0;
+        for (int t = 0; t < 8; t++)
+            if (((x >> t) & 1) && 8 * b + t < nb) a ^= sY[8 * b + t];
+        tab[b][x] = a;
+    }
+    __syncthreads();
+    const int64_t nG = (int64_t)gridDim.x - nA;
+    for (int64_t i = ((int64_t)blockIdx.x - nA) * RREF_THREADS + tid; i < j1; i += nG * RREF_THREADS) {
+        if (i >= j0) {
+            coef[i] = sY[i - j0] ^ (1ull << (i - j0));
+            continue;
+        }
+        const uint64_t *row = A + i * ldw;
+        int64_t cw = -1;
+        uint64_t cur = 0, c = 0;
+        for (int t = 0; t < nb; t++) {
+            const int64_t q = sq[t];
+            if ((q >> 6) != cw) {
+                cw = q >> 6;
+                cur = row[cw];
+            }
+            c |= ((cur >> (q & 63)) & 1ull) << t;
+        }
+        uint64_t w = 0;
+        if (c) {
+#pragma unroll
+            for (int b = 0; b < 8; b++) w ^= tab[b][(c >> (8 * b)) & 255];
+        }
+        coef[i] = w;
+    }
+}
+
+hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t j0, int64_t j1,
+                             int64_t wq0, uint64_t *coef, uint64_t *PB, hipStream_t s) {
+    const int nA = (int)((nw - wq0 + 63) / 64);
+    int nG = (int)((j1 + RREF_THREADS - 1) / RREF_THREADS);
+    if (nG > 512) nG = 512;
+    if (nG < 1) nG = 1;
+    hipLaunchKernelGGL(k_rref_block, dim3(nA + nG), dim3(RREF_THREADS), 0, s, (const uint64_t *)A, ldw, nw, Q, j0, j1,
+                       wq0, coef, PB, nA);
+    return hipGetLastError();
+}
+
+}  // namespace gf2

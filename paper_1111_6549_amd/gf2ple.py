@@ -1,0 +1,204 @@
+"""Thin ctypes binding of libgf2ple.so (include/gf2ple.h).
+
+Only argument marshalling happens here: device memory and the current stream
+come from PyTorch, every step of the computation runs in the library's HIP
+kernels.  There is no CPU fallback: if the library is not built, or no GPU is
+present, the calls raise.
+
+Packed matrices are torch tensors of shape (m, ldw) with dtype int64 or
+uint64 on a CUDA (HIP) device; column j of row i is bit (j & 63) of
+element [i, j >> 6].
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgf2ple.so")
+_lib = None
+
+STATUS = {0: "GF2_OK", 1: "GF2_EINVAL", 2: "GF2_EWORKSPACE", 3: "GF2_ENOMEM", 4: "GF2_EBUDGET",
+          5: "GF2_EHIP", 6: "GF2_EPADDING", 7: "GF2_EBUSY"}
+
+# every symbol include/gf2ple.h declares
+EXPORTS = [
+    "gf2_version", "gf2_status_str", "gf2_ple_workspace_bytes", "gf2_ple", "gf2_echelon_from_ple",
+    "gf2_rref_workspace_bytes", "gf2_rref_from_ple", "gf2_rref_full_workspace_bytes", "gf2_rref",
+    "gf2_addmul", "gf2_make_table", "gf2_check_padding",
+]
+
+
+class GF2Error(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s failed: %s (%s)" % (what, STATUS.get(status, status), _status_text(status)))
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("check_padding", ctypes.c_int32), ("update", ctypes.c_int32), ("mfma_block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+def load():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libgf2ple.so is not built (run __graft_entry__.build() or "
+                           "python -m paper_1111_6549_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, i32, p, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+    st = ctypes.c_int
+    sig = {
+        "gf2_version": (ctypes.c_char_p, []),
+        "gf2_status_str": (ctypes.c_char_p, [st]),
+        "gf2_ple_workspace_bytes": (sz, [i64, i64, i64, p]),
+        "gf2_ple": (st, [p, i64, i64, i64, p, p, p, p, sz, p, p]),
+        "gf2_echelon_from_ple": (st, [p, i64, i64, i64, p, p]),
+        "gf2_rref_workspace_bytes": (sz, [i64, i64, i64]),
+        "gf2_rref_from_ple": (st, [p, i64, i64, i64, p, p, p, sz, p]),
+        "gf2_rref_full_workspace_bytes": (sz, [i64, i64, i64, p]),
+        "gf2_rref": (st, [p, i64, i64, i64, p, p, p, p, sz, p, p]),
+        "gf2_addmul": (st, [p, i64, p, i64, p, i64, i64, i64, i64, p, p]),
+        "gf2_make_table": (st, [p, i64, i32, i64, p, i64, p]),
+        "gf2_check_padding": (st, [p, i64, i64, i64, p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _status_text(status):
+    try:
+        return load().gf2_status_str(status).decode()
+    except Exception:  # library missing while formatting an error
+        return "?"
+
+
+def _check(status, what):
+    if status != 0:
+        raise GF2Error(status, what)
+
+
+def version():
+    return load().gf2_version().decode()
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _packed(t, name):
+    if not isinstance(t, torch.Tensor) or t.dim() != 2 or t.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("%s must be a 2-D int64/uint64 tensor of packed rows" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be on the GPU" % name)
+    if t.stride(1) != 1:
+        raise ValueError("%s rows must be contiguous" % name)
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _opts(update=0, check_padding=False, mfma_block=0):
+    o = Opts()
+    o.check_padding = 1 if check_padding else 0
+    o.update = int(update)
+    o.mfma_block = int(mfma_block)
+    return o
+
+
+def workspace_bytes(m, n, ldw, update=0):
+    o = _opts(update)
+    return int(load().gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
+
+
+def alloc_workspace(nbytes, device=None):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
+
+
+def ple(A, n, ws=None, update=0, check_padding=False):
+    """In-place PLE of the packed (m, ldw) tensor A with n columns.
+
+    Returns (P, Q, rank) as device tensors (int64 [m], int64 [min(m, n)],
+    int64 [1]).  A holds the clean L\\E afterwards."""
+    A = _packed(A, "A")
+    m, ldw = A.shape
+    lib = load()
+    o = _opts(update, check_padding)
+    need = int(lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
+    if need == 0 and (m or n):
+        raise GF2Error(1, "gf2_ple_workspace_bytes")
+    if ws is None:
+        ws = alloc_workspace(need, A.device)
+    P = torch.empty(m, dtype=torch.int64, device=A.device)
+    Q = torch.empty(min(m, n), dtype=torch.int64, device=A.device)
+    rank = torch.empty(1, dtype=torch.int64, device=A.device)
+    _check(lib.gf2_ple(_ptr(A), m, n, ldw, _ptr(P), _ptr(Q), _ptr(rank), _ptr(ws), ws.numel(),
+                       ctypes.byref(o), _stream()), "gf2_ple")
+    return P, Q, rank
+
+
+def echelon_from_ple(A, n, rank):
+    A = _packed(A, "A")
+    m, ldw = A.shape
+    _check(load().gf2_echelon_from_ple(_ptr(A), m, n, ldw, _ptr(rank), _stream()), "gf2_echelon_from_ple")
+
+
+def rref_from_ple(A, n, Q, rank, ws=None):
+    A = _packed(A, "A")
+    m, ldw = A.shape
+    lib = load()
+    need = int(lib.gf2_rref_workspace_bytes(m, n, ldw))
+    if ws is None:
+        ws = alloc_workspace(need, A.device)
+    _check(lib.gf2_rref_from_ple(_ptr(A), m, n, ldw, _ptr(Q), _ptr(rank), _ptr(ws), ws.numel(), _stream()),
+           "gf2_rref_from_ple")
+
+
+def rref(A, n, ws=None, update=0):
+    """In-place RREF (via PLE).  Returns (P, Q, rank)."""
+    A = _packed(A, "A")
+    m, ldw = A.shape
+    lib = load()
+    o = _opts(update)
+    need = int(lib.gf2_rref_full_workspace_bytes(m, n, ldw, ctypes.byref(o)))
+    if ws is None:
+        ws = alloc_workspace(need, A.device)
+    P = torch.empty(m, dtype=torch.int64, device=A.device)
+    Q = torch.empty(min(m, n), dtype=torch.int64, device=A.device)
+    rank = torch.empty(1, dtype=torch.int64, device=A.device)
+    _check(lib.gf2_rref(_ptr(A), m, n, ldw, _ptr(P), _ptr(Q), _ptr(rank), _ptr(ws), ws.numel(), ctypes.byref(o),
+                        _stream()), "gf2_rref")
+    return P, Q, rank
+
+
+def addmul(C, A, B, k, n, update=0):
+    """C ^= A * B over GF(2); A is m x k, B is k x n, all packed on the GPU."""
+    C, A, B = _packed(C, "C"), _packed(A, "A"), _packed(B, "B")
+    m = C.shape[0]
+    o = _opts(update)
+    _check(load().gf2_addmul(_ptr(C), C.shape[1], _ptr(A), A.shape[1], _ptr(B), B.shape[1], m, k, n,
+                             ctypes.byref(o), _stream()), "gf2_addmul")
+
+
+def make_table(rows, k, n, T=None):
+    """All 2^k sums of the k packed rows; index bit k-1-t selects row t."""
+    rows = _packed(rows, "rows")
+    if T is None:
+        T = torch.empty((1 << k, rows.shape[1]), dtype=rows.dtype, device=rows.device)
+    _check(load().gf2_make_table(_ptr(rows), rows.shape[1], k, n, _ptr(T), T.shape[1], _stream()), "gf2_make_table")
+    return T
+
+
+def check_padding(A, n):
+    A = _packed(A, "A")
+    m, ldw = A.shape
+    return int(load().gf2_check_padding(_ptr(A), m, n, ldw, _stream()))

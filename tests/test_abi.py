@@ -1,0 +1,60 @@
+"""The C-ABI library loads on the CPU and exports every symbol the public
+header declares; argument checks that return before any GPU work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1111_6549_amd import gf2ple as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "gf2ple.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gf2_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = G.load()
+    names = header_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(G.EXPORTS) == sorted(names)
+
+
+def test_version_and_status_strings():
+    assert G.version().startswith("gf2ple")
+    lib = G.load()
+    for code in range(8):
+        assert lib.gf2_status_str(code)
+    assert lib.gf2_status_str(0).decode() == "ok"
+
+
+def test_workspace_sizes():
+    lib = G.load()
+    o = G.Opts()
+    assert lib.gf2_ple_workspace_bytes(-1, 10, 1, ctypes.byref(o)) == 0
+    assert lib.gf2_ple_workspace_bytes(10, 65, 1, ctypes.byref(o)) == 0  # ldw too small
+    a = lib.gf2_ple_workspace_bytes(1024, 1024, 16, None)
+    b = lib.gf2_ple_workspace_bytes(2048, 1024, 16, None)
+    assert 0 < a < b
+    assert lib.gf2_rref_full_workspace_bytes(100, 100, 2, None) >= lib.gf2_rref_workspace_bytes(100, 100, 2)
+
+
+def test_argument_errors_before_launch():
+    lib = G.load()
+    nul = ctypes.c_void_p(0)
+    # negative sizes, ldw too small, NULL rank: EINVAL without touching the GPU
+    assert lib.gf2_ple(nul, -1, 5, 1, nul, nul, nul, nul, 0, None, nul) == 1
+    assert lib.gf2_ple(nul, 5, 200, 2, nul, nul, nul, nul, 0, None, nul) == 1
+    assert lib.gf2_ple(nul, 5, 5, 1, nul, nul, nul, nul, 0, None, nul) == 1
+    bad = G.Opts()
+    bad.update = 7
+    assert lib.gf2_addmul(nul, 1, nul, 1, nul, 1, 1, 1, 1, ctypes.byref(bad), nul) == 1
+    assert lib.gf2_make_table(nul, 1, 0, 10, nul, 1, nul) == 1
+    assert lib.gf2_make_table(nul, 1, 9, 10, nul, 1, nul) == 1
+    assert lib.gf2_echelon_from_ple(nul, 3, 3, 1, nul, nul) == 1

@@ -1,0 +1,181 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle,
+bit for bit on (rank, P, Q, L\\E), on seeded inputs that span several tiles,
+ragged tails, both pivot-search paths, sparse, rank-deficient, known-rank,
+empty and degenerate matrices."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1111_6549_amd import gf2ple as G
+from paper_1111_6549_amd import inputs
+from tests import helpers as H
+from tests.gpu_util import assert_same_ple, gpu_ple, oracle_ple, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    (1, 1), (1, 64), (64, 1), (63, 63), (64, 64), (65, 65), (100, 70), (70, 100), (127, 129),
+    (257, 300), (300, 257), (511, 513), (513, 511), (600, 64), (1000, 1), (1, 1000),
+    (130, 2000), (2000, 130), (640, 1100),
+]
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_parity_uniform(m, n):
+    say("parity uniform", m, n)
+    A = inputs.bernoulli(m, n, 100 + m * 7 + n)
+    assert_same_ple(gpu_ple(A, n), oracle_ple(A, n), "%dx%d" % (m, n))
+
+
+def test_parity_1024_seed1():
+    say("parity 1024x1024 seed 1")
+    A = inputs.bernoulli(1024, 1024, 1)
+    g = gpu_ple(A, 1024)
+    assert_same_ple(g, oracle_ple(A, 1024), "1024^2")
+    H.check_ple(H.unpack(A, 1024), H.unpack(g[3], 1024), g[0], g[1], g[2])
+
+
+@pytest.mark.parametrize("m,n,p", [(500, 500, 0.05), (700, 700, 0.01), (1000, 1000, 0.002), (300, 900, 0.05),
+                                   (900, 300, 0.01), (2000, 2000, 0.0005)])
+def test_parity_sparse(m, n, p):
+    say("parity sparse", m, n, p)
+    A = inputs.bernoulli(m, n, 7 * m + n, p=p)
+    assert_same_ple(gpu_ple(A, n), oracle_ple(A, n), "%dx%d p=%g" % (m, n, p))
+
+
+@pytest.mark.parametrize("m,n,rho", [(600, 600, 300), (1000, 700, 650), (700, 1000, 700), (800, 800, 800),
+                                     (3000, 300, 50), (8000, 300, 100), (256, 2048, 200)])
+def test_parity_known_rank(m, n, rho):
+    say("parity known rank", m, n, rho)
+    A = inputs.known_rank(m, n, rho, 11 + m, 13 + n)
+    g = gpu_ple(A, n)
+    assert g[0] == rho
+    assert_same_ple(g, oracle_ple(A, n), "%dx%d rank %d" % (m, n, rho))
+
+
+def test_parity_degenerate():
+    for m, n in [(300, 300), (65, 200)]:
+        say("zero matrix", m, n)
+        A = np.zeros((m, inputs.words(n)), np.uint64)
+        g = gpu_ple(A, n)
+        assert g[0] == 0
+        assert_same_ple(g, oracle_ple(A, n), "zero")
+    say("identity and reversed identity")
+    for rev in (False, True):
+        bits = np.eye(200, dtype=np.uint8)
+        if rev:
+            bits = bits[::-1].copy()
+        A = H.pack(bits)
+        assert_same_ple(gpu_ple(A, 200), oracle_ple(A, 200), "eye rev=%s" % rev)
+    say("all-ones")
+    A = H.pack(np.ones((150, 170), np.uint8))
+    assert_same_ple(gpu_ple(A, 170), oracle_ple(A, 170), "ones")
+    say("padding words")
+    A = inputs.bernoulli(100, 100, 5, ldw=5)
+    assert_same_ple(gpu_ple(A, 100), oracle_ple(A, 100), "ldw 5")
+
+
+def test_empty_shapes():
+    for m, n in [(0, 10), (10, 0), (0, 0)]:
+        say("empty", m, n)
+        A = np.zeros((m, inputs.words(n)), np.uint64)
+        t = torch.zeros((m, inputs.words(n)), dtype=torch.int64, device="cuda")
+        P, Q, rank = G.ple(t, n)
+        torch.cuda.synchronize()
+        assert int(rank.item()) == 0
+        assert list(P.cpu().numpy()) == list(range(m))
+        assert Q.numel() == 0
+
+
+def test_paper_examples_on_gpu():
+    blocks = dict(H.read_golden("perm_example.txt"))
+    mat = np.array(blocks["matrix"], dtype=np.uint8)
+    r, P, Q, out = gpu_ple(H.pack(mat), 5)
+    assert r == 5 and list(P) == blocks["P"]
+    for key, val in H.read_golden("postprocess_example.txt"):
+        if key == "case":
+            case = np.array(val, dtype=np.uint8)
+        else:
+            r, P, Q, out = gpu_ple(H.pack(case), 8)
+            assert list(H.unpack(out, 8)[3, :3]) == val
+
+
+@pytest.mark.parametrize("m,n,seed,rho", [(16384, 16384, 2, None), (16384, 16384, 3, 12000)])
+def test_parity_16384(m, n, seed, rho):
+    say("parity 16384^2 seed", seed, "rank", rho)
+    if rho is None:
+        A = inputs.bernoulli(m, n, seed)
+    else:
+        A = inputs.known_rank(m, n, rho, seed, seed + 1, device="cuda")
+    g = gpu_ple(A, n)
+    if rho is not None:
+        assert g[0] == rho
+    say("  gpu done, rank", g[0])
+    assert_same_ple(g, oracle_ple(A, n), "16384^2")
+
+
+# --- the other calls ---------------------------------------------------------
+
+@pytest.mark.parametrize("m,k,n", [(1, 1, 1), (100, 64, 100), (257, 130, 1000), (1000, 200, 64), (64, 1, 513),
+                                   (3000, 64, 3000)])
+def test_addmul_parity(m, k, n):
+    say("addmul", m, k, n)
+    import oracle
+    C = inputs.bernoulli(m, n, 1 + m)
+    A = inputs.bernoulli(m, k, 2 + k)
+    B = inputs.bernoulli(k, n, 3 + n)
+    want = C.copy()
+    oracle.addmul(want, A, B, k, n)
+    tC = to_dev(C)
+    G.addmul(tC, to_dev(A), to_dev(B), k, n)
+    assert np.array_equal(to_host(tC), want)
+
+
+def test_make_table_parity():
+    import oracle
+    f3 = dict(H.read_golden("fig3_m4ri.txt"))
+    piv = H.pack(np.array(f3["pivots"], np.uint8))
+    T = to_host(G.make_table(to_dev(piv), 3, 8))
+    assert np.array_equal(H.unpack(T, 8), np.array(f3["table"], np.uint8))
+    for k, n in [(1, 5), (4, 130), (8, 1000)]:
+        rows = inputs.bernoulli(k, n, 40 + k)
+        T = to_host(G.make_table(to_dev(rows), k, n))
+        assert np.array_equal(T, oracle.make_table(rows, k))
+
+
+@pytest.mark.parametrize("m,n,kind", [(300, 500, "u"), (1000, 1000, "u"), (700, 400, "r"), (129, 2000, "u"),
+                                      (2000, 700, "r"), (600, 600, "s")])
+def test_echelon_and_rref_parity(m, n, kind):
+    say("echelon/rref", m, n, kind)
+    import oracle
+    if kind == "u":
+        A = inputs.bernoulli(m, n, 21 + m)
+    elif kind == "r":
+        A = inputs.known_rank(m, n, min(m, n) // 2, 5, 6)
+    else:
+        A = inputs.bernoulli(m, n, 22 + m, p=0.01)
+    # echelon
+    t = to_dev(A)
+    P, Q, rank = G.ple(t, n)
+    G.echelon_from_ple(t, n, rank)
+    B = A.copy()
+    r, _, _ = oracle.ple(B, n)
+    oracle.echelon_from_ple(B, n, r)
+    assert np.array_equal(to_host(t), B)
+    # rref via the combined call
+    t = to_dev(A)
+    P, Q, rank = G.rref(t, n)
+    R, r2, _ = oracle.rref(A, n)
+    assert int(rank.item()) == r2
+    assert np.array_equal(to_host(t), R)
+
+
+def test_check_padding():
+    A = inputs.bernoulli(50, 70, 3)
+    t = to_dev(A)
+    assert G.check_padding(t, 70) == 0
+    A2 = A.copy()
+    A2[7, 1] |= np.uint64(1) << np.uint64(20)
+    assert G.check_padding(to_dev(A2), 70) == 6
+    with pytest.raises(G.GF2Error):
+        G.ple(to_dev(A2), 70, check_padding=True)
