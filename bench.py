@@ -1,0 +1,211 @@
+#!/usr/bin/env python
+"""Benchmark: PLE decomposition of a dense 65536 x 65536 GF(2) matrix on one
+MI355X through the C ABI (gf2_ple).
+
+One step = one full PLE (every pass of Algorithm 2: panel, permute, trailing
+update) of the resident matrix.  Before each step the input is restored from
+a pristine device copy (a 512 MiB device-to-device copy, inside the timed
+region, about 0.1 ms of a step).  Prints ONE JSON line on stdout; progress
+goes to stderr.
+
+  value      whole-job throughput in PLE decompositions per second
+  roofline   the dominant kernel (the Four-Russians trailing update k_m4rm):
+             algorithmic bytes per launch / average launch time, both from a
+             second, event-timed repetition of the same steps (HIP events on
+             the launch stream, recorded by the library itself)
+  cpu_baseline  the CPU oracle (plain Gaussian elimination) timed on this
+             host on a bounded sample, scaled by n^3 to the full matrix
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+KW = 64
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of k_m4rm on this workload, per
+# launch averaged over the run, with the source hash of the kernel file they
+# were taken on; reported only while that source is unchanged.
+TRAFFIC = None
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes_m4rm(m, n, Q, r):
+    """Algorithmic bytes of the trailing-update launches of one PLE: one
+    8-byte read and one 8-byte write per trailing row word per pass
+    (rows r_t .. m-1, words after the stripe), for passes with a pivot."""
+    import numpy as np
+    nw = (n + 63) // 64
+    q = np.asarray(Q[:r], dtype=np.int64)
+    total = 0
+    active = 0
+    npass = nw
+    counts = np.bincount(q // KW, minlength=npass) if r else np.zeros(npass, np.int64)
+    r_t = 0
+    for t in range(npass):
+        rbar = int(counts[t])
+        if r_t < m and rbar > 0 and t + 1 < nw:
+            total += 16 * (m - r_t) * (nw - t - 1)
+            active += 1
+        r_t += rbar
+    return total, active
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1111_6549_amd", "csrc", "ple_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(n_full, sample):
+    """The oracle, untouched, on a sample x sample Bernoulli(0.5) matrix."""
+    import oracle
+    from paper_1111_6549_amd import inputs
+    A = inputs.bernoulli(sample, sample, 2)
+    oracle.ple(A[:64, :1].copy(), 64)  # load/compile outside the timing
+    t0 = time.perf_counter()
+    r, _, _ = oracle.ple(A, sample)
+    dt = time.perf_counter() - t0
+    scale = (n_full / sample) ** 3
+    return {
+        "value": 1.0 / (dt * scale),
+        "unit": "matrices/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": "%dx%d Bernoulli(0.5) seed 2, whole oracle PLE in %.2f s (rank %d), scaled by (%d/%d)^3"
+                  % (sample, sample, dt, r, n_full, sample),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--m4-variant", type=int, default=0, help="update schedule 1..8 (0 = library default)")
+    ap.add_argument("--m4-blocks", type=int, default=0, help="target blocks per update launch (0 = default)")
+    ap.add_argument("--panel-regs", type=int, default=0, help="panel register window 2/4/8 (0 = default)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the PLE of one matrix is not split across GPUs here "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1111_6549_amd import gf2ple as G
+    from paper_1111_6549_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    G.load()
+    m = n = args.n
+    ldw = inputs.words(n)
+    log("generating %dx%d Bernoulli(0.5) seed %d" % (m, n, args.seed))
+    A = inputs.bernoulli(m, n, args.seed)
+    pristine = torch.from_numpy(A.view(np.int64)).cuda()
+    del A
+    work = torch.empty_like(pristine)
+    ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw))
+    torch.cuda.synchronize()
+
+    sched = dict(m4_variant=args.m4_variant, m4_blocks=args.m4_blocks, panel_regs=args.panel_regs)
+
+    def step():
+        work.copy_(pristine)
+        return G.ple(work, n, ws=ws, **sched)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log("warmup %d done" % i)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        P, Q, rank = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    r = int(rank.item())
+    log("timed %d steps: %.3f ms/step, rank %d" % (args.steps, ms_per_step, r))
+
+    Qh = Q.cpu().numpy()
+    abytes, active = alg_bytes_m4rm(m, n, Qh, r)
+
+    roofline = None
+    kernels = None
+    if not args.no_profile:
+        G.profile_start()
+        for i in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        kernels = G.profile_stop()
+        k = kernels.get("m4rm")
+        if k and k["total_ms"] > 0:
+            launches_per_step = k["launches"] / args.steps
+            bytes_per_launch = abytes / launches_per_step
+            avg_ms = k["total_ms"] / k["launches"]
+            achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+            traffic = None
+            if TRAFFIC and TRAFFIC.get("source") == kernel_source_hash():
+                traffic = TRAFFIC["bytes_per_launch"]
+            roofline = {
+                "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": "k_m4rm", "launches_per_step": launches_per_step,
+                "alg_bytes_per_launch": round(bytes_per_launch), "avg_launch_ms": round(avg_ms, 5),
+            }
+        log("profiled: %s" % json.dumps(kernels))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on %d^2" % args.cpu_sample)
+        cpu = cpu_baseline(n, args.cpu_sample)
+        log("cpu baseline done: %s" % cpu["sample"])
+
+    out = {
+        "metric": "PLE time & HBM GB/s (% roofline), 65536² GF(2); batched matrices/s vs plain",
+        "value": round(1000.0 / ms_per_step, 4),
+        "unit": "matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "PLE of a dense %dx%d GF(2) matrix, Bernoulli(0.5), seed %d, uint64 row words"
+                               % (m, n, args.seed),
+                   "m": m, "n": n, "pass_width_K": KW, "table_bits": 8, "tables_per_pass": 8,
+                   "tile_words": 8, "update": "xor-table", "schedule": sched},
+        "rank": r,
+        "alg_bytes_per_step": abytes,
+        "alg_GBps_whole_ple": round(abytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels_ms_per_step": {k: round(v["total_ms"] / args.steps, 3) for k, v in (kernels or {}).items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

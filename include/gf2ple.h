@@ -49,7 +49,10 @@ typedef struct gf2_ple_opts {
     int32_t check_padding; /* 1: scan for set bits at columns >= n first (synchronises) */
     int32_t update;        /* trailing update: 0 = default, 1 = XOR table (Four Russians), 2 = int8 MFMA */
     int32_t mfma_block;    /* MFMA outer panel width in columns (multiple of 64; 0 = default 256) */
-    int32_t reserved[5];
+    int32_t m4_variant;    /* Four-Russians update schedule: 0 = default, 1..8 = a fixed (tile, threads, unroll) */
+    int32_t m4_blocks;     /* target blocks per update launch (0 = default 512) */
+    int32_t panel_regs;    /* pivot-search register window of the panel: 0 = default, 2, 4 or 8 x 64 rows */
+    int32_t reserved[2];
 } gf2_ple_opts;
 
 /* Library version string, e.g. "gf2ple 0.1.0 gfx950". */
@@ -136,6 +139,26 @@ gf2_status gf2_make_table(const uint64_t *rows, int64_t ldr, int32_t k, int64_t 
 /* Scan for set bits at columns >= n (padding); synchronises the stream.
  * Returns GF2_OK or GF2_EPADDING. */
 gf2_status gf2_check_padding(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, void *stream);
+
+/*
+ * Kernel timing.  Between gf2_profile_start() and gf2_profile_stop() every
+ * kernel the library launches is bracketed by two HIP events recorded on its
+ * launch stream (a small overhead per launch).  gf2_profile_stop waits for
+ * the recorded events and writes up to max_entries per-kernel totals
+ * (launch count, summed/min/max elapsed milliseconds) to `out` (host memory),
+ * and the number of kernels seen to *count.  Process-wide; not for
+ * concurrent use from several host threads.
+ */
+typedef struct gf2_kernel_time {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+    double min_ms;
+    double max_ms;
+} gf2_kernel_time;
+
+gf2_status gf2_profile_start(void);
+gf2_status gf2_profile_stop(gf2_kernel_time *out, int32_t max_entries, int32_t *count);
 
 #ifdef __cplusplus
 }

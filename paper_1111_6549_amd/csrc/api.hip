@@ -9,11 +9,12 @@
 
 namespace gf2 {
 hipError_t launch_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *rank, PassRec *rec, hipStream_t s);
-hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, PassRec *rec, int64_t *P,
-                       int64_t *Q, int64_t *rank, uint64_t *coef, uint64_t *PB, uint64_t *gsv, int32_t *gsid,
-                       hipStream_t s);
+hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
+                       int64_t *P, int64_t *Q, int64_t *rank, uint64_t *coef, uint64_t *PB, uint64_t *gsv,
+                       int32_t *gsid, int m4_variant, int m4_target, int panel_regs, hipStream_t s);
 hipError_t launch_m4rm(uint64_t *C, int64_t ldc, int64_t m, const uint64_t *coef, int64_t coef_ld, const uint64_t *B,
-                       int64_t ldb, int nbits, int64_t w_begin, int64_t w_end, hipStream_t s);
+                       int64_t ldb, int nbits, int64_t w_begin, int64_t w_end, int m4_variant, int m4_target,
+                       hipStream_t s);
 hipError_t launch_echelon(uint64_t *A, int64_t m, int64_t ldw, const int64_t *rank, hipStream_t s);
 hipError_t launch_padding(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, int *flag, hipStream_t s);
 hipError_t launch_make_table(const uint64_t *rows, int64_t ldr, int k, int64_t nw, uint64_t *T, int64_t ldt,
@@ -39,7 +40,7 @@ PleLayout ple_layout(int64_t m, int64_t ldw) {
     PleLayout L;
     size_t off = 0;
     L.rec = off;
-    off += align_up(sizeof(PassRec));
+    off += align_up(2 * sizeof(PassRec));  // records of consecutive passes alternate
     L.coef = off;
     off += align_up((size_t)m * 8);
     L.pb = off;
@@ -142,7 +143,9 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
     if (m > 0 && (!P || !aligned(P, 8))) return GF2_EINVAL;
     if (mn > 0 && (!Q || !aligned(Q, 8))) return GF2_EINVAL;
     if (m > 0 && ldw > 0 && (!A || !aligned(A, 8))) return GF2_EINVAL;
-    if (opts && (opts->update < 0 || opts->update > 2)) return GF2_EINVAL;
+    if (opts && (opts->update < 0 || opts->update > 2 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
+    if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
+        return GF2_EINVAL;
     if (opts && opts->update == 2) return GF2_EINVAL;  // MFMA trailing update: see gf2_addmul
     const PleLayout L = ple_layout(m, ldw);
     if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;
@@ -153,13 +156,13 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
         if (st != GF2_OK) return st;
     }
     char *base = (char *)ws;
-    PassRec *rec = (PassRec *)(base + L.rec);
+    PassRec *recs = (PassRec *)(base + L.rec);
     uint64_t *coef = (uint64_t *)(base + L.coef);
     uint64_t *PB = (uint64_t *)(base + L.pb);
     uint64_t *gsv = (uint64_t *)(base + L.gsv);
     int32_t *gsid = (int32_t *)(base + L.gsid);
 
-    if (launch_init(P, m, Q, mn, rank, rec, s) != hipSuccess) return GF2_EHIP;
+    if (launch_init(P, m, Q, mn, rank, recs, s) != hipSuccess) return GF2_EHIP;
     if (m == 0 || n == 0) return GF2_OK;
 
     const int64_t npasses = words_for(n);
@@ -176,7 +179,10 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
             }
             since_check = (since_check + 1) % 8;
         }
-        if (launch_pass(A, m, n, ldw, c, rec, P, Q, rank, coef, PB, gsv, gsid, s) != hipSuccess) return GF2_EHIP;
+        if (launch_pass(A, m, n, ldw, c, &recs[(t + 1) & 1], &recs[t & 1], P, Q, rank, coef, PB, gsv, gsid,
+                        opts ? opts->m4_variant : 0, opts ? opts->m4_blocks : 0, opts ? opts->panel_regs : 0,
+                        s) != hipSuccess)
+            return GF2_EHIP;
     }
     return hip_status(hipGetLastError());
 }
@@ -224,7 +230,7 @@ gf2_status gf2_rref_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, con
         const int64_t j1 = j0 + KW < r ? j0 + KW : r;
         const int64_t wq0 = hq[(size_t)j0] >> 6;
         if (launch_rref_block(A, ldw, nw, Q, j0, j1, wq0, coef, PB, s) != hipSuccess) return GF2_EHIP;
-        if (launch_m4rm(A, ldw, j1, coef, 1, PB, ldw, (int)(j1 - j0), wq0, nw, s) != hipSuccess) return GF2_EHIP;
+        if (launch_m4rm(A, ldw, j1, coef, 1, PB, ldw, (int)(j1 - j0), wq0, nw, 0, 0, s) != hipSuccess) return GF2_EHIP;
     }
     return hip_status(hipGetLastError());
 }
@@ -247,7 +253,7 @@ gf2_status gf2_addmul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, 
                       int64_t m, int64_t k, int64_t n, const gf2_ple_opts *opts, void *stream) {
     if (m < 0 || k < 0 || n < 0) return GF2_EINVAL;
     if (ldc < words_for(n) || lda < words_for(k) || ldb < words_for(n)) return GF2_EINVAL;
-    if (opts && (opts->update < 0 || opts->update > 2)) return GF2_EINVAL;
+    if (opts && (opts->update < 0 || opts->update > 2 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
     if (m == 0 || n == 0 || k == 0) return GF2_OK;
     if (!C || !A || !B || !aligned(C, 8) || !aligned(A, 8) || !aligned(B, 8)) return GF2_EINVAL;
     if (opts && opts->update == 2) return GF2_EINVAL;  // not built yet
@@ -255,7 +261,9 @@ gf2_status gf2_addmul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, 
     const int64_t nw = words_for(n);
     for (int64_t kb = 0; kb * KW < k; kb++) {
         const int nb = (int)(k - kb * KW < KW ? k - kb * KW : KW);
-        if (launch_m4rm(C, ldc, m, A + kb, lda, B + kb * KW * ldb, ldb, nb, 0, nw, s) != hipSuccess) return GF2_EHIP;
+        if (launch_m4rm(C, ldc, m, A + kb, lda, B + kb * KW * ldb, ldb, nb, 0, nw, opts ? opts->m4_variant : 0,
+                        opts ? opts->m4_blocks : 0, s) != hipSuccess)
+            return GF2_EHIP;
     }
     return hip_status(hipGetLastError());
 }

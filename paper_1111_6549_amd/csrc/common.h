@@ -10,7 +10,7 @@ namespace gf2 {
 // the stripe one aligned 64-bit word per row, since c advances by the full
 // stripe width every pass whatever the stripe's rank.
 constexpr int KW = 64;
-// Pivot search window held in registers by the panel wave: WIN_Q x 64 rows.
+// Largest pivot-search window held in registers by the panel wave: WIN_Q x 64 rows.
 constexpr int WIN_Q = 8;
 // Pivot rows plus rows displaced by the pass's swaps (each swap moves <= 2).
 constexpr int MAX_SPEC = 2 * KW;
@@ -41,5 +41,23 @@ struct PassRec {
 };
 
 __host__ __device__ inline int64_t words_for(int64_t n) { return (n + 63) >> 6; }
+
+// Kernel timing: when enabled (gf2_profile_start), every launch site brackets
+// its kernel with HIP events on the launch stream.
+enum KernelId { KID_PANEL = 0, KID_PERMUTE, KID_M4RM, KID_INIT, KID_RREF, KID_ECHELON, KID_MFMA, KID_BATCH, KID_COUNT };
+bool prof_enabled();
+void prof_mark(int kid, hipStream_t s, bool begin);
+
+struct ProfScope {
+    int kid;
+    hipStream_t s;
+    bool on;
+    ProfScope(int k, hipStream_t st) : kid(k), s(st), on(prof_enabled()) {
+        if (on) prof_mark(kid, s, true);
+    }
+    ~ProfScope() {
+        if (on) prof_mark(kid, s, false);
+    }
+};
 
 }  // namespace gf2

@@ -1,0 +1,45 @@
+// Small device helpers shared by the kernels (wave64 cross-lane moves).
+#pragma once
+#include "common.h"
+
+namespace gf2 {
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int readlane32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// lane l takes the (uniform) value v, the other lanes keep theirs
+__device__ __forceinline__ uint64_t writelane64(uint64_t old, uint64_t v, int l) {
+    return (int)__lane_id() == l ? v : old;
+}
+
+__device__ __forceinline__ int writelane32(int old, int v, int l) { return (int)__lane_id() == l ? v : old; }
+
+// a value the whole wave agrees on, kept in a scalar register
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        lo |= (uint32_t)__shfl_xor((int)lo, off, 64);
+        hi |= (uint32_t)__shfl_xor((int)hi, off, 64);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// bits strictly above column j of a word
+__device__ __forceinline__ uint64_t above(int j) { return j >= 63 ? 0ull : (~0ull << (j + 1)); }
+
+// The part of the rbar-bit vector u (bit l = column r + l) that falls into word w.
+__device__ __forceinline__ uint64_t place_bits(uint64_t u, int64_t w, int64_t wr0, int sh) {
+    if (w == wr0) return u << sh;
+    if (sh && w == wr0 + 1) return u >> (64 - sh);
+    return 0;
+}
+
+}  // namespace gf2

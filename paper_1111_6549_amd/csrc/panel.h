@@ -1,0 +1,355 @@
+// The panel of one pass: Algorithm 1 (PartialPle) on a 64-column stripe,
+// run by one wavefront.  Included by the kernels that launch it.
+//
+// Search.  For each stripe column j in turn, the pivot is the first row at or
+// below the current rank position, in the current row order, whose entry is
+// 1 after reduction by the pivots already found (Algorithm 1's search loop);
+// it is swapped in whole.  Laziness (Algorithm 1): rows are fetched and
+// reduced only when the search reaches them, 64 at a time into the wave's
+// registers (lane = row, ballot = "which rows have a 1 in column j").  If the
+// register window (WQ x 64 rows) runs out, the search restarts over every
+// remaining row in LDS or workspace ("slow" path).
+//
+// Replay.  The pass's maps (Section 3.2's T and T') come out of one more run
+// of the same eliminations that carries, next to each stripe word, the sum h
+// of the pivot "histories" it was reduced by and the set u of pivots used.
+// A pivot row's history starts as its own unit vector, so it ends as its row
+// of L11^-1 (the TRSM of Algorithm 2); a non-pivot row ends with h = its
+// coefficients on the pivot rows as they were (Orig) and u = its L bits.
+// Replaying the 64 unit stripe vectors gives both maps for every other row
+// by linearity: a row with stripe word v becomes row + w*Orig with
+// w = xor of h(e_j) over the set bits j of v, and gets the L bits
+// u = xor of u(e_j).
+#pragma once
+#include "dev.h"
+
+namespace gf2 {
+
+struct PanelLds {
+    int64_t dst[MAX_SPEC], src[MAX_SPEC];
+    uint64_t sv[SLOW_LDS_ROWS];
+    int32_t sid[SLOW_LDS_ROWS];
+};
+
+// One wave (lane = threadIdx.x & 63) computes the panel of the stripe at
+// column c.  `prev` is the previous pass's record (its r + rbar is this
+// pass's r), `rec` receives this pass.  Writes P[r..r+rbar), Q[r..r+rbar)
+// and *rank_out = r + rbar.
+template <int WQ>
+__device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64_t m, int64_t n, int64_t ldw, int64_t c,
+                                           const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
+                                           int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelLds &L,
+                                           const int lane) {
+#ifdef GF2_PANEL_TIMING
+    uint64_t *dbg = gsv + (c >> 6) * 8;
+#define PANEL_STAMP(k) \
+    if (lane == 0) dbg[k] = wall_clock64();
+#else
+#define PANEL_STAMP(k)
+#endif
+    PANEL_STAMP(0)
+    const int64_t r = prev->r + prev->rbar;
+    if (r >= m || c >= n) {
+        if (lane == 0) {
+            rec->r = r;
+            rec->rbar = 0;
+            rec->nspec = 0;
+            rec->active = 0;
+            rec->slow = 0;
+            *rank_out = r;
+        }
+        return;
+    }
+    const int kp = (int)((n - c) < KW ? (n - c) : KW);
+    const uint64_t kmask = kp == 64 ? ~0ull : ((1ull << kp) - 1);
+    const int64_t sw = c >> 6;
+    const int64_t rows = m - r;
+
+    // lane l keeps pivot l: stripe column, reduced stripe word, window position
+    int my_q = 0;
+    uint64_t my_fin = 0;
+    int my_p = 0;
+    int npiv = 0;
+    int nspec = 0;
+    bool slow = false;
+
+    // ---- search over a register window, grown 64 rows at a time -------------
+    {
+        uint64_t val[WQ];
+        int id[WQ];
+#pragma unroll
+        for (int q = 0; q < WQ; q++) {
+            val[q] = 0;
+            id[q] = 64 * q + lane;
+        }
+        const int nmax = (int)(rows < 64 * WQ ? rows : 64 * WQ);
+        const int nregmax = (nmax + 63) >> 6;
+        int nreg = 0;
+        // fetch registers [nreg, want) and reduce them by the pivots so far
+        auto extend = [&](int want) {
+            uint64_t tmp[WQ];
+#pragma unroll
+            for (int q = 0; q < WQ; q++) {
+                if (q >= nreg && q < want) {
+                    const int pos = 64 * q + lane;
+                    const int64_t row = r + (pos < rows ? pos : rows - 1);
+                    tmp[q] = A[row * ldw + sw];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < WQ; q++) {
+                if (q >= nreg && q < want) val[q] = (64 * q + lane) < nmax ? (tmp[q] & kmask) : 0ull;
+            }
+            for (int l = 0; l < npiv; l++) {
+                const int ql = uni(readlane32(my_q, l));
+                const uint64_t fl = readlane64(my_fin, l) & above(ql);
+#pragma unroll
+                for (int q = 0; q < WQ; q++) {
+                    if (q >= nreg && q < want && ((val[q] >> ql) & 1ull)) val[q] ^= fl;
+                }
+            }
+            nreg = want;
+        };
+        extend(nregmax < 2 ? nregmax : 2);
+        PANEL_STAMP(1)
+
+        for (int j = 0; j < kp; j++) {
+            int found = -1;
+            for (;;) {
+#pragma unroll
+                for (int q = 0; q < WQ; q++) {
+                    if (found < 0 && q < nreg && 64 * q + 64 > npiv) {
+                        const int pos = 64 * q + lane;
+                        const bool b = pos >= npiv && pos < nmax && ((val[q] >> j) & 1ull);
+                        const uint64_t msk = __ballot(b);
+                        if (msk) found = 64 * q + (int)__builtin_ctzll(msk);
+                    }
+                }
+                found = uni(found);
+                if (found >= 0 || nreg >= nregmax) break;
+                extend(uni(nreg + 1));
+            }
+            if (found < 0) {
+                if (nmax < rows) {  // a row outside the window may hold the pivot
+                    slow = true;
+                    break;
+                }
+                continue;  // column j has no pivot
+            }
+            const int qf = found >> 6, lf = found & 63, qn = npiv >> 6, ln = npiv & 63;
+            uint64_t pv = 0;
+#pragma unroll
+            for (int q = 0; q < WQ; q++)
+                if (q == qf) pv = readlane64(val[q], lf);
+            if (found != npiv) {  // the row at npiv moves to `found`
+                uint64_t vr = 0;
+                int idr = 0, idp = 0;
+#pragma unroll
+                for (int q = 0; q < WQ; q++) {
+                    if (q == qn) {
+                        vr = readlane64(val[q], ln);
+                        idr = readlane32(id[q], ln);
+                    }
+                    if (q == qf) idp = readlane32(id[q], lf);
+                }
+#pragma unroll
+                for (int q = 0; q < WQ; q++) {
+                    if (q == qf) {
+                        val[q] = writelane64(val[q], vr, lf);
+                        id[q] = writelane32(id[q], idr, lf);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < WQ; q++) {
+                    if (q == qn) {
+                        val[q] = writelane64(val[q], pv, ln);
+                        id[q] = writelane32(id[q], idp, ln);
+                    }
+                }
+            }
+            const uint64_t pe = pv & above(j);
+#pragma unroll
+            for (int q = 0; q < WQ; q++) {
+                if (q < nreg && 64 * q + 64 > npiv) {
+                    const int pos = 64 * q + lane;
+                    if (pos > npiv && ((val[q] >> j) & 1ull)) val[q] ^= pe;
+                }
+            }
+            my_q = writelane32(my_q, j, npiv);
+            my_fin = writelane64(my_fin, pv, npiv);
+            my_p = writelane32(my_p, found, npiv);
+            npiv = uni(npiv + 1);
+            if (npiv == rows) break;
+        }
+        PANEL_STAMP(2)
+        if (!slow) {
+            int base = 0;
+#pragma unroll
+            for (int q = 0; q < WQ; q++) {
+                if (q < nreg) {
+                    const int pos = 64 * q + lane;
+                    const bool f = pos < nmax && (pos < npiv || id[q] != pos);
+                    const uint64_t msk = __ballot(f);
+                    const int idx = base + __popcll(msk & ((1ull << lane) - 1ull));
+                    if (f) {
+                        L.dst[idx] = r + pos;
+                        L.src[idx] = r + id[q];
+                    }
+                    base += __popcll(msk);
+                }
+            }
+            nspec = uni(base);
+        }
+    }
+
+    // ---- slow path: every remaining row, window in LDS or workspace ---------
+    if (slow) {
+        npiv = 0;
+        my_q = 0;
+        my_fin = 0;
+        my_p = 0;
+        volatile uint64_t *sv = rows <= SLOW_LDS_ROWS ? (volatile uint64_t *)L.sv : (volatile uint64_t *)gsv;
+        volatile int32_t *sid = rows <= SLOW_LDS_ROWS ? (volatile int32_t *)L.sid : (volatile int32_t *)gsid;
+        uint64_t orv = 0;
+        for (int64_t pos = lane; pos < rows; pos += 64) {
+            const uint64_t v = A[(r + pos) * ldw + sw] & kmask;
+            sv[pos] = v;
+            sid[pos] = (int32_t)pos;
+            orv |= v;
+        }
+        orv = wave_or64(orv);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        for (int j = 0; j < kp && npiv < rows; j++) {
+            if (!((orv >> j) & 1ull)) continue;  // no remaining row has a 1 here
+            int64_t found = -1;
+            for (int64_t base = npiv & ~(int64_t)63; base < rows; base += 64) {
+                const int64_t pos = base + lane;
+                const bool b = pos >= npiv && pos < rows && ((sv[pos] >> j) & 1ull);
+                const uint64_t msk = __ballot(b);
+                if (msk) {
+                    found = base + __builtin_ctzll(msk);
+                    break;
+                }
+            }
+            if (found < 0) continue;  // unreachable: orv says a row has bit j
+            const uint64_t pv = sv[found];
+            const int32_t idp = sid[found];
+            const uint64_t vr = sv[npiv];
+            const int32_t idr = sid[npiv];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (lane == 0) {
+                sv[found] = vr;
+                sid[found] = idr;
+                sv[npiv] = pv;
+                sid[npiv] = idp;
+            }
+            my_q = writelane32(my_q, j, npiv);
+            my_fin = writelane64(my_fin, pv, npiv);
+            my_p = writelane32(my_p, (int)found, npiv);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const uint64_t pe = pv & above(j);
+            orv = 0;
+            for (int64_t pos = npiv + 1 + lane; pos < rows; pos += 64) {
+                uint64_t v = sv[pos];
+                if ((v >> j) & 1ull) {
+                    v ^= pe;
+                    sv[pos] = v;
+                }
+                orv |= v;
+            }
+            orv = wave_or64(orv);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            npiv = uni(npiv + 1);
+        }
+        int base = 0;
+        for (int64_t pb = 0; pb < rows; pb += 64) {
+            const int64_t pos = pb + lane;
+            const bool f = pos < rows && (pos < npiv || sid[pos] != (int32_t)pos);
+            const uint64_t msk = __ballot(f);
+            const int idx = base + __popcll(msk & ((1ull << lane) - 1ull));
+            if (f) {
+                L.dst[idx] = r + pos;
+                L.src[idx] = r + sid[pos];
+            }
+            base += __popcll(msk);
+        }
+        nspec = uni(base);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    PANEL_STAMP(3)
+
+    // ---- replay with histories ---------------------------------------------
+    const int rbar = uni(npiv);
+    const int ndisp = nspec - rbar;  // <= rbar <= 64
+    // displaced rows (lane d <-> special entry rbar + d): their stripe words as
+    // they were when the pass began
+    uint64_t vD = 0;
+    if (lane < ndisp) vD = A[L.src[rbar + lane] * ldw + sw] & kmask;
+    uint64_t vV = (lane < kp) ? (1ull << lane) : 0ull;  // unit stripe vectors
+    uint64_t hP = (lane < rbar) ? (1ull << lane) : 0ull, uP = 0;
+    uint64_t hV = 0, uV = 0, hD = 0, uD = 0;
+    for (int l = 0; l < rbar; l++) {
+        const int ql = uni(readlane32(my_q, l));
+        const uint64_t pe = readlane64(my_fin, l) & above(ql);
+        const uint64_t hl = readlane64(hP, l);  // final: pivot l is reduced by pivots < l only
+        const uint64_t bl = 1ull << l;
+        if (lane > l && ((my_fin >> ql) & 1ull)) {
+            hP ^= hl;
+            uP |= bl;
+        }
+        if ((vV >> ql) & 1ull) {
+            vV ^= pe;
+            hV ^= hl;
+            uV |= bl;
+        }
+        if ((vD >> ql) & 1ull) {
+            vD ^= pe;
+            hD ^= hl;
+            uD |= bl;
+        }
+    }
+    PANEL_STAMP(4)
+    rec->img_w[lane] = hV;
+    rec->img_u[lane] = uV;
+    for (int kb = 0; kb < nspec; kb += 64) {
+        const int k = kb + lane;
+        if (k < nspec) {
+            rec->spec_dst[k] = L.dst[k];
+            rec->spec_src[k] = L.src[k];
+        }
+    }
+    if (lane < ndisp) {
+        rec->spec_coef[rbar + lane] = hD;
+        rec->spec_lbits[rbar + lane] = uD;
+        rec->spec_stripe[rbar + lane] = 0;
+    }
+    if (lane < rbar) {
+        rec->spec_coef[lane] = hP ^ (1ull << lane);  // row of L11^-1 without its diagonal
+        rec->spec_lbits[lane] = uP;                   // row of L11
+        rec->spec_stripe[lane] = my_fin & ~((1ull << my_q) - 1ull);
+        P[r + lane] = r + my_p;
+        Q[r + lane] = c + my_q;
+    }
+    if (lane == 0) {
+        rec->r = r;
+        rec->rbar = rbar;
+        rec->nspec = nspec;
+        rec->active = rbar > 0;
+        rec->slow = slow ? 1 : 0;
+        *rank_out = r + rbar;
+    }
+    PANEL_STAMP(5)
+#undef PANEL_STAMP
+}
+
+}  // namespace gf2

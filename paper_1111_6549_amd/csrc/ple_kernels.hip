@@ -22,331 +22,38 @@
 //              Algorithm 2 folded into the lookup.
 //
 // The same k_m4rm kernel is the public GF(2) product gf2_addmul.
-#include "common.h"
+#include "m4rm.h"
+#include "panel.h"
 
 namespace gf2 {
-
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
-    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ int readlane32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-
-__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
-    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        lo |= (uint32_t)__shfl_xor((int)lo, off, 64);
-        hi |= (uint32_t)__shfl_xor((int)hi, off, 64);
-    }
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// bits strictly above column j of a word
-__device__ __forceinline__ uint64_t above(int j) { return j >= 63 ? 0ull : (~0ull << (j + 1)); }
-
-// The part of the rbar-bit vector u (bit l = column r + l) that falls into word w.
-__device__ __forceinline__ uint64_t place_bits(uint64_t u, int64_t w, int64_t wr0, int sh) {
-    if (w == wr0) return u << sh;
-    if (sh && w == wr0 + 1) return u >> (64 - sh);
-    return 0;
-}
 
 // ---------------------------------------------------------------------------
 // k_init: P = identity, Q = -1, rank = 0, empty pass record.
 // ---------------------------------------------------------------------------
-__global__ void k_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *rank, PassRec *rec) {
+__global__ void k_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *rank, PassRec *recs) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = i; t < m; t += stride) P[t] = t;
     for (int64_t t = i; t < mn; t += stride) Q[t] = -1;
-    if (i == 0) {
-        *rank = 0;
-        rec->r = 0;
-        rec->rbar = 0;
-        rec->nspec = 0;
-        rec->active = 0;
-        rec->slow = 0;
+    if (i < 2 && recs) {
+        if (i == 0) *rank = 0;
+        recs[i].r = 0;
+        recs[i].rbar = 0;
+        recs[i].nspec = 0;
+        recs[i].active = 0;
+        recs[i].slow = 0;
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_panel: Algorithm 1 on the stripe word of rows r .. m-1 (one wave).
+// k_panel: one wave runs the panel of the stripe at column c.
 // ---------------------------------------------------------------------------
+template <int WQ>
 __global__ __launch_bounds__(64) void k_panel(const uint64_t *__restrict__ A, int64_t m, int64_t n, int64_t ldw,
-                                              int64_t c, PassRec *rec, int64_t *P, int64_t *Q, int64_t *rank_out,
-                                              uint64_t *gsv, int32_t *gsid) {
-    __shared__ uint64_t s_img_w[KW], s_img_u[KW];
-    __shared__ int64_t s_dst[MAX_SPEC], s_src[MAX_SPEC];
-    __shared__ uint64_t s_sv[SLOW_LDS_ROWS];
-    __shared__ int32_t s_sid[SLOW_LDS_ROWS];
-
-    const int lane = threadIdx.x;
-    const int64_t r = rec->r + rec->rbar;  // rank after the previous pass
-    __syncthreads();
-    if (r >= m || c >= n) {
-        if (lane == 0) {
-            rec->r = r;
-            rec->rbar = 0;
-            rec->nspec = 0;
-            rec->active = 0;
-            rec->slow = 0;
-            *rank_out = r;
-        }
-        return;
-    }
-    const int kp = (int)((n - c) < KW ? (n - c) : KW);
-    const uint64_t kmask = kp == 64 ? ~0ull : ((1ull << kp) - 1);
-    const int64_t sw = c >> 6;
-    const int64_t rows = m - r;
-
-    // lane l keeps pivot l: its stripe column, its reduced stripe word, and
-    // the window position it was found at
-    int my_q = 0;
-    uint64_t my_fin = 0;
-    int64_t my_p = 0;
-    int npiv = 0;
-    int nspec = 0;
-    bool slow = false;
-
-    // ---- fast path: rows r .. r + 64*WIN_Q - 1 in registers ------------------
-    {
-        uint64_t val[WIN_Q];
-        int32_t id[WIN_Q];
-        const int nload = (int)(rows < 64 * WIN_Q ? rows : 64 * WIN_Q);
-#pragma unroll
-        for (int q = 0; q < WIN_Q; q++) {
-            int pos = 64 * q + lane;
-            val[q] = pos < nload ? (A[(r + pos) * ldw + sw] & kmask) : 0ull;
-            id[q] = pos;
-        }
-        for (int j = 0; j < kp; j++) {
-            int found = -1;
-#pragma unroll
-            for (int q = 0; q < WIN_Q; q++) {
-                if (found < 0 && 64 * q < nload && 64 * q + 64 > npiv) {
-                    int pos = 64 * q + lane;
-                    bool b = pos >= npiv && pos < nload && ((val[q] >> j) & 1ull);
-                    uint64_t msk = __ballot(b);
-                    if (msk) found = 64 * q + __builtin_ctzll(msk);
-                }
-            }
-            if (found < 0) {
-                if (nload < rows) {  // a row outside the window may hold the pivot
-                    slow = true;
-                    break;
-                }
-                continue;  // column j has no pivot
-            }
-            uint64_t pv = 0, vr = 0;
-            int32_t idp = 0, idr = 0;
-#pragma unroll
-            for (int q = 0; q < WIN_Q; q++) {
-                if (q == (found >> 6)) {
-                    pv = readlane64(val[q], found & 63);
-                    idp = readlane32(id[q], found & 63);
-                }
-                if (q == (npiv >> 6)) {
-                    vr = readlane64(val[q], npiv & 63);
-                    idr = readlane32(id[q], npiv & 63);
-                }
-            }
-            const uint64_t pe = pv & above(j);
-#pragma unroll
-            for (int q = 0; q < WIN_Q; q++) {
-                int pos = 64 * q + lane;
-                if (pos == found) {
-                    val[q] = vr;
-                    id[q] = idr;
-                }
-                if (pos == npiv) {
-                    val[q] = pv;
-                    id[q] = idp;
-                } else if (pos > npiv && pos < nload && ((val[q] >> j) & 1ull)) {
-                    val[q] ^= pe;
-                }
-            }
-            if (lane == npiv) {
-                my_q = j;
-                my_fin = pv;
-                my_p = found;
-            }
-            npiv++;
-            if (npiv == rows) break;
-        }
-        if (!slow) {
-            int base = 0;
-#pragma unroll
-            for (int q = 0; q < WIN_Q; q++) {
-                int pos = 64 * q + lane;
-                bool f = pos < nload && (pos < npiv || id[q] != pos);
-                uint64_t msk = __ballot(f);
-                int idx = base + __popcll(msk & ((1ull << lane) - 1ull));
-                if (f) {
-                    s_dst[idx] = r + pos;
-                    s_src[idx] = r + id[q];
-                }
-                base += __popcll(msk);
-            }
-            nspec = base;
-        }
-    }
-
-    // ---- slow path: every remaining row, window in LDS or workspace ---------
-    if (slow) {
-        npiv = 0;
-        my_q = 0;
-        my_fin = 0;
-        my_p = 0;
-        volatile uint64_t *sv = rows <= SLOW_LDS_ROWS ? (volatile uint64_t *)s_sv : (volatile uint64_t *)gsv;
-        volatile int32_t *sid = rows <= SLOW_LDS_ROWS ? (volatile int32_t *)s_sid : (volatile int32_t *)gsid;
-        uint64_t orv = 0;
-        for (int64_t pos = lane; pos < rows; pos += 64) {
-            uint64_t v = A[(r + pos) * ldw + sw] & kmask;
-            sv[pos] = v;
-            sid[pos] = (int32_t)pos;
-            orv |= v;
-        }
-        orv = wave_or64(orv);
-        __syncthreads();
-        for (int j = 0; j < kp && npiv < rows; j++) {
-            if (!((orv >> j) & 1ull)) continue;  // no remaining row has a 1 here
-            int64_t found = -1;
-            for (int64_t base = npiv & ~(int64_t)63; base < rows; base += 64) {
-                int64_t pos = base + lane;
-                bool b = pos >= npiv && pos < rows && ((sv[pos] >> j) & 1ull);
-                uint64_t msk = __ballot(b);
-                if (msk) {
-                    found = base + __builtin_ctzll(msk);
-                    break;
-                }
-            }
-            if (found < 0) continue;  // unreachable: orv says a row has bit j
-            const uint64_t pv = sv[found];
-            const int32_t idp = sid[found];
-            const uint64_t vr = sv[npiv];
-            const int32_t idr = sid[npiv];
-            __syncthreads();
-            if (lane == 0) {
-                sv[found] = vr;
-                sid[found] = idr;
-                sv[npiv] = pv;
-                sid[npiv] = idp;
-            }
-            if (lane == npiv) {
-                my_q = j;
-                my_fin = pv;
-                my_p = found;
-            }
-            __syncthreads();
-            const uint64_t pe = pv & above(j);
-            orv = 0;
-            for (int64_t pos = npiv + 1 + lane; pos < rows; pos += 64) {
-                uint64_t v = sv[pos];
-                if ((v >> j) & 1ull) {
-                    v ^= pe;
-                    sv[pos] = v;
-                }
-                orv |= v;
-            }
-            orv = wave_or64(orv);
-            __syncthreads();
-            npiv++;
-        }
-        int base = 0;
-        for (int64_t pb = 0; pb < rows; pb += 64) {
-            int64_t pos = pb + lane;
-            bool f = pos < rows && (pos < npiv || sid[pos] != (int32_t)pos);
-            uint64_t msk = __ballot(f);
-            int idx = base + __popcll(msk & ((1ull << lane) - 1ull));
-            if (f) {
-                s_dst[idx] = r + pos;
-                s_src[idx] = r + sid[pos];
-            }
-            base += __popcll(msk);
-        }
-        nspec = base;
-    }
-    __syncthreads();
-
-    // ---- the pass's linear maps (Section 3.2, T and T') ---------------------
-    // F = pivot row's reduced stripe at the pivot columns: strictly below the
-    // diagonal the multipliers (L11), on and above it E11 restricted to the
-    // pivot columns (unit upper triangular).
-    const int rbar = npiv;
-    uint64_t F = 0;
-    for (int l2 = 0; l2 < rbar; l2++) {
-        int q2 = readlane32(my_q, l2);
-        F |= ((my_fin >> q2) & 1ull) << l2;
-    }
-    const uint64_t low = (1ull << lane) - 1ull;  // lane < 64
-    const uint64_t Ls = F & low;
-    const uint64_t Eu = F & ~low;
-    // X = L11^-1 (forward substitution, column by column)
-    uint64_t X = 1ull << lane;
-    for (int l2 = 0; l2 < rbar; l2++) {
-        uint64_t x2 = readlane64(X, l2);
-        if (lane > l2 && ((Ls >> l2) & 1ull)) X ^= x2;
-    }
-    // Y = E11pc^-1 (backward substitution)
-    uint64_t Y = 1ull << lane;
-    for (int l2 = rbar - 1; l2 >= 0; l2--) {
-        uint64_t y2 = readlane64(Y, l2);
-        if (lane < l2 && ((Eu >> l2) & 1ull)) Y ^= y2;
-    }
-    // Z = Y X = (L11 E11pc)^-1 = (Orig rows at the pivot columns)^-1
-    uint64_t Z = 0;
-    for (int l2 = 0; l2 < rbar; l2++) {
-        uint64_t x2 = readlane64(X, l2);
-        if ((Y >> l2) & 1ull) Z ^= x2;
-    }
-    s_img_w[lane] = 0;
-    s_img_u[lane] = 0;
-    __syncthreads();
-    if (lane < rbar) {
-        s_img_w[my_q] = Z;  // stripe bit q_l -> w
-        s_img_u[my_q] = Y;  // stripe bit q_l -> u
-    }
-    __syncthreads();
-    rec->img_w[lane] = s_img_w[lane];
-    rec->img_u[lane] = s_img_u[lane];
-
-    // special rows: pivots first (position r + k), then displaced rows
-    for (int k = lane; k < nspec; k += 64) {
-        const int64_t dst = s_dst[k], src = s_src[k];
-        rec->spec_dst[k] = dst;
-        rec->spec_src[k] = src;
-        if (k >= rbar) {
-            const uint64_t v = A[src * ldw + sw] & kmask;
-            uint64_t w = 0, u = 0;
-            for (int j = 0; j < kp; j++) {
-                if ((v >> j) & 1ull) {
-                    w ^= s_img_w[j];
-                    u ^= s_img_u[j];
-                }
-            }
-            rec->spec_coef[k] = w;
-            rec->spec_lbits[k] = u;
-            rec->spec_stripe[k] = 0;
-        }
-    }
-    if (lane < rbar) {
-        rec->spec_coef[lane] = X ^ (1ull << lane);  // L11^-1 row without its diagonal
-        rec->spec_lbits[lane] = Ls;                   // L11 row
-        rec->spec_stripe[lane] = my_fin & ~((1ull << my_q) - 1ull);
-        P[r + lane] = r + my_p;
-        Q[r + lane] = c + my_q;
-    }
-    if (lane == 0) {
-        rec->r = r;
-        rec->rbar = rbar;
-        rec->nspec = nspec;
-        rec->active = rbar > 0;
-        rec->slow = slow ? 1 : 0;
-        *rank_out = r + rbar;
-    }
+                                              int64_t c, const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
+                                              int64_t *rank_out, uint64_t *gsv, int32_t *gsid) {
+    __shared__ PanelLds L;
+    panel_body<WQ>(A, m, n, ldw, c, prev, rec, P, Q, rank_out, gsv, gsid, L, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -471,94 +178,170 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// k_m4rm: C[rows, words] ^= sum_b T_b[byte b of coef[row]] over one column
-// tile of TILE_W words per block.  T_b (b < 8) holds all 256 sums of B rows
-// 8b .. 8b+7 restricted to the tile (MakeTable); each row adds one entry per
-// non-zero byte (AddRowsFromTable).  With `rec` the rows are rec->r .. m-1
-// and B has rec->rbar rows; without it, rows 0 .. m-1 and `nbits` rows.
-// Block -> (tile, chunk) with tiles fastest; consecutive logical blocks are
-// placed on the same XCD so neighbouring tiles share L2 lines.
+// k_m4rm / k_m4rm_w: the trailing update (m4rm.h).  With `rec` the rows are
+// rec->r .. m-1 and B has rec->rbar rows; without it, rows 0 .. m-1 and
+// `nbits` rows.  Column tiles are aligned to absolute multiples of the tile
+// width (the first may be partial).  Block -> (tile, row chunk) with tiles
+// fastest, so the blocks running at one time sweep whole rows together.
 // ---------------------------------------------------------------------------
-constexpr int M4_UNROLL = 4;
+__device__ __forceinline__ bool m4_block_rows(int64_t m, int64_t row0, int ntiles, int nchunks, int *tile,
+                                              int64_t *rb, int64_t *re) {
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    *tile = logical % ntiles;
+    const int chunk = logical / ntiles;
+    if (chunk >= nchunks) return false;
+    const int64_t rows = m - row0;
+    const int64_t per = (rows + nchunks - 1) / nchunks;
+    *rb = row0 + (int64_t)chunk * per;
+    *re = *rb + per < m ? *rb + per : m;
+    return *rb < *re;
+}
 
-__global__ __launch_bounds__(WIDE_THREADS) void k_m4rm(uint64_t *__restrict__ C, int64_t ldc, int64_t m,
-                                                       const uint64_t *__restrict__ coef, int64_t coef_ld,
-                                                       const uint64_t *__restrict__ B, int64_t ldb, int nbits,
-                                                       int64_t w_begin, int64_t w_end, int ntiles, int nchunks,
-                                                       const PassRec *__restrict__ rec) {
-    __shared__ uint64_t T[8][256][TILE_W];
-    __shared__ uint64_t Bt[KW][TILE_W];
-
+template <int TW, int NT, int U>
+__global__ __launch_bounds__(NT) void k_m4rm(uint64_t *__restrict__ C, int64_t ldc, int64_t m,
+                                             const uint64_t *__restrict__ coef, int64_t coef_ld,
+                                             const uint64_t *__restrict__ B, int64_t ldb, int nbits, int64_t w_begin,
+                                             int64_t w_end, int ntiles, int nchunks, const PassRec *__restrict__ rec) {
+    __shared__ M4Lds<TW> L;
     int64_t row0 = 0;
     if (rec) {
         if (!rec->active) return;
         row0 = rec->r;
         nbits = rec->rbar;
     }
-    const int G = gridDim.x;
-    const int bid = blockIdx.x;
-    const int xcd = bid & 7, jx = bid >> 3;
-    const int g8 = G >> 3, rem = G & 7;
-    const int logical = xcd * g8 + (xcd < rem ? xcd : rem) + jx;
-    const int tile = logical % ntiles;
-    const int chunk = logical / ntiles;
-    if (chunk >= nchunks) return;
-    const int64_t rows = m - row0;
-    const int64_t per = (rows + nchunks - 1) / nchunks;
-    const int64_t rb = row0 + (int64_t)chunk * per;
-    const int64_t re = rb + per < m ? rb + per : m;
-    if (rb >= re) return;
-    const int64_t wt0 = w_begin + (int64_t)tile * TILE_W;
-    const int tid = threadIdx.x;
+    int tile;
+    int64_t rb, re;
+    if (!m4_block_rows(m, row0, ntiles, nchunks, &tile, &rb, &re)) return;
+    const int64_t wt0 = (w_begin & ~(int64_t)(TW - 1)) + (int64_t)tile * TW;
+    m4_build_tables<TW, NT>(L, B, ldb, nbits, wt0, w_begin, w_end, threadIdx.x);
+    m4_rows<TW, NT, U>(L, C, ldc, coef, coef_ld, nbits, rb, re, wt0, w_begin, w_end, threadIdx.x);
+}
 
-    for (int e = tid; e < KW * TILE_W; e += WIDE_THREADS) {
-        const int k = e / TILE_W, wl = e % TILE_W;
-        const int64_t w = wt0 + wl;
-        Bt[k][wl] = (k < nbits && w < w_end) ? B[(int64_t)k * ldb + w] : 0ull;
+template <int NT, int U>
+__global__ __launch_bounds__(NT) void k_m4rm_w(uint64_t *__restrict__ C, int64_t ldc, int64_t m,
+                                               const uint64_t *__restrict__ coef, int64_t coef_ld,
+                                               const uint64_t *__restrict__ B, int64_t ldb, int nbits, int64_t w_begin,
+                                               int64_t w_end, int ntiles, int nchunks, const PassRec *__restrict__ rec) {
+    __shared__ uint64_t T[16 * 16 * WR_TW];
+    int64_t row0 = 0;
+    if (rec) {
+        if (!rec->active) return;
+        row0 = rec->r;
+        nbits = rec->rbar;
     }
-    __syncthreads();
-    const int nbytes = (nbits + 7) >> 3;
-    for (int e = tid; e < 8 * 256 * TILE_W; e += WIDE_THREADS) {
-        const int wl = e % TILE_W;
-        const int x = (e / TILE_W) & 255;
-        const int b = e / (TILE_W * 256);
-        uint64_t acc = 0;
-        if (b < nbytes) {
-#pragma unroll
-            for (int t = 0; t < 8; t++)
-                if ((x >> t) & 1) acc ^= Bt[8 * b + t][wl];
-        }
-        T[b][x][wl] = acc;
-    }
-    __syncthreads();
+    int tile;
+    int64_t rb, re;
+    if (!m4_block_rows(m, row0, ntiles, nchunks, &tile, &rb, &re)) return;
+    const int64_t wt0 = (w_begin & ~(int64_t)(WR_TW - 1)) + (int64_t)tile * WR_TW;
+    m4w_build_tables<NT>(T, B, ldb, nbits, wt0, w_begin, w_end, threadIdx.x);
+    m4w_rows<NT, U>(T, C, ldc, coef, coef_ld, nbits, rb, re, wt0, w_begin, w_end, threadIdx.x);
+}
 
-    const int wl = tid % TILE_W;
-    const int rs = tid / TILE_W;
-    constexpr int RS = WIDE_THREADS / TILE_W;
-    const int64_t w = wt0 + wl;
-    const bool wok = w < w_end;
-    for (int64_t i0 = rb + rs; i0 < re; i0 += (int64_t)RS * M4_UNROLL) {
-        uint64_t cw[M4_UNROLL], x[M4_UNROLL];
-#pragma unroll
-        for (int u = 0; u < M4_UNROLL; u++) {
-            const int64_t i = i0 + (int64_t)u * RS;
-            cw[u] = i < re ? coef[i * coef_ld] : 0ull;
-            x[u] = (i < re && wok) ? C[i * ldc + w] : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < M4_UNROLL; u++) {
-            uint64_t acc = 0;
-#pragma unroll
-            for (int b = 0; b < 8; b++)
-                if (b < nbytes) acc ^= T[b][(cw[u] >> (8 * b)) & 255][wl];
-            x[u] ^= acc;
-        }
-#pragma unroll
-        for (int u = 0; u < M4_UNROLL; u++) {
-            const int64_t i = i0 + (int64_t)u * RS;
-            if (i < re && wok && cw[u]) C[i * ldc + w] = x[u];
+// Schedules of the update kernel (index = M4Variant id).
+struct M4Variant {
+    int tw, nt, u;
+    const char *name;
+};
+constexpr int M4_NVARIANTS = 12;
+static const M4Variant kM4Variants[M4_NVARIANTS] = {
+    {8, 1024, 4, "tw8_nt1024_u4"},   {8, 1024, 2, "tw8_nt1024_u2"},   {8, 512, 8, "tw8_nt512_u8"},
+    {8, 512, 4, "tw8_nt512_u4"},     {4, 512, 8, "tw4_nt512_u8"},     {4, 256, 16, "tw4_nt256_u16"},
+    {4, 1024, 4, "tw4_nt1024_u4"},   {8, 256, 16, "tw8_nt256_u16"},   {64, 1024, 4, "row_nt1024_u4"},
+    {64, 1024, 8, "row_nt1024_u8"},  {64, 512, 8, "row_nt512_u8"},    {64, 512, 16, "row_nt512_u16"},
+};
+
+// Default schedule of one update launch, from sweeps on MI355X: the
+// wave-per-row kernel (512-byte row segments) when the trailing block does
+// not fit the 256 MB Infinity Cache, the 8-word tiles otherwise.
+static int m4_auto(int64_t rows, int64_t words) {
+    const double bytes = (double)rows * (double)words * 8.0;
+    if (words >= 48 && bytes > 192.0 * 1024 * 1024) return 9;
+    return 0;
+}
+
+static void m4_launch_variant(int v, dim3 grid, hipStream_t s, uint64_t *C, int64_t ldc, int64_t m, const uint64_t *coef,
+                              int64_t coef_ld, const uint64_t *B, int64_t ldb, int nbits, int64_t w_begin,
+                              int64_t w_end, int ntiles, int nchunks, const PassRec *rec) {
+#define M4_CASE(ID, TW, NT, U)                                                                                       \
+    case ID:                                                                                                          \
+        hipLaunchKernelGGL((k_m4rm<TW, NT, U>), grid, dim3(NT), 0, s, C, ldc, m, coef, coef_ld, B, ldb, nbits,      \
+                           w_begin, w_end, ntiles, nchunks, rec);                                                     \
+        break;
+    switch (v) {
+        M4_CASE(0, 8, 1024, 4)
+        M4_CASE(1, 8, 1024, 2)
+        M4_CASE(2, 8, 512, 8)
+        M4_CASE(3, 8, 512, 4)
+        M4_CASE(4, 4, 512, 8)
+        M4_CASE(5, 4, 256, 16)
+        M4_CASE(6, 4, 1024, 4)
+        M4_CASE(7, 8, 256, 16)
+#define M4W_CASE(ID, NT, U)                                                                                         \
+    case ID:                                                                                                          \
+        hipLaunchKernelGGL((k_m4rm_w<NT, U>), grid, dim3(NT), 0, s, C, ldc, m, coef, coef_ld, B, ldb, nbits, w_begin,  \
+                           w_end, ntiles, nchunks, rec);                                                              \
+        break;
+        M4W_CASE(8, 1024, 4)
+        M4W_CASE(9, 1024, 8)
+        M4W_CASE(10, 512, 8)
+        M4W_CASE(11, 512, 16)
+#undef M4W_CASE
+        default:
+            break;
+    }
+#undef M4_CASE
+}
+
+// Grid of one update launch over words [w_begin, w_end): ntiles aligned
+// column tiles x nchunks row chunks.  The chunk count is chosen so that the
+// blocks fill whole rounds of the device's block slots (one block with
+// 128 KB of tables per CU, two with 64 KB): e.g. 15 tiles x 17 chunks = 255
+// blocks on 256 CUs rather than 270 blocks that need a second round.
+// `target` > 0 asks for about that many blocks instead.
+static int g_cus = 0;
+static int device_cus() {
+    if (g_cus <= 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            g_cus = cus;
+        else
+            g_cus = 256;
+    }
+    return g_cus;
+}
+
+static void m4_grid(int v, int64_t rows_est, int64_t w_begin, int64_t w_end, int target, int *ntiles, int *nchunks) {
+    const int tw = kM4Variants[v].tw;
+    const int64_t base = w_begin & ~(int64_t)(tw - 1);
+    const int nt = (int)((w_end - base + tw - 1) / tw);
+    *ntiles = nt;
+    int64_t maxc = rows_est / 128;  // at least 128 rows per chunk
+    if (maxc < 1) maxc = 1;
+    if (target > 0) {
+        int64_t nc = (target + nt - 1) / nt;
+        *nchunks = (int)(nc < 1 ? 1 : (nc > maxc ? maxc : nc));
+        return;
+    }
+    const int64_t slots = (int64_t)device_cus() * (tw == 4 ? 2 : 1);
+    if (maxc > 4 * slots) maxc = 4 * slots;
+    int best = 1;
+    double best_eff = -1.0;
+    for (int64_t nc = 1; nc <= maxc; nc++) {
+        const int64_t g = nt * nc;
+        const int64_t rounds = (g + slots - 1) / slots;
+        // filled share of the rounds, discounted slightly per extra round
+        const double eff = (double)g / (double)(rounds * slots) - 0.02 * (double)(rounds - 1);
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = (int)nc;
         }
     }
+    *nchunks = best;
+}
+
+static int m4_pick(int variant, int64_t rows, int64_t words) {
+    return (variant > 0 && variant <= M4_NVARIANTS) ? variant - 1 : m4_auto(rows, words);
 }
 
 // ---------------------------------------------------------------------------
@@ -619,46 +402,60 @@ hipError_t launch_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *r
     int blocks = (int)((work + 255) / 256);
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
+    ProfScope ps(KID_INIT, s);
     hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, P, m, Q, mn, rank, rec);
     return hipGetLastError();
 }
 
-hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, PassRec *rec, int64_t *P,
-                       int64_t *Q, int64_t *rank, uint64_t *coef, uint64_t *PB, uint64_t *gsv, int32_t *gsid,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_panel, dim3(1), dim3(64), 0, s, (const uint64_t *)A, m, n, ldw, c, rec, P, Q, rank, gsv, gsid);
+hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
+                       int64_t *P, int64_t *Q, int64_t *rank, uint64_t *coef, uint64_t *PB, uint64_t *gsv,
+                       int32_t *gsid, int m4_variant, int m4_target, int panel_regs, hipStream_t s) {
+    {
+        ProfScope ps(KID_PANEL, s);
+        if (panel_regs == 0 || panel_regs == 2)
+            hipLaunchKernelGGL(k_panel<2>, dim3(1), dim3(64), 0, s, (const uint64_t *)A, m, n, ldw, c, prev, rec, P, Q,
+                               rank, gsv, gsid);
+        else if (panel_regs == 4)
+            hipLaunchKernelGGL(k_panel<4>, dim3(1), dim3(64), 0, s, (const uint64_t *)A, m, n, ldw, c, prev, rec, P, Q,
+                               rank, gsv, gsid);
+        else
+            hipLaunchKernelGGL(k_panel<8>, dim3(1), dim3(64), 0, s, (const uint64_t *)A, m, n, ldw, c, prev, rec, P, Q,
+                               rank, gsv, gsid);
+    }
     const int nA = (int)((ldw + 63) / 64);
     int64_t rows_est = m - (c < m ? c : m);
     if (rows_est < 1) rows_est = 1;
     int nB = (int)((rows_est + WIDE_THREADS - 1) / WIDE_THREADS);
     if (nB > 256) nB = 256;
     if (nB < 1) nB = 1;
-    hipLaunchKernelGGL(k_permute, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, (const PassRec *)rec, coef, PB,
-                       nA);
+    {
+        ProfScope ps(KID_PERMUTE, s);
+        hipLaunchKernelGGL(k_permute, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, (const PassRec *)rec, coef,
+                           PB, nA);
+    }
     const int64_t nw = words_for(n);
     const int64_t tw0 = (c >> 6) + 1;
     if (tw0 < nw) {
-        const int ntiles = (int)((nw - tw0 + TILE_W - 1) / TILE_W);
-        int nchunks = (int)((rows_est + 127) / 128);
-        const int want = (512 + ntiles - 1) / ntiles;
-        if (nchunks > want) nchunks = want;
-        if (nchunks < 1) nchunks = 1;
-        hipLaunchKernelGGL(k_m4rm, dim3(ntiles * nchunks), dim3(WIDE_THREADS), 0, s, A, ldw, m, (const uint64_t *)coef,
-                           (int64_t)1, (const uint64_t *)PB, ldw, KW, tw0, nw, ntiles, nchunks, (const PassRec *)rec);
+        const int v = m4_pick(m4_variant, rows_est, nw - tw0);
+        int ntiles, nchunks;
+        m4_grid(v, rows_est, tw0, nw, m4_target, &ntiles, &nchunks);
+        ProfScope ps(KID_M4RM, s);
+        m4_launch_variant(v, dim3(ntiles * nchunks), s, A, ldw, m, (const uint64_t *)coef, (int64_t)1,
+                          (const uint64_t *)PB, ldw, KW, tw0, nw, ntiles, nchunks, (const PassRec *)rec);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_m4rm(uint64_t *C, int64_t ldc, int64_t m, const uint64_t *coef, int64_t coef_ld, const uint64_t *B,
-                       int64_t ldb, int nbits, int64_t w_begin, int64_t w_end, hipStream_t s) {
+                       int64_t ldb, int nbits, int64_t w_begin, int64_t w_end, int m4_variant, int m4_target,
+                       hipStream_t s) {
     if (w_begin >= w_end || m <= 0) return hipSuccess;
-    const int ntiles = (int)((w_end - w_begin + TILE_W - 1) / TILE_W);
-    int nchunks = (int)((m + 127) / 128);
-    const int want = (512 + ntiles - 1) / ntiles;
-    if (nchunks > want) nchunks = want;
-    if (nchunks < 1) nchunks = 1;
-    hipLaunchKernelGGL(k_m4rm, dim3(ntiles * nchunks), dim3(WIDE_THREADS), 0, s, C, ldc, m, coef, coef_ld, B, ldb, nbits,
-                       w_begin, w_end, ntiles, nchunks, (const PassRec *)nullptr);
+    const int v = m4_pick(m4_variant, m, w_end - w_begin);
+    int ntiles, nchunks;
+    m4_grid(v, m, w_begin, w_end, m4_target, &ntiles, &nchunks);
+    ProfScope ps(KID_M4RM, s);
+    m4_launch_variant(v, dim3(ntiles * nchunks), s, C, ldc, m, coef, coef_ld, B, ldb, nbits, w_begin, w_end, ntiles,
+                      nchunks, (const PassRec *)nullptr);
     return hipGetLastError();
 }
 
@@ -667,6 +464,7 @@ hipError_t launch_echelon(uint64_t *A, int64_t m, int64_t ldw, const int64_t *ra
     int blocks = (int)((total + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
+    ProfScope ps(KID_ECHELON, s);
     hipLaunchKernelGGL(k_echelon, dim3(blocks), dim3(256), 0, s, A, m, ldw, rank);
     return hipGetLastError();
 }

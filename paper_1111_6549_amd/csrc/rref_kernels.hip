@@ -103,6 +103,7 @@ hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t
     int nG = (int)((j1 + RREF_THREADS - 1) / RREF_THREADS);
     if (nG > 512) nG = 512;
     if (nG < 1) nG = 1;
+    ProfScope ps(KID_RREF, s);
     hipLaunchKernelGGL(k_rref_block, dim3(nA + nG), dim3(RREF_THREADS), 0, s, (const uint64_t *)A, ldw, nw, Q, j0, j1,
                        wq0, coef, PB, nA);
     return hipGetLastError();

@@ -25,7 +25,7 @@ STATUS = {0: "GF2_OK", 1: "GF2_EINVAL", 2: "GF2_EWORKSPACE", 3: "GF2_ENOMEM", 4:
 EXPORTS = [
     "gf2_version", "gf2_status_str", "gf2_ple_workspace_bytes", "gf2_ple", "gf2_echelon_from_ple",
     "gf2_rref_workspace_bytes", "gf2_rref_from_ple", "gf2_rref_full_workspace_bytes", "gf2_rref",
-    "gf2_addmul", "gf2_make_table", "gf2_check_padding",
+    "gf2_addmul", "gf2_make_table", "gf2_check_padding", "gf2_profile_start", "gf2_profile_stop",
 ]
 
 
@@ -35,9 +35,15 @@ class GF2Error(RuntimeError):
         super().__init__("%s failed: %s (%s)" % (what, STATUS.get(status, status), _status_text(status)))
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("check_padding", ctypes.c_int32), ("update", ctypes.c_int32), ("mfma_block", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("m4_variant", ctypes.c_int32), ("m4_blocks", ctypes.c_int32), ("panel_regs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 def load():
@@ -64,6 +70,8 @@ def load():
         "gf2_addmul": (st, [p, i64, p, i64, p, i64, i64, i64, i64, p, p]),
         "gf2_make_table": (st, [p, i64, i32, i64, p, i64, p]),
         "gf2_check_padding": (st, [p, i64, i64, i64, p]),
+        "gf2_profile_start": (st, []),
+        "gf2_profile_stop": (st, [p, i32, p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -107,11 +115,14 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
 
 
-def _opts(update=0, check_padding=False, mfma_block=0):
+def _opts(update=0, check_padding=False, mfma_block=0, m4_variant=0, m4_blocks=0, panel_regs=0):
     o = Opts()
     o.check_padding = 1 if check_padding else 0
     o.update = int(update)
     o.mfma_block = int(mfma_block)
+    o.m4_variant = int(m4_variant)
+    o.m4_blocks = int(m4_blocks)
+    o.panel_regs = int(panel_regs)
     return o
 
 
@@ -124,7 +135,7 @@ def alloc_workspace(nbytes, device=None):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
 
 
-def ple(A, n, ws=None, update=0, check_padding=False):
+def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0, panel_regs=0):
     """In-place PLE of the packed (m, ldw) tensor A with n columns.
 
     Returns (P, Q, rank) as device tensors (int64 [m], int64 [min(m, n)],
@@ -132,7 +143,7 @@ def ple(A, n, ws=None, update=0, check_padding=False):
     A = _packed(A, "A")
     m, ldw = A.shape
     lib = load()
-    o = _opts(update, check_padding)
+    o = _opts(update, check_padding, m4_variant=m4_variant, m4_blocks=m4_blocks, panel_regs=panel_regs)
     need = int(lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
     if need == 0 and (m or n):
         raise GF2Error(1, "gf2_ple_workspace_bytes")
@@ -180,11 +191,11 @@ def rref(A, n, ws=None, update=0):
     return P, Q, rank
 
 
-def addmul(C, A, B, k, n, update=0):
+def addmul(C, A, B, k, n, update=0, m4_variant=0, m4_blocks=0):
     """C ^= A * B over GF(2); A is m x k, B is k x n, all packed on the GPU."""
     C, A, B = _packed(C, "C"), _packed(A, "A"), _packed(B, "B")
     m = C.shape[0]
-    o = _opts(update)
+    o = _opts(update, m4_variant=m4_variant, m4_blocks=m4_blocks)
     _check(load().gf2_addmul(_ptr(C), C.shape[1], _ptr(A), A.shape[1], _ptr(B), B.shape[1], m, k, n,
                              ctypes.byref(o), _stream()), "gf2_addmul")
 
@@ -202,3 +213,20 @@ def check_padding(A, n):
     A = _packed(A, "A")
     m, ldw = A.shape
     return int(load().gf2_check_padding(_ptr(A), m, n, ldw, _stream()))
+
+
+def profile_start():
+    _check(load().gf2_profile_start(), "gf2_profile_start")
+
+
+def profile_stop():
+    """Per-kernel event timings since profile_start(): {name: dict}."""
+    out = (KernelTime * 16)()
+    cnt = ctypes.c_int32(0)
+    _check(load().gf2_profile_stop(out, 16, ctypes.byref(cnt)), "gf2_profile_stop")
+    res = {}
+    for i in range(min(cnt.value, 16)):
+        k = out[i]
+        res[k.name.decode()] = {"launches": int(k.launches), "total_ms": k.total_ms, "min_ms": k.min_ms,
+                                "max_ms": k.max_ms}
+    return res

@@ -179,3 +179,24 @@ def test_check_padding():
     assert G.check_padding(to_dev(A2), 70) == 6
     with pytest.raises(G.GF2Error):
         G.ple(to_dev(A2), 70, check_padding=True)
+
+
+@pytest.mark.parametrize("variant", list(range(0, 13)))
+def test_schedule_invariance(variant):
+    """Every update schedule (tile width, threads, unroll, grid size) gives
+    the same bits."""
+    say("schedule variant", variant)
+    m, n = 1500, 1300
+    A = inputs.bernoulli(m, n, 77)
+    o = oracle_ple(A, n)
+    for blocks in (0, 37, 4096):
+        assert_same_ple(gpu_ple(A, n, m4_variant=variant, m4_blocks=blocks), o, "variant %d" % variant)
+    C = inputs.bernoulli(700, 900, 1)
+    Am = inputs.bernoulli(700, 150, 2)
+    Bm = inputs.bernoulli(150, 900, 3)
+    import oracle
+    want = C.copy()
+    oracle.addmul(want, Am, Bm, 150, 900)
+    tC = to_dev(C)
+    G.addmul(tC, to_dev(Am), to_dev(Bm), 150, 900, m4_variant=variant)
+    assert np.array_equal(to_host(tC), want)
