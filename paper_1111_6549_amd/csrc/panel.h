@@ -113,21 +113,26 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
         extend(nregmax < 2 ? nregmax : 2);
         PANEL_STAMP(1)
 
+        // act[q]: lanes of register q that are candidates (loaded, position
+        // >= npiv, row < m); kept as scalar masks and updated as npiv grows
+        uint64_t act[WQ];
+#pragma unroll
+        for (int q = 0; q < WQ; q++) act[q] = __ballot(q < nreg && 64 * q + lane < nmax);
         for (int j = 0; j < kp; j++) {
+            uint64_t msk[WQ];
             int found = -1;
             for (;;) {
 #pragma unroll
-                for (int q = 0; q < WQ; q++) {
-                    if (found < 0 && q < nreg && 64 * q + 64 > npiv) {
-                        const int pos = 64 * q + lane;
-                        const bool b = pos >= npiv && pos < nmax && ((val[q] >> j) & 1ull);
-                        const uint64_t msk = __ballot(b);
-                        if (msk) found = 64 * q + (int)__builtin_ctzll(msk);
-                    }
-                }
+                for (int q = 0; q < WQ; q++) msk[q] = __ballot(((val[q] >> j) & 1ull) != 0) & act[q];
+                found = -1;
+#pragma unroll
+                for (int q = WQ - 1; q >= 0; q--)
+                    if (msk[q]) found = 64 * q + (int)__builtin_ctzll(msk[q]);
                 found = uni(found);
                 if (found >= 0 || nreg >= nregmax) break;
                 extend(uni(nreg + 1));
+#pragma unroll
+                for (int q = 0; q < WQ; q++) act[q] = __ballot(q < nreg && 64 * q + lane < nmax && 64 * q + lane >= npiv);
             }
             if (found < 0) {
                 if (nmax < rows) {  // a row outside the window may hold the pivot
@@ -136,48 +141,39 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
                 }
                 continue;  // column j has no pivot
             }
-            const int qf = found >> 6, lf = found & 63, qn = npiv >> 6, ln = npiv & 63;
+            const int qf = found >> 6, lf = found & 63;
+            // the pivot row (at `found`) and the row at npiv (register 0, npiv < 64)
             uint64_t pv = 0;
+            int idp = 0;
 #pragma unroll
-            for (int q = 0; q < WQ; q++)
-                if (q == qf) pv = readlane64(val[q], lf);
-            if (found != npiv) {  // the row at npiv moves to `found`
-                uint64_t vr = 0;
-                int idr = 0, idp = 0;
-#pragma unroll
-                for (int q = 0; q < WQ; q++) {
-                    if (q == qn) {
-                        vr = readlane64(val[q], ln);
-                        idr = readlane32(id[q], ln);
-                    }
-                    if (q == qf) idp = readlane32(id[q], lf);
-                }
-#pragma unroll
-                for (int q = 0; q < WQ; q++) {
-                    if (q == qf) {
-                        val[q] = writelane64(val[q], vr, lf);
-                        id[q] = writelane32(id[q], idr, lf);
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < WQ; q++) {
-                    if (q == qn) {
-                        val[q] = writelane64(val[q], pv, ln);
-                        id[q] = writelane32(id[q], idp, ln);
-                    }
-                }
+            for (int q = 0; q < WQ; q++) {
+                const uint64_t t = readlane64(val[q], lf);
+                const int ti = readlane32(id[q], lf);
+                pv = q == qf ? t : pv;
+                idp = q == qf ? ti : idp;
             }
+            const uint64_t vr = readlane64(val[0], npiv);
+            const int idr = readlane32(id[0], npiv);
+            // swap the two rows, then eliminate column j from the later rows
+            // that have it (the row now at `found` never has it)
             const uint64_t pe = pv & above(j);
 #pragma unroll
             for (int q = 0; q < WQ; q++) {
-                if (q < nreg && 64 * q + 64 > npiv) {
-                    const int pos = 64 * q + lane;
-                    if (pos > npiv && ((val[q] >> j) & 1ull)) val[q] ^= pe;
-                }
+                uint64_t e = msk[q];
+                if (q == 0) e &= ~(1ull << npiv);
+                if (q == qf) e &= ~(1ull << lf);
+                const bool at_found = (q == qf) && lane == lf;
+                const bool at_npiv = (q == 0) && lane == npiv;
+                uint64_t v = at_found ? vr : val[q];
+                v = at_npiv ? pv : v;
+                id[q] = at_npiv ? idp : (at_found ? idr : id[q]);
+                val[q] = v ^ (pe & (0ull - ((e >> lane) & 1ull)));
             }
-            my_q = writelane32(my_q, j, npiv);
-            my_fin = writelane64(my_fin, pv, npiv);
-            my_p = writelane32(my_p, found, npiv);
+            act[0] &= ~(1ull << npiv);
+            const bool me = lane == npiv;
+            my_q = me ? j : my_q;
+            my_fin = me ? pv : my_fin;
+            my_p = me ? found : my_p;
             npiv = uni(npiv + 1);
             if (npiv == rows) break;
         }
@@ -303,20 +299,17 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
         const uint64_t pe = readlane64(my_fin, l) & above(ql);
         const uint64_t hl = readlane64(hP, l);  // final: pivot l is reduced by pivots < l only
         const uint64_t bl = 1ull << l;
-        if (lane > l && ((my_fin >> ql) & 1ull)) {
-            hP ^= hl;
-            uP |= bl;
-        }
-        if ((vV >> ql) & 1ull) {
-            vV ^= pe;
-            hV ^= hl;
-            uV |= bl;
-        }
-        if ((vD >> ql) & 1ull) {
-            vD ^= pe;
-            hD ^= hl;
-            uD |= bl;
-        }
+        const uint64_t mp = (lane > l) ? (0ull - ((my_fin >> ql) & 1ull)) : 0ull;
+        const uint64_t mv = 0ull - ((vV >> ql) & 1ull);
+        const uint64_t md = 0ull - ((vD >> ql) & 1ull);
+        hP ^= hl & mp;
+        uP |= bl & mp;
+        vV ^= pe & mv;
+        hV ^= hl & mv;
+        uV |= bl & mv;
+        vD ^= pe & md;
+        hD ^= hl & md;
+        uD |= bl & md;
     }
     PANEL_STAMP(4)
     rec->img_w[lane] = hV;

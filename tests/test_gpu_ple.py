@@ -200,3 +200,20 @@ def test_schedule_invariance(variant):
     tC = to_dev(C)
     G.addmul(tC, to_dev(Am), to_dev(Bm), 150, 900, m4_variant=variant)
     assert np.array_equal(to_host(tC), want)
+
+
+@pytest.mark.parametrize("m,n,kind", [(1500, 1300, "u"), (3000, 300, "r"), (8000, 300, "r"), (900, 900, "s"),
+                                      (700, 2000, "u")])
+def test_panel_modes(m, n, kind):
+    """Every register window of the panel's pivot search gives the same bits
+    (the smaller windows fall back to the all-rows search more often)."""
+    say("panel modes", m, n, kind)
+    if kind == "u":
+        A = inputs.bernoulli(m, n, 5 + m)
+    elif kind == "r":
+        A = inputs.known_rank(m, n, min(m, n) // 5, 3, 4)
+    else:
+        A = inputs.bernoulli(m, n, 6 + m, p=0.01)
+    o = oracle_ple(A, n)
+    for regs in (0, 2, 4, 8):
+        assert_same_ple(gpu_ple(A, n, panel_regs=regs), o, "regs=%d" % regs)
