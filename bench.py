@@ -28,10 +28,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 KW = 64
-# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of k_m4rm on this workload, per
-# launch averaged over the run, with the source hash of the kernel file they
-# were taken on; reported only while that source is unchanged.
-TRAFFIC = None
+# HBM bytes per k_m4rm launch on the 65536^2 seed-5 workload: rocprofv3
+# --pmc FETCH_SIZE and --pmc WRITE_SIZE, averaged over the 1023 launches of
+# one PLE and scaled by the same counters on the 512 MiB restore copy
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Reported only while the kernel
+# sources hash to the value the counters were taken on.
+TRAFFIC = {"source": "fc3f6b7349aadd79", "n": 65536, "seed": 5, "bytes_per_launch": 364947061}
 
 
 def log(*a):
@@ -60,9 +62,11 @@ def alg_bytes_m4rm(m, n, Q, r):
 
 
 def kernel_source_hash():
+    """Hash of the sources k_m4rm is compiled from."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1111_6549_amd", "csrc", "ple_kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for f in ("ple_kernels.hip", "m4rm.h", "dev.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_1111_6549_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -93,7 +97,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--m4-variant", type=int, default=0, help="update schedule 1..8 (0 = library default)")
@@ -164,7 +168,8 @@ def main():
             avg_ms = k["total_ms"] / k["launches"]
             achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
             traffic = None
-            if TRAFFIC and TRAFFIC.get("source") == kernel_source_hash():
+            if (TRAFFIC and TRAFFIC.get("source") == kernel_source_hash() and TRAFFIC.get("n") == args.n
+                    and TRAFFIC.get("seed") == args.seed and not args.m4_variant and not args.m4_blocks):
                 traffic = TRAFFIC["bytes_per_launch"]
             roofline = {
                 "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -195,8 +200,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "PLE of a dense %dx%d GF(2) matrix, Bernoulli(0.5), seed %d, uint64 row words"
                                % (m, n, args.seed),
-                   "m": m, "n": n, "pass_width_K": KW, "table_bits": 8, "tables_per_pass": 8,
-                   "tile_words": 8, "update": "xor-table", "schedule": sched},
+                   "m": m, "n": n, "pass_width_K": KW, "update": "xor-table",
+                   "update_schedule": "16 nibble tables x 64-word tiles while the trailing matrix exceeds "
+                                      "192 MB, then 8 byte tables x 8-word tiles" if not args.m4_variant
+                                      else "fixed variant %d" % args.m4_variant,
+                   "schedule": sched},
         "rank": r,
         "alg_bytes_per_step": abytes,
         "alg_GBps_whole_ple": round(abytes / (ms_per_step * 1e-3) / 1e9, 1),
