@@ -141,6 +141,76 @@ gf2_status gf2_make_table(const uint64_t *rows, int64_t ldr, int32_t k, int64_t 
 gf2_status gf2_check_padding(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, void *stream);
 
 /*
+ * Batched PLE: many independent matrices of uneven shape, each decomposed
+ * exactly as gf2_ple would (same P, Q, rank and L\E, bit for bit), by one
+ * persistent kernel per size class whose workgroups take matrices from a
+ * device-side queue.  The method per matrix is Algorithm 2 with Algorithm 1
+ * panels and a Four-Russians update (Section 3.2, Appendix A); batching is an
+ * extension for throughput, not part of the paper.
+ *
+ * A plan is made once per set of shapes (host descriptors), then executed any
+ * number of times on arenas holding those shapes.  The first execution with a
+ * given (arena, P, Q, ranks, ws) records the plan's launches into a HIP graph
+ * that later executions with the same pointers replay.
+ */
+typedef struct gf2_desc {
+    int64_t a_off; /* first word of the matrix in the uint64 arena: m rows of ldw words */
+    int64_t m, n, ldw;
+    int64_t p_off; /* first of its m entries in the P arena */
+    int64_t q_off; /* first of its min(m, n) entries in the Q arena */
+} gf2_desc;
+
+typedef struct gf2_batch_opts {
+    int32_t autotune;  /* 1: time every candidate schedule per size class on synthetic matrices of the
+                          plan's shapes when the plan is made, keep the fastest (allocates and
+                          synchronises during gf2_batch_plan_create); 0: built-in choice */
+    int32_t config;    /* 1..gf2_batch_num_configs(): force that schedule for every class; 0: choose */
+    int32_t no_graph;  /* 1: launch directly on each execution instead of replaying a HIP graph */
+    int32_t reserved[5];
+} gf2_batch_opts;
+
+typedef struct gf2_batch_plan gf2_batch_plan;
+
+/* Class of a batch plan as chosen: matrices whose larger side is at most
+ * max_dim, the schedule used for them, and the persistent grid size. */
+typedef struct gf2_batch_class {
+    int64_t max_dim;
+    int64_t count;
+    int32_t config;   /* 1-based schedule index */
+    int32_t grid;     /* workgroups of the persistent launch */
+    double tuned_ms;  /* time of the chosen schedule when autotuned, else 0 */
+} gf2_batch_class;
+
+/* Make a plan.  descs: `count` HOST descriptors (copied).  arena_words,
+ * p_len, q_len: element counts of the arenas the plan will be executed on;
+ * every descriptor must lie inside them (GF2_EINVAL otherwise), as must
+ * ldw >= ceil(n/64), m, n >= 0.  Descriptors must not overlap (not checked).
+ * Allocates device memory for the descriptors; *plan receives the handle. */
+gf2_status gf2_batch_plan_create(const gf2_desc *descs, int64_t count, int64_t arena_words, int64_t p_len,
+                                 int64_t q_len, const gf2_batch_opts *opts, gf2_batch_plan **plan);
+
+/* Device workspace gf2_ple_batched needs with this plan (256-byte aligned). */
+size_t gf2_batch_workspace_bytes(const gf2_batch_plan *plan);
+
+/* Execute: every matrix of the plan is decomposed in place in `arena`
+ * (device), its P and Q written at p_off / q_off of the device arenas P and
+ * Q, and its rank to ranks[i] (device, `count` int64).  Stream-ordered.
+ * Executions of one plan must not overlap unless they use distinct
+ * workspaces; each execution needs the full workspace. */
+gf2_status gf2_ple_batched(gf2_batch_plan *plan, uint64_t *arena, int64_t *P, int64_t *Q, int64_t *ranks, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* The chosen classes (up to max entries; *nclasses = number of classes). */
+gf2_status gf2_batch_plan_info(const gf2_batch_plan *plan, gf2_batch_class *out, int32_t max, int32_t *nclasses);
+
+/* Release a plan (waits for nothing: the caller makes sure no execution is in flight). */
+gf2_status gf2_batch_plan_destroy(gf2_batch_plan *plan);
+
+/* Number of batched schedules and the name of schedule i (1-based). */
+int32_t gf2_batch_num_configs(void);
+const char *gf2_batch_config_name(int32_t config);
+
+/*
  * Kernel timing.  Between gf2_profile_start() and gf2_profile_stop() every
  * kernel the library launches is bracketed by two HIP events recorded on its
  * launch stream (a small overhead per launch).  gf2_profile_stop waits for

@@ -42,4 +42,15 @@ __device__ __forceinline__ uint64_t place_bits(uint64_t u, int64_t w, int64_t wr
     return 0;
 }
 
+// New value of word w of a special row (a pivot or a row displaced by the
+// pass's swaps): the stripe word becomes its L bits and, for a pivot, its E
+// part; the words holding columns [r, c) get the L bits or-ed in; the rest
+// move unchanged.
+__device__ __forceinline__ uint64_t special_word(uint64_t old, int64_t w, int64_t sw, int64_t wr0, int sh,
+                                                 uint64_t lbits, uint64_t stripe) {
+    if (w == sw) return place_bits(lbits, w, wr0, sh) | stripe;
+    if (w >= wr0 && w < sw) return old | place_bits(lbits, w, wr0, sh);
+    return old;
+}
+
 }  // namespace gf2

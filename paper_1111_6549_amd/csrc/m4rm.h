@@ -203,3 +203,69 @@ __device__ __forceinline__ void m4w_rows(const uint64_t *__restrict__ T, uint64_
 }
 
 }  // namespace gf2
+
+namespace gf2 {
+
+// Nibble-table schedule for one block working alone (the batched kernel):
+// sixteen 16-entry tables T_t[x] = sum of B rows 4t..4t+3 selected by x, over
+// a tile of TW words; a thread owns one word of the tile and U rows in
+// flight.  Tables are built from the tile's B rows staged in LDS.
+template <int TW>
+struct M4NLds {
+    uint64_t T[16][16][TW];
+    uint64_t Bt[KW][TW];
+};
+
+template <int TW, int NT>
+__device__ __forceinline__ void m4n_build_tables(M4NLds<TW> &L, const uint64_t *__restrict__ B, int64_t ldb, int nbits,
+                                                 int64_t wt0, int64_t w_begin, int64_t w_end, int tid) {
+    for (int e = tid; e < KW * TW; e += NT) {
+        const int k = e / TW, wl = e % TW;
+        const int64_t w = wt0 + wl;
+        L.Bt[k][wl] = (k < nbits && w >= w_begin && w < w_end) ? B[(int64_t)k * ldb + w] : 0ull;
+    }
+    __syncthreads();
+    for (int e = tid; e < 16 * 16 * TW; e += NT) {
+        const int wl = e % TW;
+        const int x = (e / TW) & 15;
+        const int t = e / (TW * 16);
+        uint64_t acc = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+            if ((x >> b) & 1) acc ^= L.Bt[4 * t + b][wl];
+        L.T[t][x][wl] = acc;
+    }
+    __syncthreads();
+}
+
+template <int TW, int NT, int U>
+__device__ __forceinline__ void m4n_rows(const M4NLds<TW> &L, uint64_t *__restrict__ C, int64_t ldc,
+                                         const uint64_t *__restrict__ coef, int nbits, int64_t rb, int64_t re,
+                                         int64_t wt0, int64_t w_begin, int64_t w_end, int tid) {
+    constexpr int RS = NT / TW;
+    const int wl = tid % TW;
+    const int rs = tid / TW;
+    const int64_t w = wt0 + wl;
+    const bool wok = w >= w_begin && w < w_end;
+    const int ntab = (nbits + 3) >> 2;
+    for (int64_t i0 = rb + rs; i0 < re; i0 += (int64_t)RS * U) {
+        uint64_t cw[U], x[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i = i0 + (int64_t)u * RS;
+            cw[u] = i < re ? coef[i] : 0ull;
+            x[u] = (i < re && wok && cw[u]) ? C[i * ldc + w] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            uint64_t acc = 0;
+#pragma unroll
+            for (int t = 0; t < 16; t++)
+                if (t < ntab) acc ^= L.T[t][(cw[u] >> (4 * t)) & 15][wl];
+            const int64_t i = i0 + (int64_t)u * RS;
+            if (i < re && wok && cw[u]) C[i * ldc + w] = x[u] ^ acc;
+        }
+    }
+}
+
+}  // namespace gf2

@@ -25,20 +25,25 @@
 
 namespace gf2 {
 
-struct PanelLds {
+// LDS of the panel: the special-row lists and, for stripes of at most SR
+// rows, the slow search's window (larger stripes use the workspace arrays).
+template <int SR>
+struct PanelLdsT {
     int64_t dst[MAX_SPEC], src[MAX_SPEC];
-    uint64_t sv[SLOW_LDS_ROWS];
-    int32_t sid[SLOW_LDS_ROWS];
+    uint64_t sv[SR > 0 ? SR : 1];
+    int32_t sid[SR > 0 ? SR : 1];
 };
+using PanelLds = PanelLdsT<SLOW_LDS_ROWS>;
 
 // One wave (lane = threadIdx.x & 63) computes the panel of the stripe at
 // column c.  `prev` is the previous pass's record (its r + rbar is this
-// pass's r), `rec` receives this pass.  Writes P[r..r+rbar), Q[r..r+rbar)
+// pass's r; it is read before `rec` is written, so the two may be the same
+// record), `rec` receives this pass.  Writes P[r..r+rbar), Q[r..r+rbar)
 // and *rank_out = r + rbar.
-template <int WQ>
+template <int WQ, int SR>
 __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64_t m, int64_t n, int64_t ldw, int64_t c,
                                            const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
-                                           int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelLds &L,
+                                           int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelLdsT<SR> &L,
                                            const int lane) {
 #ifdef GF2_PANEL_TIMING
     uint64_t *dbg = gsv + (c >> 6) * 8;
@@ -204,8 +209,8 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
         my_q = 0;
         my_fin = 0;
         my_p = 0;
-        volatile uint64_t *sv = rows <= SLOW_LDS_ROWS ? (volatile uint64_t *)L.sv : (volatile uint64_t *)gsv;
-        volatile int32_t *sid = rows <= SLOW_LDS_ROWS ? (volatile int32_t *)L.sid : (volatile int32_t *)gsid;
+        volatile uint64_t *sv = rows <= SR ? (volatile uint64_t *)L.sv : (volatile uint64_t *)gsv;
+        volatile int32_t *sid = rows <= SR ? (volatile int32_t *)L.sid : (volatile int32_t *)gsid;
         uint64_t orv = 0;
         for (int64_t pos = lane; pos < rows; pos += 64) {
             const uint64_t v = A[(r + pos) * ldw + sw] & kmask;

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(64) void k_panel(const uint64_t *__restrict__ A, in
                                               int64_t c, const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
                                               int64_t *rank_out, uint64_t *gsv, int32_t *gsid) {
     __shared__ PanelLds L;
-    panel_body<WQ>(A, m, n, ldw, c, prev, rec, P, Q, rank_out, gsv, gsid, L, threadIdx.x);
+    panel_body<WQ, SLOW_LDS_ROWS>(A, m, n, ldw, c, prev, rec, P, Q, rank_out, gsv, gsid, L, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -92,13 +92,8 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
             if (k < nspec && w < ldw) {
                 const int64_t src = rec->spec_src[k];
                 const uint64_t old = A[src * ldw + w];
-                uint64_t nw = old;
-                if (w == sw)
-                    nw = place_bits(rec->spec_lbits[k], w, wr0, sh) | rec->spec_stripe[k];
-                else if (w >= wr0 && w < sw)
-                    nw = old | place_bits(rec->spec_lbits[k], w, wr0, sh);
                 if (k < rbar && w > sw) PB[(int64_t)k * ldw + w] = old;
-                nv[t] = nw;
+                nv[t] = special_word(old, w, sw, wr0, sh, rec->spec_lbits[k], rec->spec_stripe[k]);
             }
         }
         __syncthreads();  // every read of these columns precedes every write

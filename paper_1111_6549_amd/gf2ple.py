@@ -26,6 +26,8 @@ EXPORTS = [
     "gf2_version", "gf2_status_str", "gf2_ple_workspace_bytes", "gf2_ple", "gf2_echelon_from_ple",
     "gf2_rref_workspace_bytes", "gf2_rref_from_ple", "gf2_rref_full_workspace_bytes", "gf2_rref",
     "gf2_addmul", "gf2_make_table", "gf2_check_padding", "gf2_profile_start", "gf2_profile_stop",
+    "gf2_batch_plan_create", "gf2_batch_workspace_bytes", "gf2_ple_batched", "gf2_batch_plan_info",
+    "gf2_batch_plan_destroy", "gf2_batch_num_configs", "gf2_batch_config_name",
 ]
 
 
@@ -44,6 +46,21 @@ class Opts(ctypes.Structure):
     _fields_ = [("check_padding", ctypes.c_int32), ("update", ctypes.c_int32), ("mfma_block", ctypes.c_int32),
                 ("m4_variant", ctypes.c_int32), ("m4_blocks", ctypes.c_int32), ("panel_regs", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 2)]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("a_off", ctypes.c_int64), ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("ldw", ctypes.c_int64),
+                ("p_off", ctypes.c_int64), ("q_off", ctypes.c_int64)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_int32), ("config", ctypes.c_int32), ("no_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class BatchClass(ctypes.Structure):
+    _fields_ = [("max_dim", ctypes.c_int64), ("count", ctypes.c_int64), ("config", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("tuned_ms", ctypes.c_double)]
 
 
 def load():
@@ -72,6 +89,13 @@ def load():
         "gf2_check_padding": (st, [p, i64, i64, i64, p]),
         "gf2_profile_start": (st, []),
         "gf2_profile_stop": (st, [p, i32, p]),
+        "gf2_batch_plan_create": (st, [p, i64, i64, i64, i64, p, p]),
+        "gf2_batch_workspace_bytes": (sz, [p]),
+        "gf2_ple_batched": (st, [p, p, p, p, p, p, sz, p]),
+        "gf2_batch_plan_info": (st, [p, p, i32, p]),
+        "gf2_batch_plan_destroy": (st, [p]),
+        "gf2_batch_num_configs": (i32, []),
+        "gf2_batch_config_name": (ctypes.c_char_p, [i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -230,3 +254,80 @@ def profile_stop():
         res[k.name.decode()] = {"launches": int(k.launches), "total_ms": k.total_ms, "min_ms": k.min_ms,
                                 "max_ms": k.max_ms}
     return res
+
+
+# ---------------------------------------------------------------------------
+# Batched PLE
+# ---------------------------------------------------------------------------
+ARENA_ALIGN_WORDS = 32  # 256-byte aligned matrices in the arena
+
+
+def batch_layout(shapes):
+    """Arena layout for a list of (m, n) or (m, n, ldw): returns
+    (descs as a list of dicts, arena_words, p_len, q_len)."""
+    descs = []
+    a = p = q = 0
+    for sh in shapes:
+        m, n = int(sh[0]), int(sh[1])
+        ldw = int(sh[2]) if len(sh) > 2 else (n + 63) // 64
+        descs.append({"a_off": a, "m": m, "n": n, "ldw": ldw, "p_off": p, "q_off": q})
+        a += -(-(m * ldw) // ARENA_ALIGN_WORDS) * ARENA_ALIGN_WORDS
+        p += m
+        q += min(m, n)
+    return descs, a, p, q
+
+
+def batch_num_configs():
+    return int(load().gf2_batch_num_configs())
+
+
+def batch_config_name(i):
+    return load().gf2_batch_config_name(int(i)).decode()
+
+
+class BatchPlan:
+    """A batched-PLE plan over fixed shapes (gf2_batch_plan_*)."""
+
+    def __init__(self, descs, arena_words, p_len, q_len, autotune=False, config=0, graph=True):
+        lib = load()
+        arr = (Desc * max(len(descs), 1))()
+        for i, d in enumerate(descs):
+            arr[i] = Desc(d["a_off"], d["m"], d["n"], d["ldw"], d["p_off"], d["q_off"])
+        o = BatchOpts()
+        o.autotune = 1 if autotune else 0
+        o.config = int(config)
+        o.no_graph = 0 if graph else 1
+        self._h = ctypes.c_void_p(0)
+        self.count = len(descs)
+        _check(lib.gf2_batch_plan_create(arr, len(descs), int(arena_words), int(p_len), int(q_len), ctypes.byref(o),
+                                         ctypes.byref(self._h)), "gf2_batch_plan_create")
+
+    def workspace_bytes(self):
+        return int(load().gf2_batch_workspace_bytes(self._h))
+
+    def run(self, arena, P, Q, ranks, ws):
+        """Decompose every matrix of `arena` (flat int64/uint64 device tensor) in place."""
+        for t, nm in ((arena, "arena"), (P, "P"), (Q, "Q"), (ranks, "ranks"), (ws, "ws")):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda:
+                raise ValueError("%s must be a device tensor" % nm)
+        _check(load().gf2_ple_batched(self._h, _ptr(arena), _ptr(P), _ptr(Q), _ptr(ranks), _ptr(ws), ws.numel(),
+                                      _stream()), "gf2_ple_batched")
+
+    def info(self):
+        out = (BatchClass * 16)()
+        cnt = ctypes.c_int32(0)
+        _check(load().gf2_batch_plan_info(self._h, out, 16, ctypes.byref(cnt)), "gf2_batch_plan_info")
+        return [{"max_dim": int(c.max_dim), "count": int(c.count), "config": int(c.config),
+                 "config_name": batch_config_name(c.config), "grid": int(c.grid), "tuned_ms": c.tuned_ms}
+                for c in out[:min(cnt.value, 16)]]
+
+    def close(self):
+        if self._h and self._h.value:
+            load().gf2_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -58,3 +58,31 @@ def test_argument_errors_before_launch():
     assert lib.gf2_make_table(nul, 1, 0, 10, nul, 1, nul) == 1
     assert lib.gf2_make_table(nul, 1, 9, 10, nul, 1, nul) == 1
     assert lib.gf2_echelon_from_ple(nul, 3, 3, 1, nul, nul) == 1
+
+
+def test_batch_plan_rejects_bad_descriptors():
+    """Descriptor checks of gf2_batch_plan_create return GF2_EINVAL before
+    any device call."""
+    lib = G.load()
+    descs, aw, pl, ql = G.batch_layout([(10, 100), (20, 30)])
+    end = descs[1]["a_off"] + descs[1]["m"] * descs[1]["ldw"]
+
+    def create(ds, arena_words, p_len, q_len, config=0):
+        arr = (G.Desc * len(ds))(*[G.Desc(d["a_off"], d["m"], d["n"], d["ldw"], d["p_off"], d["q_off"]) for d in ds])
+        o = G.BatchOpts()
+        o.config = config
+        h = ctypes.c_void_p(0)
+        return lib.gf2_batch_plan_create(arr, len(ds), arena_words, p_len, q_len, ctypes.byref(o), ctypes.byref(h))
+
+    assert create(descs, end - 1, pl, ql) == 1  # second matrix overruns the arena
+    assert create(descs, aw, pl - 1, ql) == 1   # P arena too short
+    assert create(descs, aw, pl, ql - 1) == 1   # Q arena too short
+    bad = [dict(d) for d in descs]
+    bad[0]["ldw"] = 1  # 100 columns need 2 words
+    assert create(bad, aw, pl, ql) == 1
+    bad = [dict(d) for d in descs]
+    bad[1]["m"] = -1
+    assert create(bad, aw, pl, ql) == 1
+    assert create(descs, aw, pl, ql, config=G.batch_num_configs() + 1) == 1
+    assert G.batch_num_configs() >= 4
+    assert G.batch_config_name(1) and G.batch_config_name(0) == ""
