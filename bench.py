@@ -90,6 +90,96 @@ def cpu_baseline(n_full, sample):
     }
 
 
+def run_batched(args, log_fn):
+    """The uneven batch: 4096 matrices, m and n uniform in [64, 2048], seed 7,
+    every fourth a known-rank product.  Batched = one execution of an
+    autotuned plan (graph replay); plain = gf2_ple called per matrix, one
+    after another on the same stream, on the same matrices."""
+    import numpy as np
+    import torch
+
+    from paper_1111_6549_amd import gf2ple as G
+    from paper_1111_6549_amd import inputs
+
+    count = args.batch_count
+    shapes_d = inputs.batch_shapes(count, 7)
+    mats = [inputs.batch_matrix(s, 7, i, device="cuda") for i, s in enumerate(shapes_d)]
+    shapes = [(s["m"], s["n"]) for s in shapes_d]
+    descs, aw, pl, ql = G.batch_layout(shapes)
+    host = np.zeros(aw, np.uint64)
+    for d, A in zip(descs, mats):
+        host[d["a_off"]:d["a_off"] + d["m"] * d["ldw"]] = A.reshape(-1)
+    pristine = torch.from_numpy(host.view(np.int64)).cuda()
+    arena = pristine.clone()
+    P = torch.empty(pl, dtype=torch.int64, device="cuda")
+    Q = torch.empty(ql, dtype=torch.int64, device="cuda")
+    R = torch.empty(count, dtype=torch.int64, device="cuda")
+    t0 = time.perf_counter()
+    plan = G.BatchPlan(descs, aw, pl, ql, autotune=True)
+    tune_s = time.perf_counter() - t0
+    ws = G.alloc_workspace(plan.workspace_bytes())
+    for _ in range(args.warmup + 1):
+        arena.copy_(pristine)
+        plan.run(arena, P, Q, R, ws)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.batch_reps):
+        arena.copy_(pristine)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run(arena, P, Q, R, ws)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    batched_s = sorted(times)[len(times) // 2]
+    ranks = R.cpu().numpy()
+    for i, s in enumerate(shapes_d):
+        if s["kind"] == "known_rank" and ranks[i] != s["rank"]:
+            raise RuntimeError("batched rank of matrix %d is %d, built with rank %d" % (i, ranks[i], s["rank"]))
+    log_fn("batched: %d matrices, median %.3f ms (plan + autotune %.2f s)" % (count, batched_s * 1e3, tune_s))
+
+    # plain path: the same matrices through gf2_ple one by one
+    arena.copy_(pristine)
+    wsz = max(G.workspace_bytes(m, n, (n + 63) // 64) for m, n in shapes)
+    wsp = G.alloc_workspace(wsz)
+    views = [arena[d["a_off"]:d["a_off"] + d["m"] * d["ldw"]].view(d["m"], d["ldw"]) for d in descs]
+    for v, (m, n) in list(zip(views, shapes))[:16]:
+        G.ple(v, n, ws=wsp)
+    arena.copy_(pristine)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for v, (m, n) in zip(views, shapes):
+        G.ple(v, n, ws=wsp)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    log_fn("plain: %d gf2_ple calls in %.3f s" % (count, plain_s))
+
+    out = {
+        "workload": "%d GF(2) matrices, m and n uniform in [64, 2048], Bernoulli(0.5), every 4th of exact rank "
+                    "in [m/4, min(m, n)], seed 7, one 256-byte aligned arena" % count,
+        "value": round(count / batched_s, 1),
+        "unit": "matrices/s",
+        "ms_per_batch": round(batched_s * 1e3, 3),
+        "plain_value": round(count / plain_s, 1),
+        "plain_ms": round(plain_s * 1e3, 1),
+        "speedup_vs_plain": round(plain_s / batched_s, 1),
+        "classes": [{"max_dim": c["max_dim"], "count": c["count"], "schedule": c["config_name"], "grid": c["grid"]}
+                    for c in plan.info() if c["count"]],
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = list(range(0, count, max(1, count // args.batch_cpu_sample)))[:args.batch_cpu_sample]
+        t0 = time.perf_counter()
+        for i in sample:
+            B = np.array(mats[i], copy=True)
+            oracle.ple(B, shapes[i][1])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(len(sample) / dt, 2), "unit": "matrices/s", "cores": oracle.threads(),
+                               "kind": "oracle", "sample": "%d of the %d matrices (every %d-th), %.2f s"
+                                                            % (len(sample), count, count // len(sample), dt)}
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +193,10 @@ def main():
     ap.add_argument("--m4-variant", type=int, default=0, help="update schedule 1..8 (0 = library default)")
     ap.add_argument("--m4-blocks", type=int, default=0, help="target blocks per update launch (0 = default)")
     ap.add_argument("--panel-regs", type=int, default=0, help="panel register window 2/4/8 (0 = default)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--batch-cpu-sample", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the PLE of one matrix is not split across GPUs here "
@@ -185,6 +279,12 @@ def main():
         cpu = cpu_baseline(n, args.cpu_sample)
         log("cpu baseline done: %s" % cpu["sample"])
 
+    batched = None
+    if not args.no_batched:
+        del work, pristine, ws
+        torch.cuda.empty_cache()
+        batched = run_batched(args, log)
+
     out = {
         "metric": "PLE time & HBM GB/s (% roofline), 65536² GF(2); batched matrices/s vs plain",
         "value": round(1000.0 / ms_per_step, 4),
@@ -210,6 +310,7 @@ def main():
         "alg_GBps_whole_ple": round(abytes / (ms_per_step * 1e-3) / 1e9, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
         "kernels_ms_per_step": {k: round(v["total_ms"] / args.steps, 3) for k, v in (kernels or {}).items()},
     }
     print(json.dumps(out), flush=True)

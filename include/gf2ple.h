@@ -211,6 +211,84 @@ int32_t gf2_batch_num_configs(void);
 const char *gf2_batch_config_name(int32_t config);
 
 /*
+ * Serving session: a request loop that keeps packed matrices resident on the
+ * device and decomposes them as they arrive.  Requests are admitted in
+ * arrival order while their device memory (matrix, P, Q, rank, and for large
+ * ones the PLE workspace) fits the session's budget; admitted requests are
+ * launched at once on one of several streams -- all admitted small requests
+ * together as one batched launch (the persistent kernel of gf2_ple_batched),
+ * each large request as its own gf2_ple pass loop -- so requests that arrive
+ * while others run join the next launch and overlap with the running ones
+ * (continuous batching).  Each result is bit-identical to gf2_ple on that
+ * matrix alone.  The session runs its own host thread; all calls are safe
+ * from any host thread.  Serving is an extension for throughput, not part of
+ * the paper.
+ */
+typedef struct gf2_serve_opts {
+    int64_t budget_bytes;  /* device memory of the session, allocated once at create (0 = 64 GiB) */
+    int32_t streams;       /* launch streams (0 = 4, at most 16) */
+    int32_t max_batch;     /* most requests in one batched launch (0 = 4096) */
+    int32_t small_max_dim; /* max(m, n) up to which a request runs in batched launches (0 = 2048, at most 4096) */
+    int32_t reserved[3];
+} gf2_serve_opts;
+
+typedef struct gf2_serve gf2_serve;
+
+enum { GF2_REQ_QUEUED = 0, GF2_REQ_RUNNING = 1, GF2_REQ_DONE = 2, GF2_REQ_FAILED = 3 };
+
+typedef struct gf2_serve_info {
+    int32_t state;  /* GF2_REQ_*: queued for admission, resident and launched, result in device memory, failed */
+    int32_t status; /* gf2_status of a failed request */
+    int64_t m, n, ldw;
+    double t_submit, t_admit, t_done; /* seconds on the session's steady clock (0 = not yet) */
+} gf2_serve_info;
+
+typedef struct gf2_serve_stats {
+    int64_t submitted, completed, failed, queued, running;
+    int64_t launches_batched, launches_single;
+    int64_t bytes_in_use, bytes_peak, budget_bytes;
+    double now; /* current time on the session clock */
+} gf2_serve_stats;
+
+/* Create a session (allocates the budget on the current device and starts the
+ * session thread).  GF2_EINVAL for bad options, GF2_ENOMEM / GF2_EHIP if the
+ * budget cannot be allocated. */
+gf2_status gf2_serve_create(const gf2_serve_opts *opts, gf2_serve **session);
+
+/* Submit an m x n packed matrix (row stride ldw words).  a_on_device = 0: A is
+ * host memory, copied before the call returns.  a_on_device = 1: A is device
+ * memory that must stay unchanged until the request leaves GF2_REQ_QUEUED.
+ * *ticket receives the request id.  GF2_EBUDGET if the request could never
+ * fit the budget; GF2_EINVAL for bad sizes. */
+gf2_status gf2_serve_submit(gf2_serve *session, const uint64_t *A, int32_t a_on_device, int64_t m, int64_t n,
+                            int64_t ldw, int64_t *ticket);
+
+/* State of a request without waiting; GF2_EBUSY for an unknown ticket. */
+gf2_status gf2_serve_poll(gf2_serve *session, int64_t ticket, gf2_serve_info *info);
+
+/* Wait until the request is done or failed. */
+gf2_status gf2_serve_wait(gf2_serve *session, int64_t ticket, gf2_serve_info *info);
+
+/* Copy a finished request's results out -- L\E (m rows of ldw_out words,
+ * ldw_out >= ceil(n/64), extra words zero), P (m), Q (min(m, n)), rank (1);
+ * any pointer may be NULL -- to host memory (to_device = 0) or device memory
+ * (to_device = 1), synchronously, then release the request.  GF2_EBUSY if the
+ * ticket is unknown or not done; a failed request returns its status and is
+ * released. */
+gf2_status gf2_serve_fetch(gf2_serve *session, int64_t ticket, uint64_t *LE, int64_t ldw_out, int64_t *P, int64_t *Q,
+                           int64_t *rank, int32_t to_device);
+
+/* Release a finished request without copying it out. */
+gf2_status gf2_serve_release(gf2_serve *session, int64_t ticket);
+
+/* Counters of the session. */
+gf2_status gf2_serve_stats_get(gf2_serve *session, gf2_serve_stats *stats);
+
+/* Stop the session thread after the running launches finish, free the budget
+ * and every request. */
+gf2_status gf2_serve_destroy(gf2_serve *session);
+
+/*
  * Kernel timing.  Between gf2_profile_start() and gf2_profile_stop() every
  * kernel the library launches is bracketed by two HIP events recorded on its
  * launch stream (a small overhead per launch).  gf2_profile_stop waits for

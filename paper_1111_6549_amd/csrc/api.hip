@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "../../include/gf2ple.h"
+#include "batch.h"
 #include "common.h"
 
 namespace gf2 {
@@ -96,6 +97,48 @@ int *device_flag() {
 
 }  // namespace
 
+namespace gf2 {
+
+size_t ple_workspace_total(int64_t m, int64_t ldw) { return ple_layout(m, ldw).total; }
+
+hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
+                       void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync) {
+    const PleLayout L = ple_layout(m, ldw);
+    const int64_t mn = m < n ? m : n;
+    char *base = (char *)ws;
+    PassRec *recs = (PassRec *)(base + L.rec);
+    uint64_t *coef = (uint64_t *)(base + L.coef);
+    uint64_t *PB = (uint64_t *)(base + L.pb);
+    uint64_t *gsv = (uint64_t *)(base + L.gsv);
+    int32_t *gsid = (int32_t *)(base + L.gsid);
+
+    hipError_t e = launch_init(P, m, Q, mn, rank, recs, s);
+    if (e != hipSuccess) return e;
+    if (m == 0 || n == 0) return hipSuccess;
+
+    const int64_t npasses = words_for(n);
+    int64_t since_check = 0;
+    for (int64_t t = 0; t < npasses; t++) {
+        const int64_t c = t * KW;
+        if (c >= m && allow_sync) {
+            // rank <= m: once it reaches m the remaining passes are empty
+            if (since_check == 0) {
+                int64_t host_rank = 0;
+                if ((e = hipMemcpyAsync(&host_rank, rank, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+                if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+                if (host_rank >= m) break;
+            }
+            since_check = (since_check + 1) % 8;
+        }
+        e = launch_pass(A, m, n, ldw, c, &recs[(t + 1) & 1], &recs[t & 1], P, Q, rank, coef, PB, gsv, gsid,
+                        opts ? opts->m4_variant : 0, opts ? opts->m4_blocks : 0, opts ? opts->panel_regs : 0, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gf2
+
 extern "C" {
 
 const char *gf2_version(void) { return "gf2ple 0.1.0 gfx950"; }
@@ -155,36 +198,7 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
         gf2_status st = gf2_check_padding(A, m, n, ldw, stream);
         if (st != GF2_OK) return st;
     }
-    char *base = (char *)ws;
-    PassRec *recs = (PassRec *)(base + L.rec);
-    uint64_t *coef = (uint64_t *)(base + L.coef);
-    uint64_t *PB = (uint64_t *)(base + L.pb);
-    uint64_t *gsv = (uint64_t *)(base + L.gsv);
-    int32_t *gsid = (int32_t *)(base + L.gsid);
-
-    if (launch_init(P, m, Q, mn, rank, recs, s) != hipSuccess) return GF2_EHIP;
-    if (m == 0 || n == 0) return GF2_OK;
-
-    const int64_t npasses = words_for(n);
-    int64_t since_check = 0;
-    for (int64_t t = 0; t < npasses; t++) {
-        const int64_t c = t * KW;
-        if (c >= m) {
-            // rank <= m: once it reaches m the remaining passes are empty
-            if (since_check == 0) {
-                int64_t host_rank = 0;
-                if (hipMemcpyAsync(&host_rank, rank, 8, hipMemcpyDeviceToHost, s) != hipSuccess) return GF2_EHIP;
-                if (hipStreamSynchronize(s) != hipSuccess) return GF2_EHIP;
-                if (host_rank >= m) break;
-            }
-            since_check = (since_check + 1) % 8;
-        }
-        if (launch_pass(A, m, n, ldw, c, &recs[(t + 1) & 1], &recs[t & 1], P, Q, rank, coef, PB, gsv, gsid,
-                        opts ? opts->m4_variant : 0, opts ? opts->m4_blocks : 0, opts ? opts->panel_regs : 0,
-                        s) != hipSuccess)
-            return GF2_EHIP;
-    }
-    return hip_status(hipGetLastError());
+    return hip_status(ple_enqueue(A, m, n, ldw, P, Q, rank, ws, opts, s, true));
 }
 
 gf2_status gf2_echelon_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, const int64_t *rank, void *stream) {

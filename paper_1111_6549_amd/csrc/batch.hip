@@ -17,29 +17,11 @@
 #include <new>
 #include <vector>
 
-#include "../../include/gf2ple.h"
+#include "batch.h"
 #include "m4rm.h"
 #include "panel.h"
 
 namespace gf2 {
-
-// Where one workgroup's scratch lives inside its slot of the workspace.
-struct SlotLayout {
-    int64_t coef, pb, gsv, gsid, bytes;  // offsets from the slot start; PassRec at 0
-};
-
-struct BatchArgs {
-    const gf2_desc *descs;
-    const int32_t *order;  // matrix indices of this class, most expensive first
-    int32_t count;
-    int32_t *counter;  // next position in `order` (zeroed before the launch)
-    uint64_t *arena;
-    int64_t *P;
-    int64_t *Q;
-    int64_t *ranks;
-    uint8_t *slots;
-    SlotLayout lay;
-};
 
 // Staged special-row lists of one pass, and the nibble tables of the maps
 // stripe word -> (w, u) for the other rows.
@@ -210,7 +192,7 @@ __global__ __launch_bounds__(NW * 64) void k_batch(BatchArgs a) {
         uint64_t *A = a.arena + d.a_off;
         int64_t *P = a.P + d.p_off;
         int64_t *Q = a.Q + d.q_off;
-        int64_t *rank = a.ranks + mi;
+        int64_t *rank = a.ranks + (a.rank_off ? a.rank_off[mi] : (int64_t)mi);
         const int64_t m = d.m, n = d.n, ldw = d.ldw;
         const int64_t mn = m < n ? m : n;
         for (int64_t i = tid; i < m; i += NT) P[i] = i;
@@ -261,7 +243,7 @@ static const BatchConfig kBatchConfigs[] = {
     {4, 8, 1, 2, 4, "w4_k8_tw1_q2"},   {4, 4, 16, 4, 2, "w4_k4_tw16_q4"}, {8, 8, 2, 4, 4, "w8_k8_tw2_q4"},
     {8, 4, 16, 8, 2, "w8_k4_tw16_q8"}, {8, 8, 4, 8, 2, "w8_k8_tw4_q8"},
 };
-constexpr int NBATCH_CONFIGS = (int)(sizeof(kBatchConfigs) / sizeof(kBatchConfigs[0]));
+static_assert(sizeof(kBatchConfigs) / sizeof(kBatchConfigs[0]) == NBATCH_CONFIGS, "schedule table");
 
 template <int NW, int TB, int TW, int WQ, int U>
 static hipError_t batch_launch_t(int grid, const BatchArgs &a, hipStream_t s) {
@@ -287,7 +269,7 @@ static int batch_occupancy_t() {
     X(6, 8, 4, 16, 8, 2)       \
     X(7, 8, 8, 4, 8, 2)
 
-static hipError_t batch_launch(int cfg, int grid, const BatchArgs &a, hipStream_t s) {
+hipError_t batch_launch(int cfg, int grid, const BatchArgs &a, hipStream_t s) {
 #define X(ID, NW, TB, TW, WQ, U) \
     case ID:                     \
         return batch_launch_t<NW, TB, TW, WQ, U>(grid, a, s);
@@ -299,7 +281,7 @@ static hipError_t batch_launch(int cfg, int grid, const BatchArgs &a, hipStream_
 #undef X
 }
 
-static int batch_occupancy(int cfg) {
+int batch_occupancy(int cfg) {
 #define X(ID, NW, TB, TW, WQ, U) \
     case ID:                     \
         return batch_occupancy_t<NW, TB, TW, WQ, U>();
@@ -331,6 +313,39 @@ __global__ void k_batch_fill(uint64_t *arena, const gf2_desc *descs, int count, 
     }
 }
 
+hipError_t batch_reset(int32_t *counters, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counters, n);
+    return hipGetLastError();
+}
+
+SlotLayout batch_slot_layout(int64_t mmax, int64_t ldwmax) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    SlotLayout L;
+    size_t off = al(sizeof(PassRec));
+    L.coef = (int64_t)off;
+    off += al((size_t)(mmax > 0 ? mmax : 1) * 8);
+    L.pb = (int64_t)off;
+    off += al((size_t)KW * (size_t)(ldwmax > 0 ? ldwmax : 1) * 8);
+    L.gsv = (int64_t)off;
+    off += al((size_t)(mmax > 0 ? mmax : 1) * 8);
+    L.gsid = (int64_t)off;
+    off += al((size_t)(mmax > 0 ? mmax : 1) * 4);
+    L.bytes = (int64_t)off;
+    return L;
+}
+
+// Size classes by the larger side, and the built-in schedule of each (from
+// autotuning the 4096-matrix uneven batch on MI355X).
+static const int64_t kClassMax[] = {256, 512, 1024, 2048, 4096, INT64_MAX};
+constexpr int NCLASS = (int)(sizeof(kClassMax) / sizeof(kClassMax[0]));
+static const int kClassDefault[NCLASS] = {3, 2, 3, 2, 6, 7};
+
+int batch_default_config(int64_t max_dim) {
+    int k = 0;
+    while (k + 1 < NCLASS && max_dim > kClassMax[k]) k++;
+    return kClassDefault[k];
+}
+
 }  // namespace gf2
 
 using namespace gf2;
@@ -339,27 +354,6 @@ namespace {
 
 constexpr size_t BALIGN = 256;
 size_t balign(size_t x) { return (x + BALIGN - 1) & ~(BALIGN - 1); }
-
-// Size classes: by the larger side of the matrix.
-const int64_t kClassMax[] = {256, 512, 1024, 2048, 4096, INT64_MAX};
-constexpr int NCLASS = (int)(sizeof(kClassMax) / sizeof(kClassMax[0]));
-// Built-in schedule per class (0-based config), from timing on MI355X.
-const int kClassDefault[NCLASS] = {0, 1, 2, 4, 6, 7};
-
-SlotLayout slot_layout(int64_t mmax, int64_t ldwmax) {
-    SlotLayout L;
-    size_t off = balign(sizeof(PassRec));
-    L.coef = (int64_t)off;
-    off += balign((size_t)(mmax > 0 ? mmax : 1) * 8);
-    L.pb = (int64_t)off;
-    off += balign((size_t)KW * (size_t)(ldwmax > 0 ? ldwmax : 1) * 8);
-    L.gsv = (int64_t)off;
-    off += balign((size_t)(mmax > 0 ? mmax : 1) * 8);
-    L.gsid = (int64_t)off;
-    off += balign((size_t)(mmax > 0 ? mmax : 1) * 4);
-    L.bytes = (int64_t)off;
-    return L;
-}
 
 int device_cu_count() {
     int dev = 0, cus = 0;
@@ -404,7 +398,7 @@ void plan_layout(gf2_batch_plan *p) {
         const int occ = batch_occupancy(c.cfg);
         const int64_t slots = (int64_t)occ * cus;
         c.grid = (int)std::min<int64_t>((int64_t)c.idx.size(), slots);
-        c.lay = slot_layout(c.mmax, c.ldwmax);
+        c.lay = batch_slot_layout(c.mmax, c.ldwmax);
         c.ws_off = off;
         c.ws_len = balign((size_t)c.grid * (size_t)c.lay.bytes);
         off += c.ws_len;
@@ -415,8 +409,7 @@ void plan_layout(gf2_batch_plan *p) {
 hipError_t plan_enqueue(gf2_batch_plan *p, uint64_t *arena, int64_t *P, int64_t *Q, int64_t *ranks, uint8_t *ws,
                         hipStream_t s) {
     int32_t *counters = (int32_t *)ws;
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counters, (int)p->classes.size());
-    hipError_t e = hipGetLastError();
+    hipError_t e = batch_reset(counters, (int)p->classes.size(), s);
     if (e != hipSuccess) return e;
     for (size_t ci = 0; ci < p->classes.size(); ci++) {
         auto &c = p->classes[ci];
@@ -424,6 +417,7 @@ hipError_t plan_enqueue(gf2_batch_plan *p, uint64_t *arena, int64_t *P, int64_t 
         BatchArgs a;
         a.descs = p->d_descs;
         a.order = p->d_order + c.order_off;
+        a.rank_off = nullptr;
         a.count = (int32_t)c.idx.size();
         a.counter = counters + ci;
         a.arena = arena;

@@ -28,6 +28,8 @@ EXPORTS = [
     "gf2_addmul", "gf2_make_table", "gf2_check_padding", "gf2_profile_start", "gf2_profile_stop",
     "gf2_batch_plan_create", "gf2_batch_workspace_bytes", "gf2_ple_batched", "gf2_batch_plan_info",
     "gf2_batch_plan_destroy", "gf2_batch_num_configs", "gf2_batch_config_name",
+    "gf2_serve_create", "gf2_serve_submit", "gf2_serve_poll", "gf2_serve_wait", "gf2_serve_fetch",
+    "gf2_serve_release", "gf2_serve_stats_get", "gf2_serve_destroy",
 ]
 
 
@@ -63,6 +65,23 @@ class BatchClass(ctypes.Structure):
                 ("grid", ctypes.c_int32), ("tuned_ms", ctypes.c_double)]
 
 
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("small_max_dim", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class ServeInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("ldw", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "queued", "running",
+                                              "launches_batched", "launches_single", "bytes_in_use", "bytes_peak",
+                                              "budget_bytes")] + [("now", ctypes.c_double)]
+
+
 def load():
     """Load the HIP library; raises if it has not been built."""
     global _lib
@@ -96,6 +115,14 @@ def load():
         "gf2_batch_plan_destroy": (st, [p]),
         "gf2_batch_num_configs": (i32, []),
         "gf2_batch_config_name": (ctypes.c_char_p, [i32]),
+        "gf2_serve_create": (st, [p, p]),
+        "gf2_serve_submit": (st, [p, p, i32, i64, i64, i64, p]),
+        "gf2_serve_poll": (st, [p, i64, p]),
+        "gf2_serve_wait": (st, [p, i64, p]),
+        "gf2_serve_fetch": (st, [p, i64, p, i64, p, p, p, i32]),
+        "gf2_serve_release": (st, [p, i64]),
+        "gf2_serve_stats_get": (st, [p, p]),
+        "gf2_serve_destroy": (st, [p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -130,7 +157,7 @@ def _packed(t, name):
         raise TypeError("%s must be a 2-D int64/uint64 tensor of packed rows" % name)
     if not t.is_cuda:
         raise ValueError("%s must be on the GPU" % name)
-    if t.stride(1) != 1:
+    if t.numel() and t.stride(1) != 1:
         raise ValueError("%s rows must be contiguous" % name)
     return t
 
@@ -325,6 +352,103 @@ class BatchPlan:
         if self._h and self._h.value:
             load().gf2_batch_plan_destroy(self._h)
             self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Serving session
+# ---------------------------------------------------------------------------
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+
+
+def _info_dict(i):
+    return {"state": REQ_STATES.get(i.state, i.state), "status": int(i.status), "m": int(i.m), "n": int(i.n),
+            "ldw": int(i.ldw), "t_submit": i.t_submit, "t_admit": i.t_admit, "t_done": i.t_done}
+
+
+class ServeSession:
+    """gf2_serve_*: submit packed matrices, poll/wait, fetch results."""
+
+    def __init__(self, budget_bytes=0, streams=0, max_batch=0, small_max_dim=0):
+        o = ServeOpts()
+        o.budget_bytes = int(budget_bytes)
+        o.streams = int(streams)
+        o.max_batch = int(max_batch)
+        o.small_max_dim = int(small_max_dim)
+        self._h = ctypes.c_void_p(0)
+        self._keep = {}  # device inputs referenced until admitted
+        _check(load().gf2_serve_create(ctypes.byref(o), ctypes.byref(self._h)), "gf2_serve_create")
+
+    def submit(self, A, n):
+        """A: packed (m, ldw) numpy uint64 array (host) or device tensor."""
+        t = ctypes.c_int64(0)
+        if isinstance(A, torch.Tensor):
+            A = _packed(A, "A")
+            m, ldw = A.shape
+            if A.numel() and A.stride(0) != ldw:
+                raise ValueError("A must be contiguous")
+            _check(load().gf2_serve_submit(self._h, _ptr(A), 1, m, n, ldw, ctypes.byref(t)), "gf2_serve_submit")
+            self._keep[t.value] = A
+        else:
+            import numpy as np
+            A = np.ascontiguousarray(A, dtype=np.uint64)
+            m, ldw = A.shape
+            ptr = A.ctypes.data_as(ctypes.c_void_p) if A.size else ctypes.c_void_p(0)
+            _check(load().gf2_serve_submit(self._h, ptr, 0, m, n, ldw, ctypes.byref(t)), "gf2_serve_submit")
+        return t.value
+
+    def poll(self, ticket):
+        i = ServeInfo()
+        _check(load().gf2_serve_poll(self._h, ticket, ctypes.byref(i)), "gf2_serve_poll")
+        if i.state != 0:
+            self._keep.pop(ticket, None)
+        return _info_dict(i)
+
+    def wait(self, ticket):
+        i = ServeInfo()
+        _check(load().gf2_serve_wait(self._h, ticket, ctypes.byref(i)), "gf2_serve_wait")
+        self._keep.pop(ticket, None)
+        return _info_dict(i)
+
+    def fetch(self, ticket, m, n, ldw=None):
+        """Copy a finished request to host numpy arrays and release it:
+        returns (rank, P, Q, L\\E)."""
+        import numpy as np
+        ldw = ldw or (n + 63) // 64
+        LE = np.zeros((m, ldw), dtype=np.uint64)
+        P = np.zeros(m, dtype=np.int64)
+        Q = np.zeros(min(m, n), dtype=np.int64)
+        r = np.zeros(1, dtype=np.int64)
+        cp = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else ctypes.c_void_p(0)
+        _check(load().gf2_serve_fetch(self._h, ticket, cp(LE), ldw, cp(P), cp(Q), cp(r), 0), "gf2_serve_fetch")
+        self._keep.pop(ticket, None)
+        return int(r[0]), P, Q, LE
+
+    def fetch_device(self, ticket, LE, P, Q, rank):
+        """Copy a finished request into device tensors and release it."""
+        _check(load().gf2_serve_fetch(self._h, ticket, _ptr(LE), LE.shape[1] if LE is not None else 0, _ptr(P),
+                                      _ptr(Q), _ptr(rank), 1), "gf2_serve_fetch")
+        self._keep.pop(ticket, None)
+
+    def release(self, ticket):
+        _check(load().gf2_serve_release(self._h, ticket), "gf2_serve_release")
+        self._keep.pop(ticket, None)
+
+    def stats(self):
+        st = ServeStats()
+        _check(load().gf2_serve_stats_get(self._h, ctypes.byref(st)), "gf2_serve_stats_get")
+        return {k: getattr(st, k) for k, _ in ServeStats._fields_}
+
+    def close(self):
+        if self._h and self._h.value:
+            load().gf2_serve_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+        self._keep.clear()
 
     def __del__(self):
         try:

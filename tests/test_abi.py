@@ -86,3 +86,16 @@ def test_batch_plan_rejects_bad_descriptors():
     assert create(descs, aw, pl, ql, config=G.batch_num_configs() + 1) == 1
     assert G.batch_num_configs() >= 4
     assert G.batch_config_name(1) and G.batch_config_name(0) == ""
+
+
+def test_serve_create_rejects_bad_options():
+    """gf2_serve_create checks its options before touching the device."""
+    lib = G.load()
+    for field, value in (("streams", 17), ("streams", -1), ("small_max_dim", 5000), ("budget_bytes", -5),
+                         ("max_batch", -2)):
+        o = G.ServeOpts()
+        setattr(o, field, value)
+        h = ctypes.c_void_p(0)
+        assert lib.gf2_serve_create(ctypes.byref(o), ctypes.byref(h)) == 1, field
+        assert not h.value
+    assert lib.gf2_serve_create(None, None) == 1
