@@ -85,8 +85,9 @@ def cpu_baseline(n_full, sample):
         "unit": "matrices/s",
         "cores": oracle.threads(),
         "kind": "oracle",
-        "sample": "%dx%d Bernoulli(0.5) seed 2, whole oracle PLE in %.2f s (rank %d), scaled by (%d/%d)^3"
-                  % (sample, sample, dt, r, n_full, sample),
+        "sample": "%dx%d Bernoulli(0.5) seed 2, whole oracle PLE in %.2f s (rank %d), scaled by (%d/%d)^3; "
+                  "the sample is small enough to stay in the host's caches, so the scaled rate overstates the "
+                  "oracle on the full matrix" % (sample, sample, dt, r, n_full, sample),
     }
 
 
@@ -180,6 +181,112 @@ def run_batched(args, log_fn):
     return out
 
 
+def run_serving(args, log_fn):
+    """Serving: a request stream (sides log-uniform in [128, 16384], square or
+    s x ceil(s/2), density 0.5 or 0.05; seed 8), inputs resident on the device.
+    Plain = gf2_ple per request in arrival order on one stream.  Served = the
+    serving session (64 GiB budget) fed Poisson arrivals at 0.9x the measured
+    plain capacity (latency = arrival -> result in device memory), and the
+    same requests all at once (saturated throughput).  The plain latency at
+    the same arrivals is a FIFO replay of the measured plain service times."""
+    import numpy as np
+    import torch
+
+    from paper_1111_6549_amd import gf2ple as G
+    from paper_1111_6549_amd import inputs
+
+    count = args.serve_count
+    reqs = inputs.serving_requests(count, seed=8)
+    dev = [torch.from_numpy(inputs.bernoulli(r["m"], r["n"], r["seed"], p=r["p"]).view(np.int64)).cuda() for r in reqs]
+    torch.cuda.synchronize()
+    log_fn("serving: %d requests resident (%.2f GB)" % (count, sum(t.numel() for t in dev) * 8 / 1e9))
+
+    # plain: gf2_ple per request, each on a fresh copy, timed per request
+    big = max(t.numel() for t in dev)
+    scratch = torch.empty(big, dtype=torch.int64, device="cuda")
+    wsz = max(G.workspace_bytes(r["m"], r["n"], (r["n"] + 63) // 64) for r in reqs)
+    wsp = G.alloc_workspace(wsz)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in reqs]
+    for r, t in list(zip(reqs, dev))[:8]:
+        w = scratch[:t.numel()].view(t.shape)
+        w.copy_(t)
+        G.ple(w, r["n"], ws=wsp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (r, t), (a, b) in zip(zip(reqs, dev), ev):
+        w = scratch[:t.numel()].view(t.shape)
+        w.copy_(t)
+        a.record()
+        G.ple(w, r["n"], ws=wsp)
+        b.record()
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    service = np.array([a.elapsed_time(b) * 1e-3 for a, b in ev])
+    capacity = count / plain_s
+    log_fn("serving: plain %.3f s (%.1f req/s)" % (plain_s, capacity))
+    del scratch, wsp
+
+    def serve(arrivals):
+        S = G.ServeSession(budget_bytes=64 << 30)
+        tickets = []
+        start = time.perf_counter()
+        for r, t, at in zip(reqs, dev, arrivals):
+            while time.perf_counter() - start < at:
+                pass
+            tickets.append(S.submit(t, r["n"]))
+        infos = [S.wait(tk) for tk in tickets]
+        st = S.stats()
+        for tk in tickets:
+            S.release(tk)
+        S.close()
+        lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+        span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+        return lat, span, st
+
+    rate = 0.9 * capacity
+    rng = np.random.Generator(np.random.PCG64(8))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    arrivals -= arrivals[0]
+    lat, span, st = serve(arrivals)
+    # FIFO replay of the plain service times at the same arrivals
+    fin = 0.0
+    plain_lat = np.empty(count)
+    for i in range(count):
+        fin = max(arrivals[i], fin) + service[i]
+        plain_lat[i] = fin - arrivals[i]
+    log_fn("serving: poisson %.1f req/s: p50 %.2f ms p99 %.2f ms" % (rate, np.median(lat) * 1e3,
+                                                                     np.percentile(lat, 99) * 1e3))
+    lat_sat, span_sat, st_sat = serve(np.zeros(count))
+    log_fn("serving: saturated %.3f s for %d requests" % (span_sat, count))
+    pct = lambda x, q: round(float(np.percentile(x, q)) * 1e3, 3)
+    out = {
+        "workload": "%d requests, sides log-uniform in [128, 16384], square or s x ceil(s/2), density 0.5 or 0.05, "
+                    "seed 8, inputs resident on the device, 64 GiB budget" % count,
+        "plain_capacity_per_s": round(capacity, 1),
+        "poisson": {"rate_per_s": round(rate, 1), "served_p50_ms": pct(lat, 50), "served_p99_ms": pct(lat, 99),
+                    "served_matrices_per_s": round(count / span, 1), "plain_fifo_p50_ms": pct(plain_lat, 50),
+                    "plain_fifo_p99_ms": pct(plain_lat, 99),
+                    "launches": {"batched": st["launches_batched"], "single": st["launches_single"]}},
+        "saturated": {"served_matrices_per_s": round(count / span_sat, 1),
+                      "plain_matrices_per_s": round(capacity, 1),
+                      "speedup_vs_plain": round((count / span_sat) / capacity, 2),
+                      "served_p50_ms": pct(lat_sat, 50), "served_p99_ms": pct(lat_sat, 99),
+                      "launches": {"batched": st_sat["launches_batched"], "single": st_sat["launches_single"]}},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = [i for i in range(count) if max(reqs[i]["m"], reqs[i]["n"]) <= 8192][:args.serve_cpu_sample]
+        t0 = time.perf_counter()
+        for i in sample:
+            B = dev[i].cpu().numpy().view(np.uint64).copy()
+            oracle.ple(B, reqs[i]["n"])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(len(sample) / dt, 2), "unit": "matrices/s", "cores": oracle.threads(),
+                               "kind": "oracle", "sample": "the first %d requests with sides <= 8192, in order, "
+                                                           "%.2f s" % (len(sample), dt)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +304,9 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--batch-cpu-sample", type=int, default=512)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-count", type=int, default=600)
+    ap.add_argument("--serve-cpu-sample", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the PLE of one matrix is not split across GPUs here "
@@ -284,6 +394,12 @@ def main():
         del work, pristine, ws
         torch.cuda.empty_cache()
         batched = run_batched(args, log)
+    serving = None
+    if not args.no_serving:
+        if args.no_batched:
+            del work, pristine, ws
+            torch.cuda.empty_cache()
+        serving = run_serving(args, log)
 
     out = {
         "metric": "PLE time & HBM GB/s (% roofline), 65536² GF(2); batched matrices/s vs plain",
@@ -311,6 +427,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "serving": serving,
         "kernels_ms_per_step": {k: round(v["total_ms"] / args.steps, 3) for k, v in (kernels or {}).items()},
     }
     print(json.dumps(out), flush=True)
