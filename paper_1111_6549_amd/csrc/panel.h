@@ -78,8 +78,89 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
     int nspec = 0;
     bool slow = false;
 
-    // ---- search over a register window, grown 64 rows at a time -------------
-    {
+    // ---- search over a register window ---------------------------------------
+    if constexpr (WQ == 2) {
+        // Two registers (128 rows), loaded at once.  Per column: the candidate
+        // masks are ballots, the pivot is their first set bit, the swap and the
+        // elimination are selects on scalar masks.
+        const int nmax = (int)(rows < 128 ? rows : 128);
+        uint64_t v0 = 0, v1 = 0;
+        {
+            const int64_t row0 = r + (lane < rows ? lane : rows - 1);
+            const int64_t row1 = r + (64 + lane < rows ? 64 + lane : rows - 1);
+            const uint64_t t0 = A[row0 * ldw + sw];
+            const uint64_t t1 = A[row1 * ldw + sw];
+            v0 = lane < nmax ? (t0 & kmask) : 0ull;
+            v1 = 64 + lane < nmax ? (t1 & kmask) : 0ull;
+        }
+        PANEL_STAMP(1)
+        int id0 = lane, id1 = 64 + lane;  // original position of the row each lane holds
+        uint64_t act0 = nmax >= 64 ? ~0ull : ((1ull << nmax) - 1ull);
+        uint64_t act1 = nmax >= 128 ? ~0ull : (nmax <= 64 ? 0ull : ((1ull << (nmax - 64)) - 1ull));
+        for (int j = 0; j < kp; j++) {
+            const uint64_t bj = 1ull << j;
+            const uint64_t m0 = __ballot((v0 & bj) != 0) & act0;
+            const uint64_t m1 = __ballot((v1 & bj) != 0) & act1;
+            if (!(m0 | m1)) {
+                if (nmax < rows) {  // a row outside the window may hold the pivot
+                    slow = true;
+                    break;
+                }
+                continue;  // column j has no pivot
+            }
+            const bool in0 = m0 != 0;
+            const int lf = (int)__builtin_ctzll(in0 ? m0 : m1);
+            const uint64_t pv = in0 ? readlane64(v0, lf) : readlane64(v1, lf);
+            const uint64_t vr = readlane64(v0, npiv);
+            const int idp = in0 ? readlane32(id0, lf) : readlane32(id1, lf);
+            const int idr = readlane32(id0, npiv);
+            const uint64_t pe = pv & above(j);
+            const uint64_t lbit = 1ull << lf, nbit = 1ull << npiv;
+            // rows below the pivot with a 1 in column j (the row moving to the
+            // pivot's old place has a 0 there)
+            const uint64_t e0 = in0 ? (m0 & ~lbit) : m0;
+            const uint64_t e1 = in0 ? m1 : (m1 & ~lbit);
+            const bool at_f = __builtin_amdgcn_inverse_ballot_w64(lbit);
+            if (in0) {
+                v0 = at_f ? vr : v0;
+                id0 = at_f ? idr : id0;
+            } else {
+                v1 = at_f ? vr : v1;
+                id1 = at_f ? idr : id1;
+            }
+            const bool me = __builtin_amdgcn_inverse_ballot_w64(nbit);
+            v0 = me ? pv : v0;
+            id0 = me ? idp : id0;
+            v0 ^= __builtin_amdgcn_inverse_ballot_w64(e0) ? pe : 0ull;
+            v1 ^= __builtin_amdgcn_inverse_ballot_w64(e1) ? pe : 0ull;
+            my_q = me ? j : my_q;
+            my_fin = me ? pv : my_fin;
+            my_p = me ? (in0 ? lf : 64 + lf) : my_p;
+            act0 &= ~nbit;
+            npiv++;
+            if (npiv == rows) break;
+        }
+        npiv = uni(npiv);
+        PANEL_STAMP(2)
+        if (!slow) {
+            int base = 0;
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                const int pos = 64 * q + lane;
+                const int idq = q ? id1 : id0;
+                const bool f = pos < nmax && (pos < npiv || idq != pos);
+                const uint64_t msk = __ballot(f);
+                const int idx = base + __popcll(msk & ((1ull << lane) - 1ull));
+                if (f) {
+                    L.dst[idx] = r + pos;
+                    L.src[idx] = r + idq;
+                }
+                base += __popcll(msk);
+            }
+            nspec = uni(base);
+        }
+    } else {
+
         uint64_t val[WQ];
         int id[WQ];
 #pragma unroll
@@ -299,11 +380,15 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
     uint64_t vV = (lane < kp) ? (1ull << lane) : 0ull;  // unit stripe vectors
     uint64_t hP = (lane < rbar) ? (1ull << lane) : 0ull, uP = 0;
     uint64_t hV = 0, uV = 0, hD = 0, uD = 0;
-    for (int l = 0; l < rbar; l++) {
-        const int ql = uni(readlane32(my_q, l));
+    // fully unrolled (constant lane indices let the independent reads of
+    // my_q / my_fin run ahead); iterations l >= rbar change nothing: their
+    // my_fin, hP are 0 and bl is 0
+#pragma unroll
+    for (int l = 0; l < KW; l++) {
+        const int ql = readlane32(my_q, l);
         const uint64_t pe = readlane64(my_fin, l) & above(ql);
         const uint64_t hl = readlane64(hP, l);  // final: pivot l is reduced by pivots < l only
-        const uint64_t bl = 1ull << l;
+        const uint64_t bl = l < rbar ? 1ull << l : 0ull;
         const uint64_t mp = (lane > l) ? (0ull - ((my_fin >> ql) & 1ull)) : 0ull;
         const uint64_t mv = 0ull - ((vV >> ql) & 1ull);
         const uint64_t md = 0ull - ((vD >> ql) & 1ull);
