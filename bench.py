@@ -300,6 +300,7 @@ def main():
     ap.add_argument("--m4-variant", type=int, default=0, help="update schedule 1..8 (0 = library default)")
     ap.add_argument("--m4-blocks", type=int, default=0, help="target blocks per update launch (0 = default)")
     ap.add_argument("--panel-regs", type=int, default=0, help="panel register window 2/4/8 (0 = default)")
+    ap.add_argument("--lookahead", type=int, default=0, help="0 = library default, 1 = off, 2 = every pass")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -333,7 +334,8 @@ def main():
     ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw))
     torch.cuda.synchronize()
 
-    sched = dict(m4_variant=args.m4_variant, m4_blocks=args.m4_blocks, panel_regs=args.panel_regs)
+    sched = dict(m4_variant=args.m4_variant, m4_blocks=args.m4_blocks, panel_regs=args.panel_regs,
+                 lookahead=args.lookahead)
 
     def step():
         work.copy_(pristine)

@@ -10,9 +10,14 @@
 
 namespace gf2 {
 hipError_t launch_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *rank, PassRec *rec, hipStream_t s);
-hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
-                       int64_t *P, int64_t *Q, int64_t *rank, uint64_t *coef, uint64_t *PB, uint64_t *gsv,
-                       int32_t *gsid, int m4_variant, int m4_target, int panel_regs, hipStream_t s);
+hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
+                        int64_t *P, int64_t *Q, int64_t *rank, uint64_t *gsv, int32_t *gsid, int panel_regs, bool la,
+                        hipStream_t s);
+hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
+                          uint64_t *coef, uint64_t *PB, bool la, hipStream_t s);
+hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
+                         const uint64_t *coef, const uint64_t *PB, int first, int m4_variant, int m4_target,
+                         hipStream_t s);
 hipError_t launch_m4rm(uint64_t *C, int64_t ldc, int64_t m, const uint64_t *coef, int64_t coef_ld, const uint64_t *B,
                        int64_t ldb, int nbits, int64_t w_begin, int64_t w_end, int m4_variant, int m4_target,
                        hipStream_t s);
@@ -99,8 +104,48 @@ int *device_flag() {
 
 namespace gf2 {
 
+// Second stream and events of the look-ahead: one set per host thread and
+// device, made on first use and kept for the life of the thread.
+struct LookCtx {
+    hipStream_t s2 = nullptr;
+    hipEvent_t evA = nullptr, evN = nullptr;
+};
+
+static LookCtx *look_ctx() {
+    thread_local std::vector<LookCtx> ctx;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if ((int)ctx.size() <= dev) ctx.resize(dev + 1);
+    LookCtx &c = ctx[dev];
+    if (!c.s2) {
+        hipStream_t s2 = nullptr;
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(s2);
+            return nullptr;
+        }
+        c.s2 = s2;
+        c.evA = a;
+        c.evN = b;
+    }
+    return &c;
+}
+
+// Trailing blocks above this many bytes take the look-ahead in the default
+// mode: their update outlasts the next panel.
+constexpr double LOOKAHEAD_BYTES = 64.0 * 1024 * 1024;
+
 size_t ple_workspace_total(int64_t m, int64_t ldw) { return ple_layout(m, ldw).total; }
 
+// The pass loop of Algorithm 2.  Pass t: panel(t) (Algorithm 1 on the stripe
+// at c = 64 t), permute(t) (swaps, coefficients, compressed L bits), then the
+// trailing update.  With look-ahead the next stripe word is brought up to
+// date by permute(t) (ordinary rows) and panel(t + 1) (the pass's special
+// rows), so panel(t + 1) -- which reads only that word -- runs on a second
+// stream beside the update of the words beyond; the next permute waits for
+// both.
 hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
                        void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync) {
     const PleLayout L = ple_layout(m, ldw);
@@ -111,16 +156,54 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
     uint64_t *PB = (uint64_t *)(base + L.pb);
     uint64_t *gsv = (uint64_t *)(base + L.gsv);
     int32_t *gsid = (int32_t *)(base + L.gsid);
+    const int m4v = opts ? opts->m4_variant : 0;
+    const int m4t = opts ? opts->m4_blocks : 0;
+    const int pr = opts ? opts->panel_regs : 0;
+    const int mode = opts ? opts->lookahead : 0;
 
     hipError_t e = launch_init(P, m, Q, mn, rank, recs, s);
     if (e != hipSuccess) return e;
     if (m == 0 || n == 0) return hipSuccess;
 
     const int64_t npasses = words_for(n);
+    LookCtx *lc = mode == 1 ? nullptr : look_ctx();
+    auto want_la = [&](int64_t t) {
+        if (!lc || t + 1 >= npasses) return false;
+        if (mode == 2) return true;
+        const int64_t c = t * KW;
+        const double rows = (double)(m - (c < m ? c : m));
+        return rows * (double)(npasses - t - 2) * 8.0 > LOOKAHEAD_BYTES;
+    };
+    if ((e = launch_panel(A, m, n, ldw, 0, &recs[1], &recs[0], P, Q, rank, gsv, gsid, pr, false, s)) != hipSuccess)
+        return e;
+    bool pending = false;  // this pass's panel ran on the second stream
     int64_t since_check = 0;
     for (int64_t t = 0; t < npasses; t++) {
         const int64_t c = t * KW;
-        if (c >= m && allow_sync) {
+        PassRec *rec = &recs[t & 1], *nxt = &recs[(t + 1) & 1];
+        if (pending) {
+            if ((e = hipStreamWaitEvent(s, lc->evN, 0)) != hipSuccess) return e;
+            pending = false;
+        }
+        if (want_la(t)) {
+            // permute also updates the next stripe word of the ordinary rows;
+            // the next panel finishes the special rows' one, then searches,
+            // while the update of the words beyond runs
+            if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, true, s)) != hipSuccess) return e;
+            if ((e = hipEventRecord(lc->evA, s)) != hipSuccess) return e;
+            if ((e = launch_update(A, m, n, ldw, c, rec, coef, PB, 2, m4v, m4t, s)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(lc->s2, lc->evA, 0)) != hipSuccess) return e;
+            if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, true, lc->s2)) !=
+                hipSuccess)
+                return e;
+            if ((e = hipEventRecord(lc->evN, lc->s2)) != hipSuccess) return e;
+            pending = true;
+            continue;
+        }
+        if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, false, s)) != hipSuccess) return e;
+        if ((e = launch_update(A, m, n, ldw, c, rec, coef, PB, 1, m4v, m4t, s)) != hipSuccess) return e;
+        if (t + 1 >= npasses) break;
+        if (c + KW >= m && allow_sync) {
             // rank <= m: once it reaches m the remaining passes are empty
             if (since_check == 0) {
                 int64_t host_rank = 0;
@@ -130,9 +213,8 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
             }
             since_check = (since_check + 1) % 8;
         }
-        e = launch_pass(A, m, n, ldw, c, &recs[(t + 1) & 1], &recs[t & 1], P, Q, rank, coef, PB, gsv, gsid,
-                        opts ? opts->m4_variant : 0, opts ? opts->m4_blocks : 0, opts ? opts->panel_regs : 0, s);
-        if (e != hipSuccess) return e;
+        if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, false, s)) != hipSuccess)
+            return e;
     }
     return hipGetLastError();
 }
@@ -189,6 +271,7 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
     if (opts && (opts->update < 0 || opts->update > 2 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
     if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
         return GF2_EINVAL;
+    if (opts && (opts->lookahead < 0 || opts->lookahead > 2)) return GF2_EINVAL;
     if (opts && opts->update == 2) return GF2_EINVAL;  // MFMA trailing update: see gf2_addmul
     const PleLayout L = ple_layout(m, ldw);
     if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;

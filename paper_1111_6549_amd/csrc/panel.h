@@ -35,16 +35,47 @@ struct PanelLdsT {
 };
 using PanelLds = PanelLdsT<SLOW_LDS_ROWS>;
 
+// Stripe words are read past the L1 cache: with the look-ahead the panel
+// itself has just rewritten some of them (fix_deferred_rows).
+__device__ __forceinline__ uint64_t ld_stripe(const uint64_t *p) { return *(const volatile uint64_t *)p; }
+
+// With the look-ahead, the previous pass's permute leaves the special rows
+// (its pivots and the rows they displaced) unmoved and un-updated in the word
+// that is this pass's stripe: row k goes from position src_k to dst_k and gets
+// the sum of the previous pivots' old words selected by its coefficient word.
+// One wave: read all 128 entries first, then write them.
+__device__ __forceinline__ void fix_deferred_rows(uint64_t *A, int64_t ldw, int64_t sw, const PassRec *pr,
+                                                  const int lane) {
+    const int fr = pr->rbar, fn = pr->nspec;
+    if (!pr->active || fn <= 0) return;
+    const bool h0 = lane < fn, h1 = 64 + lane < fn;
+    const uint64_t o0 = h0 ? ld_stripe(A + pr->spec_src[lane] * ldw + sw) : 0ull;
+    const uint64_t o1 = h1 ? ld_stripe(A + pr->spec_src[64 + lane] * ldw + sw) : 0ull;
+    const uint64_t c0 = h0 ? pr->spec_coef[lane] : 0ull;
+    const uint64_t c1 = h1 ? pr->spec_coef[64 + lane] : 0ull;
+    uint64_t n0 = o0, n1 = o1;
+    for (int b = 0; b < fr; b++) {  // entries 0 .. rbar-1 are the pivots
+        const uint64_t pb = readlane64(o0, b);
+        n0 ^= ((c0 >> b) & 1ull) ? pb : 0ull;
+        n1 ^= ((c1 >> b) & 1ull) ? pb : 0ull;
+    }
+    if (h0) A[pr->spec_dst[lane] * ldw + sw] = n0;
+    if (h1) A[pr->spec_dst[64 + lane] * ldw + sw] = n1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // One wave (lane = threadIdx.x & 63) computes the panel of the stripe at
 // column c.  `prev` is the previous pass's record (its r + rbar is this
 // pass's r; it is read before `rec` is written, so the two may be the same
 // record), `rec` receives this pass.  Writes P[r..r+rbar), Q[r..r+rbar)
 // and *rank_out = r + rbar.
 template <int WQ, int SR>
-__device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64_t m, int64_t n, int64_t ldw, int64_t c,
+__device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c,
                                            const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
                                            int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelLdsT<SR> &L,
-                                           const int lane) {
+                                           const int lane, bool fix_prev = false) {
 #ifdef GF2_PANEL_TIMING
     uint64_t *dbg = gsv + (c >> 6) * 8;
 #define PANEL_STAMP(k) \
@@ -53,6 +84,7 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
 #define PANEL_STAMP(k)
 #endif
     PANEL_STAMP(0)
+    if (fix_prev && c < n) fix_deferred_rows(A, ldw, c >> 6, prev, lane);
     const int64_t r = prev->r + prev->rbar;
     if (r >= m || c >= n) {
         if (lane == 0) {
@@ -88,8 +120,8 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
         {
             const int64_t row0 = r + (lane < rows ? lane : rows - 1);
             const int64_t row1 = r + (64 + lane < rows ? 64 + lane : rows - 1);
-            const uint64_t t0 = A[row0 * ldw + sw];
-            const uint64_t t1 = A[row1 * ldw + sw];
+            const uint64_t t0 = ld_stripe(A + row0 * ldw + sw);
+            const uint64_t t1 = ld_stripe(A + row1 * ldw + sw);
             v0 = lane < nmax ? (t0 & kmask) : 0ull;
             v1 = 64 + lane < nmax ? (t1 & kmask) : 0ull;
         }
@@ -179,7 +211,7 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
                 if (q >= nreg && q < want) {
                     const int pos = 64 * q + lane;
                     const int64_t row = r + (pos < rows ? pos : rows - 1);
-                    tmp[q] = A[row * ldw + sw];
+                    tmp[q] = ld_stripe(A + row * ldw + sw);
                 }
             }
 #pragma unroll
@@ -294,7 +326,7 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
         volatile int32_t *sid = rows <= SR ? (volatile int32_t *)L.sid : (volatile int32_t *)gsid;
         uint64_t orv = 0;
         for (int64_t pos = lane; pos < rows; pos += 64) {
-            const uint64_t v = A[(r + pos) * ldw + sw] & kmask;
+            const uint64_t v = ld_stripe(A + (r + pos) * ldw + sw) & kmask;
             sv[pos] = v;
             sid[pos] = (int32_t)pos;
             orv |= v;
@@ -376,7 +408,7 @@ __device__ __forceinline__ void panel_body(const uint64_t *__restrict__ A, int64
     // displaced rows (lane d <-> special entry rbar + d): their stripe words as
     // they were when the pass began
     uint64_t vD = 0;
-    if (lane < ndisp) vD = A[L.src[rbar + lane] * ldw + sw] & kmask;
+    if (lane < ndisp) vD = ld_stripe(A + L.src[rbar + lane] * ldw + sw) & kmask;
     uint64_t vV = (lane < kp) ? (1ull << lane) : 0ull;  // unit stripe vectors
     uint64_t hP = (lane < rbar) ? (1ull << lane) : 0ull, uP = 0;
     uint64_t hV = 0, uV = 0, hD = 0, uD = 0;

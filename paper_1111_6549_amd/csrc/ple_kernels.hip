@@ -48,12 +48,16 @@ __global__ void k_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *r
 // ---------------------------------------------------------------------------
 // k_panel: one wave runs the panel of the stripe at column c.
 // ---------------------------------------------------------------------------
-template <int WQ>
-__global__ __launch_bounds__(64) void k_panel(const uint64_t *__restrict__ A, int64_t m, int64_t n, int64_t ldw,
-                                              int64_t c, const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
-                                              int64_t *rank_out, uint64_t *gsv, int32_t *gsid) {
-    __shared__ PanelLds L;
-    panel_body<WQ, SLOW_LDS_ROWS>(A, m, n, ldw, c, prev, rec, P, Q, rank_out, gsv, gsid, L, threadIdx.x);
+// SR: rows of the all-rows search kept in LDS.  The look-ahead panel runs
+// beside the update kernels on their CUs, so it uses SR = 0 (workspace) and
+// a raised wave priority.
+template <int WQ, int SR>
+__global__ __launch_bounds__(64) void k_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c,
+                                              const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
+                                              int64_t *rank_out, uint64_t *gsv, int32_t *gsid, int fix_prev) {
+    __shared__ PanelLdsT<SR> L;
+    if (SR == 0) __builtin_amdgcn_s_setprio(3);
+    panel_body<WQ, SR>(A, m, n, ldw, c, prev, rec, P, Q, rank_out, gsv, gsid, L, threadIdx.x, fix_prev != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -64,9 +68,9 @@ __global__ __launch_bounds__(64) void k_panel(const uint64_t *__restrict__ A, in
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__ A, int64_t m, int64_t ldw, int64_t c,
                                                           const PassRec *__restrict__ rec, uint64_t *__restrict__ coef,
-                                                          uint64_t *__restrict__ PB, int nA) {
-    __shared__ uint64_t tw[8][256], tu[8][256];
-    __shared__ uint64_t simg_w[KW], simg_u[KW];
+                                                          uint64_t *__restrict__ PB, int nA, int64_t nw, int la) {
+    __shared__ uint64_t tw[8][256], tu[8][256], tn[8][256];
+    __shared__ uint64_t simg_w[KW], simg_u[KW], simg_n[KW];
     __shared__ int64_t sdisp[KW];
     __shared__ uint64_t sdcoef[KW];
 
@@ -89,7 +93,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         for (int t = 0; t < PER; t++) {
             const int k = slot + SLOTS * t;
             nv[t] = 0;
-            if (k < nspec && w < ldw) {
+            if (k < nspec && w < ldw && !(la && w == sw + 1)) {
                 const int64_t src = rec->spec_src[k];
                 const uint64_t old = A[src * ldw + w];
                 if (k < rbar && w > sw) PB[(int64_t)k * ldw + w] = old;
@@ -100,7 +104,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int k = slot + SLOTS * t;
-            if (k < nspec && w < ldw) {
+            if (k < nspec && w < ldw && !(la && w == sw + 1)) {
                 const int64_t src = rec->spec_src[k], dst = rec->spec_dst[k];
                 if (dst != src || (w >= wr0 && w <= sw)) A[dst * ldw + w] = nv[t];
             }
@@ -121,17 +125,24 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
     }
     __syncthreads();
     for (int d = 0; d < ndisp; d++) maxdisp = sdisp[d] > maxdisp ? sdisp[d] : maxdisp;
+    // look-ahead: the pivots' words of the next stripe, as they were (group A
+    // leaves that column alone in this mode)
+    const bool nxt = la && sw + 1 < nw;
+    if (nxt && tid < KW) simg_n[tid] = tid < rbar ? A[rec->spec_src[tid] * ldw + sw + 1] : 0ull;
+    __syncthreads();
     for (int e = tid; e < 8 * 256; e += WIDE_THREADS) {
         const int b = e >> 8, x = e & 255;
-        uint64_t a = 0, bb = 0;
+        uint64_t a = 0, bb = 0, nn = 0;
 #pragma unroll
         for (int t = 0; t < 8; t++)
             if ((x >> t) & 1) {
                 a ^= simg_w[8 * b + t];
                 bb ^= simg_u[8 * b + t];
+                if (nxt) nn ^= simg_n[8 * b + t];
             }
         tw[b][x] = a;
         tu[b][x] = bb;
+        if (nxt) tn[b][x] = nn;
     }
     __syncthreads();
     const int64_t nB = (int64_t)gridDim.x - nA;
@@ -169,6 +180,12 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
             if (sh && wr0 + 1 < sw) row[wr0 + 1] |= u >> (64 - sh);
         }
         row[sw] = place_bits(u, sw, wr0, sh);
+        if (nxt && wv) {
+            uint64_t acc = 0;
+#pragma unroll
+            for (int b = 0; b < 8; b++) acc ^= tn[b][(wv >> (8 * b)) & 255];
+            row[sw + 1] ^= acc;
+        }
     }
 }
 
@@ -402,43 +419,69 @@ hipError_t launch_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *r
     return hipGetLastError();
 }
 
-hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
-                       int64_t *P, int64_t *Q, int64_t *rank, uint64_t *coef, uint64_t *PB, uint64_t *gsv,
-                       int32_t *gsid, int m4_variant, int m4_target, int panel_regs, hipStream_t s) {
-    {
-        ProfScope ps(KID_PANEL, s);
-        if (panel_regs == 0 || panel_regs == 2)
-            hipLaunchKernelGGL(k_panel<2>, dim3(1), dim3(64), 0, s, (const uint64_t *)A, m, n, ldw, c, prev, rec, P, Q,
-                               rank, gsv, gsid);
-        else if (panel_regs == 4)
-            hipLaunchKernelGGL(k_panel<4>, dim3(1), dim3(64), 0, s, (const uint64_t *)A, m, n, ldw, c, prev, rec, P, Q,
-                               rank, gsv, gsid);
-        else
-            hipLaunchKernelGGL(k_panel<8>, dim3(1), dim3(64), 0, s, (const uint64_t *)A, m, n, ldw, c, prev, rec, P, Q,
-                               rank, gsv, gsid);
+// la: the previous pass ran with the look-ahead (fix its deferred rows
+// first) and this panel runs beside the update.
+hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
+                        int64_t *P, int64_t *Q, int64_t *rank, uint64_t *gsv, int32_t *gsid, int panel_regs, bool la,
+                        hipStream_t s) {
+    ProfScope ps(KID_PANEL, s);
+    const int fx = la ? 1 : 0;
+#define PANEL_LAUNCH(WQ, SR) \
+    hipLaunchKernelGGL((k_panel<WQ, SR>), dim3(1), dim3(64), 0, s, A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, fx)
+    if (panel_regs == 0 || panel_regs == 2) {
+        if (la) PANEL_LAUNCH(2, 0);
+        else PANEL_LAUNCH(2, SLOW_LDS_ROWS);
+    } else if (panel_regs == 4) {
+        if (la) PANEL_LAUNCH(4, 0);
+        else PANEL_LAUNCH(4, SLOW_LDS_ROWS);
+    } else {
+        if (la) PANEL_LAUNCH(8, 0);
+        else PANEL_LAUNCH(8, SLOW_LDS_ROWS);
     }
+#undef PANEL_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
+                          uint64_t *coef, uint64_t *PB, bool la, hipStream_t s) {
     const int nA = (int)((ldw + 63) / 64);
     int64_t rows_est = m - (c < m ? c : m);
     if (rows_est < 1) rows_est = 1;
     int nB = (int)((rows_est + WIDE_THREADS - 1) / WIDE_THREADS);
     if (nB > 256) nB = 256;
     if (nB < 1) nB = 1;
-    {
-        ProfScope ps(KID_PERMUTE, s);
-        hipLaunchKernelGGL(k_permute, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, (const PassRec *)rec, coef,
-                           PB, nA);
-    }
-    const int64_t nw = words_for(n);
-    const int64_t tw0 = (c >> 6) + 1;
-    if (tw0 < nw) {
-        const int v = m4_pick(m4_variant, rows_est, nw - tw0);
-        int ntiles, nchunks;
-        m4_grid(v, rows_est, tw0, nw, m4_target, &ntiles, &nchunks);
-        ProfScope ps(KID_M4RM, s);
-        m4_launch_variant(v, dim3(ntiles * nchunks), s, A, ldw, m, (const uint64_t *)coef, (int64_t)1,
-                          (const uint64_t *)PB, ldw, KW, tw0, nw, ntiles, nchunks, (const PassRec *)rec);
-    }
+    ProfScope ps(KID_PERMUTE, s);
+    hipLaunchKernelGGL(k_permute, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, rec, coef, PB, nA,
+                       words_for(n), la ? 1 : 0);
     return hipGetLastError();
+}
+
+// Trailing update of one pass over words [sw + first, nw): first = 1 for the
+// whole trailing block, 2 when the next stripe was updated on its own.
+hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
+                         const uint64_t *coef, const uint64_t *PB, int first, int m4_variant, int m4_target,
+                         hipStream_t s) {
+    const int64_t nw = words_for(n);
+    const int64_t tw0 = (c >> 6) + first;
+    if (tw0 >= nw) return hipSuccess;
+    int64_t rows_est = m - (c < m ? c : m);
+    if (rows_est < 1) rows_est = 1;
+    const int v = m4_pick(m4_variant, rows_est, nw - tw0);
+    int ntiles, nchunks;
+    m4_grid(v, rows_est, tw0, nw, m4_target, &ntiles, &nchunks);
+    ProfScope ps(KID_M4RM, s);
+    m4_launch_variant(v, dim3(ntiles * nchunks), s, A, ldw, m, coef, (int64_t)1, PB, ldw, KW, tw0, nw, ntiles, nchunks,
+                      rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
+                       int64_t *P, int64_t *Q, int64_t *rank, uint64_t *coef, uint64_t *PB, uint64_t *gsv,
+                       int32_t *gsid, int m4_variant, int m4_target, int panel_regs, hipStream_t s) {
+    hipError_t e = launch_panel(A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, panel_regs, false, s);
+    if (e != hipSuccess) return e;
+    if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, false, s)) != hipSuccess) return e;
+    return launch_update(A, m, n, ldw, c, rec, coef, PB, 1, m4_variant, m4_target, s);
 }
 
 hipError_t launch_m4rm(uint64_t *C, int64_t ldc, int64_t m, const uint64_t *coef, int64_t coef_ld, const uint64_t *B,

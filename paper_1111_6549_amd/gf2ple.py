@@ -47,7 +47,7 @@ class KernelTime(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("check_padding", ctypes.c_int32), ("update", ctypes.c_int32), ("mfma_block", ctypes.c_int32),
                 ("m4_variant", ctypes.c_int32), ("m4_blocks", ctypes.c_int32), ("panel_regs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("lookahead", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class Desc(ctypes.Structure):
@@ -166,8 +166,9 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
 
 
-def _opts(update=0, check_padding=False, mfma_block=0, m4_variant=0, m4_blocks=0, panel_regs=0):
+def _opts(update=0, check_padding=False, mfma_block=0, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0):
     o = Opts()
+    o.lookahead = int(lookahead)
     o.check_padding = 1 if check_padding else 0
     o.update = int(update)
     o.mfma_block = int(mfma_block)
@@ -186,7 +187,7 @@ def alloc_workspace(nbytes, device=None):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
 
 
-def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0, panel_regs=0):
+def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0):
     """In-place PLE of the packed (m, ldw) tensor A with n columns.
 
     Returns (P, Q, rank) as device tensors (int64 [m], int64 [min(m, n)],
@@ -194,7 +195,8 @@ def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0,
     A = _packed(A, "A")
     m, ldw = A.shape
     lib = load()
-    o = _opts(update, check_padding, m4_variant=m4_variant, m4_blocks=m4_blocks, panel_regs=panel_regs)
+    o = _opts(update, check_padding, m4_variant=m4_variant, m4_blocks=m4_blocks, panel_regs=panel_regs,
+              lookahead=lookahead)
     need = int(lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
     if need == 0 and (m or n):
         raise GF2Error(1, "gf2_ple_workspace_bytes")

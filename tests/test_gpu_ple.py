@@ -217,3 +217,33 @@ def test_panel_modes(m, n, kind):
     o = oracle_ple(A, n)
     for regs in (0, 2, 4, 8):
         assert_same_ple(gpu_ple(A, n, panel_regs=regs), o, "regs=%d" % regs)
+
+
+@pytest.mark.parametrize("m,n,kind", [(1500, 1300, "u"), (3000, 300, "r"), (8000, 300, "r"), (900, 900, "s"),
+                                      (700, 2000, "u"), (300, 5000, "u"), (2100, 2100, "r")])
+def test_lookahead_modes(m, n, kind):
+    """The look-ahead (next stripe updated first, next panel on a second
+    stream beside the update) gives the same bits as the serial pass loop,
+    on full-rank, rank-deficient (all-rows panel search) and sparse inputs,
+    and on wide matrices whose rank saturates before the last pass."""
+    say("lookahead modes", m, n, kind)
+    if kind == "u":
+        A = inputs.bernoulli(m, n, 15 + m)
+    elif kind == "r":
+        A = inputs.known_rank(m, n, min(m, n) // 3, 5, 6)
+    else:
+        A = inputs.bernoulli(m, n, 16 + m, p=0.01)
+    o = oracle_ple(A, n)
+    for mode in (0, 1, 2):
+        for regs in (0, 8):
+            assert_same_ple(gpu_ple(A, n, lookahead=mode, panel_regs=regs), o, "lookahead=%d regs=%d" % (mode, regs))
+
+
+def test_lookahead_16384_seed2():
+    """Default and forced look-ahead on the 16384^2 input equal the serial
+    pass loop bit for bit."""
+    say("lookahead 16384^2")
+    A = inputs.bernoulli(16384, 16384, 2)
+    serial = gpu_ple(A, 16384, lookahead=1)
+    for mode in (0, 2):
+        assert_same_ple(gpu_ple(A, 16384, lookahead=mode), serial, "lookahead=%d" % mode)
