@@ -122,8 +122,10 @@ gf2_status gf2_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, 
  * standalone call.  A is m x k (row stride lda words), B is k x n (ldb),
  * C is m x n (ldc).  For each 64-column slice of A the 64 matching rows of B
  * are tabulated 8 at a time (256-entry tables) and one table row per byte of
- * A's word is added to C.  opts->update = 2 selects the int8 MFMA product
- * instead (bit-identical).  No workspace.
+ * A's word is added to C.  No workspace.  opts->update = 2 selects the int8
+ * matrix-core product instead (bit-identical): bits become 0/1 int8
+ * operands, the int32 sums are taken mod 2; it takes stream-ordered device
+ * scratch (hipMallocAsync) for the bit transpose of B, k x n bits.
  */
 gf2_status gf2_addmul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *B, int64_t ldb,
                       int64_t m, int64_t k, int64_t n, const gf2_ple_opts *opts, void *stream);

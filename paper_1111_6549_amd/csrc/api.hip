@@ -18,6 +18,10 @@ hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_
 hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
                          const uint64_t *coef, const uint64_t *PB, int first, int m4_variant, int m4_target,
                          hipStream_t s);
+hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int64_t n, uint64_t *Bt, int64_t ldbt,
+                                 hipStream_t s);
+hipError_t launch_mfma_gf2(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *Bt, int64_t ldbt,
+                           int64_t m, int64_t k, int64_t n, hipStream_t s);
 hipError_t launch_m4rm(uint64_t *C, int64_t ldc, int64_t m, const uint64_t *coef, int64_t coef_ld, const uint64_t *B,
                        int64_t ldb, int nbits, int64_t w_begin, int64_t w_end, int m4_variant, int m4_target,
                        hipStream_t s);
@@ -353,9 +357,18 @@ gf2_status gf2_addmul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, 
     if (opts && (opts->update < 0 || opts->update > 2 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
     if (m == 0 || n == 0 || k == 0) return GF2_OK;
     if (!C || !A || !B || !aligned(C, 8) || !aligned(A, 8) || !aligned(B, 8)) return GF2_EINVAL;
-    if (opts && opts->update == 2) return GF2_EINVAL;  // not built yet
     hipStream_t s = (hipStream_t)stream;
     const int64_t nw = words_for(n);
+    if (opts && opts->update == 2) {
+        // int8 matrix cores: B transposed into stream-ordered scratch first
+        const int64_t kw = words_for(k);
+        void *bt = nullptr;
+        if (hipMallocAsync(&bt, (size_t)nw * 64 * (size_t)kw * 8, s) != hipSuccess) return GF2_EHIP;
+        hipError_t e = launch_transpose_bits(B, ldb, k, n, (uint64_t *)bt, kw, s);
+        if (e == hipSuccess) e = launch_mfma_gf2(C, ldc, A, lda, (const uint64_t *)bt, kw, m, k, n, s);
+        const hipError_t f = hipFreeAsync(bt, s);
+        return (e == hipSuccess && f == hipSuccess) ? GF2_OK : GF2_EHIP;
+    }
     for (int64_t kb = 0; kb * KW < k; kb++) {
         const int nb = (int)(k - kb * KW < KW ? k - kb * KW : KW);
         if (launch_m4rm(C, ldc, m, A + kb, lda, B + kb * KW * ldb, ldb, nb, 0, nw, opts ? opts->m4_variant : 0,

@@ -1,0 +1,135 @@
+// GF(2) product on the int8 matrix cores: C ^= A B with A m x k, B k x n
+// (Section 3.2's trailing update A22 <- L21 A12 + A22, done as a dense
+// product, the way Algorithm 3 reduces its update to matrix multiplication).
+//
+// Bits are expanded to int8 0/1 operands of v_mfma_i32_32x32x32_i8, the
+// int32 sums are reduced mod 2 (& 1) and packed back into words with
+// ballots.  The matrix-core operands hold K-consecutive values per lane, so
+// B is first bit-transposed (Bt, n x k bits) into scratch.  A and B use the
+// same K order inside each operand, so only the accumulator layout matters:
+// lane l holds column l % 32 of a 32 x 32 tile, register i its row
+// 8 (i / 4) + 4 (l / 32) + i % 4.
+#include "common.h"
+#include "dev.h"
+
+namespace gf2 {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// 16 bits -> 16 bytes 0/1 (byte j = bit j).  For a 4-bit x, x * 0x204081
+// puts bit t of x at bit 8t (the four shifted copies do not overlap); the
+// mask keeps exactly those bits.
+__device__ __forceinline__ v4i bits_to_bytes16(uint32_t b) {
+    v4i r;
+    r[0] = (int)(((b & 15u) * 0x204081u) & 0x01010101u);
+    r[1] = (int)((((b >> 4) & 15u) * 0x204081u) & 0x01010101u);
+    r[2] = (int)((((b >> 8) & 15u) * 0x204081u) & 0x01010101u);
+    r[3] = (int)((((b >> 12) & 15u) * 0x204081u) & 0x01010101u);
+    return r;
+}
+
+// Bt[j][.] = column j of B: one wave transposes a 64 x 64 bit block in
+// registers (six butterfly stages: lanes l and l ^ s trade the s-bit halves
+// of their s-aligned groups).  Rows of B at or past k and columns at or past
+// n come out zero; Bt has words(n) * 64 rows of ldbt >= words(k) words.
+__global__ __launch_bounds__(256) void k_transpose_bits(const uint64_t *__restrict__ B, int64_t ldb, int64_t k,
+                                                        int64_t n, uint64_t *__restrict__ Bt, int64_t ldbt) {
+    const int lane = threadIdx.x & 63;
+    const int64_t kw = words_for(k), nw = words_for(n);
+    const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (blk >= kw * nw) return;
+    const int64_t kb = blk % kw, wb = blk / kw;
+    const int64_t row = kb * 64 + lane;
+    uint64_t x = row < k ? B[row * ldb + wb] : 0ull;
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int st = 0; st < 6; st++) {
+        const int s = 32 >> st;
+        const uint64_t M = masks[st];
+        const uint32_t lo = __shfl_xor((int)(uint32_t)x, s, 64);
+        const uint32_t hi = __shfl_xor((int)(uint32_t)(x >> 32), s, 64);
+        const uint64_t y = ((uint64_t)hi << 32) | lo;
+        x = (lane & s) ? (((y & ~M) >> s) | (x & ~M)) : ((x & M) | ((y & M) << s));
+    }
+    const int64_t col = wb * 64 + lane;
+    Bt[col * ldbt + kb] = col < n ? x : 0ull;
+}
+
+// One wave computes a 64 x 64 block of C (64 rows, one output word): 2 x 2
+// matrix-core tiles of 32 x 32, K consumed 32 bits per instruction.
+template <int NWR, int NWC>
+__global__ __launch_bounds__(NWR *NWC * 64) void k_mfma_gf2(uint64_t *__restrict__ C, int64_t ldc,
+                                                           const uint64_t *__restrict__ A, int64_t lda,
+                                                           const uint64_t *__restrict__ Bt, int64_t ldbt, int64_t m,
+                                                           int64_t kw, int64_t nw, int64_t gcols) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t bid = blockIdx.x;
+    const int64_t bc = bid % gcols, br = bid / gcols;  // column blocks fastest: neighbours share A rows
+    const int64_t r0 = (br * NWR + wave / NWC) * 64;
+    const int64_t w0 = bc * NWC + wave % NWC;
+    if (r0 >= m || w0 >= nw) return;
+    const int lr = lane & 31, kh = lane >> 5;
+    const int64_t ra = r0 + lr, rb = r0 + 32 + lr;
+    const uint64_t *pa = A + (ra < m ? ra : 0) * lda;
+    const uint64_t *pb = A + (rb < m ? rb : 0) * lda;
+    const uint64_t *qa = Bt + (w0 * 64 + lr) * ldbt;
+    const uint64_t *qb = Bt + (w0 * 64 + 32 + lr) * ldbt;
+    const bool va = ra < m, vb = rb < m;
+    v16i c00 = {}, c01 = {}, c10 = {}, c11 = {};
+    for (int64_t kk = 0; kk < kw; kk++) {
+        const uint64_t xa = va ? pa[kk] : 0ull, xb = vb ? pb[kk] : 0ull;
+        const uint64_t ya = qa[kk], yb = qb[kk];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int sh = 32 * h + 16 * kh;
+            const v4i A0 = bits_to_bytes16((uint32_t)(xa >> sh) & 0xFFFFu);
+            const v4i A1 = bits_to_bytes16((uint32_t)(xb >> sh) & 0xFFFFu);
+            const v4i B0 = bits_to_bytes16((uint32_t)(ya >> sh) & 0xFFFFu);
+            const v4i B1 = bits_to_bytes16((uint32_t)(yb >> sh) & 0xFFFFu);
+            c00 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B0, c00, 0, 0, 0);
+            c01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B1, c01, 0, 0, 0);
+            c10 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B0, c10, 0, 0, 0);
+            c11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B1, c11, 0, 0, 0);
+        }
+    }
+    // sums mod 2 -> bits; lane L collects the output word of row r0 + L
+    uint64_t out = 0;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const int q = (i >> 2) * 8 + (i & 3);  // rows q (lanes < 32) and q + 4 (lanes >= 32) of a tile
+        const uint64_t b00 = __ballot(c00[i] & 1), b01 = __ballot(c01[i] & 1);
+        const uint64_t b10 = __ballot(c10[i] & 1), b11 = __ballot(c11[i] & 1);
+        const uint64_t lo32 = 0xFFFFFFFFull;
+        out = lane == q ? ((b00 & lo32) | (b01 << 32)) : out;
+        out = lane == q + 4 ? ((b00 >> 32) | (b01 & ~lo32)) : out;
+        out = lane == 32 + q ? ((b10 & lo32) | (b11 << 32)) : out;
+        out = lane == 36 + q ? ((b10 >> 32) | (b11 & ~lo32)) : out;
+    }
+    const int64_t row = r0 + lane;
+    if (row < m && out) C[row * ldc + w0] ^= out;
+}
+
+hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int64_t n, uint64_t *Bt, int64_t ldbt,
+                                 hipStream_t s) {
+    const int64_t blocks = (words_for(k) * words_for(n) + 3) / 4;
+    if (blocks <= 0) return hipSuccess;
+    ProfScope ps(KID_MFMA, s);
+    hipLaunchKernelGGL(k_transpose_bits, dim3((unsigned)blocks), dim3(256), 0, s, B, ldb, k, n, Bt, ldbt);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_gf2(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *Bt, int64_t ldbt,
+                           int64_t m, int64_t k, int64_t n, hipStream_t s) {
+    constexpr int NWR = 2, NWC = 2;
+    const int64_t nw = words_for(n), kw = words_for(k);
+    const int64_t gcols = (nw + NWC - 1) / NWC, grows = (m + 64 * NWR - 1) / (64 * NWR);
+    if (gcols <= 0 || grows <= 0) return hipSuccess;
+    ProfScope ps(KID_MFMA, s);
+    hipLaunchKernelGGL((k_mfma_gf2<NWR, NWC>), dim3((unsigned)(gcols * grows)), dim3(NWR * NWC * 64), 0, s, C, ldc, A,
+                       lda, Bt, ldbt, m, kw, nw, gcols);
+    return hipGetLastError();
+}
+
+}  // namespace gf2
