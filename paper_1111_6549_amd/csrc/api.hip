@@ -108,33 +108,36 @@ int *device_flag() {
 
 namespace gf2 {
 
-// Second stream and events of the look-ahead: one set per host thread and
-// device, made on first use and kept for the life of the thread.
+// Second stream and events of the look-ahead, one set per (host thread,
+// device, caller's stream) so that PLEs enqueued on different streams keep
+// their panels apart; made on first use and kept for the life of the thread.
 struct LookCtx {
+    int dev = -1;
+    hipStream_t user = nullptr;
     hipStream_t s2 = nullptr;
     hipEvent_t evA = nullptr, evN = nullptr;
 };
 
-static LookCtx *look_ctx() {
+static LookCtx *look_ctx(hipStream_t user) {
+    constexpr size_t MAX_CTX = 32;
     thread_local std::vector<LookCtx> ctx;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    if ((int)ctx.size() <= dev) ctx.resize(dev + 1);
-    LookCtx &c = ctx[dev];
-    if (!c.s2) {
-        hipStream_t s2 = nullptr;
-        hipEvent_t a = nullptr, b = nullptr;
-        if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) return nullptr;
-        if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
-            (void)hipStreamDestroy(s2);
-            return nullptr;
-        }
-        c.s2 = s2;
-        c.evA = a;
-        c.evN = b;
+    for (auto &c : ctx)
+        if (c.dev == dev && c.user == user) return &c;
+    if (ctx.size() >= MAX_CTX) return nullptr;  // no look-ahead beyond this many streams
+    LookCtx c;
+    c.dev = dev;
+    c.user = user;
+    if (hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&c.evA, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c.evN, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(c.s2);
+        return nullptr;
     }
-    return &c;
+    ctx.reserve(MAX_CTX);  // addresses stay valid
+    ctx.push_back(c);
+    return &ctx.back();
 }
 
 // Trailing blocks above this many bytes take the look-ahead in the default
@@ -170,7 +173,7 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
     if (m == 0 || n == 0) return hipSuccess;
 
     const int64_t npasses = words_for(n);
-    LookCtx *lc = mode == 1 ? nullptr : look_ctx();
+    LookCtx *lc = mode == 1 ? nullptr : look_ctx(s);
     auto want_la = [&](int64_t t) {
         if (!lc || t + 1 >= npasses) return false;
         if (mode == 2) return true;

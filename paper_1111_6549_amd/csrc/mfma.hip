@@ -111,6 +111,91 @@ __global__ __launch_bounds__(NWR *NWC * 64) void k_mfma_gf2(uint64_t *__restrict
     if (row < m && out) C[row * ldc + w0] ^= out;
 }
 
+// One wave computes a (32 TR) x (32 TC) block of C with TR x TC matrix-core
+// tiles (TC even: TC / 2 output words); the accumulators live in the AGPRs.
+// Lane L finishes rows r0 + L + 64 p of the block.
+template <int TR, int TC>
+__global__ __launch_bounds__(256) void k_mfma_gf2t(uint64_t *__restrict__ C, int64_t ldc,
+                                                  const uint64_t *__restrict__ A, int64_t lda,
+                                                  const uint64_t *__restrict__ Bt, int64_t ldbt, int64_t m,
+                                                  int64_t kw, int64_t nw, int64_t gcols) {
+    constexpr int WPB = 4;  // waves per block, side by side in columns
+    constexpr int NWD = TC / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t bid = blockIdx.x;
+    const int64_t bc = bid % gcols, br = bid / gcols;
+    const int64_t r0 = br * 32 * TR;
+    const int64_t w0 = (bc * WPB + wave) * NWD;
+    if (r0 >= m || w0 >= nw) return;
+    const int lr = lane & 31, kh = lane >> 5;
+    const uint64_t *pa[TR];
+    bool va[TR];
+#pragma unroll
+    for (int i = 0; i < TR; i++) {
+        const int64_t r = r0 + 32 * i + lr;
+        va[i] = r < m;
+        pa[i] = A + (va[i] ? r : 0) * lda;
+    }
+    const uint64_t *qb[TC];
+#pragma unroll
+    for (int j = 0; j < TC; j++) {
+        const int64_t cidx = w0 * 64 + 32 * j + lr;
+        qb[j] = Bt + (cidx < nw * 64 ? cidx : 0) * ldbt;
+    }
+    v16i acc[TR][TC];
+#pragma unroll
+    for (int i = 0; i < TR; i++)
+#pragma unroll
+        for (int j = 0; j < TC; j++) acc[i][j] = v16i{};
+    for (int64_t kk = 0; kk < kw; kk++) {
+        uint64_t x[TR], y[TC];
+#pragma unroll
+        for (int i = 0; i < TR; i++) x[i] = va[i] ? pa[i][kk] : 0ull;
+#pragma unroll
+        for (int j = 0; j < TC; j++) y[j] = qb[j][kk];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int sh = 32 * h + 16 * kh;
+            v4i a[TR], b[TC];
+#pragma unroll
+            for (int i = 0; i < TR; i++) a[i] = bits_to_bytes16((uint32_t)(x[i] >> sh) & 0xFFFFu);
+#pragma unroll
+            for (int j = 0; j < TC; j++) b[j] = bits_to_bytes16((uint32_t)(y[j] >> sh) & 0xFFFFu);
+#pragma unroll
+            for (int i = 0; i < TR; i++)
+#pragma unroll
+                for (int j = 0; j < TC; j++) acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    constexpr int NP = (TR + 1) / 2;  // 64-row groups
+    uint64_t out[NP][NWD];
+#pragma unroll
+    for (int p = 0; p < NP; p++)
+#pragma unroll
+        for (int d = 0; d < NWD; d++) out[p][d] = 0;
+    const uint64_t lo32 = 0xFFFFFFFFull;
+#pragma unroll
+    for (int i = 0; i < TR; i++) {
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+            const int q = 32 * i + (e >> 2) * 8 + (e & 3);  // rows q (lanes < 32) and q + 4 (lanes >= 32)
+#pragma unroll
+            for (int d = 0; d < NWD; d++) {
+                const uint64_t b0 = __ballot(acc[i][2 * d][e] & 1), b1 = __ballot(acc[i][2 * d + 1][e] & 1);
+                out[q >> 6][d] = lane == (q & 63) ? ((b0 & lo32) | (b1 << 32)) : out[q >> 6][d];
+                out[(q + 4) >> 6][d] = lane == ((q + 4) & 63) ? ((b0 >> 32) | (b1 & ~lo32)) : out[(q + 4) >> 6][d];
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+        const int64_t row = r0 + 64 * p + lane;
+#pragma unroll
+        for (int d = 0; d < NWD; d++)
+            if (row < m && w0 + d < nw && out[p][d]) C[row * ldc + w0 + d] ^= out[p][d];
+    }
+}
+
 hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int64_t n, uint64_t *Bt, int64_t ldbt,
                                  hipStream_t s) {
     const int64_t blocks = (words_for(k) * words_for(n) + 3) / 4;
@@ -122,6 +207,17 @@ hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int6
 
 hipError_t launch_mfma_gf2(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *Bt, int64_t ldbt,
                            int64_t m, int64_t k, int64_t n, hipStream_t s) {
+    if (k >= 128) {
+        // 128 x 128 per wave, four waves side by side
+        constexpr int TR = 4, TC = 4;
+        const int64_t nw = words_for(n), kw = words_for(k);
+        const int64_t gcols = (nw + 4 * (TC / 2) - 1) / (4 * (TC / 2)), grows = (m + 32 * TR - 1) / (32 * TR);
+        if (gcols <= 0 || grows <= 0) return hipSuccess;
+        ProfScope ps(KID_MFMA, s);
+        hipLaunchKernelGGL((k_mfma_gf2t<TR, TC>), dim3((unsigned)(gcols * grows)), dim3(256), 0, s, C, ldc, A, lda, Bt,
+                           ldbt, m, kw, nw, gcols);
+        return hipGetLastError();
+    }
     constexpr int NWR = 2, NWC = 2;
     const int64_t nw = words_for(n), kw = words_for(k);
     const int64_t gcols = (nw + NWC - 1) / NWC, grows = (m + 64 * NWR - 1) / (64 * NWR);
