@@ -52,8 +52,9 @@ typedef struct gf2_ple_opts {
     int32_t m4_variant;    /* Four-Russians update schedule: 0 = default, 1..8 = a fixed (tile, threads, unroll) */
     int32_t m4_blocks;     /* target blocks per update launch (0 = default 512) */
     int32_t panel_regs;    /* pivot-search register window of the panel: 0 = default, 2, 4 or 8 x 64 rows */
-    int32_t lookahead;     /* 0 = while the trailing block is large, 1 = never, 2 = every pass: the next stripe is
-                              updated first and the next panel runs on a second stream beside the update */
+    int32_t lookahead;     /* 0 = while the trailing block is large: pairs of passes share one trailing update and
+                              the next panel runs on a second stream beside it; 1 = neither (serial passes);
+                              2 = look-ahead on every pass, no pairs; 3 = pairs and look-ahead on every pass */
     int32_t reserved[1];
 } gf2_ple_opts;
 

@@ -7,14 +7,20 @@
 #include "../../include/gf2ple.h"
 #include "batch.h"
 #include "common.h"
+#include "panel.h"
 
 namespace gf2 {
 hipError_t launch_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *rank, PassRec *rec, hipStream_t s);
 hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
-                        int64_t *P, int64_t *Q, int64_t *rank, uint64_t *gsv, int32_t *gsid, int panel_regs, bool la,
-                        hipStream_t s);
+                        int64_t *P, int64_t *Q, int64_t *rank, uint64_t *gsv, int32_t *gsid, int panel_regs,
+                        const PanelFix &fix, bool beside, hipStream_t s);
 hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
-                          uint64_t *coef, uint64_t *PB, bool la, hipStream_t s);
+                          uint64_t *coef, uint64_t *PB, int mode, const PassRec *rect, const uint64_t *coefT,
+                          uint64_t *coefP, const uint64_t *PBt, hipStream_t s);
+hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t ct, const PassRec *rect,
+                              const PassRec *recu, const uint64_t *coefP, const uint64_t *coefU,
+                              const uint64_t *coefT, const uint64_t *PBt, const uint64_t *PBu, int m4_target,
+                              hipStream_t s);
 hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
                          const uint64_t *coef, const uint64_t *PB, int first, int m4_variant, int m4_target,
                          hipStream_t s);
@@ -41,19 +47,27 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct PleLayout {
-    size_t rec, coef, pb, gsv, gsid, total;
+    size_t rec, coef, coefp, coef2, pb, pb2, gsv, gsid, total;
 };
 
-// workspace of gf2_ple: pass record | coef[m] | pivot block 64 x ldw |
-// slow-search values[m] | slow-search ids[m]
+// workspace of gf2_ple: pass records (a ring of NREC) | coef[m] | coefP[m] |
+// coef2[m] | pivot block 64 x ldw | second pivot block | slow-search
+// values[m] | slow-search ids[m].  coefP, coef2 and the second pivot block
+// serve the fused update of a pair of passes.
 PleLayout ple_layout(int64_t m, int64_t ldw) {
     PleLayout L;
     size_t off = 0;
     L.rec = off;
-    off += align_up(2 * sizeof(PassRec));  // records of consecutive passes alternate
+    off += align_up(NREC * sizeof(PassRec));
     L.coef = off;
     off += align_up((size_t)m * 8);
+    L.coefp = off;
+    off += align_up((size_t)m * 8);
+    L.coef2 = off;
+    off += align_up((size_t)m * 8);
     L.pb = off;
+    off += align_up((size_t)KW * (size_t)ldw * 8);
+    L.pb2 = off;
     off += align_up((size_t)KW * (size_t)ldw * 8);
     L.gsv = off;
     off += align_up((size_t)m * 8);
@@ -160,7 +174,10 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
     char *base = (char *)ws;
     PassRec *recs = (PassRec *)(base + L.rec);
     uint64_t *coef = (uint64_t *)(base + L.coef);
+    uint64_t *coefP = (uint64_t *)(base + L.coefp);
+    uint64_t *coef2 = (uint64_t *)(base + L.coef2);
     uint64_t *PB = (uint64_t *)(base + L.pb);
+    uint64_t *PB2 = (uint64_t *)(base + L.pb2);
     uint64_t *gsv = (uint64_t *)(base + L.gsv);
     int32_t *gsid = (int32_t *)(base + L.gsid);
     const int m4v = opts ? opts->m4_variant : 0;
@@ -174,40 +191,88 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
 
     const int64_t npasses = words_for(n);
     LookCtx *lc = mode == 1 ? nullptr : look_ctx(s);
-    auto want_la = [&](int64_t t) {
-        if (!lc || t + 1 >= npasses) return false;
-        if (mode == 2) return true;
+    auto big = [&](int64_t t) {
         const int64_t c = t * KW;
         const double rows = (double)(m - (c < m ? c : m));
         return rows * (double)(npasses - t - 2) * 8.0 > LOOKAHEAD_BYTES;
     };
-    if ((e = launch_panel(A, m, n, ldw, 0, &recs[1], &recs[0], P, Q, rank, gsv, gsid, pr, false, s)) != hipSuccess)
+    // look-ahead for pass t (modes 0, 2, 3)
+    auto want_la = [&](int64_t t) {
+        if (!lc || t + 1 >= npasses) return false;
+        return mode >= 2 || big(t);
+    };
+    // passes t and t + 1 fused (modes 0 and 3): needs a word right of both stripes
+    auto want_pair = [&](int64_t t) {
+        if (!lc || (mode != 0 && mode != 3) || t + 3 >= npasses) return false;
+        return mode == 3 || big(t + 1);
+    };
+    auto rec_of = [&](int64_t t) { return &recs[t % NREC]; };
+    if ((e = launch_panel(A, m, n, ldw, 0, rec_of(NREC - 1), rec_of(0), P, Q, rank, gsv, gsid, pr, PanelFix(), false,
+                          s)) != hipSuccess)
         return e;
     bool pending = false;  // this pass's panel ran on the second stream
     int64_t since_check = 0;
-    for (int64_t t = 0; t < npasses; t++) {
+    for (int64_t t = 0; t < npasses;) {
         const int64_t c = t * KW;
-        PassRec *rec = &recs[t & 1], *nxt = &recs[(t + 1) & 1];
+        PassRec *rec = rec_of(t), *nxt = rec_of(t + 1);
         if (pending) {
             if ((e = hipStreamWaitEvent(s, lc->evN, 0)) != hipSuccess) return e;
             pending = false;
+        }
+        if (want_pair(t)) {
+            // pass t: permute with the next stripe word updated; its bulk
+            // update waits for pass t + 1
+            if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 1, nullptr, nullptr, nullptr, nullptr, s)) !=
+                hipSuccess)
+                return e;
+            PanelFix f1;
+            f1.mode = 1;
+            if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, f1, false, s)) !=
+                hipSuccess)
+                return e;
+            // pass u = t + 1 carries pass t's coefficients along
+            if ((e = launch_permute(A, m, n, ldw, c + KW, nxt, coef2, PB2, 2, rec, coef, coefP, PB, s)) != hipSuccess)
+                return e;
+            if ((e = hipEventRecord(lc->evA, s)) != hipSuccess) return e;
+            if ((e = launch_update_pair(A, m, n, ldw, c, rec, nxt, coefP, coef2, coef, PB, PB2, m4t, s)) != hipSuccess)
+                return e;
+            if ((e = hipStreamWaitEvent(lc->s2, lc->evA, 0)) != hipSuccess) return e;
+            PanelFix f2;
+            f2.mode = 2;
+            f2.pt = rec;
+            f2.coefT = coef;
+            f2.PBt = PB;
+            if ((e = launch_panel(A, m, n, ldw, c + 2 * KW, nxt, rec_of(t + 2), P, Q, rank, gsv, gsid, pr, f2, true,
+                                  lc->s2)) != hipSuccess)
+                return e;
+            if ((e = hipEventRecord(lc->evN, lc->s2)) != hipSuccess) return e;
+            pending = true;
+            t += 2;
+            continue;
         }
         if (want_la(t)) {
             // permute also updates the next stripe word of the ordinary rows;
             // the next panel finishes the special rows' one, then searches,
             // while the update of the words beyond runs
-            if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, true, s)) != hipSuccess) return e;
+            if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 1, nullptr, nullptr, nullptr, nullptr, s)) !=
+                hipSuccess)
+                return e;
             if ((e = hipEventRecord(lc->evA, s)) != hipSuccess) return e;
             if ((e = launch_update(A, m, n, ldw, c, rec, coef, PB, 2, m4v, m4t, s)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(lc->s2, lc->evA, 0)) != hipSuccess) return e;
-            if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, true, lc->s2)) !=
+            PanelFix f1;
+            f1.mode = 1;
+            if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, f1, true, lc->s2)) !=
                 hipSuccess)
                 return e;
             if ((e = hipEventRecord(lc->evN, lc->s2)) != hipSuccess) return e;
             pending = true;
+            t += 1;
             continue;
         }
-        if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, false, s)) != hipSuccess) return e;
+        if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 0, nullptr, nullptr, nullptr, nullptr, s)) !=
+            hipSuccess)
+            return e;
         if ((e = launch_update(A, m, n, ldw, c, rec, coef, PB, 1, m4v, m4t, s)) != hipSuccess) return e;
         if (t + 1 >= npasses) break;
         if (c + KW >= m && allow_sync) {
@@ -220,8 +285,10 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
             }
             since_check = (since_check + 1) % 8;
         }
-        if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, false, s)) != hipSuccess)
+        if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, PanelFix(), false, s)) !=
+            hipSuccess)
             return e;
+        t += 1;
     }
     return hipGetLastError();
 }
@@ -278,7 +345,7 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
     if (opts && (opts->update < 0 || opts->update > 2 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
     if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
         return GF2_EINVAL;
-    if (opts && (opts->lookahead < 0 || opts->lookahead > 2)) return GF2_EINVAL;
+    if (opts && (opts->lookahead < 0 || opts->lookahead > 3)) return GF2_EINVAL;
     if (opts && opts->update == 2) return GF2_EINVAL;  // MFMA trailing update: see gf2_addmul
     const PleLayout L = ple_layout(m, ldw);
     if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;

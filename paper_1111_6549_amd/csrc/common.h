@@ -16,6 +16,9 @@ constexpr int WIN_Q = 8;
 constexpr int MAX_SPEC = 2 * KW;
 // Rows the slow pivot search keeps in LDS; beyond this it uses workspace.
 constexpr int SLOW_LDS_ROWS = 6144;
+// Pass records kept in the workspace ring: a pass's record is still read by
+// the fused update of its pair while the panel two passes later writes its own.
+constexpr int NREC = 4;
 // Columns per trailing-update tile (words): 8 words = 64 B of each row.
 constexpr int TILE_W = 8;
 // Threads per block of the wide kernels.

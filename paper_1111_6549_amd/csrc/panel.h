@@ -66,6 +66,50 @@ __device__ __forceinline__ void fix_deferred_rows(uint64_t *A, int64_t ldw, int6
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// After a fused pair (t, u = t + 1), u's special rows are unmoved and lack
+// both passes' updates in this stripe word.  Row k (entry k of u's record)
+// first gets pass t's update -- coefficient coefT[src_k], tables of t's
+// staged pivot words PBt -- which also gives u's pivots' words as they stood
+// at u's start; then u's update from those.
+__device__ __forceinline__ void fix_deferred_rows_pair(uint64_t *A, int64_t ldw, int64_t sw, const PassRec *pu,
+                                                       const PassRec *pt, const uint64_t *coefT, const uint64_t *PBt,
+                                                       const int lane) {
+    const int fn = pu->active ? pu->nspec : 0, fr = pu->active ? pu->rbar : 0;
+    if (fn <= 0) return;
+    const int rt = pt->active ? pt->rbar : 0;
+    const bool h0 = lane < fn, h1 = 64 + lane < fn;
+    const int64_t s0 = h0 ? pu->spec_src[lane] : 0, s1 = h1 ? pu->spec_src[64 + lane] : 0;
+    uint64_t x0 = h0 ? ld_stripe(A + s0 * ldw + sw) : 0ull;
+    uint64_t x1 = h1 ? ld_stripe(A + s1 * ldw + sw) : 0ull;
+    const uint64_t t0 = h0 ? coefT[s0] : 0ull, t1 = h1 ? coefT[s1] : 0ull;
+    const uint64_t pbt = lane < rt ? PBt[(int64_t)lane * ldw + sw] : 0ull;
+    for (int b = 0; b < rt; b++) {
+        const uint64_t pb = readlane64(pbt, b);
+        x0 ^= ((t0 >> b) & 1ull) ? pb : 0ull;
+        x1 ^= ((t1 >> b) & 1ull) ? pb : 0ull;
+    }
+    const uint64_t c0 = h0 ? pu->spec_coef[lane] : 0ull, c1 = h1 ? pu->spec_coef[64 + lane] : 0ull;
+    uint64_t n0 = x0, n1 = x1;
+    for (int b = 0; b < fr; b++) {  // entries 0 .. rbar-1 are u's pivots
+        const uint64_t ob = readlane64(x0, b);
+        n0 ^= ((c0 >> b) & 1ull) ? ob : 0ull;
+        n1 ^= ((c1 >> b) & 1ull) ? ob : 0ull;
+    }
+    if (h0) A[pu->spec_dst[lane] * ldw + sw] = n0;
+    if (h1) A[pu->spec_dst[64 + lane] * ldw + sw] = n1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// What the previous passes left for the panel to finish in its stripe word.
+struct PanelFix {
+    int mode = 0;                     // 0 nothing, 1 after a look-ahead pass, 2 after a fused pair
+    const PassRec *pt = nullptr;      // mode 2: the pair's first pass
+    const uint64_t *coefT = nullptr;  // mode 2: its coefficient words, by position
+    const uint64_t *PBt = nullptr;    // mode 2: its staged pivot rows (row stride ldw)
+};
+
 // One wave (lane = threadIdx.x & 63) computes the panel of the stripe at
 // column c.  `prev` is the previous pass's record (its r + rbar is this
 // pass's r; it is read before `rec` is written, so the two may be the same
@@ -75,7 +119,7 @@ template <int WQ, int SR>
 __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c,
                                            const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
                                            int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelLdsT<SR> &L,
-                                           const int lane, bool fix_prev = false) {
+                                           const int lane, PanelFix fix = PanelFix()) {
 #ifdef GF2_PANEL_TIMING
     uint64_t *dbg = gsv + (c >> 6) * 8;
 #define PANEL_STAMP(k) \
@@ -84,7 +128,8 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
 #define PANEL_STAMP(k)
 #endif
     PANEL_STAMP(0)
-    if (fix_prev && c < n) fix_deferred_rows(A, ldw, c >> 6, prev, lane);
+    if (fix.mode == 1 && c < n) fix_deferred_rows(A, ldw, c >> 6, prev, lane);
+    if (fix.mode == 2 && c < n) fix_deferred_rows_pair(A, ldw, c >> 6, prev, fix.pt, fix.coefT, fix.PBt, lane);
     const int64_t r = prev->r + prev->rbar;
     if (r >= m || c >= n) {
         if (lane == 0) {

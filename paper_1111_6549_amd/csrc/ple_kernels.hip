@@ -35,7 +35,7 @@ __global__ void k_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *r
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = i; t < m; t += stride) P[t] = t;
     for (int64_t t = i; t < mn; t += stride) Q[t] = -1;
-    if (i < 2 && recs) {
+    if (i < NREC && recs) {
         if (i == 0) *rank = 0;
         recs[i].r = 0;
         recs[i].rbar = 0;
@@ -54,31 +54,48 @@ __global__ void k_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *r
 template <int WQ, int SR>
 __global__ __launch_bounds__(64) void k_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c,
                                               const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
-                                              int64_t *rank_out, uint64_t *gsv, int32_t *gsid, int fix_prev) {
+                                              int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelFix fix) {
     __shared__ PanelLdsT<SR> L;
     if (SR == 0) __builtin_amdgcn_s_setprio(3);
-    panel_body<WQ, SR>(A, m, n, ldw, c, prev, rec, P, Q, rank_out, gsv, gsid, L, threadIdx.x, fix_prev != 0);
+    panel_body<WQ, SR>(A, m, n, ldw, c, prev, rec, P, Q, rank_out, gsv, gsid, L, threadIdx.x, fix);
 }
 
 // ---------------------------------------------------------------------------
 // k_permute: swaps, pivot staging, coefficients, L bits.
 //   blocks [0, nA): 64 word columns each, every special row (read all, then
 //                   write all, so the permutation is applied in place);
-//   blocks [nA, ..): grid-stride over the other rows r .. m-1.
+//   blocks [nA, ..): grid-stride over the other rows.
+// MODE 0: serial pass loop.
+// MODE 1: look-ahead.  The special rows' next stripe word (sw + 1) is left
+//         for the next panel; the other rows' next stripe word gets the
+//         pass's update here (tables of the pivots' old words at sw + 1).
+// MODE 2: second pass u of a fused pair (t, u = t + 1): as MODE 1, and pass
+//         t's update is still pending on every word right of sw for the rows
+//         from r_t on: its coefficient words (coefT, by position before this
+//         pass's swaps) are carried to the rows' new positions (coefP), and
+//         the next stripe word gets both passes' updates (pass u's pivots'
+//         words there first get pass t's).
 // ---------------------------------------------------------------------------
+template <int MODE>
 __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__ A, int64_t m, int64_t ldw, int64_t c,
                                                           const PassRec *__restrict__ rec, uint64_t *__restrict__ coef,
-                                                          uint64_t *__restrict__ PB, int nA, int64_t nw, int la) {
-    __shared__ uint64_t tw[8][256], tu[8][256], tn[8][256];
-    __shared__ uint64_t simg_w[KW], simg_u[KW], simg_n[KW];
-    __shared__ int64_t sdisp[KW];
+                                                          uint64_t *__restrict__ PB, int nA, int64_t nw,
+                                                          const PassRec *__restrict__ rect,
+                                                          const uint64_t *__restrict__ coefT,
+                                                          uint64_t *__restrict__ coefP,
+                                                          const uint64_t *__restrict__ PBt) {
+    __shared__ uint64_t tw[8][256], tu[8][256], tn[8][256], tt[MODE == 2 ? 8 : 1][MODE == 2 ? 256 : 1];
+    __shared__ uint64_t simg_w[KW], simg_u[KW], simg_n[KW], spbt[KW];
+    __shared__ int64_t sdisp[KW], sdsrc[KW];
     __shared__ uint64_t sdcoef[KW];
+    constexpr bool LA = MODE >= 1;
 
-    if (!rec->active) return;
+    const int active = rec->active;
+    if (MODE != 2 && !active) return;
     const int tid = threadIdx.x;
     const int64_t r = rec->r;
-    const int rbar = rec->rbar;
-    const int nspec = rec->nspec;
+    const int rbar = active ? rec->rbar : 0;
+    const int nspec = active ? rec->nspec : 0;
     const int64_t sw = c >> 6;
     const int64_t wr0 = r >> 6;
     const int sh = (int)(r & 63);
@@ -93,7 +110,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         for (int t = 0; t < PER; t++) {
             const int k = slot + SLOTS * t;
             nv[t] = 0;
-            if (k < nspec && w < ldw && !(la && w == sw + 1)) {
+            if (k < nspec && w < ldw && !(LA && w == sw + 1)) {
                 const int64_t src = rec->spec_src[k];
                 const uint64_t old = A[src * ldw + w];
                 if (k < rbar && w > sw) PB[(int64_t)k * ldw + w] = old;
@@ -104,7 +121,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int k = slot + SLOTS * t;
-            if (k < nspec && w < ldw && !(la && w == sw + 1)) {
+            if (k < nspec && w < ldw && !(LA && w == sw + 1)) {
                 const int64_t src = rec->spec_src[k], dst = rec->spec_dst[k];
                 if (dst != src || (w >= wr0 && w <= sw)) A[dst * ldw + w] = nv[t];
             }
@@ -114,21 +131,48 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
 
     // ---- other rows ----
     const int ndisp = nspec - rbar;
+    const bool nxt = LA && sw + 1 < nw;
+    const int rt = (MODE == 2 && rect->active) ? rect->rbar : 0;
     if (tid < KW) {
-        simg_w[tid] = rec->img_w[tid];
-        simg_u[tid] = rec->img_u[tid];
+        simg_w[tid] = active ? rec->img_w[tid] : 0ull;
+        simg_u[tid] = active ? rec->img_u[tid] : 0ull;
+        if (MODE == 2) spbt[tid] = (nxt && tid < rt) ? PBt[(int64_t)tid * ldw + sw + 1] : 0ull;
     }
     int64_t maxdisp = -1;
     if (tid < ndisp) {
         sdisp[tid] = rec->spec_dst[rbar + tid];
+        sdsrc[tid] = rec->spec_src[rbar + tid];
         sdcoef[tid] = rec->spec_coef[rbar + tid];
     }
     __syncthreads();
     for (int d = 0; d < ndisp; d++) maxdisp = sdisp[d] > maxdisp ? sdisp[d] : maxdisp;
-    // look-ahead: the pivots' words of the next stripe, as they were (group A
-    // leaves that column alone in this mode)
-    const bool nxt = la && sw + 1 < nw;
-    if (nxt && tid < KW) simg_n[tid] = tid < rbar ? A[rec->spec_src[tid] * ldw + sw + 1] : 0ull;
+    if (MODE == 2) {
+        // tables of pass t's update of the next stripe word
+        for (int e = tid; e < 8 * 256; e += WIDE_THREADS) {
+            const int b = e >> 8, x = e & 255;
+            uint64_t a = 0;
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                if ((x >> t) & 1) a ^= spbt[8 * b + t];
+            tt[b][x] = a;
+        }
+        __syncthreads();
+    }
+    // the pivots' words of the next stripe as they stand at the pass start
+    // (group A leaves that column alone); in MODE 2 with pass t's update
+    if (nxt && tid < KW) {
+        uint64_t v = 0;
+        if (tid < rbar) {
+            const int64_t src = rec->spec_src[tid];
+            v = A[src * ldw + sw + 1];
+            if (MODE == 2) {
+                const uint64_t ct = coefT[src];
+#pragma unroll
+                for (int b = 0; b < 8; b++) v ^= tt[b][(ct >> (8 * b)) & 255];
+            }
+        }
+        simg_n[tid] = v;
+    }
     __syncthreads();
     for (int e = tid; e < 8 * 256; e += WIDE_THREADS) {
         const int b = e >> 8, x = e & 255;
@@ -146,9 +190,27 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
     }
     __syncthreads();
     const int64_t nB = (int64_t)gridDim.x - nA;
-    for (int64_t i = r + ((int64_t)blockIdx.x - nA) * WIDE_THREADS + tid; i < m; i += nB * WIDE_THREADS) {
+    const int64_t row0 = MODE == 2 ? rect->r : r;
+    for (int64_t i = row0 + ((int64_t)blockIdx.x - nA) * WIDE_THREADS + tid; i < m; i += nB * WIDE_THREADS) {
+        uint64_t *row = A + i * ldw;
+        uint64_t ct = 0;
+        if (MODE == 2) {
+            ct = coefT[i];
+            if (i < r) {  // pass t's pivot rows: only its update (the TRSM) is pending
+                coefP[i] = ct;
+                coef[i] = 0;
+                if (nxt && ct) {
+                    uint64_t acc = 0;
+#pragma unroll
+                    for (int b = 0; b < 8; b++) acc ^= tt[b][(ct >> (8 * b)) & 255];
+                    row[sw + 1] ^= acc;
+                }
+                continue;
+            }
+        }
         if (i < r + rbar) {
             coef[i] = rec->spec_coef[i - r];
+            if (MODE == 2) coefP[i] = coefT[rec->spec_src[i - r]];
             continue;
         }
         if (i <= maxdisp) {
@@ -156,34 +218,38 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
             for (int d = 0; d < ndisp; d++)
                 if (sdisp[d] == i) {
                     coef[i] = sdcoef[d];
+                    if (MODE == 2) coefP[i] = coefT[sdsrc[d]];
                     disp = true;
                     break;
                 }
             if (disp) continue;
         }
-        uint64_t *row = A + i * ldw;
+        if (MODE == 2) coefP[i] = ct;
         const uint64_t v = row[sw];
-        if (!v) {
-            coef[i] = 0;
-            continue;
-        }
-        uint64_t wv = 0, u = 0;
+        uint64_t wv = 0;
+        if (v) {
+            uint64_t u = 0;
 #pragma unroll
-        for (int b = 0; b < 8; b++) {
-            const int x = (int)((v >> (8 * b)) & 255);
-            wv ^= tw[b][x];
-            u ^= tu[b][x];
+            for (int b = 0; b < 8; b++) {
+                const int x = (int)((v >> (8 * b)) & 255);
+                wv ^= tw[b][x];
+                u ^= tu[b][x];
+            }
+            if (wr0 < sw) {
+                row[wr0] |= u << sh;
+                if (sh && wr0 + 1 < sw) row[wr0 + 1] |= u >> (64 - sh);
+            }
+            row[sw] = place_bits(u, sw, wr0, sh);
         }
         coef[i] = wv;
-        if (wr0 < sw) {
-            row[wr0] |= u << sh;
-            if (sh && wr0 + 1 < sw) row[wr0 + 1] |= u >> (64 - sh);
-        }
-        row[sw] = place_bits(u, sw, wr0, sh);
-        if (nxt && wv) {
+        if (nxt && (wv || ct)) {
             uint64_t acc = 0;
 #pragma unroll
             for (int b = 0; b < 8; b++) acc ^= tn[b][(wv >> (8 * b)) & 255];
+            if (MODE == 2) {
+#pragma unroll
+                for (int b = 0; b < 8; b++) acc ^= tt[b][(ct >> (8 * b)) & 255];
+            }
             row[sw + 1] ^= acc;
         }
     }
@@ -247,6 +313,122 @@ __global__ __launch_bounds__(NT) void k_m4rm_w(uint64_t *__restrict__ C, int64_t
     const int64_t wt0 = (w_begin & ~(int64_t)(WR_TW - 1)) + (int64_t)tile * WR_TW;
     m4w_build_tables<NT>(T, B, ldb, nbits, wt0, w_begin, w_end, threadIdx.x);
     m4w_rows<NT, U>(T, C, ldc, coef, coef_ld, nbits, rb, re, wt0, w_begin, w_end, threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// k_m4rm_pair: the updates of a fused pair of passes (t, u = t + 1) in one
+// sweep over rows r_t .. m-1 and words [w_begin, w_end):
+//   C[i][w] ^= T_t[coefP[i]][w] ^ T_u[coefU[i]][w],
+// T_t the sixteen 4-bit tables of pass t's staged pivot rows (PBt), T_u
+// those of pass u's (PBu, staged before pass t's update reached them, so
+// they first get it: coefficient coefT[src] of their position then).
+// Tiles of 32 words; 16 lanes per row, two words per lane, 128-bit table
+// reads; 128 KB of tables per block.
+// ---------------------------------------------------------------------------
+constexpr int PR_TW = 32;
+
+template <int BASE, int NT>
+__device__ __forceinline__ void pair_combos(uint64_t (*T)[16][PR_TW], int tid) {
+    for (int e = tid; e < 16 * 16 * PR_TW; e += NT) {
+        const int wl = e % PR_TW;
+        const int x = (e / PR_TW) & 15;
+        const int q = e / (PR_TW * 16);
+        if (__popc(x) < 2) continue;
+        uint64_t acc = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+            if ((x >> b) & 1) acc ^= T[BASE + q][1 << b][wl];
+        T[BASE + q][x][wl] = acc;
+    }
+}
+
+template <int NT, int U>
+__global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int64_t ldc, int64_t m,
+                                                  const uint64_t *__restrict__ coefP,
+                                                  const uint64_t *__restrict__ coefU,
+                                                  const uint64_t *__restrict__ coefT,
+                                                  const uint64_t *__restrict__ PBt, const uint64_t *__restrict__ PBu,
+                                                  int64_t ldb, int64_t w_begin, int64_t w_end, int ntiles, int nchunks,
+                                                  const PassRec *__restrict__ rect, const PassRec *__restrict__ recu) {
+    __shared__ __align__(16) uint64_t T[32][16][PR_TW];
+    const int at = rect->active, au = recu->active;
+    if (!at && !au) return;
+    const int nbt = at ? rect->rbar : 0, nbu = au ? recu->rbar : 0;
+    int tile;
+    int64_t rb, re;
+    if (!m4_block_rows(m, rect->r, ntiles, nchunks, &tile, &rb, &re)) return;
+    const int64_t wt0 = (w_begin & ~(int64_t)(PR_TW - 1)) + (int64_t)tile * PR_TW;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < KW * PR_TW; e += NT) {
+        const int k = e / PR_TW, wl = e % PR_TW;
+        const int64_t w = wt0 + wl;
+        const int q = k >> 2, b = k & 3;
+        T[q][1 << b][wl] = (k < nbt && w >= w_begin && w < w_end) ? PBt[(int64_t)k * ldb + w] : 0ull;
+        if (b == 0) T[q][0][wl] = 0ull;
+    }
+    __syncthreads();
+    pair_combos<0, NT>(T, tid);
+    __syncthreads();
+    for (int e = tid; e < KW * PR_TW; e += NT) {
+        const int k = e / PR_TW, wl = e % PR_TW;
+        const int64_t w = wt0 + wl;
+        const int q = k >> 2, b = k & 3;
+        uint64_t v = 0;
+        if (k < nbu && w >= w_begin && w < w_end) {
+            v = PBu[(int64_t)k * ldb + w];
+            if (nbt) {
+                const uint64_t ct = coefT[recu->spec_src[k]];
+#pragma unroll
+                for (int qq = 0; qq < 16; qq++) v ^= T[qq][(ct >> (4 * qq)) & 15][wl];
+            }
+        }
+        T[16 + q][1 << b][wl] = v;
+        if (b == 0) T[16 + q][0][wl] = 0ull;
+    }
+    __syncthreads();
+    pair_combos<16, NT>(T, tid);
+    __syncthreads();
+
+    constexpr int LPR = PR_TW / 2;  // lanes per row
+    constexpr int RS = NT / LPR;    // rows per step
+    const int wp = tid % LPR, rs = tid / LPR;
+    const int64_t w2 = wt0 + 2 * wp;
+    const bool ok0 = w2 >= w_begin && w2 < w_end, ok1 = w2 + 1 >= w_begin && w2 + 1 < w_end;
+    const int ntt = (nbt + 3) >> 2, ntu = (nbu + 3) >> 2;
+    for (int64_t i0 = rb + rs; i0 < re; i0 += (int64_t)RS * U) {
+        uint64_t cp[U], cu[U], x0[U], x1[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i = i0 + (int64_t)u * RS;
+            cp[u] = i < re ? coefP[i] : 0ull;
+            cu[u] = i < re ? coefU[i] : 0ull;
+            const bool any = i < re && (cp[u] | cu[u]);
+            x0[u] = (any && ok0) ? C[i * ldc + w2] : 0ull;
+            x1[u] = (any && ok1) ? C[i * ldc + w2 + 1] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i = i0 + (int64_t)u * RS;
+            uint64_t a0 = 0, a1 = 0;
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                if (q < ntt) {
+                    const ulonglong2 t = *(const ulonglong2 *)&T[q][(cp[u] >> (4 * q)) & 15][2 * wp];
+                    a0 ^= t.x;
+                    a1 ^= t.y;
+                }
+                if (q < ntu) {
+                    const ulonglong2 t = *(const ulonglong2 *)&T[16 + q][(cu[u] >> (4 * q)) & 15][2 * wp];
+                    a0 ^= t.x;
+                    a1 ^= t.y;
+                }
+            }
+            if (i < re && (cp[u] | cu[u])) {
+                if (ok0) C[i * ldc + w2] = x0[u] ^ a0;
+                if (ok1) C[i * ldc + w2 + 1] = x1[u] ^ a1;
+            }
+        }
+    }
 }
 
 // Schedules of the update kernel (index = M4Variant id).
@@ -419,23 +601,23 @@ hipError_t launch_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *r
     return hipGetLastError();
 }
 
-// la: the previous pass ran with the look-ahead (fix its deferred rows
-// first) and this panel runs beside the update.
+// fix: what the previous pass(es) left in this stripe word; beside: the
+// panel runs on a second stream beside an update kernel (no LDS window,
+// raised wave priority).
 hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
-                        int64_t *P, int64_t *Q, int64_t *rank, uint64_t *gsv, int32_t *gsid, int panel_regs, bool la,
-                        hipStream_t s) {
+                        int64_t *P, int64_t *Q, int64_t *rank, uint64_t *gsv, int32_t *gsid, int panel_regs,
+                        const PanelFix &fix, bool beside, hipStream_t s) {
     ProfScope ps(KID_PANEL, s);
-    const int fx = la ? 1 : 0;
 #define PANEL_LAUNCH(WQ, SR) \
-    hipLaunchKernelGGL((k_panel<WQ, SR>), dim3(1), dim3(64), 0, s, A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, fx)
+    hipLaunchKernelGGL((k_panel<WQ, SR>), dim3(1), dim3(64), 0, s, A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, fix)
     if (panel_regs == 0 || panel_regs == 2) {
-        if (la) PANEL_LAUNCH(2, 0);
+        if (beside) PANEL_LAUNCH(2, 0);
         else PANEL_LAUNCH(2, SLOW_LDS_ROWS);
     } else if (panel_regs == 4) {
-        if (la) PANEL_LAUNCH(4, 0);
+        if (beside) PANEL_LAUNCH(4, 0);
         else PANEL_LAUNCH(4, SLOW_LDS_ROWS);
     } else {
-        if (la) PANEL_LAUNCH(8, 0);
+        if (beside) PANEL_LAUNCH(8, 0);
         else PANEL_LAUNCH(8, SLOW_LDS_ROWS);
     }
 #undef PANEL_LAUNCH
@@ -443,16 +625,26 @@ hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t 
 }
 
 hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
-                          uint64_t *coef, uint64_t *PB, bool la, hipStream_t s) {
+                          uint64_t *coef, uint64_t *PB, int mode, const PassRec *rect, const uint64_t *coefT,
+                          uint64_t *coefP, const uint64_t *PBt, hipStream_t s) {
     const int nA = (int)((ldw + 63) / 64);
     int64_t rows_est = m - (c < m ? c : m);
+    if (mode == 2) rows_est += KW;  // also the first pass's pivot rows
     if (rows_est < 1) rows_est = 1;
     int nB = (int)((rows_est + WIDE_THREADS - 1) / WIDE_THREADS);
     if (nB > 256) nB = 256;
     if (nB < 1) nB = 1;
+    const int64_t nw = words_for(n);
     ProfScope ps(KID_PERMUTE, s);
-    hipLaunchKernelGGL(k_permute, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, rec, coef, PB, nA,
-                       words_for(n), la ? 1 : 0);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_permute<0>, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, rec, coef, PB, nA, nw,
+                           rect, coefT, coefP, PBt);
+    else if (mode == 1)
+        hipLaunchKernelGGL(k_permute<1>, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, rec, coef, PB, nA, nw,
+                           rect, coefT, coefP, PBt);
+    else
+        hipLaunchKernelGGL(k_permute<2>, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, rec, coef, PB, nA, nw,
+                           rect, coefT, coefP, PBt);
     return hipGetLastError();
 }
 
@@ -475,12 +667,52 @@ hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t
     return hipGetLastError();
 }
 
+// Fused update of a pair (t, u): words [sw_t + 3, nw) of rows r_t .. m-1.
+hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t ct, const PassRec *rect,
+                              const PassRec *recu, const uint64_t *coefP, const uint64_t *coefU,
+                              const uint64_t *coefT, const uint64_t *PBt, const uint64_t *PBu, int m4_target,
+                              hipStream_t s) {
+    const int64_t nw = words_for(n);
+    const int64_t tw0 = (ct >> 6) + 3;
+    if (tw0 >= nw) return hipSuccess;
+    int64_t rows_est = m - (ct < m ? ct : m);
+    if (rows_est < 1) rows_est = 1;
+    const int64_t base = tw0 & ~(int64_t)(PR_TW - 1);
+    const int nt = (int)((nw - base + PR_TW - 1) / PR_TW);
+    int nchunks = 1;
+    if (m4_target > 0) {
+        nchunks = (m4_target + nt - 1) / nt;
+    } else {
+        // whole rounds of one block per CU
+        const int64_t slots = device_cus();
+        int64_t maxc = rows_est / 256;
+        if (maxc < 1) maxc = 1;
+        if (maxc > 4 * slots) maxc = 4 * slots;
+        double best_eff = -1.0;
+        for (int64_t nc = 1; nc <= maxc; nc++) {
+            const int64_t g = nt * nc;
+            const int64_t rounds = (g + slots - 1) / slots;
+            const double eff = (double)g / (double)(rounds * slots) - 0.02 * (double)(rounds - 1);
+            if (eff > best_eff + 1e-9) {
+                best_eff = eff;
+                nchunks = (int)nc;
+            }
+        }
+    }
+    if (nchunks < 1) nchunks = 1;
+    ProfScope ps(KID_M4RM, s);
+    hipLaunchKernelGGL((k_m4rm_pair<1024, 4>), dim3(nt * nchunks), dim3(1024), 0, s, A, ldw, m, coefP, coefU, coefT,
+                       PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu);
+    return hipGetLastError();
+}
+
 hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
                        int64_t *P, int64_t *Q, int64_t *rank, uint64_t *coef, uint64_t *PB, uint64_t *gsv,
                        int32_t *gsid, int m4_variant, int m4_target, int panel_regs, hipStream_t s) {
-    hipError_t e = launch_panel(A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, panel_regs, false, s);
+    hipError_t e = launch_panel(A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, panel_regs, PanelFix(), false, s);
     if (e != hipSuccess) return e;
-    if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, false, s)) != hipSuccess) return e;
+    if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 0, nullptr, nullptr, nullptr, nullptr, s)) != hipSuccess)
+        return e;
     return launch_update(A, m, n, ldw, c, rec, coef, PB, 1, m4_variant, m4_target, s);
 }
 

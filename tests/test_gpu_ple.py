@@ -223,7 +223,8 @@ def test_panel_modes(m, n, kind):
                                       (700, 2000, "u"), (300, 5000, "u"), (2100, 2100, "r")])
 def test_lookahead_modes(m, n, kind):
     """The look-ahead (next stripe updated first, next panel on a second
-    stream beside the update) gives the same bits as the serial pass loop,
+    stream beside the update) and the fused pairs of passes (one trailing
+    update for two passes) give the same bits as the serial pass loop,
     on full-rank, rank-deficient (all-rows panel search) and sparse inputs,
     and on wide matrices whose rank saturates before the last pass."""
     say("lookahead modes", m, n, kind)
@@ -234,7 +235,7 @@ def test_lookahead_modes(m, n, kind):
     else:
         A = inputs.bernoulli(m, n, 16 + m, p=0.01)
     o = oracle_ple(A, n)
-    for mode in (0, 1, 2):
+    for mode in (0, 1, 2, 3):
         for regs in (0, 8):
             assert_same_ple(gpu_ple(A, n, lookahead=mode, panel_regs=regs), o, "lookahead=%d regs=%d" % (mode, regs))
 
@@ -245,5 +246,5 @@ def test_lookahead_16384_seed2():
     say("lookahead 16384^2")
     A = inputs.bernoulli(16384, 16384, 2)
     serial = gpu_ple(A, 16384, lookahead=1)
-    for mode in (0, 2):
+    for mode in (0, 2, 3):
         assert_same_ple(gpu_ple(A, 16384, lookahead=mode), serial, "lookahead=%d" % mode)
