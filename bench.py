@@ -40,25 +40,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def alg_bytes_m4rm(m, n, Q, r):
-    """Algorithmic bytes of the trailing-update launches of one PLE: one
-    8-byte read and one 8-byte write per trailing row word per pass
-    (rows r_t .. m-1, words after the stripe), for passes with a pivot."""
+def alg_bytes_m4rm(m, n, Q, r, kinds):
+    """Algorithmic bytes of the trailing-update launches of one PLE, following
+    the library's pass schedule (gf2_ple_schedule): one 8-byte read and one
+    8-byte write per row word an update launch covers -- rows r_t .. m-1;
+    words right of the stripe (serial pass), from the stripe + 2 (look-ahead
+    pass) or, for a fused pair, from the pair's first stripe + 3, once for
+    both passes.  Launches of passes without a pivot move nothing."""
     import numpy as np
     nw = (n + 63) // 64
     q = np.asarray(Q[:r], dtype=np.int64)
+    counts = np.bincount(q // KW, minlength=nw) if r else np.zeros(nw, np.int64)
+    r_at = np.concatenate([[0], np.cumsum(counts)])
     total = 0
-    active = 0
-    npass = nw
-    counts = np.bincount(q // KW, minlength=npass) if r else np.zeros(npass, np.int64)
-    r_t = 0
-    for t in range(npass):
-        rbar = int(counts[t])
-        if r_t < m and rbar > 0 and t + 1 < nw:
-            total += 16 * (m - r_t) * (nw - t - 1)
-            active += 1
-        r_t += rbar
-    return total, active
+    for t, k in enumerate(kinds):
+        if k == 0 and counts[t] > 0 and t + 1 < nw:
+            total += 16 * (m - r_at[t]) * (nw - t - 1)
+        elif k == 1 and counts[t] > 0 and t + 2 < nw:
+            total += 16 * (m - r_at[t]) * (nw - t - 2)
+        elif k == 3 and (counts[t - 1] > 0 or counts[t] > 0) and t + 2 < nw:
+            total += 16 * (m - r_at[t - 1]) * (nw - (t - 1) - 3)
+    return int(total)
+
+
+def alg_bytes_k64(m, n, Q, r):
+    """The same count for a schedule of serial 64-column passes only (the
+    byte count the paper's per-pass update implies): the reference figure
+    for the whole-PLE rate."""
+    return alg_bytes_m4rm(m, n, Q, r, [0] * ((n + 63) // 64))
 
 
 def kernel_source_hash():
@@ -300,7 +309,9 @@ def main():
     ap.add_argument("--m4-variant", type=int, default=0, help="update schedule 1..8 (0 = library default)")
     ap.add_argument("--m4-blocks", type=int, default=0, help="target blocks per update launch (0 = default)")
     ap.add_argument("--panel-regs", type=int, default=0, help="panel register window 2/4/8 (0 = default)")
-    ap.add_argument("--lookahead", type=int, default=0, help="0 = library default, 1 = off, 2 = every pass")
+    ap.add_argument("--lookahead", type=int, default=0,
+                    help="0 = library default, 1 = serial passes, 2 = look-ahead only, 3 = pairs everywhere")
+    ap.add_argument("--pair-variant", type=int, default=0, help="fused pair update schedule 1..5 (0 = default)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -335,7 +346,7 @@ def main():
     torch.cuda.synchronize()
 
     sched = dict(m4_variant=args.m4_variant, m4_blocks=args.m4_blocks, panel_regs=args.panel_regs,
-                 lookahead=args.lookahead)
+                 lookahead=args.lookahead, pair_variant=args.pair_variant)
 
     def step():
         work.copy_(pristine)
@@ -357,7 +368,9 @@ def main():
     log("timed %d steps: %.3f ms/step, rank %d" % (args.steps, ms_per_step, r))
 
     Qh = Q.cpu().numpy()
-    abytes, active = alg_bytes_m4rm(m, n, Qh, r)
+    kinds = G.ple_schedule(m, n, lookahead=args.lookahead)
+    abytes = alg_bytes_m4rm(m, n, Qh, r, kinds)
+    abytes64 = alg_bytes_k64(m, n, Qh, r)
 
     roofline = None
     kernels = None
@@ -375,12 +388,14 @@ def main():
             achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
             traffic = None
             if (TRAFFIC and TRAFFIC.get("source") == kernel_source_hash() and TRAFFIC.get("n") == args.n
-                    and TRAFFIC.get("seed") == args.seed and not args.m4_variant and not args.m4_blocks):
+                    and TRAFFIC.get("seed") == args.seed and not args.m4_variant and not args.m4_blocks
+                    and not args.pair_variant and not args.lookahead):
                 traffic = TRAFFIC["bytes_per_launch"]
             roofline = {
                 "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "k_m4rm", "launches_per_step": launches_per_step,
+                "kernel": "trailing update (k_m4rm_pair for fused pairs, k_m4rm / k_m4rm_w otherwise)",
+                "launches_per_step": launches_per_step,
                 "alg_bytes_per_launch": round(bytes_per_launch), "avg_launch_ms": round(avg_ms, 5),
             }
         log("profiled: %s" % json.dumps(kernels))
@@ -424,8 +439,11 @@ def main():
                                       else "fixed variant %d" % args.m4_variant,
                    "schedule": sched},
         "rank": r,
-        "alg_bytes_per_step": abytes,
-        "alg_GBps_whole_ple": round(abytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "schedule": {"passes": len(kinds), "serial": kinds.count(0), "lookahead": kinds.count(1),
+                     "fused_pairs": kinds.count(3)},
+        "update_alg_bytes_per_step": abytes,
+        "k64_alg_bytes_per_step": abytes64,
+        "k64_alg_GBps_whole_ple": round(abytes64 / (ms_per_step * 1e-3) / 1e9, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,

@@ -55,7 +55,7 @@ typedef struct gf2_ple_opts {
     int32_t lookahead;     /* 0 = while the trailing block is large: pairs of passes share one trailing update and
                               the next panel runs on a second stream beside it; 1 = neither (serial passes);
                               2 = look-ahead on every pass, no pairs; 3 = pairs and look-ahead on every pass */
-    int32_t reserved[1];
+    int32_t pair_variant;  /* schedule of the fused pair update: 0 = default, 1..5 = a fixed (threads, rows, reads) */
 } gf2_ple_opts;
 
 /* Library version string, e.g. "gf2ple 0.1.0 gfx950". */
@@ -95,6 +95,22 @@ size_t gf2_ple_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf2_ple_
  */
 gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
                    void *ws, size_t ws_bytes, const gf2_ple_opts *opts, void *stream);
+
+/*
+ * The pass schedule gf2_ple follows for an m x n matrix with these options
+ * (host only, no device call): kinds[t] for each 64-column pass t of
+ * Algorithm 2, for up to max passes:
+ *   0 serial: panel, permute, update of every word right of the stripe;
+ *   1 look-ahead: the update covers the words from the stripe + 2 (permute
+ *     and the next panel take the next stripe word) and the next panel runs
+ *     on a second stream beside it;
+ *   2, 3 a fused pair: pass 2 has no update of its own, pass 3's update
+ *     covers both passes on the words from the pair's first stripe + 3.
+ * Returns the number of passes, ceil(n/64), or -1 for invalid arguments.
+ * (Where the look-ahead's second stream cannot be made, the passes run
+ * serially instead.)
+ */
+int64_t gf2_ple_schedule(int64_t m, int64_t n, const gf2_ple_opts *opts, int32_t *kinds, int64_t max);
 
 /* Echelon form from a PLE result (Section 2, row echelon form): in place,
  * A <- E: rows i < r keep columns >= i (their L part is cleared), rows

@@ -20,7 +20,7 @@ hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_
 hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t ct, const PassRec *rect,
                               const PassRec *recu, const uint64_t *coefP, const uint64_t *coefU,
                               const uint64_t *coefT, const uint64_t *PBt, const uint64_t *PBu, int m4_target,
-                              hipStream_t s);
+                              int pair_variant, hipStream_t s);
 hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
                          const uint64_t *coef, const uint64_t *PB, int first, int m4_variant, int m4_target,
                          hipStream_t s);
@@ -160,6 +160,33 @@ constexpr double LOOKAHEAD_BYTES = 64.0 * 1024 * 1024;
 
 size_t ple_workspace_total(int64_t m, int64_t ldw) { return ple_layout(m, ldw).total; }
 
+// How each 64-column pass is run (host decision, made before any launch):
+// serial; look-ahead (its update starts at the stripe + 2, the next panel
+// runs beside it); or a fused pair (the first pass has no update, the second
+// pass's update covers both from the first stripe + 3).  mode = the
+// lookahead option (1: serial only).
+enum PassKind { PK_SERIAL = 0, PK_LOOK = 1, PK_PAIR1 = 2, PK_PAIR2 = 3 };
+
+static void pass_kinds(int64_t m, int64_t n, int mode, std::vector<int8_t> &kind) {
+    const int64_t npasses = words_for(n);
+    kind.assign((size_t)npasses, (int8_t)PK_SERIAL);
+    auto big = [&](int64_t t) {
+        const int64_t c = t * KW;
+        const double rows = (double)(m - (c < m ? c : m));
+        return rows * (double)(npasses - t - 2) * 8.0 > LOOKAHEAD_BYTES;
+    };
+    for (int64_t t = 0; t < npasses;) {
+        if ((mode == 0 || mode == 3) && t + 3 < npasses && (mode == 3 || big(t + 1))) {
+            kind[t] = PK_PAIR1;
+            kind[t + 1] = PK_PAIR2;
+            t += 2;
+            continue;
+        }
+        if (mode != 1 && t + 1 < npasses && (mode >= 2 || big(t))) kind[t] = PK_LOOK;
+        t += 1;
+    }
+}
+
 // The pass loop of Algorithm 2.  Pass t: panel(t) (Algorithm 1 on the stripe
 // at c = 64 t), permute(t) (swaps, coefficients, compressed L bits), then the
 // trailing update.  With look-ahead the next stripe word is brought up to
@@ -184,6 +211,7 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
     const int m4t = opts ? opts->m4_blocks : 0;
     const int pr = opts ? opts->panel_regs : 0;
     const int mode = opts ? opts->lookahead : 0;
+    const int pv = opts ? opts->pair_variant : 0;
 
     hipError_t e = launch_init(P, m, Q, mn, rank, recs, s);
     if (e != hipSuccess) return e;
@@ -191,21 +219,10 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
 
     const int64_t npasses = words_for(n);
     LookCtx *lc = mode == 1 ? nullptr : look_ctx(s);
-    auto big = [&](int64_t t) {
-        const int64_t c = t * KW;
-        const double rows = (double)(m - (c < m ? c : m));
-        return rows * (double)(npasses - t - 2) * 8.0 > LOOKAHEAD_BYTES;
-    };
-    // look-ahead for pass t (modes 0, 2, 3)
-    auto want_la = [&](int64_t t) {
-        if (!lc || t + 1 >= npasses) return false;
-        return mode >= 2 || big(t);
-    };
-    // passes t and t + 1 fused (modes 0 and 3): needs a word right of both stripes
-    auto want_pair = [&](int64_t t) {
-        if (!lc || (mode != 0 && mode != 3) || t + 3 >= npasses) return false;
-        return mode == 3 || big(t + 1);
-    };
+    std::vector<int8_t> kind;
+    pass_kinds(m, n, lc ? mode : 1, kind);
+    auto want_pair = [&](int64_t t) { return kind[t] == PK_PAIR1; };
+    auto want_la = [&](int64_t t) { return kind[t] == PK_LOOK; };
     auto rec_of = [&](int64_t t) { return &recs[t % NREC]; };
     if ((e = launch_panel(A, m, n, ldw, 0, rec_of(NREC - 1), rec_of(0), P, Q, rank, gsv, gsid, pr, PanelFix(), false,
                           s)) != hipSuccess)
@@ -234,7 +251,8 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
             if ((e = launch_permute(A, m, n, ldw, c + KW, nxt, coef2, PB2, 2, rec, coef, coefP, PB, s)) != hipSuccess)
                 return e;
             if ((e = hipEventRecord(lc->evA, s)) != hipSuccess) return e;
-            if ((e = launch_update_pair(A, m, n, ldw, c, rec, nxt, coefP, coef2, coef, PB, PB2, m4t, s)) != hipSuccess)
+            if ((e = launch_update_pair(A, m, n, ldw, c, rec, nxt, coefP, coef2, coef, PB, PB2, m4t, pv, s)) !=
+                hipSuccess)
                 return e;
             if ((e = hipStreamWaitEvent(lc->s2, lc->evA, 0)) != hipSuccess) return e;
             PanelFix f2;
@@ -346,6 +364,7 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
     if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
         return GF2_EINVAL;
     if (opts && (opts->lookahead < 0 || opts->lookahead > 3)) return GF2_EINVAL;
+    if (opts && (opts->pair_variant < 0 || opts->pair_variant > 5)) return GF2_EINVAL;
     if (opts && opts->update == 2) return GF2_EINVAL;  // MFMA trailing update: see gf2_addmul
     const PleLayout L = ple_layout(m, ldw);
     if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;
@@ -356,6 +375,17 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
         if (st != GF2_OK) return st;
     }
     return hip_status(ple_enqueue(A, m, n, ldw, P, Q, rank, ws, opts, s, true));
+}
+
+int64_t gf2_ple_schedule(int64_t m, int64_t n, const gf2_ple_opts *opts, int32_t *kinds, int64_t max) {
+    if (m < 0 || n < 0) return -1;
+    const int mode = opts ? opts->lookahead : 0;
+    if (mode < 0 || mode > 3) return -1;
+    std::vector<int8_t> kind;
+    pass_kinds(m, n, mode, kind);
+    const int64_t np = (int64_t)kind.size();
+    for (int64_t t = 0; t < np && t < max && kinds; t++) kinds[t] = kind[t];
+    return np;
 }
 
 gf2_status gf2_echelon_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, const int64_t *rank, void *stream) {

@@ -342,7 +342,7 @@ __device__ __forceinline__ void pair_combos(uint64_t (*T)[16][PR_TW], int tid) {
     }
 }
 
-template <int NT, int U>
+template <int NT, int U, int G>
 __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int64_t ldc, int64_t m,
                                                   const uint64_t *__restrict__ coefP,
                                                   const uint64_t *__restrict__ coefU,
@@ -389,12 +389,14 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
     pair_combos<16, NT>(T, tid);
     __syncthreads();
 
+    // rows: every table is read (those past a pass's pivots are zero), so the
+    // 32 reads of a row carry no branch and can all be in flight at once
     constexpr int LPR = PR_TW / 2;  // lanes per row
     constexpr int RS = NT / LPR;    // rows per step
     const int wp = tid % LPR, rs = tid / LPR;
     const int64_t w2 = wt0 + 2 * wp;
     const bool ok0 = w2 >= w_begin && w2 < w_end, ok1 = w2 + 1 >= w_begin && w2 + 1 < w_end;
-    const int ntt = (nbt + 3) >> 2, ntu = (nbu + 3) >> 2;
+    const uint32_t tbase = (uint32_t)(2 * wp) * 8u;  // byte offset of this lane's pair of words
     for (int64_t i0 = rb + rs; i0 < re; i0 += (int64_t)RS * U) {
         uint64_t cp[U], cu[U], x0[U], x1[U];
 #pragma unroll
@@ -409,19 +411,28 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int64_t i = i0 + (int64_t)u * RS;
+            // coefficient halves: tables 0-7, 8-15 (pass t), 16-23, 24-31 (pass u)
+            const uint32_t h[4] = {(uint32_t)cp[u], (uint32_t)(cp[u] >> 32), (uint32_t)cu[u],
+                                   (uint32_t)(cu[u] >> 32)};
             uint64_t a0 = 0, a1 = 0;
 #pragma unroll
-            for (int q = 0; q < 16; q++) {
-                if (q < ntt) {
-                    const ulonglong2 t = *(const ulonglong2 *)&T[q][(cp[u] >> (4 * q)) & 15][2 * wp];
-                    a0 ^= t.x;
-                    a1 ^= t.y;
+            for (int g = 0; g < 32; g += G) {
+                ulonglong2 t[G];
+#pragma unroll
+                for (int j = 0; j < G; j++) {
+                    const int q = g + j;
+                    const uint32_t nib = (h[q >> 3] >> (4 * (q & 7))) & 15u;
+                    t[j] = *(const ulonglong2 *)((const char *)&T[0][0][0] + tbase +
+                                                 ((uint32_t)q * 16u + nib) * (uint32_t)(PR_TW * 8));
                 }
-                if (q < ntu) {
-                    const ulonglong2 t = *(const ulonglong2 *)&T[16 + q][(cu[u] >> (4 * q)) & 15][2 * wp];
-                    a0 ^= t.x;
-                    a1 ^= t.y;
+#pragma unroll
+                for (int j = 0; j < G; j++) {
+                    a0 ^= t[j].x;
+                    a1 ^= t[j].y;
                 }
+                // materialise the partial sums here: otherwise the xor chain is
+                // reassociated into one tree that keeps all 32 reads live
+                __asm__ volatile("" : "+v"(a0), "+v"(a1));
             }
             if (i < re && (cp[u] | cu[u])) {
                 if (ok0) C[i * ldc + w2] = x0[u] ^ a0;
@@ -671,7 +682,7 @@ hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t
 hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t ct, const PassRec *rect,
                               const PassRec *recu, const uint64_t *coefP, const uint64_t *coefU,
                               const uint64_t *coefT, const uint64_t *PBt, const uint64_t *PBu, int m4_target,
-                              hipStream_t s) {
+                              int pair_variant, hipStream_t s) {
     const int64_t nw = words_for(n);
     const int64_t tw0 = (ct >> 6) + 3;
     if (tw0 >= nw) return hipSuccess;
@@ -701,8 +712,19 @@ hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, in
     }
     if (nchunks < 1) nchunks = 1;
     ProfScope ps(KID_M4RM, s);
-    hipLaunchKernelGGL((k_m4rm_pair<1024, 4>), dim3(nt * nchunks), dim3(1024), 0, s, A, ldw, m, coefP, coefU, coefT,
-                       PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu);
+#define PAIR_LAUNCH(NT, U, G)                                                                                     \
+    hipLaunchKernelGGL((k_m4rm_pair<NT, U, G>), dim3(nt * nchunks), dim3(NT), 0, s, A, ldw, m, coefP, coefU, coefT, \
+                       PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu)
+    // (threads, rows in flight per thread, table reads per group); the
+    // default was the fastest on MI355X for the 65536^2 PLE
+    switch (pair_variant) {
+        case 1: PAIR_LAUNCH(1024, 2, 2); break;
+        case 3: PAIR_LAUNCH(1024, 4, 1); break;
+        case 4: PAIR_LAUNCH(1024, 4, 2); break;
+        case 5: PAIR_LAUNCH(1024, 1, 4); break;
+        default: PAIR_LAUNCH(1024, 2, 4); break;
+    }
+#undef PAIR_LAUNCH
     return hipGetLastError();
 }
 

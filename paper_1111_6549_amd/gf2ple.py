@@ -23,7 +23,7 @@ STATUS = {0: "GF2_OK", 1: "GF2_EINVAL", 2: "GF2_EWORKSPACE", 3: "GF2_ENOMEM", 4:
 
 # every symbol include/gf2ple.h declares
 EXPORTS = [
-    "gf2_version", "gf2_status_str", "gf2_ple_workspace_bytes", "gf2_ple", "gf2_echelon_from_ple",
+    "gf2_version", "gf2_status_str", "gf2_ple_workspace_bytes", "gf2_ple", "gf2_ple_schedule", "gf2_echelon_from_ple",
     "gf2_rref_workspace_bytes", "gf2_rref_from_ple", "gf2_rref_full_workspace_bytes", "gf2_rref",
     "gf2_addmul", "gf2_make_table", "gf2_check_padding", "gf2_profile_start", "gf2_profile_stop",
     "gf2_batch_plan_create", "gf2_batch_workspace_bytes", "gf2_ple_batched", "gf2_batch_plan_info",
@@ -47,7 +47,7 @@ class KernelTime(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("check_padding", ctypes.c_int32), ("update", ctypes.c_int32), ("mfma_block", ctypes.c_int32),
                 ("m4_variant", ctypes.c_int32), ("m4_blocks", ctypes.c_int32), ("panel_regs", ctypes.c_int32),
-                ("lookahead", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("lookahead", ctypes.c_int32), ("pair_variant", ctypes.c_int32)]
 
 
 class Desc(ctypes.Structure):
@@ -99,6 +99,7 @@ def load():
         "gf2_ple_workspace_bytes": (sz, [i64, i64, i64, p]),
         "gf2_ple": (st, [p, i64, i64, i64, p, p, p, p, sz, p, p]),
         "gf2_echelon_from_ple": (st, [p, i64, i64, i64, p, p]),
+        "gf2_ple_schedule": (i64, [i64, i64, p, p, i64]),
         "gf2_rref_workspace_bytes": (sz, [i64, i64, i64]),
         "gf2_rref_from_ple": (st, [p, i64, i64, i64, p, p, p, sz, p]),
         "gf2_rref_full_workspace_bytes": (sz, [i64, i64, i64, p]),
@@ -166,9 +167,11 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
 
 
-def _opts(update=0, check_padding=False, mfma_block=0, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0):
+def _opts(update=0, check_padding=False, mfma_block=0, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0,
+          pair_variant=0):
     o = Opts()
     o.lookahead = int(lookahead)
+    o.pair_variant = int(pair_variant)
     o.check_padding = 1 if check_padding else 0
     o.update = int(update)
     o.mfma_block = int(mfma_block)
@@ -187,7 +190,8 @@ def alloc_workspace(nbytes, device=None):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
 
 
-def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0):
+def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0,
+        pair_variant=0):
     """In-place PLE of the packed (m, ldw) tensor A with n columns.
 
     Returns (P, Q, rank) as device tensors (int64 [m], int64 [min(m, n)],
@@ -196,7 +200,7 @@ def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0,
     m, ldw = A.shape
     lib = load()
     o = _opts(update, check_padding, m4_variant=m4_variant, m4_blocks=m4_blocks, panel_regs=panel_regs,
-              lookahead=lookahead)
+              lookahead=lookahead, pair_variant=pair_variant)
     need = int(lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
     if need == 0 and (m or n):
         raise GF2Error(1, "gf2_ple_workspace_bytes")
@@ -208,6 +212,18 @@ def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0,
     _check(lib.gf2_ple(_ptr(A), m, n, ldw, _ptr(P), _ptr(Q), _ptr(rank), _ptr(ws), ws.numel(),
                        ctypes.byref(o), _stream()), "gf2_ple")
     return P, Q, rank
+
+
+def ple_schedule(m, n, lookahead=0):
+    """Per-pass kinds of gf2_ple's schedule (0 serial, 1 look-ahead, 2/3 the
+    first/second pass of a fused pair)."""
+    o = _opts(lookahead=lookahead)
+    np_ = int(load().gf2_ple_schedule(m, n, ctypes.byref(o), None, 0))
+    if np_ < 0:
+        raise GF2Error(1, "gf2_ple_schedule")
+    arr = (ctypes.c_int32 * max(np_, 1))()
+    load().gf2_ple_schedule(m, n, ctypes.byref(o), arr, np_)
+    return [int(arr[i]) for i in range(np_)]
 
 
 def echelon_from_ple(A, n, rank):
