@@ -13,10 +13,10 @@ namespace gf2 {
 hipError_t launch_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *rank, PassRec *rec, hipStream_t s);
 hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
                         int64_t *P, int64_t *Q, int64_t *rank, uint64_t *gsv, int32_t *gsid, int panel_regs,
-                        const PanelFix &fix, bool beside, hipStream_t s);
+                        const PanelFix &fix, bool beside, hipStream_t s, hipEvent_t done);
 hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
                           uint64_t *coef, uint64_t *PB, int mode, const PassRec *rect, const uint64_t *coefT,
-                          uint64_t *coefP, const uint64_t *PBt, hipStream_t s);
+                          uint64_t *coefP, const uint64_t *PBt, hipStream_t s, hipEvent_t done);
 hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t ct, const PassRec *rect,
                               const PassRec *recu, const uint64_t *coefP, const uint64_t *coefU,
                               const uint64_t *coefT, const uint64_t *PBt, const uint64_t *PBu, int m4_target,
@@ -144,8 +144,7 @@ static LookCtx *look_ctx(hipStream_t user) {
     c.dev = dev;
     c.user = user;
     if (hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&c.evA, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c.evN, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreate(&c.evA) != hipSuccess || hipEventCreate(&c.evN) != hipSuccess) {
         (void)hipStreamDestroy(c.s2);
         return nullptr;
     }
@@ -225,7 +224,7 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
     auto want_la = [&](int64_t t) { return kind[t] == PK_LOOK; };
     auto rec_of = [&](int64_t t) { return &recs[t % NREC]; };
     if ((e = launch_panel(A, m, n, ldw, 0, rec_of(NREC - 1), rec_of(0), P, Q, rank, gsv, gsid, pr, PanelFix(), false,
-                          s)) != hipSuccess)
+                          s, nullptr)) != hipSuccess)
         return e;
     bool pending = false;  // this pass's panel ran on the second stream
     int64_t since_check = 0;
@@ -239,18 +238,18 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
         if (want_pair(t)) {
             // pass t: permute with the next stripe word updated; its bulk
             // update waits for pass t + 1
-            if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 1, nullptr, nullptr, nullptr, nullptr, s)) !=
-                hipSuccess)
+            if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 1, nullptr, nullptr, nullptr, nullptr, s,
+                                    nullptr)) != hipSuccess)
                 return e;
             PanelFix f1;
             f1.mode = 1;
-            if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, f1, false, s)) !=
-                hipSuccess)
+            if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, f1, false, s,
+                                  nullptr)) != hipSuccess)
                 return e;
             // pass u = t + 1 carries pass t's coefficients along
-            if ((e = launch_permute(A, m, n, ldw, c + KW, nxt, coef2, PB2, 2, rec, coef, coefP, PB, s)) != hipSuccess)
+            if ((e = launch_permute(A, m, n, ldw, c + KW, nxt, coef2, PB2, 2, rec, coef, coefP, PB, s, lc->evA)) !=
+                hipSuccess)
                 return e;
-            if ((e = hipEventRecord(lc->evA, s)) != hipSuccess) return e;
             if ((e = launch_update_pair(A, m, n, ldw, c, rec, nxt, coefP, coef2, coef, PB, PB2, m4t, pv, s)) !=
                 hipSuccess)
                 return e;
@@ -261,9 +260,8 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
             f2.coefT = coef;
             f2.PBt = PB;
             if ((e = launch_panel(A, m, n, ldw, c + 2 * KW, nxt, rec_of(t + 2), P, Q, rank, gsv, gsid, pr, f2, true,
-                                  lc->s2)) != hipSuccess)
+                                  lc->s2, lc->evN)) != hipSuccess)
                 return e;
-            if ((e = hipEventRecord(lc->evN, lc->s2)) != hipSuccess) return e;
             pending = true;
             t += 2;
             continue;
@@ -272,24 +270,22 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
             // permute also updates the next stripe word of the ordinary rows;
             // the next panel finishes the special rows' one, then searches,
             // while the update of the words beyond runs
-            if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 1, nullptr, nullptr, nullptr, nullptr, s)) !=
-                hipSuccess)
+            if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 1, nullptr, nullptr, nullptr, nullptr, s,
+                                    lc->evA)) != hipSuccess)
                 return e;
-            if ((e = hipEventRecord(lc->evA, s)) != hipSuccess) return e;
             if ((e = launch_update(A, m, n, ldw, c, rec, coef, PB, 2, m4v, m4t, s)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(lc->s2, lc->evA, 0)) != hipSuccess) return e;
             PanelFix f1;
             f1.mode = 1;
-            if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, f1, true, lc->s2)) !=
-                hipSuccess)
+            if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, f1, true, lc->s2,
+                                  lc->evN)) != hipSuccess)
                 return e;
-            if ((e = hipEventRecord(lc->evN, lc->s2)) != hipSuccess) return e;
             pending = true;
             t += 1;
             continue;
         }
-        if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 0, nullptr, nullptr, nullptr, nullptr, s)) !=
-            hipSuccess)
+        if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 0, nullptr, nullptr, nullptr, nullptr, s,
+                                nullptr)) != hipSuccess)
             return e;
         if ((e = launch_update(A, m, n, ldw, c, rec, coef, PB, 1, m4v, m4t, s)) != hipSuccess) return e;
         if (t + 1 >= npasses) break;
@@ -303,8 +299,8 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
             }
             since_check = (since_check + 1) % 8;
         }
-        if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, PanelFix(), false, s)) !=
-            hipSuccess)
+        if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, PanelFix(), false, s,
+                              nullptr)) != hipSuccess)
             return e;
         t += 1;
     }

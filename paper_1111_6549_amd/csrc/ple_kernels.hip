@@ -22,6 +22,8 @@
 //              Algorithm 2 folded into the lookup.
 //
 // The same k_m4rm kernel is the public GF(2) product gf2_addmul.
+#include <hip/hip_ext.h>
+
 #include "m4rm.h"
 #include "panel.h"
 
@@ -615,12 +617,15 @@ hipError_t launch_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *r
 // fix: what the previous pass(es) left in this stripe word; beside: the
 // panel runs on a second stream beside an update kernel (no LDS window,
 // raised wave priority).
+// done: if given, recorded when the kernel completes (carried by the
+// kernel's own completion signal rather than a separate marker)
 hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
                         int64_t *P, int64_t *Q, int64_t *rank, uint64_t *gsv, int32_t *gsid, int panel_regs,
-                        const PanelFix &fix, bool beside, hipStream_t s) {
+                        const PanelFix &fix, bool beside, hipStream_t s, hipEvent_t done) {
     ProfScope ps(KID_PANEL, s);
-#define PANEL_LAUNCH(WQ, SR) \
-    hipLaunchKernelGGL((k_panel<WQ, SR>), dim3(1), dim3(64), 0, s, A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, fix)
+#define PANEL_LAUNCH(WQ, SR)                                                                                      \
+    hipExtLaunchKernelGGL((k_panel<WQ, SR>), dim3(1), dim3(64), 0, s, nullptr, done, 0, A, m, n, ldw, c, prev, rec, P, \
+                          Q, rank, gsv, gsid, fix)
     if (panel_regs == 0 || panel_regs == 2) {
         if (beside) PANEL_LAUNCH(2, 0);
         else PANEL_LAUNCH(2, SLOW_LDS_ROWS);
@@ -637,7 +642,7 @@ hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t 
 
 hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
                           uint64_t *coef, uint64_t *PB, int mode, const PassRec *rect, const uint64_t *coefT,
-                          uint64_t *coefP, const uint64_t *PBt, hipStream_t s) {
+                          uint64_t *coefP, const uint64_t *PBt, hipStream_t s, hipEvent_t done) {
     const int nA = (int)((ldw + 63) / 64);
     int64_t rows_est = m - (c < m ? c : m);
     if (mode == 2) rows_est += KW;  // also the first pass's pivot rows
@@ -647,15 +652,13 @@ hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_
     if (nB < 1) nB = 1;
     const int64_t nw = words_for(n);
     ProfScope ps(KID_PERMUTE, s);
-    if (mode == 0)
-        hipLaunchKernelGGL(k_permute<0>, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, rec, coef, PB, nA, nw,
-                           rect, coefT, coefP, PBt);
-    else if (mode == 1)
-        hipLaunchKernelGGL(k_permute<1>, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, rec, coef, PB, nA, nw,
-                           rect, coefT, coefP, PBt);
-    else
-        hipLaunchKernelGGL(k_permute<2>, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, A, m, ldw, c, rec, coef, PB, nA, nw,
-                           rect, coefT, coefP, PBt);
+#define PERMUTE_LAUNCH(MODE)                                                                                    \
+    hipExtLaunchKernelGGL(k_permute<MODE>, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, nullptr, done, 0, A, m, ldw, c, \
+                          rec, coef, PB, nA, nw, rect, coefT, coefP, PBt)
+    if (mode == 0) PERMUTE_LAUNCH(0);
+    else if (mode == 1) PERMUTE_LAUNCH(1);
+    else PERMUTE_LAUNCH(2);
+#undef PERMUTE_LAUNCH
     return hipGetLastError();
 }
 
@@ -731,9 +734,11 @@ hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, in
 hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
                        int64_t *P, int64_t *Q, int64_t *rank, uint64_t *coef, uint64_t *PB, uint64_t *gsv,
                        int32_t *gsid, int m4_variant, int m4_target, int panel_regs, hipStream_t s) {
-    hipError_t e = launch_panel(A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, panel_regs, PanelFix(), false, s);
+    hipError_t e =
+        launch_panel(A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, panel_regs, PanelFix(), false, s, nullptr);
     if (e != hipSuccess) return e;
-    if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 0, nullptr, nullptr, nullptr, nullptr, s)) != hipSuccess)
+    if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 0, nullptr, nullptr, nullptr, nullptr, s, nullptr)) !=
+        hipSuccess)
         return e;
     return launch_update(A, m, n, ldw, c, rec, coef, PB, 1, m4_variant, m4_target, s);
 }
