@@ -42,6 +42,14 @@ __device__ __forceinline__ uint64_t place_bits(uint64_t u, int64_t w, int64_t wr
     return 0;
 }
 
+// a ^ b ^ c in one instruction per 32-bit half (v_bitop3_b32 with the
+// three-input XOR truth table 0x96).
+__device__ __forceinline__ uint64_t xor3_64(uint64_t a, uint64_t b, uint64_t c) {
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0x96);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0x96);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // New value of word w of a special row (a pivot or a row displaced by the
 // pass's swaps): the stripe word becomes its L bits and, for a pivot, its E
 // part; the words holding columns [r, c) get the L bits or-ed in; the rest

@@ -427,10 +427,18 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
                     t[j] = *(const ulonglong2 *)((const char *)&T[0][0][0] + tbase +
                                                  ((uint32_t)q * 16u + nib) * (uint32_t)(PR_TW * 8));
                 }
+                if constexpr (G % 2 == 0) {
 #pragma unroll
-                for (int j = 0; j < G; j++) {
-                    a0 ^= t[j].x;
-                    a1 ^= t[j].y;
+                    for (int j = 0; j < G; j += 2) {
+                        a0 = xor3_64(a0, t[j].x, t[j + 1].x);
+                        a1 = xor3_64(a1, t[j].y, t[j + 1].y);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < G; j++) {
+                        a0 ^= t[j].x;
+                        a1 ^= t[j].y;
+                    }
                 }
                 // materialise the partial sums here: otherwise the xor chain is
                 // reassociated into one tree that keeps all 32 reads live
