@@ -28,12 +28,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 KW = 64
-# HBM bytes per k_m4rm launch on the 65536^2 seed-5 workload: rocprofv3
-# --pmc FETCH_SIZE and --pmc WRITE_SIZE, averaged over the 1023 launches of
-# one PLE and scaled by the same counters on the 512 MiB restore copy
+# HBM bytes per trailing-update launch on the 65536^2 seed-5 workload:
+# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE, averaged over the update
+# launches of one PLE and scaled by the same counters on the 512 MiB restore copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Reported only while the kernel
 # sources hash to the value the counters were taken on.
-TRAFFIC = {"source": "35ae2c58d9bf9d1a", "n": 65536, "seed": 5, "bytes_per_launch": 364489954}
+TRAFFIC = {"source": "e2ee39e4036321b3", "n": 65536, "seed": 5, "bytes_per_launch": 283264979}
 
 
 def log(*a):
@@ -236,7 +236,7 @@ def run_serving(args, log_fn):
     del scratch, wsp
 
     def serve(arrivals):
-        S = G.ServeSession(budget_bytes=64 << 30)
+        S = G.ServeSession(budget_bytes=64 << 30, small_max_dim=args.serve_small_max)
         tickets = []
         start = time.perf_counter()
         for r, t, at in zip(reqs, dev, arrivals):
@@ -319,6 +319,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-count", type=int, default=600)
     ap.add_argument("--serve-cpu-sample", type=int, default=60)
+    ap.add_argument("--serve-small-max", type=int, default=0,
+                    help="largest side served by batched launches (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the PLE of one matrix is not split across GPUs here "
