@@ -52,10 +52,12 @@ typedef struct gf2_ple_opts {
     int32_t m4_variant;    /* Four-Russians update schedule: 0 = default, 1..8 = a fixed (tile, threads, unroll) */
     int32_t m4_blocks;     /* target blocks per update launch (0 = default 512) */
     int32_t panel_regs;    /* pivot-search register window of the panel: 0 = default, 2, 4 or 8 x 64 rows */
-    int32_t lookahead;     /* 0 = while the trailing block is large: pairs of passes share one trailing update and
-                              the next panel runs on a second stream beside it; 1 = neither (serial passes);
-                              2 = look-ahead on every pass, no pairs; 3 = pairs and look-ahead on every pass */
-    int32_t pair_variant;  /* schedule of the fused pair update: 0 = default, 1..5 = a fixed (threads, rows, reads) */
+    int32_t lookahead;     /* 0 = pairs of passes share one trailing update (the later pass's next panel runs
+                              inside that update) while rows remain below the stripe, then serial passes;
+                              1 = serial passes only; 2 = look-ahead on every pass (next panel on a second
+                              stream beside the update), no pairs; 3 = pairs on every pass */
+    int32_t pair_variant;  /* schedule of the fused pair update: 0 = default; 1..7 = a fixed (threads, rows in
+                              flight, table reads per group, coefficient prefetch) */
 } gf2_ple_opts;
 
 /* Library version string, e.g. "gf2ple 0.1.0 gfx950". */

@@ -1,6 +1,7 @@
 // C-ABI entry points of libgf2ple (declared in include/gf2ple.h): argument
 // checks, workspace layout and the pass loop of Algorithm 2.  All arithmetic
 // runs in the HIP kernels of ple_kernels.hip / rref_kernels.hip.
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -20,7 +21,7 @@ hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_
 hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t ct, const PassRec *rect,
                               const PassRec *recu, const uint64_t *coefP, const uint64_t *coefU,
                               const uint64_t *coefT, const uint64_t *PBt, const uint64_t *PBu, int m4_target,
-                              int pair_variant, hipStream_t s);
+                              int pair_variant, const PairPanel &pp, hipStream_t s);
 hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
                          const uint64_t *coef, const uint64_t *PB, int first, int m4_variant, int m4_target,
                          hipStream_t s);
@@ -144,7 +145,12 @@ static LookCtx *look_ctx(hipStream_t user) {
     c.dev = dev;
     c.user = user;
     if (hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipEventCreate(&c.evA) != hipSuccess || hipEventCreate(&c.evN) != hipSuccess) {
+    // the events only order the two streams on this device: a device-scope
+    // release and no timestamps (a default event also writes back the caches
+    // for the host, which delays the next kernel by microseconds)
+    constexpr unsigned EV_FLAGS = hipEventDisableTiming | hipEventReleaseToDevice;
+    if (hipEventCreateWithFlags(&c.evA, EV_FLAGS) != hipSuccess ||
+        hipEventCreateWithFlags(&c.evN, EV_FLAGS) != hipSuccess) {
         (void)hipStreamDestroy(c.s2);
         return nullptr;
     }
@@ -154,7 +160,7 @@ static LookCtx *look_ctx(hipStream_t user) {
 }
 
 // Trailing blocks above this many bytes take the look-ahead in the default
-// mode: their update outlasts the next panel.
+// mode when a pass is not paired: their update outlasts the next panel.
 constexpr double LOOKAHEAD_BYTES = 64.0 * 1024 * 1024;
 
 size_t ple_workspace_total(int64_t m, int64_t ldw) { return ple_layout(m, ldw).total; }
@@ -169,13 +175,15 @@ enum PassKind { PK_SERIAL = 0, PK_LOOK = 1, PK_PAIR1 = 2, PK_PAIR2 = 3 };
 static void pass_kinds(int64_t m, int64_t n, int mode, std::vector<int8_t> &kind) {
     const int64_t npasses = words_for(n);
     kind.assign((size_t)npasses, (int8_t)PK_SERIAL);
-    auto big = [&](int64_t t) {
+    auto rows = [&](int64_t t) {
         const int64_t c = t * KW;
-        const double rows = (double)(m - (c < m ? c : m));
-        return rows * (double)(npasses - t - 2) * 8.0 > LOOKAHEAD_BYTES;
+        return m - (c < m ? c : m);
     };
+    auto big = [&](int64_t t) { return (double)rows(t) * (double)(npasses - t - 2) * 8.0 > LOOKAHEAD_BYTES; };
     for (int64_t t = 0; t < npasses;) {
-        if ((mode == 0 || mode == 3) && t + 3 < npasses && (mode == 3 || big(t + 1))) {
+        // pairs while rows remain below the stripe (past that, the serial
+        // loop stops as soon as the rank reaches m)
+        if ((mode == 0 || mode == 3) && t + 3 < npasses && (mode == 3 || rows(t + 1) > 0)) {
             kind[t] = PK_PAIR1;
             kind[t + 1] = PK_PAIR2;
             t += 2;
@@ -217,9 +225,17 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
     if (m == 0 || n == 0) return hipSuccess;
 
     const int64_t npasses = words_for(n);
-    LookCtx *lc = mode == 1 ? nullptr : look_ctx(s);
     std::vector<int8_t> kind;
-    pass_kinds(m, n, lc ? mode : 1, kind);
+    pass_kinds(m, n, mode, kind);
+    // the second stream exists only for look-ahead passes; without one they
+    // run serially
+    LookCtx *lc = nullptr;
+    if (std::find(kind.begin(), kind.end(), (int8_t)PK_LOOK) != kind.end()) {
+        lc = look_ctx(s);
+        if (!lc)
+            for (auto &k : kind)
+                if (k == PK_LOOK) k = PK_SERIAL;
+    }
     auto want_pair = [&](int64_t t) { return kind[t] == PK_PAIR1; };
     auto want_la = [&](int64_t t) { return kind[t] == PK_LOOK; };
     auto rec_of = [&](int64_t t) { return &recs[t % NREC]; };
@@ -246,23 +262,24 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
             if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, f1, false, s,
                                   nullptr)) != hipSuccess)
                 return e;
-            // pass u = t + 1 carries pass t's coefficients along
-            if ((e = launch_permute(A, m, n, ldw, c + KW, nxt, coef2, PB2, 2, rec, coef, coefP, PB, s, lc->evA)) !=
+            // pass u = t + 1 carries pass t's coefficients along; the pair's
+            // update also runs the panel of pass t + 2 (no second stream)
+            if ((e = launch_permute(A, m, n, ldw, c + KW, nxt, coef2, PB2, 2, rec, coef, coefP, PB, s, nullptr)) !=
                 hipSuccess)
                 return e;
-            if ((e = launch_update_pair(A, m, n, ldw, c, rec, nxt, coefP, coef2, coef, PB, PB2, m4t, pv, s)) !=
+            PairPanel pp;
+            pp.on = 1;
+            pp.n = n;
+            pp.c = c + 2 * KW;
+            pp.rec = rec_of(t + 2);
+            pp.P = P;
+            pp.Q = Q;
+            pp.rank = rank;
+            pp.gsv = gsv;
+            pp.gsid = gsid;
+            if ((e = launch_update_pair(A, m, n, ldw, c, rec, nxt, coefP, coef2, coef, PB, PB2, m4t, pv, pp, s)) !=
                 hipSuccess)
                 return e;
-            if ((e = hipStreamWaitEvent(lc->s2, lc->evA, 0)) != hipSuccess) return e;
-            PanelFix f2;
-            f2.mode = 2;
-            f2.pt = rec;
-            f2.coefT = coef;
-            f2.PBt = PB;
-            if ((e = launch_panel(A, m, n, ldw, c + 2 * KW, nxt, rec_of(t + 2), P, Q, rank, gsv, gsid, pr, f2, true,
-                                  lc->s2, lc->evN)) != hipSuccess)
-                return e;
-            pending = true;
             t += 2;
             continue;
         }
@@ -360,7 +377,7 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
     if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
         return GF2_EINVAL;
     if (opts && (opts->lookahead < 0 || opts->lookahead > 3)) return GF2_EINVAL;
-    if (opts && (opts->pair_variant < 0 || opts->pair_variant > 5)) return GF2_EINVAL;
+    if (opts && (opts->pair_variant < 0 || opts->pair_variant > 7)) return GF2_EINVAL;
     if (opts && opts->update == 2) return GF2_EINVAL;  // MFMA trailing update: see gf2_addmul
     const PleLayout L = ple_layout(m, ldw);
     if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;

@@ -110,6 +110,18 @@ struct PanelFix {
     const uint64_t *PBt = nullptr;    // mode 2: its staged pivot rows (row stride ldw)
 };
 
+// A panel launched inside a fused pair's update kernel: pass t + 2 on the
+// stripe at c, writing record `rec` (the pair's second record is its
+// previous one).
+struct PairPanel {
+    int on = 0;
+    int64_t n = 0, c = 0;
+    PassRec *rec = nullptr;
+    int64_t *P = nullptr, *Q = nullptr, *rank = nullptr;
+    uint64_t *gsv = nullptr;
+    int32_t *gsid = nullptr;
+};
+
 // One wave (lane = threadIdx.x & 63) computes the panel of the stripe at
 // column c.  `prev` is the previous pass's record (its r + rbar is this
 // pass's r; it is read before `rec` is written, so the two may be the same
@@ -157,66 +169,93 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
 
     // ---- search over a register window ---------------------------------------
     if constexpr (WQ == 2) {
-        // Two registers (128 rows), loaded at once.  Per column: the candidate
-        // masks are ballots, the pivot is their first set bit, the swap and the
-        // elimination are selects on scalar masks.
+        // Two registers (128 rows), loaded at once, kept as 32-bit halves:
+        // lane l holds positions l (x0) and 64 + l (x1).  Per column the
+        // candidate masks are ballots of one half, the pivot is their first
+        // set bit, and every move is a select on a scalar lane mask: the
+        // rows with the bit (but the pivot) get the pivot's part above the
+        // column, the row at npiv moves to the pivot's place and the pivot
+        // row to npiv.  Positions below npiv are never written again, so at
+        // the end they hold the pivot rows as found.  No branch but the exit.
         const int nmax = (int)(rows < 128 ? rows : 128);
-        uint64_t v0 = 0, v1 = 0;
+        uint32_t x0l, x0h, x1l, x1h;
         {
             const int64_t row0 = r + (lane < rows ? lane : rows - 1);
             const int64_t row1 = r + (64 + lane < rows ? 64 + lane : rows - 1);
             const uint64_t t0 = ld_stripe(A + row0 * ldw + sw);
             const uint64_t t1 = ld_stripe(A + row1 * ldw + sw);
-            v0 = lane < nmax ? (t0 & kmask) : 0ull;
-            v1 = 64 + lane < nmax ? (t1 & kmask) : 0ull;
+            const uint64_t v0 = lane < nmax ? (t0 & kmask) : 0ull;
+            const uint64_t v1 = 64 + lane < nmax ? (t1 & kmask) : 0ull;
+            x0l = (uint32_t)v0;
+            x0h = (uint32_t)(v0 >> 32);
+            x1l = (uint32_t)v1;
+            x1h = (uint32_t)(v1 >> 32);
         }
         PANEL_STAMP(1)
         int id0 = lane, id1 = 64 + lane;  // original position of the row each lane holds
         uint64_t act0 = nmax >= 64 ? ~0ull : ((1ull << nmax) - 1ull);
         uint64_t act1 = nmax >= 128 ? ~0ull : (nmax <= 64 ? 0ull : ((1ull << (nmax - 64)) - 1ull));
-        for (int j = 0; j < kp; j++) {
-            const uint64_t bj = 1ull << j;
-            const uint64_t m0 = __ballot((v0 & bj) != 0) & act0;
-            const uint64_t m1 = __ballot((v1 & bj) != 0) & act1;
-            if (!(m0 | m1)) {
-                if (nmax < rows) {  // a row outside the window may hold the pivot
-                    slow = true;
-                    break;
-                }
-                continue;  // column j has no pivot
+        const int rows_i = rows < 4096 ? (int)rows : 4096;  // npiv stays below 65
+        // one column: HI selects the half that holds bit j; returns false to
+        // leave the loop.  A column without a pivot in the window is a no-op
+        // (all masks empty) unless rows past the window remain.
+        auto column = [&](const int j, const bool HI) -> bool {
+            const uint32_t bj = 1u << (j & 31);
+            const uint64_t m0 = __ballot(((HI ? x0h : x0l) & bj) != 0) & act0;
+            const uint64_t m1 = __ballot(((HI ? x1h : x1l) & bj) != 0) & act1;
+            const bool none = !(m0 | m1);
+            if (none && nmax < rows) {  // a row outside the window may hold the pivot
+                slow = true;
+                return false;
             }
             const bool in0 = m0 != 0;
-            const int lf = (int)__builtin_ctzll(in0 ? m0 : m1);
-            const uint64_t pv = in0 ? readlane64(v0, lf) : readlane64(v1, lf);
-            const uint64_t vr = readlane64(v0, npiv);
-            const int idp = in0 ? readlane32(id0, lf) : readlane32(id1, lf);
+            const int f0 = m0 ? (int)__builtin_ctzll(m0) : 0;
+            const int f1 = m1 ? (int)__builtin_ctzll(m1) : 0;
+            const int lf = in0 ? f0 : f1;
+            // the pivot row and the row at npiv, as they stand
+            const uint32_t a0l = (uint32_t)readlane32((int)x0l, lf), a0h = (uint32_t)readlane32((int)x0h, lf);
+            const uint32_t a1l = (uint32_t)readlane32((int)x1l, lf), a1h = (uint32_t)readlane32((int)x1h, lf);
+            const int ia0 = readlane32(id0, lf), ia1 = readlane32(id1, lf);
+            const uint32_t pvl = in0 ? a0l : a1l, pvh = in0 ? a0h : a1h;
+            const int idp = in0 ? ia0 : ia1;
+            const uint32_t vrl = (uint32_t)readlane32((int)x0l, npiv), vrh = (uint32_t)readlane32((int)x0h, npiv);
             const int idr = readlane32(id0, npiv);
-            const uint64_t pe = pv & above(j);
-            const uint64_t lbit = 1ull << lf, nbit = 1ull << npiv;
-            // rows below the pivot with a 1 in column j (the row moving to the
-            // pivot's old place has a 0 there)
-            const uint64_t e0 = in0 ? (m0 & ~lbit) : m0;
-            const uint64_t e1 = in0 ? m1 : (m1 & ~lbit);
-            const bool at_f = __builtin_amdgcn_inverse_ballot_w64(lbit);
-            if (in0) {
-                v0 = at_f ? vr : v0;
-                id0 = at_f ? idr : id0;
-            } else {
-                v1 = at_f ? vr : v1;
-                id1 = at_f ? idr : id1;
+            // the pivot's part strictly above column j
+            const uint32_t pel = HI ? 0u : (j == 31 ? 0u : pvl & (~0u << (j + 1)));
+            const uint32_t peh = HI ? (j == 63 ? 0u : pvh & (~0u << ((j & 31) + 1))) : pvh;
+            const uint64_t lbit = none ? 0ull : 1ull << lf, nbit = none ? 0ull : 1ull << npiv;
+            const uint64_t f0m = in0 ? lbit : 0ull, f1m = in0 ? 0ull : lbit;
+            const bool e0 = __builtin_amdgcn_inverse_ballot_w64(m0 & ~f0m);
+            const bool e1 = __builtin_amdgcn_inverse_ballot_w64(m1 & ~f1m);
+            const bool s0 = __builtin_amdgcn_inverse_ballot_w64(f0m);
+            const bool s1 = __builtin_amdgcn_inverse_ballot_w64(f1m);
+            const bool sn = __builtin_amdgcn_inverse_ballot_w64(nbit);
+            if (!HI) {
+                x0l = e0 ? x0l ^ pel : x0l;
+                x1l = e1 ? x1l ^ pel : x1l;
             }
-            const bool me = __builtin_amdgcn_inverse_ballot_w64(nbit);
-            v0 = me ? pv : v0;
-            id0 = me ? idp : id0;
-            v0 ^= __builtin_amdgcn_inverse_ballot_w64(e0) ? pe : 0ull;
-            v1 ^= __builtin_amdgcn_inverse_ballot_w64(e1) ? pe : 0ull;
-            my_q = me ? j : my_q;
-            my_fin = me ? pv : my_fin;
-            my_p = me ? (in0 ? lf : 64 + lf) : my_p;
+            x0h = e0 ? x0h ^ peh : x0h;
+            x1h = e1 ? x1h ^ peh : x1h;
+            x0l = s0 ? vrl : x0l;
+            x0h = s0 ? vrh : x0h;
+            x1l = s1 ? vrl : x1l;
+            x1h = s1 ? vrh : x1h;
+            id0 = s0 ? idr : id0;
+            id1 = s1 ? idr : id1;
+            x0l = sn ? pvl : x0l;
+            x0h = sn ? pvh : x0h;
+            id0 = sn ? idp : id0;
+            my_q = sn ? j : my_q;
+            my_p = sn ? (in0 ? lf : 64 + lf) : my_p;
             act0 &= ~nbit;
-            npiv++;
-            if (npiv == rows) break;
-        }
+            npiv += (int)((m0 | m1) != 0);
+            return npiv < rows_i;
+        };
+        const int klo = kp < 32 ? kp : 32;
+        bool go = true;
+        for (int j = 0; j < klo && go; j++) go = column(j, false);
+        for (int j = 32; j < kp && go; j++) go = column(j, true);
+        my_fin = lane < npiv ? (((uint64_t)x0h << 32) | x0l) : 0ull;
         npiv = uni(npiv);
         PANEL_STAMP(2)
         if (!slow) {
@@ -454,30 +493,60 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
     // they were when the pass began
     uint64_t vD = 0;
     if (lane < ndisp) vD = ld_stripe(A + L.src[rbar + lane] * ldw + sw) & kmask;
-    uint64_t vV = (lane < kp) ? (1ull << lane) : 0ull;  // unit stripe vectors
-    uint64_t hP = (lane < rbar) ? (1ull << lane) : 0ull, uP = 0;
-    uint64_t hV = 0, uV = 0, hD = 0, uD = 0;
-    // fully unrolled (constant lane indices let the independent reads of
-    // my_q / my_fin run ahead); iterations l >= rbar change nothing: their
-    // my_fin, hP are 0 and bl is 0
-#pragma unroll
-    for (int l = 0; l < KW; l++) {
+    // 32-bit halves throughout: every update below is one three-input logic
+    // instruction per half
+    uint32_t vVl = 0, vVh = 0;  // unit stripe vectors
+    if (lane < kp) {
+        vVl = lane < 32 ? 1u << lane : 0u;
+        vVh = lane >= 32 ? 1u << (lane - 32) : 0u;
+    }
+    uint32_t vDl = (uint32_t)vD, vDh = (uint32_t)(vD >> 32);
+    uint32_t hPl = 0, hPh = 0, uPl = 0, uPh = 0;
+    if (lane < rbar) {
+        hPl = lane < 32 ? 1u << lane : 0u;
+        hPh = lane >= 32 ? 1u << (lane - 32) : 0u;
+    }
+    uint32_t hVl = 0, hVh = 0, uVl = 0, uVh = 0, hDl = 0, hDh = 0, uDl = 0, uDh = 0;
+    // a pivot row's bits below its own pivot column are its L bits: bit q_l
+    // of them is set only on later pivots reduced by pivot l
+    const uint64_t finL = lane < rbar ? my_fin & ((1ull << my_q) - 1ull) : 0ull;
+    const uint32_t fLl = (uint32_t)finL, fLh = (uint32_t)(finL >> 32);
+    // pivot columns increase with l: those in the low half come first
+    const int nlo = __popcll(__ballot(lane < rbar && my_q < 32));
+    auto step = [&](const int l, const bool HIQ) {
         const int ql = readlane32(my_q, l);
         const uint64_t pe = readlane64(my_fin, l) & above(ql);
-        const uint64_t hl = readlane64(hP, l);  // final: pivot l is reduced by pivots < l only
-        const uint64_t bl = l < rbar ? 1ull << l : 0ull;
-        const uint64_t mp = (lane > l) ? (0ull - ((my_fin >> ql) & 1ull)) : 0ull;
-        const uint64_t mv = 0ull - ((vV >> ql) & 1ull);
-        const uint64_t md = 0ull - ((vD >> ql) & 1ull);
-        hP ^= hl & mp;
-        uP |= bl & mp;
-        vV ^= pe & mv;
-        hV ^= hl & mv;
-        uV |= bl & mv;
-        vD ^= pe & md;
-        hD ^= hl & md;
-        uD |= bl & md;
-    }
+        const uint32_t pel = (uint32_t)pe, peh = (uint32_t)(pe >> 32);
+        // final: pivot l is reduced by pivots < l only
+        const uint32_t hll = (uint32_t)readlane32((int)hPl, l), hlh = (uint32_t)readlane32((int)hPh, l);
+        const uint64_t bl = 1ull << l;
+        const uint32_t bll = (uint32_t)bl, blh = (uint32_t)(bl >> 32);
+        const int sh = ql & 31;
+        const uint32_t mp = 0u - (((HIQ ? fLh : fLl) >> sh) & 1u);
+        const uint32_t mv = 0u - (((HIQ ? vVh : vVl) >> sh) & 1u);
+        const uint32_t md = 0u - (((HIQ ? vDh : vDl) >> sh) & 1u);
+        hPl ^= hll & mp;
+        hPh ^= hlh & mp;
+        uPl |= bll & mp;
+        uPh |= blh & mp;
+        if (!HIQ) vVl ^= pel & mv;
+        vVh ^= peh & mv;
+        hVl ^= hll & mv;
+        hVh ^= hlh & mv;
+        uVl |= bll & mv;
+        uVh |= blh & mv;
+        if (!HIQ) vDl ^= pel & md;
+        vDh ^= peh & md;
+        hDl ^= hll & md;
+        hDh ^= hlh & md;
+        uDl |= bll & md;
+        uDh |= blh & md;
+    };
+    for (int l = 0; l < nlo; l++) step(l, false);
+    for (int l = nlo; l < rbar; l++) step(l, true);
+    const uint64_t hP = ((uint64_t)hPh << 32) | hPl, uP = ((uint64_t)uPh << 32) | uPl;
+    const uint64_t hV = ((uint64_t)hVh << 32) | hVl, uV = ((uint64_t)uVh << 32) | uVl;
+    const uint64_t hD = ((uint64_t)hDh << 32) | hDl, uD = ((uint64_t)uDh << 32) | uDl;
     PANEL_STAMP(4)
     rec->img_w[lane] = hV;
     rec->img_u[lane] = uV;

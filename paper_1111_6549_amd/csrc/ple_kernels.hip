@@ -88,7 +88,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
                                                           const uint64_t *__restrict__ PBt) {
     __shared__ uint64_t tw[8][256], tu[8][256], tn[8][256], tt[MODE == 2 ? 8 : 1][MODE == 2 ? 256 : 1];
     __shared__ uint64_t simg_w[KW], simg_u[KW], simg_n[KW], spbt[KW];
-    __shared__ int64_t sdisp[KW], sdsrc[KW];
+    __shared__ int64_t sdisp[KW], sdsrc[KW], smaxdisp;
     __shared__ uint64_t sdcoef[KW];
     constexpr bool LA = MODE >= 1;
 
@@ -132,22 +132,53 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
     }
 
     // ---- other rows ----
+    // Every global read that does not depend on another is issued first (this
+    // thread's first row, the pass maps, the pivots' next-stripe words), so
+    // the launch costs about one memory round trip before the table builds.
     const int ndisp = nspec - rbar;
     const bool nxt = LA && sw + 1 < nw;
     const int rt = (MODE == 2 && rect->active) ? rect->rbar : 0;
+    const int64_t nB = (int64_t)gridDim.x - nA;
+    const int64_t row0 = MODE == 2 ? rect->r : r;
+    const int64_t istep = nB * WIDE_THREADS;
+    const int64_t ifirst = row0 + ((int64_t)blockIdx.x - nA) * WIDE_THREADS + tid;
+    // first row: special rows read here are rewritten by group A meanwhile,
+    // but their values are not used (the loop skips them)
+    uint64_t f_sw = 0, f_nx = 0, f_ct = 0;
+    if (ifirst < m) {
+        const uint64_t *row = A + ifirst * ldw;
+        f_sw = row[sw];
+        if (nxt) f_nx = row[sw + 1];
+        if (MODE == 2) f_ct = coefT[ifirst];
+    }
+    uint64_t pn = 0, pct = 0;  // pivot tid's next-stripe word and (MODE 2) pass t coefficient
     if (tid < KW) {
         simg_w[tid] = active ? rec->img_w[tid] : 0ull;
         simg_u[tid] = active ? rec->img_u[tid] : 0ull;
         if (MODE == 2) spbt[tid] = (nxt && tid < rt) ? PBt[(int64_t)tid * ldw + sw + 1] : 0ull;
-    }
-    int64_t maxdisp = -1;
-    if (tid < ndisp) {
-        sdisp[tid] = rec->spec_dst[rbar + tid];
-        sdsrc[tid] = rec->spec_src[rbar + tid];
-        sdcoef[tid] = rec->spec_coef[rbar + tid];
+        // group A leaves the next stripe word of the special rows alone, so
+        // these are the pivots' words there as they stand at the pass start
+        if (nxt && tid < rbar) {
+            const int64_t src = rec->spec_src[tid];
+            pn = A[src * ldw + sw + 1];
+            if (MODE == 2) pct = coefT[src];
+        }
+        int64_t dv = -1;
+        if (tid < ndisp) {
+            dv = rec->spec_dst[rbar + tid];
+            sdisp[tid] = dv;
+            sdsrc[tid] = rec->spec_src[rbar + tid];
+            sdcoef[tid] = rec->spec_coef[rbar + tid];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int64_t ov = __shfl_xor(dv, o);
+            dv = ov > dv ? ov : dv;
+        }
+        if (tid == 0) smaxdisp = dv;
     }
     __syncthreads();
-    for (int d = 0; d < ndisp; d++) maxdisp = sdisp[d] > maxdisp ? sdisp[d] : maxdisp;
+    const int64_t maxdisp = smaxdisp;
     if (MODE == 2) {
         // tables of pass t's update of the next stripe word
         for (int e = tid; e < 8 * 256; e += WIDE_THREADS) {
@@ -160,18 +191,12 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         }
         __syncthreads();
     }
-    // the pivots' words of the next stripe as they stand at the pass start
-    // (group A leaves that column alone); in MODE 2 with pass t's update
+    // the pivots' next-stripe words (in MODE 2 with pass t's update)
     if (nxt && tid < KW) {
-        uint64_t v = 0;
-        if (tid < rbar) {
-            const int64_t src = rec->spec_src[tid];
-            v = A[src * ldw + sw + 1];
-            if (MODE == 2) {
-                const uint64_t ct = coefT[src];
+        uint64_t v = pn;
+        if (MODE == 2 && tid < rbar) {
 #pragma unroll
-                for (int b = 0; b < 8; b++) v ^= tt[b][(ct >> (8 * b)) & 255];
-            }
+            for (int b = 0; b < 8; b++) v ^= tt[b][(pct >> (8 * b)) & 255];
         }
         simg_n[tid] = v;
     }
@@ -191,13 +216,12 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         if (nxt) tn[b][x] = nn;
     }
     __syncthreads();
-    const int64_t nB = (int64_t)gridDim.x - nA;
-    const int64_t row0 = MODE == 2 ? rect->r : r;
-    for (int64_t i = row0 + ((int64_t)blockIdx.x - nA) * WIDE_THREADS + tid; i < m; i += nB * WIDE_THREADS) {
+    for (int64_t i = ifirst; i < m; i += istep) {
         uint64_t *row = A + i * ldw;
+        const bool first = i == ifirst;
         uint64_t ct = 0;
         if (MODE == 2) {
-            ct = coefT[i];
+            ct = first ? f_ct : coefT[i];
             if (i < r) {  // pass t's pivot rows: only its update (the TRSM) is pending
                 coefP[i] = ct;
                 coef[i] = 0;
@@ -205,7 +229,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
                     uint64_t acc = 0;
 #pragma unroll
                     for (int b = 0; b < 8; b++) acc ^= tt[b][(ct >> (8 * b)) & 255];
-                    row[sw + 1] ^= acc;
+                    row[sw + 1] = (first ? f_nx : row[sw + 1]) ^ acc;
                 }
                 continue;
             }
@@ -216,18 +240,17 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
             continue;
         }
         if (i <= maxdisp) {
-            bool disp = false;
-            for (int d = 0; d < ndisp; d++)
-                if (sdisp[d] == i) {
-                    coef[i] = sdcoef[d];
-                    if (MODE == 2) coefP[i] = coefT[sdsrc[d]];
-                    disp = true;
-                    break;
-                }
-            if (disp) continue;
+            // no early exit, so the compares' LDS reads can all be in flight
+            int hit = -1;
+            for (int d = 0; d < ndisp; d++) hit = sdisp[d] == i ? d : hit;
+            if (hit >= 0) {
+                coef[i] = sdcoef[hit];
+                if (MODE == 2) coefP[i] = coefT[sdsrc[hit]];
+                continue;
+            }
         }
         if (MODE == 2) coefP[i] = ct;
-        const uint64_t v = row[sw];
+        const uint64_t v = first ? f_sw : row[sw];
         uint64_t wv = 0;
         if (v) {
             uint64_t u = 0;
@@ -252,7 +275,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
 #pragma unroll
                 for (int b = 0; b < 8; b++) acc ^= tt[b][(ct >> (8 * b)) & 255];
             }
-            row[sw + 1] ^= acc;
+            row[sw + 1] = (first ? f_nx : row[sw + 1]) ^ acc;
         }
     }
 }
@@ -326,6 +349,13 @@ __global__ __launch_bounds__(NT) void k_m4rm_w(uint64_t *__restrict__ C, int64_t
 // they first get it: coefficient coefT[src] of their position then).
 // Tiles of 32 words; 16 lanes per row, two words per lane, 128-bit table
 // reads; 128 KB of tables per block.
+//
+// The panel of pass t + 2 runs inside the same launch, on the last wave of
+// block 0 (raised priority), once the block's tables are built: its stripe
+// word lies left of the words this sweep writes, so the two are independent,
+// and no event between two streams is needed to order them.  That block's
+// row chunk is shortened to the share its other waves can do in the time the
+// other blocks take.
 // ---------------------------------------------------------------------------
 constexpr int PR_TW = 32;
 
@@ -344,23 +374,72 @@ __device__ __forceinline__ void pair_combos(uint64_t (*T)[16][PR_TW], int tid) {
     }
 }
 
-template <int NT, int U, int G>
+// Rows of block `logical`: tile = logical % ntiles, chunk = logical / ntiles.
+// With `short0`, chunk 0 of tile 0 (the block that also runs the panel) gets
+// share (NW - 1) / NW of an even chunk and the tile's other chunks split the
+// rest.
+template <int NW>
+__device__ __forceinline__ bool pair_block_rows(int64_t m, int64_t row0, int ntiles, int nchunks, int logical,
+                                                bool short0, int *tile, int64_t *rb, int64_t *re) {
+    *tile = logical % ntiles;
+    const int chunk = logical / ntiles;
+    if (chunk >= nchunks) return false;
+    const int64_t rows = m - row0;
+    if (short0 && *tile == 0 && nchunks > 1) {
+        const int64_t a = rows * (NW - 1) / ((int64_t)NW * nchunks);
+        if (chunk == 0) {
+            *rb = row0;
+            *re = row0 + a;
+        } else {
+            const int64_t per = (rows - a + nchunks - 2) / (nchunks - 1);
+            *rb = row0 + a + (int64_t)(chunk - 1) * per;
+            *re = *rb + per < m ? *rb + per : m;
+        }
+    } else {
+        const int64_t per = (rows + nchunks - 1) / nchunks;
+        *rb = row0 + (int64_t)chunk * per;
+        *re = *rb + per < m ? *rb + per : m;
+    }
+    return *rb < *re;
+}
+
+template <int NT, int U, int G, bool PF>
 __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int64_t ldc, int64_t m,
                                                   const uint64_t *__restrict__ coefP,
                                                   const uint64_t *__restrict__ coefU,
                                                   const uint64_t *__restrict__ coefT,
                                                   const uint64_t *__restrict__ PBt, const uint64_t *__restrict__ PBu,
                                                   int64_t ldb, int64_t w_begin, int64_t w_end, int ntiles, int nchunks,
-                                                  const PassRec *__restrict__ rect, const PassRec *__restrict__ recu) {
+                                                  const PassRec *__restrict__ rect, const PassRec *__restrict__ recu,
+                                                  PairPanel pp) {
     __shared__ __align__(16) uint64_t T[32][16][PR_TW];
-    const int at = rect->active, au = recu->active;
-    if (!at && !au) return;
-    const int nbt = at ? rect->rbar : 0, nbu = au ? recu->rbar : 0;
-    int tile;
-    int64_t rb, re;
-    if (!m4_block_rows(m, rect->r, ntiles, nchunks, &tile, &rb, &re)) return;
-    const int64_t wt0 = (w_begin & ~(int64_t)(PR_TW - 1)) + (int64_t)tile * PR_TW;
+    __shared__ PanelLdsT<0> PL;
+    constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    const bool panel_here = pp.on && logical == 0;
+    // pass t + 2's panel: after a pair, it first brings the pair's special
+    // rows up to date in its stripe word
+    auto run_panel = [&]() {
+        __builtin_amdgcn_s_setprio(3);
+        PanelFix f;
+        f.mode = 2;
+        f.pt = rect;
+        f.coefT = coefT;
+        f.PBt = PBt;
+        panel_body<2, 0>(C, m, pp.n, ldc, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank, pp.gsv, pp.gsid, PL, tid & 63, f);
+    };
+    const int at = rect->active, au = recu->active;
+    const int nbt = at ? rect->rbar : 0, nbu = au ? recu->rbar : 0;
+    int tile = 0;
+    int64_t rb = 0, re = 0;
+    const bool rows_here =
+        (at || au) && pair_block_rows<NW>(m, rect->r, ntiles, nchunks, logical, pp.on, &tile, &rb, &re);
+    if (!rows_here) {
+        if (panel_here && tid < 64) run_panel();
+        return;
+    }
+    const int64_t wt0 = (w_begin & ~(int64_t)(PR_TW - 1)) + (int64_t)tile * PR_TW;
     for (int e = tid; e < KW * PR_TW; e += NT) {
         const int k = e / PR_TW, wl = e % PR_TW;
         const int64_t w = wt0 + wl;
@@ -390,25 +469,53 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
     __syncthreads();
     pair_combos<16, NT>(T, tid);
     __syncthreads();
+    if (panel_here && tid >= NT - 64) {
+        run_panel();
+        return;
+    }
 
     // rows: every table is read (those past a pass's pivots are zero), so the
     // 32 reads of a row carry no branch and can all be in flight at once
-    constexpr int LPR = PR_TW / 2;  // lanes per row
-    constexpr int RS = NT / LPR;    // rows per step
+    constexpr int LPR = PR_TW / 2;                       // lanes per row
+    const int RS = (panel_here ? NT - 64 : NT) / LPR;  // rows per step
     const int wp = tid % LPR, rs = tid / LPR;
     const int64_t w2 = wt0 + 2 * wp;
     const bool ok0 = w2 >= w_begin && w2 < w_end, ok1 = w2 + 1 >= w_begin && w2 + 1 < w_end;
     const uint32_t tbase = (uint32_t)(2 * wp) * 8u;  // byte offset of this lane's pair of words
+    // PF: the next step's coefficient words are loaded during this step's
+    // lookups, so a step starts with its row loads and lookups at once
+    uint64_t ncp[U], ncu[U];
+    if constexpr (PF) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i = rb + rs + (int64_t)u * RS;
+            ncp[u] = i < re ? coefP[i] : 0ull;
+            ncu[u] = i < re ? coefU[i] : 0ull;
+        }
+    }
     for (int64_t i0 = rb + rs; i0 < re; i0 += (int64_t)RS * U) {
         uint64_t cp[U], cu[U], x0[U], x1[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int64_t i = i0 + (int64_t)u * RS;
-            cp[u] = i < re ? coefP[i] : 0ull;
-            cu[u] = i < re ? coefU[i] : 0ull;
+            if constexpr (PF) {
+                cp[u] = ncp[u];
+                cu[u] = ncu[u];
+            } else {
+                cp[u] = i < re ? coefP[i] : 0ull;
+                cu[u] = i < re ? coefU[i] : 0ull;
+            }
             const bool any = i < re && (cp[u] | cu[u]);
             x0[u] = (any && ok0) ? C[i * ldc + w2] : 0ull;
             x1[u] = (any && ok1) ? C[i * ldc + w2 + 1] : 0ull;
+        }
+        if constexpr (PF) {
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int64_t i = i0 + (int64_t)(U + u) * RS;
+                ncp[u] = i < re ? coefP[i] : 0ull;
+                ncu[u] = i < re ? coefU[i] : 0ull;
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -689,14 +796,25 @@ hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t
     return hipGetLastError();
 }
 
-// Fused update of a pair (t, u): words [sw_t + 3, nw) of rows r_t .. m-1.
+// Fused update of a pair (t, u): words [sw_t + 3, nw) of rows r_t .. m-1,
+// and with pp.on the panel of pass t + 2 (inside the same launch, or alone
+// when no word is left to update).
 hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t ct, const PassRec *rect,
                               const PassRec *recu, const uint64_t *coefP, const uint64_t *coefU,
                               const uint64_t *coefT, const uint64_t *PBt, const uint64_t *PBu, int m4_target,
-                              int pair_variant, hipStream_t s) {
+                              int pair_variant, const PairPanel &pp, hipStream_t s) {
     const int64_t nw = words_for(n);
     const int64_t tw0 = (ct >> 6) + 3;
-    if (tw0 >= nw) return hipSuccess;
+    if (tw0 >= nw) {
+        if (!pp.on) return hipSuccess;
+        PanelFix f;
+        f.mode = 2;
+        f.pt = rect;
+        f.coefT = coefT;
+        f.PBt = PBt;
+        return launch_panel(A, m, n, ldw, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank, pp.gsv, pp.gsid, 2, f, false, s,
+                            nullptr);
+    }
     int64_t rows_est = m - (ct < m ? ct : m);
     if (rows_est < 1) rows_est = 1;
     const int64_t base = tw0 & ~(int64_t)(PR_TW - 1);
@@ -723,17 +841,19 @@ hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, in
     }
     if (nchunks < 1) nchunks = 1;
     ProfScope ps(KID_M4RM, s);
-#define PAIR_LAUNCH(NT, U, G)                                                                                     \
-    hipLaunchKernelGGL((k_m4rm_pair<NT, U, G>), dim3(nt * nchunks), dim3(NT), 0, s, A, ldw, m, coefP, coefU, coefT, \
-                       PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu)
-    // (threads, rows in flight per thread, table reads per group); the
-    // default was the fastest on MI355X for the 65536^2 PLE
+#define PAIR_LAUNCH(NT, U, G, PF)                                                                                 \
+    hipLaunchKernelGGL((k_m4rm_pair<NT, U, G, PF>), dim3(nt * nchunks), dim3(NT), 0, s, A, ldw, m, coefP, coefU,    \
+                       coefT, PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu, pp)
+    // (threads, rows in flight per thread, table reads per group, coefficient
+    // prefetch); the default was the fastest on MI355X for the 65536^2 PLE
     switch (pair_variant) {
-        case 1: PAIR_LAUNCH(1024, 2, 2); break;
-        case 3: PAIR_LAUNCH(1024, 4, 1); break;
-        case 4: PAIR_LAUNCH(1024, 4, 2); break;
-        case 5: PAIR_LAUNCH(1024, 1, 4); break;
-        default: PAIR_LAUNCH(1024, 2, 4); break;
+        case 1: PAIR_LAUNCH(1024, 2, 2, false); break;
+        case 3: PAIR_LAUNCH(1024, 4, 1, false); break;
+        case 4: PAIR_LAUNCH(1024, 4, 2, false); break;
+        case 5: PAIR_LAUNCH(1024, 1, 4, false); break;
+        case 6: PAIR_LAUNCH(1024, 2, 4, true); break;
+        case 7: PAIR_LAUNCH(1024, 1, 4, true); break;
+        default: PAIR_LAUNCH(1024, 2, 4, false); break;
     }
 #undef PAIR_LAUNCH
     return hipGetLastError();

@@ -185,11 +185,8 @@ hipError_t gf2_serve::enqueue(Launch &L) {
     if (L.ids.size() == 1 && !reqs[L.ids[0]]->small) {
         Req &r = *reqs[L.ids[0]];
         uint8_t *p = base + r.off;
-        // serial passes: the session's concurrency comes from overlapping
-        // requests on its streams, and a look-ahead stream per request would
-        // crowd the device's hardware queues
+        // the default pass schedule (fused pairs) stays on this stream
         gf2_ple_opts o{};
-        o.lookahead = 1;
         e = ple_enqueue((uint64_t *)(p + r.a_rel), r.m, r.n, r.ldw, (int64_t *)(p + r.p_rel), (int64_t *)(p + r.q_rel),
                         (int64_t *)(p + r.r_rel), p + r.ws_rel, &o, st, false);
         if (e != hipSuccess) return e;

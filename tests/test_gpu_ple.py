@@ -248,3 +248,25 @@ def test_lookahead_16384_seed2():
     serial = gpu_ple(A, 16384, lookahead=1)
     for mode in (0, 2, 3):
         assert_same_ple(gpu_ple(A, 16384, lookahead=mode), serial, "lookahead=%d" % mode)
+
+
+@pytest.mark.parametrize("variant", list(range(0, 8)))
+def test_pair_variants(variant):
+    """Every schedule of the fused pair update (threads, rows in flight,
+    reads per group, coefficient prefetch; the next panel inside the same
+    launch) gives the oracle's bits, with pairs forced on every pass, on
+    full-rank, rank-deficient and ragged (n not a multiple of the tile)
+    inputs."""
+    say("pair variant", variant)
+    cases = [(1500, 1300, "u"), (2100, 2100, "r"), (700, 2000, "u"), (3000, 1111, "s")]
+    for m, n, kind in cases:
+        if kind == "u":
+            A = inputs.bernoulli(m, n, 25 + m)
+        elif kind == "r":
+            A = inputs.known_rank(m, n, min(m, n) // 3, 7, 8)
+        else:
+            A = inputs.bernoulli(m, n, 26 + m, p=0.02)
+        o = oracle_ple(A, n)
+        for mode in (0, 3):
+            assert_same_ple(gpu_ple(A, n, lookahead=mode, pair_variant=variant), o,
+                            "%dx%d %s lookahead=%d pair_variant=%d" % (m, n, kind, mode, variant))
