@@ -15,7 +15,7 @@ hipError_t launch_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *r
 hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *prev, PassRec *rec,
                         int64_t *P, int64_t *Q, int64_t *rank, uint64_t *gsv, int32_t *gsid, int panel_regs,
                         const PanelFix &fix, bool beside, hipStream_t s, hipEvent_t done);
-hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
+hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, PassRec *rec,
                           uint64_t *coef, uint64_t *PB, int mode, const PassRec *rect, const uint64_t *coefT,
                           uint64_t *coefP, const uint64_t *PBt, hipStream_t s, hipEvent_t done);
 hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t ct, const PassRec *rect,

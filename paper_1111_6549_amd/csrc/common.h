@@ -39,6 +39,9 @@ struct PassRec {
     uint64_t spec_coef[MAX_SPEC];    // w of the row
     uint64_t spec_lbits[MAX_SPEC];   // u of the row (rbar bits, placed at column r)
     uint64_t spec_stripe[MAX_SPEC];  // E part of the stripe word (pivot rows), else 0
+    // look-ahead permutes only: the row's word of the next stripe with the
+    // pass's update (after a pair, both passes'), for the next panel to take
+    uint64_t spec_next[MAX_SPEC];
     uint64_t img_w[KW];  // stripe bit j -> w of a row whose stripe is e_j (linear map)
     uint64_t img_u[KW];  // stripe bit j -> u
 };

@@ -39,75 +39,45 @@ using PanelLds = PanelLdsT<SLOW_LDS_ROWS>;
 // itself has just rewritten some of them (fix_deferred_rows).
 __device__ __forceinline__ uint64_t ld_stripe(const uint64_t *p) { return *(const volatile uint64_t *)p; }
 
-// With the look-ahead, the previous pass's permute leaves the special rows
-// (its pivots and the rows they displaced) unmoved and un-updated in the word
-// that is this pass's stripe: row k goes from position src_k to dst_k and gets
-// the sum of the previous pivots' old words selected by its coefficient word.
-// One wave: read all 128 entries first, then write them.
-__device__ __forceinline__ void fix_deferred_rows(uint64_t *A, int64_t ldw, int64_t sw, const PassRec *pr,
-                                                  const int lane) {
-    const int fr = pr->rbar, fn = pr->nspec;
-    if (!pr->active || fn <= 0) return;
-    const bool h0 = lane < fn, h1 = 64 + lane < fn;
-    const uint64_t o0 = h0 ? ld_stripe(A + pr->spec_src[lane] * ldw + sw) : 0ull;
-    const uint64_t o1 = h1 ? ld_stripe(A + pr->spec_src[64 + lane] * ldw + sw) : 0ull;
-    const uint64_t c0 = h0 ? pr->spec_coef[lane] : 0ull;
-    const uint64_t c1 = h1 ? pr->spec_coef[64 + lane] : 0ull;
-    uint64_t n0 = o0, n1 = o1;
-    for (int b = 0; b < fr; b++) {  // entries 0 .. rbar-1 are the pivots
-        const uint64_t pb = readlane64(o0, b);
-        n0 ^= ((c0 >> b) & 1ull) ? pb : 0ull;
-        n1 ^= ((c1 >> b) & 1ull) ? pb : 0ull;
-    }
-    if (h0) A[pr->spec_dst[lane] * ldw + sw] = n0;
-    if (h1) A[pr->spec_dst[64 + lane] * ldw + sw] = n1;
+// The rows a fix wrote: lane l's entries l and 64 + l (position d, -1 if
+// none, and the new stripe word n).
+struct FixOut {
+    uint64_t n0 = 0, n1 = 0;
+    int64_t d0 = -1, d1 = -1;
+};
+
+__device__ __forceinline__ void fix_wait() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// After a fused pair (t, u = t + 1), u's special rows are unmoved and lack
-// both passes' updates in this stripe word.  Row k (entry k of u's record)
-// first gets pass t's update -- coefficient coefT[src_k], tables of t's
-// staged pivot words PBt -- which also gives u's pivots' words as they stood
-// at u's start; then u's update from those.
-__device__ __forceinline__ void fix_deferred_rows_pair(uint64_t *A, int64_t ldw, int64_t sw, const PassRec *pu,
-                                                       const PassRec *pt, const uint64_t *coefT, const uint64_t *PBt,
-                                                       const int lane) {
-    const int fn = pu->active ? pu->nspec : 0, fr = pu->active ? pu->rbar : 0;
-    if (fn <= 0) return;
-    const int rt = pt->active ? pt->rbar : 0;
+// With the look-ahead, the previous pass's permute leaves the special rows'
+// (its pivots' and the rows they displaced) word of this stripe in place and
+// puts their new values in its record: the panel writes them to their
+// positions.  One wave, entries lane and 64 + lane.  With `wait` the writes
+// are complete on return.
+__device__ __forceinline__ FixOut fix_from_record(uint64_t *A, int64_t ldw, int64_t sw, const PassRec *pr,
+                                                  const int lane, const bool wait) {
+    FixOut o;
+    const int fn = pr->active ? pr->nspec : 0;
+    if (fn <= 0) return o;
     const bool h0 = lane < fn, h1 = 64 + lane < fn;
-    const int64_t s0 = h0 ? pu->spec_src[lane] : 0, s1 = h1 ? pu->spec_src[64 + lane] : 0;
-    uint64_t x0 = h0 ? ld_stripe(A + s0 * ldw + sw) : 0ull;
-    uint64_t x1 = h1 ? ld_stripe(A + s1 * ldw + sw) : 0ull;
-    const uint64_t t0 = h0 ? coefT[s0] : 0ull, t1 = h1 ? coefT[s1] : 0ull;
-    const uint64_t pbt = lane < rt ? PBt[(int64_t)lane * ldw + sw] : 0ull;
-    for (int b = 0; b < rt; b++) {
-        const uint64_t pb = readlane64(pbt, b);
-        x0 ^= ((t0 >> b) & 1ull) ? pb : 0ull;
-        x1 ^= ((t1 >> b) & 1ull) ? pb : 0ull;
-    }
-    const uint64_t c0 = h0 ? pu->spec_coef[lane] : 0ull, c1 = h1 ? pu->spec_coef[64 + lane] : 0ull;
-    uint64_t n0 = x0, n1 = x1;
-    for (int b = 0; b < fr; b++) {  // entries 0 .. rbar-1 are u's pivots
-        const uint64_t ob = readlane64(x0, b);
-        n0 ^= ((c0 >> b) & 1ull) ? ob : 0ull;
-        n1 ^= ((c1 >> b) & 1ull) ? ob : 0ull;
-    }
-    if (h0) A[pu->spec_dst[lane] * ldw + sw] = n0;
-    if (h1) A[pu->spec_dst[64 + lane] * ldw + sw] = n1;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    o.d0 = h0 ? pr->spec_dst[lane] : -1;
+    o.d1 = h1 ? pr->spec_dst[64 + lane] : -1;
+    o.n0 = h0 ? pr->spec_next[lane] : 0ull;
+    o.n1 = h1 ? pr->spec_next[64 + lane] : 0ull;
+    if (h0) A[o.d0 * ldw + sw] = o.n0;
+    if (h1) A[o.d1 * ldw + sw] = o.n1;
+    if (wait) fix_wait();
+    return o;
 }
 
-// What the previous passes left for the panel to finish in its stripe word.
+// What the previous pass left for the panel to finish in its stripe word:
+// mode 1 after a look-ahead permute (the special rows' words are in the
+// previous record).
 struct PanelFix {
-    int mode = 0;                     // 0 nothing, 1 after a look-ahead pass, 2 after a fused pair
-    const PassRec *pt = nullptr;      // mode 2: the pair's first pass
-    const uint64_t *coefT = nullptr;  // mode 2: its coefficient words, by position
-    const uint64_t *PBt = nullptr;    // mode 2: its staged pivot rows (row stride ldw)
+    int mode = 0;
 };
 
 // A panel launched inside a fused pair's update kernel: pass t + 2 on the
@@ -140,9 +110,13 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
 #define PANEL_STAMP(k)
 #endif
     PANEL_STAMP(0)
-    if (fix.mode == 1 && c < n) fix_deferred_rows(A, ldw, c >> 6, prev, lane);
-    if (fix.mode == 2 && c < n) fix_deferred_rows_pair(A, ldw, c >> 6, prev, fix.pt, fix.coefT, fix.PBt, lane);
     const int64_t r = prev->r + prev->rbar;
+    // the two-register window takes the fixed rows into its registers
+    // directly (their stores need not land before the window is read); the
+    // other paths read rows back from A, so the fix completes first
+    const bool patch = WQ == 2 && fix.mode != 0 && r < m && c < n;
+    auto run_fix = [&](const bool wait) -> FixOut { return fix_from_record(A, ldw, c >> 6, prev, lane, wait); };
+    if (fix.mode != 0 && c < n && !patch) run_fix(true);
     if (r >= m || c >= n) {
         if (lane == 0) {
             rec->r = r;
@@ -182,8 +156,30 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
         {
             const int64_t row0 = r + (lane < rows ? lane : rows - 1);
             const int64_t row1 = r + (64 + lane < rows ? 64 + lane : rows - 1);
-            const uint64_t t0 = ld_stripe(A + row0 * ldw + sw);
-            const uint64_t t1 = ld_stripe(A + row1 * ldw + sw);
+            uint64_t t0 = ld_stripe(A + row0 * ldw + sw);
+            uint64_t t1 = ld_stripe(A + row1 * ldw + sw);
+            if (patch) {
+                // the previous pass(es)' special rows in the window: their
+                // loaded words are stale, the fix's new words replace them
+                const FixOut fo = run_fix(false);
+                volatile int64_t *pf = L.src;
+                volatile uint64_t *pw = (volatile uint64_t *)L.dst;
+                pf[lane] = -1;
+                pf[64 + lane] = -1;
+                __builtin_amdgcn_wave_barrier();
+                if (fo.d0 >= r && fo.d0 < r + 128) {
+                    pw[fo.d0 - r] = fo.n0;
+                    pf[fo.d0 - r] = 1;
+                }
+                if (fo.d1 >= r && fo.d1 < r + 128) {
+                    pw[fo.d1 - r] = fo.n1;
+                    pf[fo.d1 - r] = 1;
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (pf[lane] >= 0) t0 = pw[lane];
+                if (pf[64 + lane] >= 0) t1 = pw[64 + lane];
+                __builtin_amdgcn_wave_barrier();
+            }
             const uint64_t v0 = lane < nmax ? (t0 & kmask) : 0ull;
             const uint64_t v1 = 64 + lane < nmax ? (t1 & kmask) : 0ull;
             x0l = (uint32_t)v0;
@@ -402,6 +398,7 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
 
     // ---- slow path: every remaining row, window in LDS or workspace ---------
     if (slow) {
+        if (patch) fix_wait();  // the fix's stores, before every row is read back
         npiv = 0;
         my_q = 0;
         my_fin = 0;
@@ -492,6 +489,7 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
     // displaced rows (lane d <-> special entry rbar + d): their stripe words as
     // they were when the pass began
     uint64_t vD = 0;
+    if (patch) fix_wait();  // long since complete: the fix's stores precede these reads
     if (lane < ndisp) vD = ld_stripe(A + L.src[rbar + lane] * ldw + sw) & kmask;
     // 32-bit halves throughout: every update below is one three-input logic
     // instruction per half

@@ -68,9 +68,11 @@ __global__ __launch_bounds__(64) void k_panel(uint64_t *A, int64_t m, int64_t n,
 //                   write all, so the permutation is applied in place);
 //   blocks [nA, ..): grid-stride over the other rows.
 // MODE 0: serial pass loop.
-// MODE 1: look-ahead.  The special rows' next stripe word (sw + 1) is left
-//         for the next panel; the other rows' next stripe word gets the
-//         pass's update here (tables of the pivots' old words at sw + 1).
+// MODE 1: look-ahead.  The special rows' next stripe word (sw + 1) stays in
+//         place: its new value goes to the record (spec_next, from the first
+//         row block) for the next panel, which reads that column meanwhile;
+//         the other rows' next stripe word gets the pass's update here
+//         (tables of the pivots' old words at sw + 1).
 // MODE 2: second pass u of a fused pair (t, u = t + 1): as MODE 1, and pass
 //         t's update is still pending on every word right of sw for the rows
 //         from r_t on: its coefficient words (coefT, by position before this
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(64) void k_panel(uint64_t *A, int64_t m, int64_t n,
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__ A, int64_t m, int64_t ldw, int64_t c,
-                                                          const PassRec *__restrict__ rec, uint64_t *__restrict__ coef,
+                                                          PassRec *__restrict__ rec, uint64_t *__restrict__ coef,
                                                           uint64_t *__restrict__ PB, int nA, int64_t nw,
                                                           const PassRec *__restrict__ rect,
                                                           const uint64_t *__restrict__ coefT,
@@ -152,6 +154,15 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         if (MODE == 2) f_ct = coefT[ifirst];
     }
     uint64_t pn = 0, pct = 0;  // pivot tid's next-stripe word and (MODE 2) pass t coefficient
+    // the first row block also finishes the special rows' next-stripe words
+    const bool spec_blk = nxt && (int)blockIdx.x == nA;
+    uint64_t so = 0, sct = 0, scf = 0;  // special row tid: old next-stripe word, pass t and own coefficients
+    if (spec_blk && tid < nspec) {
+        const int64_t src = rec->spec_src[tid];
+        so = A[src * ldw + sw + 1];
+        if (MODE == 2) sct = coefT[src];
+        scf = rec->spec_coef[tid];
+    }
     if (tid < KW) {
         simg_w[tid] = active ? rec->img_w[tid] : 0ull;
         simg_u[tid] = active ? rec->img_u[tid] : 0ull;
@@ -216,6 +227,18 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         if (nxt) tn[b][x] = nn;
     }
     __syncthreads();
+    if (spec_blk && tid < nspec) {
+        // old word, then (MODE 2) pass t's update, then this pass's: the
+        // pivots' words in tn already carry pass t's update
+        uint64_t v = so;
+        if (MODE == 2) {
+#pragma unroll
+            for (int b = 0; b < 8; b++) v ^= tt[b][(sct >> (8 * b)) & 255];
+        }
+#pragma unroll
+        for (int b = 0; b < 8; b++) v ^= tn[b][(scf >> (8 * b)) & 255];
+        rec->spec_next[tid] = v;
+    }
     for (int64_t i = ifirst; i < m; i += istep) {
         uint64_t *row = A + i * ldw;
         const bool first = i == ifirst;
@@ -418,15 +441,12 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
     const int tid = threadIdx.x;
     const int logical = xcd_logical(blockIdx.x, gridDim.x);
     const bool panel_here = pp.on && logical == 0;
-    // pass t + 2's panel: after a pair, it first brings the pair's special
-    // rows up to date in its stripe word
+    // pass t + 2's panel: the pair's special rows' words in its stripe come
+    // from the second pass's record
     auto run_panel = [&]() {
         __builtin_amdgcn_s_setprio(3);
         PanelFix f;
-        f.mode = 2;
-        f.pt = rect;
-        f.coefT = coefT;
-        f.PBt = PBt;
+        f.mode = 1;
         panel_body<2, 0>(C, m, pp.n, ldc, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank, pp.gsv, pp.gsid, PL, tid & 63, f);
     };
     const int at = rect->active, au = recu->active;
@@ -755,7 +775,7 @@ hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, const PassRec *rec,
+hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, PassRec *rec,
                           uint64_t *coef, uint64_t *PB, int mode, const PassRec *rect, const uint64_t *coefT,
                           uint64_t *coefP, const uint64_t *PBt, hipStream_t s, hipEvent_t done) {
     const int nA = (int)((ldw + 63) / 64);
@@ -808,10 +828,7 @@ hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, in
     if (tw0 >= nw) {
         if (!pp.on) return hipSuccess;
         PanelFix f;
-        f.mode = 2;
-        f.pt = rect;
-        f.coefT = coefT;
-        f.PBt = PBt;
+        f.mode = 1;
         return launch_panel(A, m, n, ldw, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank, pp.gsv, pp.gsid, 2, f, false, s,
                             nullptr);
     }
