@@ -85,6 +85,8 @@ struct PanelFix {
 // previous one).
 struct PairPanel {
     int on = 0;
+    int share = 65536;  // block 0's row share relative to the others, in 1/65536
+
     int64_t n = 0, c = 0;
     PassRec *rec = nullptr;
     int64_t *P = nullptr, *Q = nullptr, *rank = nullptr;
@@ -244,7 +246,8 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
             my_q = sn ? j : my_q;
             my_p = sn ? (in0 ? lf : 64 + lf) : my_p;
             act0 &= ~nbit;
-            npiv += (int)((m0 | m1) != 0);
+            const uint64_t any = m0 | m1;
+            npiv += (int)((any | (0ull - any)) >> 63);  // 1 iff a pivot was found, on the scalar unit
             return npiv < rows_i;
         };
         const int klo = kp < 32 ? kp : 32;

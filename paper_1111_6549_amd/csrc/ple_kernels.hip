@@ -399,17 +399,15 @@ __device__ __forceinline__ void pair_combos(uint64_t (*T)[16][PR_TW], int tid) {
 
 // Rows of block `logical`: tile = logical % ntiles, chunk = logical / ntiles.
 // With `short0`, chunk 0 of tile 0 (the block that also runs the panel) gets
-// share (NW - 1) / NW of an even chunk and the tile's other chunks split the
-// rest.
-template <int NW>
+// share / 65536 of an even chunk and the tile's other chunks split the rest.
 __device__ __forceinline__ bool pair_block_rows(int64_t m, int64_t row0, int ntiles, int nchunks, int logical,
-                                                bool short0, int *tile, int64_t *rb, int64_t *re) {
+                                                bool short0, int share, int *tile, int64_t *rb, int64_t *re) {
     *tile = logical % ntiles;
     const int chunk = logical / ntiles;
     if (chunk >= nchunks) return false;
     const int64_t rows = m - row0;
     if (short0 && *tile == 0 && nchunks > 1) {
-        const int64_t a = rows * (NW - 1) / ((int64_t)NW * nchunks);
+        const int64_t a = rows * share / (65536 * (int64_t)nchunks);
         if (chunk == 0) {
             *rb = row0;
             *re = row0 + a;
@@ -437,7 +435,6 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
                                                   PairPanel pp) {
     __shared__ __align__(16) uint64_t T[32][16][PR_TW];
     __shared__ PanelLdsT<0> PL;
-    constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
     const int logical = xcd_logical(blockIdx.x, gridDim.x);
     const bool panel_here = pp.on && logical == 0;
@@ -454,7 +451,7 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
     int tile = 0;
     int64_t rb = 0, re = 0;
     const bool rows_here =
-        (at || au) && pair_block_rows<NW>(m, rect->r, ntiles, nchunks, logical, pp.on, &tile, &rb, &re);
+        (at || au) && pair_block_rows(m, rect->r, ntiles, nchunks, logical, pp.on, pp.share, &tile, &rb, &re);
     if (!rows_here) {
         if (panel_here && tid < 64) run_panel();
         return;
@@ -857,10 +854,19 @@ hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, in
         }
     }
     if (nchunks < 1) nchunks = 1;
+    // block 0 (16 waves) loses its panel wave for about the panel's time: its share of a
+    // chunk is the rest (about 25 us of panel against an update streaming
+    // its bytes at about 3.3 TB/s)
+    PairPanel ppl = pp;
+    if (pp.on) {
+        const double upd_us = (double)rows_est * (double)(nw - tw0) * 16.0 / 3.3e6;
+        const double busy = upd_us > 0.0 ? (25.0 / upd_us < 1.0 ? 25.0 / upd_us : 1.0) : 1.0;
+        ppl.share = (int)(65536.0 * (16.0 - busy) / 16.0);
+    }
     ProfScope ps(KID_M4RM, s);
 #define PAIR_LAUNCH(NT, U, G, PF)                                                                                 \
     hipLaunchKernelGGL((k_m4rm_pair<NT, U, G, PF>), dim3(nt * nchunks), dim3(NT), 0, s, A, ldw, m, coefP, coefU,    \
-                       coefT, PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu, pp)
+                       coefT, PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu, ppl)
     // (threads, rows in flight per thread, table reads per group, coefficient
     // prefetch); the default was the fastest on MI355X for the 65536^2 PLE
     switch (pair_variant) {
@@ -868,9 +874,11 @@ hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, in
         case 3: PAIR_LAUNCH(1024, 4, 1, false); break;
         case 4: PAIR_LAUNCH(1024, 4, 2, false); break;
         case 5: PAIR_LAUNCH(1024, 1, 4, false); break;
+        case 2: PAIR_LAUNCH(1024, 2, 4, false); break;
         case 6: PAIR_LAUNCH(1024, 2, 4, true); break;
-        case 7: PAIR_LAUNCH(1024, 1, 4, true); break;
-        default: PAIR_LAUNCH(1024, 2, 4, false); break;
+        case 8: PAIR_LAUNCH(1024, 1, 8, true); break;
+        case 9: PAIR_LAUNCH(1024, 1, 2, true); break;
+        default: PAIR_LAUNCH(1024, 1, 4, true); break;
     }
 #undef PAIR_LAUNCH
     return hipGetLastError();
