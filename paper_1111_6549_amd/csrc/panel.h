@@ -193,68 +193,98 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
         int id0 = lane, id1 = 64 + lane;  // original position of the row each lane holds
         uint64_t act0 = nmax >= 64 ? ~0ull : ((1ull << nmax) - 1ull);
         uint64_t act1 = nmax >= 128 ? ~0ull : (nmax <= 64 ? 0ull : ((1ull << (nmax - 64)) - 1ull));
-        const int rows_i = rows < 4096 ? (int)rows : 4096;  // npiv stays below 65
-        // one column: HI selects the half that holds bit j; returns false to
-        // leave the loop.  A column without a pivot in the window is a no-op
-        // (all masks empty) unless rows past the window remain.
-        auto column = [&](const int j, const bool HI) -> bool {
-            const uint32_t bj = 1u << (j & 31);
-            const uint64_t m0 = __ballot(((HI ? x0h : x0l) & bj) != 0) & act0;
-            const uint64_t m1 = __ballot(((HI ? x1h : x1l) & bj) != 0) & act1;
-            const bool none = !(m0 | m1);
-            if (none && nmax < rows) {  // a row outside the window may hold the pivot
-                slow = true;
-                return false;
-            }
-            const bool in0 = m0 != 0;
-            const int f0 = m0 ? (int)__builtin_ctzll(m0) : 0;
-            const int f1 = m1 ? (int)__builtin_ctzll(m1) : 0;
-            const int lf = in0 ? f0 : f1;
-            // the pivot row and the row at npiv, as they stand
-            const uint32_t a0l = (uint32_t)readlane32((int)x0l, lf), a0h = (uint32_t)readlane32((int)x0h, lf);
-            const uint32_t a1l = (uint32_t)readlane32((int)x1l, lf), a1h = (uint32_t)readlane32((int)x1h, lf);
-            const int ia0 = readlane32(id0, lf), ia1 = readlane32(id1, lf);
-            const uint32_t pvl = in0 ? a0l : a1l, pvh = in0 ? a0h : a1h;
-            const int idp = in0 ? ia0 : ia1;
-            const uint32_t vrl = (uint32_t)readlane32((int)x0l, npiv), vrh = (uint32_t)readlane32((int)x0h, npiv);
-            const int idr = readlane32(id0, npiv);
-            // the pivot's part strictly above column j
-            const uint32_t pel = HI ? 0u : (j == 31 ? 0u : pvl & (~0u << (j + 1)));
-            const uint32_t peh = HI ? (j == 63 ? 0u : pvh & (~0u << ((j & 31) + 1))) : pvh;
-            const uint64_t lbit = none ? 0ull : 1ull << lf, nbit = none ? 0ull : 1ull << npiv;
-            const uint64_t f0m = in0 ? lbit : 0ull, f1m = in0 ? 0ull : lbit;
-            const bool e0 = __builtin_amdgcn_inverse_ballot_w64(m0 & ~f0m);
-            const bool e1 = __builtin_amdgcn_inverse_ballot_w64(m1 & ~f1m);
-            const bool s0 = __builtin_amdgcn_inverse_ballot_w64(f0m);
-            const bool s1 = __builtin_amdgcn_inverse_ballot_w64(f1m);
-            const bool sn = __builtin_amdgcn_inverse_ballot_w64(nbit);
-            if (!HI) {
-                x0l = e0 ? x0l ^ pel : x0l;
-                x1l = e1 ? x1l ^ pel : x1l;
-            }
-            x0h = e0 ? x0h ^ peh : x0h;
-            x1h = e1 ? x1h ^ peh : x1h;
-            x0l = s0 ? vrl : x0l;
-            x0h = s0 ? vrh : x0h;
-            x1l = s1 ? vrl : x1l;
-            x1h = s1 ? vrh : x1h;
-            id0 = s0 ? idr : id0;
-            id1 = s1 ? idr : id1;
-            x0l = sn ? pvl : x0l;
-            x0h = sn ? pvh : x0h;
-            id0 = sn ? idp : id0;
-            my_q = sn ? j : my_q;
-            my_p = sn ? (in0 ? lf : 64 + lf) : my_p;
-            act0 &= ~nbit;
-            const uint64_t any = m0 | m1;
-            npiv += (int)((any | (0ull - any)) >> 63);  // 1 iff a pivot was found, on the scalar unit
-            return npiv < rows_i;
-        };
-        const int klo = kp < 32 ? kp : 32;
+        int my_qp = 0;  // pivot column | (window position where it was found) << 8
+        // Columns [jb, je) of one half (HI: the high half holds their bits).
+        // The inner loop takes the usual column, whose pivot is in register
+        // 0, without a branch; a column with no candidate in register 0
+        // leaves it for the general step (pivot in register 1, no pivot, or
+        // rows past the window).  Once every row is a pivot, the candidate
+        // masks are empty and the remaining columns cost a ballot each.
         bool go = true;
-        for (int j = 0; j < klo && go; j++) go = column(j, false);
-        for (int j = 32; j < kp && go; j++) go = column(j, true);
+        auto run = [&](const int jb, const int je, const bool HI) {
+            int j = jb;
+            while (j < je && go) {
+                for (; j < je; j++) {
+                    const uint32_t bj = 1u << (j & 31);
+                    const uint64_t m0 = __ballot(((HI ? x0h : x0l) & bj) != 0) & act0;
+                    if (!m0) break;
+                    const uint64_t m1 = __ballot(((HI ? x1h : x1l) & bj) != 0) & act1;
+                    const int lf = (int)__builtin_ctzll(m0);
+                    const uint32_t pvl = (uint32_t)readlane32((int)x0l, lf), pvh = (uint32_t)readlane32((int)x0h, lf);
+                    const int idp = readlane32(id0, lf);
+                    const uint32_t vrl = (uint32_t)readlane32((int)x0l, npiv);
+                    const uint32_t vrh = (uint32_t)readlane32((int)x0h, npiv);
+                    const int idr = readlane32(id0, npiv);
+                    // the pivot's part strictly above column j leaves the other
+                    // rows that have the bit
+                    const uint32_t pel = HI ? 0u : (j == 31 ? 0u : pvl & (~0u << (j + 1)));
+                    const uint32_t peh = HI ? (j == 63 ? 0u : pvh & (~0u << ((j & 31) + 1))) : pvh;
+                    const uint64_t lbit = 1ull << lf, nbit = 1ull << npiv;
+                    const bool e0 = __builtin_amdgcn_inverse_ballot_w64(m0 & ~lbit);
+                    const bool e1 = __builtin_amdgcn_inverse_ballot_w64(m1);
+                    if (!HI) {
+                        x0l = e0 ? x0l ^ pel : x0l;
+                        x1l = e1 ? x1l ^ pel : x1l;
+                    }
+                    x0h = e0 ? x0h ^ peh : x0h;
+                    x1h = e1 ? x1h ^ peh : x1h;
+                    // the row at npiv to the pivot's place, the pivot to npiv
+                    const bool s0 = __builtin_amdgcn_inverse_ballot_w64(lbit);
+                    x0l = s0 ? vrl : x0l;
+                    x0h = s0 ? vrh : x0h;
+                    id0 = s0 ? idr : id0;
+                    const bool sn = __builtin_amdgcn_inverse_ballot_w64(nbit);
+                    x0l = sn ? pvl : x0l;
+                    x0h = sn ? pvh : x0h;
+                    id0 = sn ? idp : id0;
+                    my_qp = sn ? (j | (lf << 8)) : my_qp;
+                    act0 &= ~nbit;
+                    npiv++;
+                }
+                if (j >= je) return;
+                // general step for column j: no candidate in register 0
+                const uint32_t bj = 1u << (j & 31);
+                const uint64_t m1 = __ballot(((HI ? x1h : x1l) & bj) != 0) & act1;
+                if (!m1) {
+                    if (nmax < rows) {  // a row outside the window may hold the pivot
+                        slow = true;
+                        go = false;
+                        return;
+                    }
+                    j++;  // column j has no pivot
+                    continue;
+                }
+                const int lf = (int)__builtin_ctzll(m1);
+                const uint32_t pvl = (uint32_t)readlane32((int)x1l, lf), pvh = (uint32_t)readlane32((int)x1h, lf);
+                const int idp = readlane32(id1, lf);
+                const uint32_t vrl = (uint32_t)readlane32((int)x0l, npiv);
+                const uint32_t vrh = (uint32_t)readlane32((int)x0h, npiv);
+                const int idr = readlane32(id0, npiv);
+                const uint32_t pel = HI ? 0u : (j == 31 ? 0u : pvl & (~0u << (j + 1)));
+                const uint32_t peh = HI ? (j == 63 ? 0u : pvh & (~0u << ((j & 31) + 1))) : pvh;
+                const uint64_t lbit = 1ull << lf, nbit = 1ull << npiv;
+                const bool e1 = __builtin_amdgcn_inverse_ballot_w64(m1 & ~lbit);
+                if (!HI) x1l = e1 ? x1l ^ pel : x1l;
+                x1h = e1 ? x1h ^ peh : x1h;
+                const bool s1 = __builtin_amdgcn_inverse_ballot_w64(lbit);
+                x1l = s1 ? vrl : x1l;
+                x1h = s1 ? vrh : x1h;
+                id1 = s1 ? idr : id1;
+                const bool sn = __builtin_amdgcn_inverse_ballot_w64(nbit);
+                x0l = sn ? pvl : x0l;
+                x0h = sn ? pvh : x0h;
+                id0 = sn ? idp : id0;
+                my_qp = sn ? (j | ((64 + lf) << 8)) : my_qp;
+                act0 &= ~nbit;
+                npiv++;
+                j++;
+            }
+        };
+        run(0, kp < 32 ? kp : 32, false);
+        if (go && kp > 32) run(32, kp, true);
         my_fin = lane < npiv ? (((uint64_t)x0h << 32) | x0l) : 0ull;
+        my_q = my_qp & 255;
+        my_p = my_qp >> 8;
         npiv = uni(npiv);
         PANEL_STAMP(2)
         if (!slow) {
@@ -514,37 +544,45 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
     const uint32_t fLl = (uint32_t)finL, fLh = (uint32_t)(finL >> 32);
     // pivot columns increase with l: those in the low half come first
     const int nlo = __popcll(__ballot(lane < rbar && my_q < 32));
-    auto step = [&](const int l, const bool HIQ) {
+    // HIQ: pivot column ql >= 32; HIL: pivot index l >= 32 (its L bit in the
+    // high half).  Both are fixed per loop, so each update touches only the
+    // halves that can change.
+    auto step = [&](const int l, const bool HIQ, const bool HIL) {
         const int ql = readlane32(my_q, l);
         const uint64_t pe = readlane64(my_fin, l) & above(ql);
         const uint32_t pel = (uint32_t)pe, peh = (uint32_t)(pe >> 32);
         // final: pivot l is reduced by pivots < l only
         const uint32_t hll = (uint32_t)readlane32((int)hPl, l), hlh = (uint32_t)readlane32((int)hPh, l);
-        const uint64_t bl = 1ull << l;
-        const uint32_t bll = (uint32_t)bl, blh = (uint32_t)(bl >> 32);
+        const uint32_t bl = 1u << (l & 31);
         const int sh = ql & 31;
-        const uint32_t mp = 0u - (((HIQ ? fLh : fLl) >> sh) & 1u);
-        const uint32_t mv = 0u - (((HIQ ? vVh : vVl) >> sh) & 1u);
-        const uint32_t md = 0u - (((HIQ ? vDh : vDl) >> sh) & 1u);
+        const uint32_t mp = (uint32_t)__builtin_amdgcn_sbfe((int)(HIQ ? fLh : fLl), sh, 1);
+        const uint32_t mv = (uint32_t)__builtin_amdgcn_sbfe((int)(HIQ ? vVh : vVl), sh, 1);
+        const uint32_t md = (uint32_t)__builtin_amdgcn_sbfe((int)(HIQ ? vDh : vDl), sh, 1);
         hPl ^= hll & mp;
         hPh ^= hlh & mp;
-        uPl |= bll & mp;
-        uPh |= blh & mp;
         if (!HIQ) vVl ^= pel & mv;
         vVh ^= peh & mv;
         hVl ^= hll & mv;
         hVh ^= hlh & mv;
-        uVl |= bll & mv;
-        uVh |= blh & mv;
         if (!HIQ) vDl ^= pel & md;
         vDh ^= peh & md;
         hDl ^= hll & md;
         hDh ^= hlh & md;
-        uDl |= bll & md;
-        uDh |= blh & md;
+        if (HIL) {
+            uPh |= bl & mp;
+            uVh |= bl & mv;
+            uDh |= bl & md;
+        } else {
+            uPl |= bl & mp;
+            uVl |= bl & mv;
+            uDl |= bl & md;
+        }
     };
-    for (int l = 0; l < nlo; l++) step(l, false);
-    for (int l = nlo; l < rbar; l++) step(l, true);
+    const int l32 = rbar < 32 ? rbar : 32;
+    const int e1 = nlo < l32 ? nlo : l32;
+    for (int l = 0; l < e1; l++) step(l, false, false);       // column < 32 implies l < 32
+    for (int l = e1; l < l32; l++) step(l, true, false);
+    for (int l = l32 > nlo ? l32 : nlo; l < rbar; l++) step(l, true, true);
     const uint64_t hP = ((uint64_t)hPh << 32) | hPl, uP = ((uint64_t)uPh << 32) | uPl;
     const uint64_t hV = ((uint64_t)hVh << 32) | hVl, uV = ((uint64_t)uVh << 32) | uVl;
     const uint64_t hD = ((uint64_t)hDh << 32) | hDl, uD = ((uint64_t)uDh << 32) | uDl;
