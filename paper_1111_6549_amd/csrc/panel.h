@@ -204,10 +204,11 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
         auto run = [&](const int jb, const int je, const bool HI) {
             int j = jb;
             while (j < je && go) {
-                for (; j < je; j++) {
+                // one exit: m0 is empty when column j has no candidate in
+                // register 0 or j reaches je
+                uint64_t m0 = __ballot(((HI ? x0h : x0l) & (1u << (j & 31))) != 0) & act0;
+                while (m0) {
                     const uint32_t bj = 1u << (j & 31);
-                    const uint64_t m0 = __ballot(((HI ? x0h : x0l) & bj) != 0) & act0;
-                    if (!m0) break;
                     const uint64_t m1 = __ballot(((HI ? x1h : x1l) & bj) != 0) & act1;
                     const int lf = (int)__builtin_ctzll(m0);
                     const uint32_t pvl = (uint32_t)readlane32((int)x0l, lf), pvh = (uint32_t)readlane32((int)x0h, lf);
@@ -240,6 +241,9 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                     my_qp = sn ? (j | (lf << 8)) : my_qp;
                     act0 &= ~nbit;
                     npiv++;
+                    j++;
+                    const uint64_t nx = __ballot(((HI ? x0h : x0l) & (1u << (j & 31))) != 0) & act0;
+                    m0 = j < je ? nx : 0ull;
                 }
                 if (j >= je) return;
                 // general step for column j: no candidate in register 0
