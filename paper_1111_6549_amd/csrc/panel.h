@@ -551,14 +551,17 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
     // HIQ: pivot column ql >= 32; HIL: pivot index l >= 32 (its L bit in the
     // high half).  Both are fixed per loop, so each update touches only the
     // halves that can change.
+    // per pivot (lane): its part above its column and its bit offset in its half
+    const uint64_t pe_lane = lane < rbar ? my_fin & above(my_q) : 0ull;
+    const uint32_t pe_lo = (uint32_t)pe_lane, pe_hi = (uint32_t)(pe_lane >> 32);
+    const int qs_lane = my_q & 31;
     auto step = [&](const int l, const bool HIQ, const bool HIL) {
-        const int ql = readlane32(my_q, l);
-        const uint64_t pe = readlane64(my_fin, l) & above(ql);
-        const uint32_t pel = (uint32_t)pe, peh = (uint32_t)(pe >> 32);
+        const uint32_t pel = HIQ ? 0u : (uint32_t)readlane32((int)pe_lo, l);
+        const uint32_t peh = (uint32_t)readlane32((int)pe_hi, l);
         // final: pivot l is reduced by pivots < l only
         const uint32_t hll = (uint32_t)readlane32((int)hPl, l), hlh = (uint32_t)readlane32((int)hPh, l);
         const uint32_t bl = 1u << (l & 31);
-        const int sh = ql & 31;
+        const int sh = readlane32(qs_lane, l);
         const uint32_t mp = (uint32_t)__builtin_amdgcn_sbfe((int)(HIQ ? fLh : fLl), sh, 1);
         const uint32_t mv = (uint32_t)__builtin_amdgcn_sbfe((int)(HIQ ? vVh : vVl), sh, 1);
         const uint32_t md = (uint32_t)__builtin_amdgcn_sbfe((int)(HIQ ? vDh : vDl), sh, 1);
