@@ -56,7 +56,7 @@ typedef struct gf2_ple_opts {
                               inside that update) while rows remain below the stripe, then serial passes;
                               1 = serial passes only; 2 = look-ahead on every pass (next panel on a second
                               stream beside the update), no pairs; 3 = pairs on every pass */
-    int32_t pair_variant;  /* schedule of the fused pair update: 0 = default; 1..9 = a fixed (threads, rows in
+    int32_t pair_variant;  /* schedule of the fused pair update: 0 = default; 1..12 = a fixed (threads, rows in
                               flight, table reads per group, coefficient prefetch) */
 } gf2_ple_opts;
 

@@ -377,7 +377,7 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
     if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
         return GF2_EINVAL;
     if (opts && (opts->lookahead < 0 || opts->lookahead > 3)) return GF2_EINVAL;
-    if (opts && (opts->pair_variant < 0 || opts->pair_variant > 9)) return GF2_EINVAL;
+    if (opts && (opts->pair_variant < 0 || opts->pair_variant > 12)) return GF2_EINVAL;
     if (opts && opts->update == 2) return GF2_EINVAL;  // MFMA trailing update: see gf2_addmul
     const PleLayout L = ple_layout(m, ldw);
     if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;

@@ -424,7 +424,7 @@ __device__ __forceinline__ bool pair_block_rows(int64_t m, int64_t row0, int nti
     return *rb < *re;
 }
 
-template <int NT, int U, int G, bool PF>
+template <int NT, int U, int G, bool PF, bool RP = false>
 __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int64_t ldc, int64_t m,
                                                   const uint64_t *__restrict__ coefP,
                                                   const uint64_t *__restrict__ coefU,
@@ -499,6 +499,76 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
     const int64_t w2 = wt0 + 2 * wp;
     const bool ok0 = w2 >= w_begin && w2 < w_end, ok1 = w2 + 1 >= w_begin && w2 + 1 < w_end;
     const uint32_t tbase = (uint32_t)(2 * wp) * 8u;  // byte offset of this lane's pair of words
+    // a lane's two words are 16-byte aligned when the row stride is even
+    // (tiles start at even words): then they move as one 16-byte access
+    const bool wide = (ldc & 1) == 0 && ((uintptr_t)C & 15) == 0;
+    // a row's words: one 16-byte access when aligned, else two
+    auto load_row = [&](const int64_t i, const bool on, uint64_t &v0, uint64_t &v1) {
+        if (wide && on && ok0 && ok1) {
+            const ulonglong2 v = *(const ulonglong2 *)(C + i * ldc + w2);
+            v0 = v.x;
+            v1 = v.y;
+        } else {
+            v0 = (on && ok0) ? C[i * ldc + w2] : 0ull;
+            v1 = (on && ok1) ? C[i * ldc + w2 + 1] : 0ull;
+        }
+    };
+    if constexpr (RP) {
+        // two steps in flight: the next step's coefficient words and row
+        // words load while this step's tables are read
+        static_assert(U == 1, "row prefetch keeps one row per step");
+        int64_t i = rb + rs;
+        uint64_t ncp1 = i < re ? coefP[i] : 0ull, ncu1 = i < re ? coefU[i] : 0ull, nx0 = 0, nx1 = 0;
+        load_row(i, i < re, nx0, nx1);
+        for (; i < re; i += RS) {
+            const uint64_t cp = ncp1, cu = ncu1, x0 = nx0, x1 = nx1;
+            const int64_t in = i + RS;
+            ncp1 = in < re ? coefP[in] : 0ull;
+            ncu1 = in < re ? coefU[in] : 0ull;
+            load_row(in, in < re, nx0, nx1);
+            const uint32_t h[4] = {(uint32_t)cp, (uint32_t)(cp >> 32), (uint32_t)cu, (uint32_t)(cu >> 32)};
+            uint64_t a0 = 0, a1 = 0;
+#pragma unroll
+            for (int g = 0; g < 32; g += G) {
+                ulonglong2 t[G];
+#pragma unroll
+                for (int j = 0; j < G; j++) {
+                    const int q = g + j;
+                    const uint32_t nib = (h[q >> 3] >> (4 * (q & 7))) & 15u;
+                    t[j] = *(const ulonglong2 *)((const char *)&T[0][0][0] + tbase +
+                                                 ((uint32_t)q * 16u + nib) * (uint32_t)(PR_TW * 8));
+                }
+                if constexpr (G % 2 == 0) {
+#pragma unroll
+                    for (int j = 0; j < G; j += 2) {
+                        a0 = xor3_64(a0, t[j].x, t[j + 1].x);
+                        a1 = xor3_64(a1, t[j].y, t[j + 1].y);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < G; j++) {
+                        a0 ^= t[j].x;
+                        a1 ^= t[j].y;
+                    }
+                }
+                // materialise the partial sums here: otherwise the xor chain is
+                // reassociated into one tree that keeps all 32 reads live
+                __asm__ volatile("" : "+v"(a0), "+v"(a1));
+            }
+            if (cp | cu) {
+                if (wide && ok0 && ok1) {
+                    ulonglong2 v;
+                    v.x = x0 ^ a0;
+                    v.y = x1 ^ a1;
+                    *(ulonglong2 *)(C + i * ldc + w2) = v;
+                } else {
+                    if (ok0) C[i * ldc + w2] = x0 ^ a0;
+                    if (ok1) C[i * ldc + w2 + 1] = x1 ^ a1;
+                }
+            }
+        }
+        return;
+    }
     // PF: the next step's coefficient words are loaded during this step's
     // lookups, so a step starts with its row loads and lookups at once
     uint64_t ncp[U], ncu[U];
@@ -523,8 +593,15 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
                 cu[u] = i < re ? coefU[i] : 0ull;
             }
             const bool any = i < re && (cp[u] | cu[u]);
-            x0[u] = (any && ok0) ? C[i * ldc + w2] : 0ull;
-            x1[u] = (any && ok1) ? C[i * ldc + w2 + 1] : 0ull;
+            if (wide && any && ok0 && ok1) {
+                // one 16-byte load: the row's 16 lanes read 256 contiguous bytes
+                const ulonglong2 v = *(const ulonglong2 *)(C + i * ldc + w2);
+                x0[u] = v.x;
+                x1[u] = v.y;
+            } else {
+                x0[u] = (any && ok0) ? C[i * ldc + w2] : 0ull;
+                x1[u] = (any && ok1) ? C[i * ldc + w2 + 1] : 0ull;
+            }
         }
         if constexpr (PF) {
 #pragma unroll
@@ -569,8 +646,15 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
                 __asm__ volatile("" : "+v"(a0), "+v"(a1));
             }
             if (i < re && (cp[u] | cu[u])) {
-                if (ok0) C[i * ldc + w2] = x0[u] ^ a0;
-                if (ok1) C[i * ldc + w2 + 1] = x1[u] ^ a1;
+                if (wide && ok0 && ok1) {
+                    ulonglong2 v;
+                    v.x = x0[u] ^ a0;
+                    v.y = x1[u] ^ a1;
+                    *(ulonglong2 *)(C + i * ldc + w2) = v;
+                } else {
+                    if (ok0) C[i * ldc + w2] = x0[u] ^ a0;
+                    if (ok1) C[i * ldc + w2 + 1] = x1[u] ^ a1;
+                }
             }
         }
     }
@@ -867,8 +951,12 @@ hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, in
 #define PAIR_LAUNCH(NT, U, G, PF)                                                                                 \
     hipLaunchKernelGGL((k_m4rm_pair<NT, U, G, PF>), dim3(nt * nchunks), dim3(NT), 0, s, A, ldw, m, coefP, coefU,    \
                        coefT, PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu, ppl)
+#define PAIR_LAUNCH_RP(NT, G)                                                                                     \
+    hipLaunchKernelGGL((k_m4rm_pair<NT, 1, G, true, true>), dim3(nt * nchunks), dim3(NT), 0, s, A, ldw, m, coefP,   \
+                       coefU, coefT, PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu, ppl)
     // (threads, rows in flight per thread, table reads per group, coefficient
-    // prefetch); the default was the fastest on MI355X for the 65536^2 PLE
+    // prefetch[, row prefetch]); the default was the fastest on MI355X for the
+    // 65536^2 PLE
     switch (pair_variant) {
         case 1: PAIR_LAUNCH(1024, 2, 2, false); break;
         case 3: PAIR_LAUNCH(1024, 4, 1, false); break;
@@ -878,9 +966,13 @@ hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, in
         case 6: PAIR_LAUNCH(1024, 2, 4, true); break;
         case 8: PAIR_LAUNCH(1024, 1, 8, true); break;
         case 9: PAIR_LAUNCH(1024, 1, 2, true); break;
-        default: PAIR_LAUNCH(1024, 1, 4, true); break;
+        case 10: PAIR_LAUNCH_RP(1024, 4); break;
+        case 11: PAIR_LAUNCH(1024, 1, 4, true); break;
+        case 12: PAIR_LAUNCH_RP(1024, 8); break;
+        default: PAIR_LAUNCH_RP(1024, 2); break;
     }
 #undef PAIR_LAUNCH
+#undef PAIR_LAUNCH_RP
     return hipGetLastError();
 }
 

@@ -250,7 +250,7 @@ def test_lookahead_16384_seed2():
         assert_same_ple(gpu_ple(A, 16384, lookahead=mode), serial, "lookahead=%d" % mode)
 
 
-@pytest.mark.parametrize("variant", list(range(0, 10)))
+@pytest.mark.parametrize("variant", list(range(0, 13)))
 def test_pair_variants(variant):
     """Every schedule of the fused pair update (threads, rows in flight,
     reads per group, coefficient prefetch; the next panel inside the same
