@@ -307,6 +307,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-helpers", action="store_true", help="skip timing the echelon / RREF helpers")
     ap.add_argument("--m4-variant", type=int, default=0, help="update schedule 1..8 (0 = library default)")
     ap.add_argument("--m4-blocks", type=int, default=0, help="target blocks per update launch (0 = default)")
     ap.add_argument("--panel-regs", type=int, default=0, help="panel register window 2/4/8 (0 = default)")
@@ -375,6 +376,29 @@ def main():
     abytes = alg_bytes_m4rm(m, n, Qh, r, kinds)
     abytes64 = alg_bytes_k64(m, n, Qh, r)
 
+    # the helpers of the paper's PLE-based reductions, on this result (not in
+    # the timed step): echelon form, and the reduced echelon form from L\E
+    helpers = None
+    if not args.no_helpers:
+        res = work.clone()
+        hk = {}
+        for name in ("echelon", "rref_from_ple"):
+            times = []
+            for rep in range(2):  # the first also sets up the workspace
+                work.copy_(res)
+                torch.cuda.synchronize()
+                h0 = time.perf_counter()
+                if name == "echelon":
+                    G.echelon_from_ple(work, n, rank)
+                else:
+                    G.rref_from_ple(work, n, Q, rank)
+                torch.cuda.synchronize()
+                times.append((time.perf_counter() - h0) * 1000.0)
+            hk[name + "_ms"] = round(min(times), 3)
+        helpers = hk
+        del res
+        log("helpers: %s" % json.dumps(helpers))
+
     roofline = None
     kernels = None
     if not args.no_profile:
@@ -438,9 +462,8 @@ def main():
         "config": {"workload": "PLE of a dense %dx%d GF(2) matrix, Bernoulli(0.5), seed %d, uint64 row words"
                                % (m, n, args.seed),
                    "m": m, "n": n, "pass_width_K": KW, "update": "xor-table",
-                   "update_schedule": "16 nibble tables x 64-word tiles while the trailing matrix exceeds "
-                                      "192 MB, then 8 byte tables x 8-word tiles" if not args.m4_variant
-                                      else "fixed variant %d" % args.m4_variant,
+                   "update_schedule": "pairs of passes: one sweep with 32 nibble tables x 32-word tiles, "
+                                      "the next panel inside it; single passes past the last pair",
                    "schedule": sched},
         "rank": r,
         "schedule": {"passes": len(kinds), "serial": kinds.count(0), "lookahead": kinds.count(1),
@@ -450,6 +473,7 @@ def main():
         "k64_alg_GBps_whole_ple": round(abytes64 / (ms_per_step * 1e-3) / 1e9, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "helpers": helpers,
         "batched": batched,
         "serving": serving,
         "kernels_ms_per_step": {k: round(v["total_ms"] / args.steps, 3) for k, v in (kernels or {}).items()},
