@@ -94,12 +94,14 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
     __shared__ uint64_t sdcoef[KW];
     constexpr bool LA = MODE >= 1;
 
+    // the record's header in one scalar load, before the first branch
+    const int64_t r = rec->r;
+    const int rbar_rec = rec->rbar, nspec_rec = rec->nspec;
     const int active = rec->active;
     if (MODE != 2 && !active) return;
     const int tid = threadIdx.x;
-    const int64_t r = rec->r;
-    const int rbar = active ? rec->rbar : 0;
-    const int nspec = active ? rec->nspec : 0;
+    const int rbar = active ? rbar_rec : 0;
+    const int nspec = active ? nspec_rec : 0;
     const int64_t sw = c >> 6;
     const int64_t wr0 = r >> 6;
     const int sh = (int)(r & 63);

@@ -99,3 +99,53 @@ def test_serve_create_rejects_bad_options():
         assert lib.gf2_serve_create(ctypes.byref(o), ctypes.byref(h)) == 1, field
         assert not h.value
     assert lib.gf2_serve_create(None, None) == 1
+
+
+def test_pass_schedule():
+    """The pass loop's schedule (host only): fused pairs while rows remain
+    below the stripe, serial passes otherwise; every pair is a first pass
+    followed by a second."""
+    k = G.ple_schedule(65536, 65536)
+    assert len(k) == 1024
+    assert k[:1022] == [2, 3] * 511 and k[1022:] == [0, 0]
+    assert set(G.ple_schedule(65536, 65536, lookahead=1)) == {0}
+    k3 = G.ple_schedule(65536, 65536, lookahead=3)
+    assert k3[:1022] == [2, 3] * 511 and k3[1022:] == [1, 0]
+    k2 = G.ple_schedule(4096, 4096, lookahead=2)
+    assert set(k2[:-1]) == {1} and k2[-1] == 0
+    # wide: rows run out at pass 15 (15 * 64 < 1000 <= 16 * 64); the passes
+    # past it are serial, where the loop can stop once the rank reaches m
+    kw = G.ple_schedule(1000, 64 * 40)
+    assert kw[:16] == [2, 3] * 8 and set(kw[16:]) == {0}
+    for ks in (k, k3, kw, G.ple_schedule(300, 5000), G.ple_schedule(2100, 1300)):
+        for i, v in enumerate(ks):
+            if v == 2:
+                assert ks[i + 1] == 3
+            if v == 3:
+                assert i > 0 and ks[i - 1] == 2
+    assert G.ple_schedule(0, 0) == []
+    with pytest.raises(G.GF2Error):
+        G.ple_schedule(10, 10, lookahead=4)
+
+
+def test_schedule_options_checked_before_launch():
+    """Out-of-range schedule options return EINVAL before any device work
+    (host buffers stand in for the device pointers; nothing is launched)."""
+    import numpy as np
+    lib = G.load()
+    m = n = 128
+    ldw = 2
+    A = np.zeros((m, ldw), dtype=np.uint64)
+    P = np.zeros(m, dtype=np.int64)
+    Q = np.zeros(m, dtype=np.int64)
+    rank = np.zeros(1, dtype=np.int64)
+    ws = np.zeros(lib.gf2_ple_workspace_bytes(m, n, ldw, None) // 8 + 64, dtype=np.uint64)
+    ws_ptr = (ws.ctypes.data + 255) // 256 * 256
+    p = lambda a: ctypes.c_void_p(a.ctypes.data)
+    for field, value in (("pair_variant", 99), ("pair_variant", -1), ("lookahead", 4), ("panel_regs", 3),
+                         ("update", 2)):
+        o = G.Opts()
+        setattr(o, field, value)
+        st = lib.gf2_ple(p(A), m, n, ldw, p(P), p(Q), p(rank), ctypes.c_void_p(ws_ptr), ws.nbytes - 256,
+                         ctypes.byref(o), ctypes.c_void_p(0))
+        assert st == 1, (field, value, st)
