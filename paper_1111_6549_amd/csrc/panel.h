@@ -221,24 +221,29 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                     const uint32_t pel = HI ? 0u : (j == 31 ? 0u : pvl & (~0u << (j + 1)));
                     const uint32_t peh = HI ? (j == 63 ? 0u : pvh & (~0u << ((j & 31) + 1))) : pvh;
                     const uint64_t lbit = 1ull << lf, nbit = 1ull << npiv;
-                    const bool e0 = __builtin_amdgcn_inverse_ballot_w64(m0 & ~lbit);
-                    const bool e1 = __builtin_amdgcn_inverse_ballot_w64(m1);
+                    // lane masks as all-ones/zero words, opaque to the compiler,
+                    // so that each update below is one three-input logic
+                    // instruction with the scalar operand (a select on a scalar
+                    // mask would first copy the scalar into a vector register)
+                    uint32_t e0 = __builtin_amdgcn_inverse_ballot_w64(m0 & ~lbit) ? ~0u : 0u;
+                    uint32_t e1 = __builtin_amdgcn_inverse_ballot_w64(m1) ? ~0u : 0u;
+                    uint32_t s0 = __builtin_amdgcn_inverse_ballot_w64(lbit) ? ~0u : 0u;
+                    uint32_t sn = __builtin_amdgcn_inverse_ballot_w64(nbit) ? ~0u : 0u;
+                    __asm__ volatile("" : "+v"(e0), "+v"(e1), "+v"(s0), "+v"(sn));
                     if (!HI) {
-                        x0l = e0 ? x0l ^ pel : x0l;
-                        x1l = e1 ? x1l ^ pel : x1l;
+                        x0l ^= pel & e0;
+                        x1l ^= pel & e1;
                     }
-                    x0h = e0 ? x0h ^ peh : x0h;
-                    x1h = e1 ? x1h ^ peh : x1h;
+                    x0h ^= peh & e0;
+                    x1h ^= peh & e1;
                     // the row at npiv to the pivot's place, the pivot to npiv
-                    const bool s0 = __builtin_amdgcn_inverse_ballot_w64(lbit);
-                    x0l = s0 ? vrl : x0l;
-                    x0h = s0 ? vrh : x0h;
-                    id0 = s0 ? idr : id0;
-                    const bool sn = __builtin_amdgcn_inverse_ballot_w64(nbit);
-                    x0l = sn ? pvl : x0l;
-                    x0h = sn ? pvh : x0h;
-                    id0 = sn ? idp : id0;
-                    my_qp = sn ? (j | (lf << 8)) : my_qp;
+                    x0l = (x0l & ~s0) | (vrl & s0);
+                    x0h = (x0h & ~s0) | (vrh & s0);
+                    id0 = (int)(((uint32_t)id0 & ~s0) | ((uint32_t)idr & s0));
+                    x0l = (x0l & ~sn) | (pvl & sn);
+                    x0h = (x0h & ~sn) | (pvh & sn);
+                    id0 = (int)(((uint32_t)id0 & ~sn) | ((uint32_t)idp & sn));
+                    my_qp = (int)(((uint32_t)my_qp & ~sn) | ((uint32_t)(j | (lf << 8)) & sn));
                     act0 &= ~nbit;
                     npiv++;
                     j++;
