@@ -80,6 +80,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+DENSITY_POINTS = (0.1, 0.2, 0.5, 1.0, 2.0, 3.0, 5.0, 8.0, 12.0, 20.0)
+
+
 def cpu_baseline(n_full, sample):
     """The oracle, untouched, on a sample x sample Bernoulli(0.5) matrix."""
     import oracle
@@ -99,6 +102,52 @@ def cpu_baseline(n_full, sample):
                   "the sample is small enough to stay in the host's caches, so the scaled rate overstates the "
                   "oracle on the full matrix" % (sample, sample, dt, r, n_full, sample),
     }
+
+
+def run_density(args, log_fn):
+    """The sparse sweep of Section 5's Figure 2 on this path: 10000 x 10000,
+    Bernoulli(x / 10000) for x non-zero entries per row on average, seed 9 +
+    the point's index.  Each point: the median of five gf2_ple calls, input
+    restored from a device copy before each (outside the timing).  The oracle
+    is timed beside three points."""
+    import numpy as np
+    import torch
+
+    from paper_1111_6549_amd import gf2ple as G
+    from paper_1111_6549_amd import inputs
+
+    side = 10000
+    ldw = inputs.words(side)
+    ws = G.alloc_workspace(G.workspace_bytes(side, side, ldw))
+    points = []
+    oracle_pts = (1.0, 5.0, 20.0)
+    for idx, x in enumerate(DENSITY_POINTS):
+        A = inputs.bernoulli(side, side, 9 + idx, p=x / side)
+        dev = torch.from_numpy(A.view(np.int64)).cuda()
+        work = torch.empty_like(dev)
+        times = []
+        for rep in range(6):
+            work.copy_(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P, Q, rank = G.ple(work, side, ws=ws, panel_regs=args.panel_regs, lookahead=args.lookahead)
+            torch.cuda.synchronize()
+            if rep:
+                times.append((time.perf_counter() - t0) * 1000.0)
+        times.sort()
+        pt = {"nnz_per_row": x, "rank": int(rank.item()), "gpu_ms": round(times[len(times) // 2], 3)}
+        if not args.no_cpu_baseline and x in oracle_pts:
+            import oracle
+            B = A.copy()
+            t0 = time.perf_counter()
+            oracle.ple(B, side)
+            pt["oracle_ms"] = round((time.perf_counter() - t0) * 1000.0, 1)
+            pt["oracle_cores"] = oracle.threads()
+        points.append(pt)
+        log_fn("density %.1f per row: %s" % (x, json.dumps(pt)))
+        del dev, work
+    return {"workload": "10000x10000, Bernoulli(x/10000), x non-zero entries per row, seed 9 + index; "
+                        "median of 5 gf2_ple calls on resident input", "points": points}
 
 
 def run_batched(args, log_fn):
@@ -319,6 +368,7 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--batch-cpu-sample", type=int, default=512)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-density", action="store_true", help="skip the 10000^2 density sweep")
     ap.add_argument("--serve-count", type=int, default=600)
     ap.add_argument("--serve-cpu-sample", type=int, default=60)
     ap.add_argument("--serve-small-max", type=int, default=0,
@@ -434,6 +484,10 @@ def main():
         cpu = cpu_baseline(n, args.cpu_sample)
         log("cpu baseline done: %s" % cpu["sample"])
 
+    density = None
+    if not args.no_density:
+        density = run_density(args, log)
+
     batched = None
     if not args.no_batched:
         del work, pristine, ws
@@ -474,6 +528,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "helpers": helpers,
+        "density_sweep": density,
         "batched": batched,
         "serving": serving,
         "kernels_ms_per_step": {k: round(v["total_ms"] / args.steps, 3) for k, v in (kernels or {}).items()},

@@ -23,6 +23,11 @@
 
 namespace gf2 {
 
+// Sparse-search registers of the batched kernels' panels (64 rows each): none,
+// their waves are already near the register limit, so these panels search
+// every row when their window runs out.
+constexpr int BATCH_SPR = 0;
+
 // Staged special-row lists of one pass, and the nibble tables of the maps
 // stripe word -> (w, u) for the other rows.
 struct BPermLds {
@@ -208,7 +213,7 @@ __global__ __launch_bounds__(NW * 64) void k_batch(BatchArgs a) {
         __syncthreads();
         const int64_t nw = words_for(n);
         for (int64_t c = 0; c < n && m > 0; c += KW) {
-            if (wave == 0) panel_body<WQ, 0>(A, m, n, ldw, c, rec, rec, P, Q, rank, gsv, gsid, PL, lane);
+            if (wave == 0) panel_body<WQ, 0, BATCH_SPR>(A, m, n, ldw, c, rec, rec, P, Q, rank, gsv, gsid, PL, lane);
             __syncthreads();
             const volatile PassRec *vrec = rec;
             const int active = vrec->active;

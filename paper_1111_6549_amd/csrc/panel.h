@@ -25,13 +25,14 @@
 
 namespace gf2 {
 
-// LDS of the panel: the special-row lists and, for stripes of at most SR
-// rows, the slow search's window (larger stripes use the workspace arrays).
+// LDS of the panel: the special-row lists and up to SR rows of the slow
+// search (beyond that it uses the workspace arrays).
 template <int SR>
 struct PanelLdsT {
     int64_t dst[MAX_SPEC], src[MAX_SPEC];
     uint64_t sv[SR > 0 ? SR : 1];
     int32_t sid[SR > 0 ? SR : 1];
+    int32_t spos[SR > 0 ? SR : 1];
 };
 using PanelLds = PanelLdsT<SLOW_LDS_ROWS>;
 
@@ -99,7 +100,7 @@ struct PairPanel {
 // pass's r; it is read before `rec` is written, so the two may be the same
 // record), `rec` receives this pass.  Writes P[r..r+rbar), Q[r..r+rbar)
 // and *rank_out = r + rbar.
-template <int WQ, int SR>
+template <int WQ, int SR, int SPR = SPARSE_CAP / 64>
 __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c,
                                            const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
                                            int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelLdsT<SR> &L,
@@ -438,87 +439,422 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
         }
     }
 
-    // ---- slow path: every remaining row, window in LDS or workspace ---------
+    // ---- slow path: every remaining row -------------------------------------
+    // The one-wave panels first make one pass over the remaining rows and keep
+    // those whose stripe word is not zero (word, position, first position, in
+    // row order): a row with a zero stripe word is never a pivot and no
+    // elimination changes it; only its position can change, when a pivot is
+    // swapped into its place.  The search then runs on the kept rows alone:
+    // held in registers when at most 64 SPR, else in LDS or workspace.  The
+    // batched kernels' panels (SPR = 0) search every row in place.
     if (slow) {
         if (patch) fix_wait();  // the fix's stores, before every row is read back
         npiv = 0;
         my_q = 0;
         my_fin = 0;
         my_p = 0;
-        volatile uint64_t *sv = rows <= SR ? (volatile uint64_t *)L.sv : (volatile uint64_t *)gsv;
-        volatile int32_t *sid = rows <= SR ? (volatile int32_t *)L.sid : (volatile int32_t *)gsid;
-        uint64_t orv = 0;
-        for (int64_t pos = lane; pos < rows; pos += 64) {
-            const uint64_t v = ld_stripe(A + (r + pos) * ldw + sw) & kmask;
-            sv[pos] = v;
-            sid[pos] = (int32_t)pos;
-            orv |= v;
-        }
-        orv = wave_or64(orv);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        for (int j = 0; j < kp && npiv < rows; j++) {
-            if (!((orv >> j) & 1ull)) continue;  // no remaining row has a 1 here
-            int64_t found = -1;
-            for (int64_t base = npiv & ~(int64_t)63; base < rows; base += 64) {
-                const int64_t pos = base + lane;
-                const bool b = pos >= npiv && pos < rows && ((sv[pos] >> j) & 1ull);
-                const uint64_t msk = __ballot(b);
-                if (msk) {
-                    found = base + __builtin_ctzll(msk);
-                    break;
-                }
-            }
-            if (found < 0) continue;  // unreachable: orv says a row has bit j
-            const uint64_t pv = sv[found];
-            const int32_t idp = sid[found];
-            const uint64_t vr = sv[npiv];
-            const int32_t idr = sid[npiv];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            if (lane == 0) {
-                sv[found] = vr;
-                sid[found] = idr;
-                sv[npiv] = pv;
-                sid[npiv] = idp;
-            }
-            my_q = writelane32(my_q, j, npiv);
-            my_fin = writelane64(my_fin, pv, npiv);
-            my_p = writelane32(my_p, (int)found, npiv);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            const uint64_t pe = pv & above(j);
-            orv = 0;
-            for (int64_t pos = npiv + 1 + lane; pos < rows; pos += 64) {
-                uint64_t v = sv[pos];
-                if ((v >> j) & 1ull) {
-                    v ^= pe;
-                    sv[pos] = v;
-                }
+        if constexpr (SPR == 0) {
+            volatile uint64_t *sv = rows <= SR ? (volatile uint64_t *)L.sv : (volatile uint64_t *)gsv;
+            volatile int32_t *sid = rows <= SR ? (volatile int32_t *)L.sid : (volatile int32_t *)gsid;
+            uint64_t orv = 0;
+            for (int64_t pos = lane; pos < rows; pos += 64) {
+                const uint64_t v = ld_stripe(A + (r + pos) * ldw + sw) & kmask;
+                sv[pos] = v;
+                sid[pos] = (int32_t)pos;
                 orv |= v;
             }
             orv = wave_or64(orv);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            npiv = uni(npiv + 1);
-        }
-        int base = 0;
-        for (int64_t pb = 0; pb < rows; pb += 64) {
-            const int64_t pos = pb + lane;
-            const bool f = pos < rows && (pos < npiv || sid[pos] != (int32_t)pos);
-            const uint64_t msk = __ballot(f);
-            const int idx = base + __popcll(msk & ((1ull << lane) - 1ull));
-            if (f) {
-                L.dst[idx] = r + pos;
-                L.src[idx] = r + sid[pos];
+            for (int j = 0; j < kp && npiv < rows; j++) {
+                if (!((orv >> j) & 1ull)) continue;  // no remaining row has a 1 here
+                int64_t found = -1;
+                for (int64_t base = npiv & ~(int64_t)63; base < rows; base += 64) {
+                    const int64_t pos = base + lane;
+                    const bool b = pos >= npiv && pos < rows && ((sv[pos] >> j) & 1ull);
+                    const uint64_t msk = __ballot(b);
+                    if (msk) {
+                        found = base + __builtin_ctzll(msk);
+                        break;
+                    }
+                }
+                if (found < 0) continue;  // unreachable: orv says a row has bit j
+                const uint64_t pv = sv[found];
+                const int32_t idp = sid[found];
+                const uint64_t vr = sv[npiv];
+                const int32_t idr = sid[npiv];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                if (lane == 0) {
+                    sv[found] = vr;
+                    sid[found] = idr;
+                    sv[npiv] = pv;
+                    sid[npiv] = idp;
+                }
+                my_q = writelane32(my_q, j, npiv);
+                my_fin = writelane64(my_fin, pv, npiv);
+                my_p = writelane32(my_p, (int)found, npiv);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const uint64_t pe = pv & above(j);
+                orv = 0;
+                for (int64_t pos = npiv + 1 + lane; pos < rows; pos += 64) {
+                    uint64_t v = sv[pos];
+                    if ((v >> j) & 1ull) {
+                        v ^= pe;
+                        sv[pos] = v;
+                    }
+                    orv |= v;
+                }
+                orv = wave_or64(orv);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                npiv = uni(npiv + 1);
             }
-            base += __popcll(msk);
+            int base = 0;
+            for (int64_t pb = 0; pb < rows; pb += 64) {
+                const int64_t pos = pb + lane;
+                const bool f = pos < rows && (pos < npiv || sid[pos] != (int32_t)pos);
+                const uint64_t msk = __ballot(f);
+                const int idx = base + __popcll(msk & ((1ull << lane) - 1ull));
+                if (f) {
+                    L.dst[idx] = r + pos;
+                    L.src[idx] = r + sid[pos];
+                }
+                base += __popcll(msk);
+            }
+            nspec = uni(base);
+        } else {
+            const uint64_t lt = (1ull << lane) - 1ull;
+            constexpr int SB = 8;  // row loads in flight per lane
+            // kept rows: word, position now, first position
+            volatile uint64_t *cv = (volatile uint64_t *)gsv;
+            volatile int32_t *ci = (volatile int32_t *)gsid;
+            volatile int32_t *cp = (volatile int32_t *)gsid + m;
+            if constexpr (SR > 0) {
+                cv = (volatile uint64_t *)L.sv;
+                ci = (volatile int32_t *)L.sid;
+                cp = (volatile int32_t *)L.spos;
+            }
+            int nc = 0;
+            uint64_t orv = 0;
+            auto keep = [&](const int cap) {
+                nc = 0;
+                orv = 0;
+                for (int64_t b0 = 0; b0 < rows; b0 += 64 * SB) {
+                    uint64_t v[SB];
+#pragma unroll
+                    for (int u = 0; u < SB; u++) {
+                        const int64_t pos = b0 + 64 * u + lane;
+                        v[u] = pos < rows ? ld_stripe(A + (r + pos) * ldw + sw) & kmask : 0ull;
+                    }
+#pragma unroll
+                    for (int u = 0; u < SB; u++) {
+                        const uint64_t msk = __ballot(v[u] != 0);
+                        const int k = nc + __popcll(msk & lt);
+                        if (v[u] && k < cap) {
+                            const int32_t pos = (int32_t)(b0 + 64 * u + lane);
+                            cv[k] = v[u];
+                            ci[k] = pos;
+                            cp[k] = pos;
+                        }
+                        nc += __popcll(msk);
+                        orv |= v[u];
+                    }
+                }
+                orv = wave_or64(orv);
+                nc = uni(nc);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            };
+            keep(SR > 0 ? SR : INT32_MAX);
+            if (SR > 0 && nc > SR) {  // more kept rows than the LDS holds
+                cv = (volatile uint64_t *)gsv;
+                ci = (volatile int32_t *)gsid;
+                cp = (volatile int32_t *)gsid + m;
+                keep(INT32_MAX);
+            }
+            // lane d: a row with a zero stripe word moved to position dzp (it
+            // started at dzi); -1 = none.  At most one per pivot.
+            int dzp = -1, dzi = 0;
+            // the row at position npiv, if it has a zero stripe word, goes to
+            // position found
+            auto move_zero_row = [&](const int found) {
+                if (__ballot(dzp == npiv)) {
+                    dzp = dzp == npiv ? found : dzp;
+                } else {
+                    const int nd = __popcll(__ballot(dzp >= 0));
+                    if (lane == nd) {
+                        dzp = found;
+                        dzi = npiv;
+                    }
+                }
+            };
+            int my_id = 0;
+            int nsp = 0;  // special rows listed
+            if (nc <= 64 * SPR) {
+                constexpr int R = SPR;
+                // kept row 64 q + lane: word, position now, first position
+                uint64_t ev[R];
+                int ep[R], ei[R];
+#pragma unroll
+                for (int q = 0; q < R; q++) {
+                    const int k = 64 * q + lane;
+                    ev[q] = k < nc ? cv[k] : 0ull;
+                    ep[q] = k < nc ? ci[k] : INT32_MAX;
+                    ei[q] = ep[q];
+                }
+                for (int j = 0; j < kp && npiv < rows; j++) {
+                    if (!((orv >> j) & 1ull)) continue;  // no remaining row has a 1 here
+                    // pivot: the row at or below npiv with bit j at the lowest position
+                    uint64_t key = ~0ull;
+#pragma unroll
+                    for (int q = 0; q < R; q++) {
+                        const uint64_t kq = ((uint64_t)(uint32_t)ep[q] << 16) | ((uint64_t)q << 6) | (uint64_t)lane;
+                        key = (ep[q] >= npiv && ((ev[q] >> j) & 1ull) && kq < key) ? kq : key;
+                    }
+                    key = wave_min64(key);
+                    if (key == ~0ull) continue;  // unreachable: orv says a row has bit j
+                    const int found = uni((int)(key >> 16));
+                    const int fq = uni((int)((key >> 6) & 63));
+                    const int fl = uni((int)(key & 63));
+                    uint64_t pv = 0;
+                    int pid = 0;
+#pragma unroll
+                    for (int q = 0; q < R; q++)
+                        if (q == fq) {
+                            pv = readlane64(ev[q], fl);
+                            pid = readlane32(ei[q], fl);
+                        }
+                    if (found != npiv) {
+                        // the row at position npiv takes the pivot's place
+                        bool kept = false;
+#pragma unroll
+                        for (int q = 0; q < R; q++) {
+                            const bool o = ep[q] == npiv;
+                            kept = kept || __ballot(o) != 0;
+                            ep[q] = o ? found : ep[q];
+                        }
+                        if (!kept) move_zero_row(found);
+                    }
+#pragma unroll
+                    for (int q = 0; q < R; q++)
+                        if (q == fq) ep[q] = lane == fl ? npiv : ep[q];
+                    my_q = writelane32(my_q, j, npiv);
+                    my_fin = writelane64(my_fin, pv, npiv);
+                    my_p = writelane32(my_p, found, npiv);
+                    my_id = writelane32(my_id, pid, npiv);
+                    const uint64_t pe = pv & above(j);
+                    uint64_t o = 0;
+#pragma unroll
+                    for (int q = 0; q < R; q++) {
+                        if (ep[q] > npiv) {
+                            ev[q] = ((ev[q] >> j) & 1ull) ? ev[q] ^ pe : ev[q];
+                            o |= ev[q];
+                        }
+                    }
+                    orv = wave_or64(o);
+                    npiv = uni(npiv + 1);
+                }
+                nsp = npiv;
+#pragma unroll
+                for (int q = 0; q < R; q++) {
+                    const bool f = ep[q] != INT32_MAX && ep[q] >= npiv && ep[q] != ei[q];
+                    const uint64_t msk = __ballot(f);
+                    if (f) {
+                        const int idx = nsp + __popcll(msk & lt);
+                        L.dst[idx] = r + ep[q];
+                        L.src[idx] = r + ei[q];
+                    }
+                    nsp += __popcll(msk);
+                }
+            } else {
+                // The kept rows are searched lazily, in row order: rows [0, wn)
+                // form the window, reduced by every pivot found so far; the rest
+                // are as read and keep their positions.  A column's search
+                // takes more rows into the window only while the window has
+                // no candidate.
+                constexpr int MB = 4;  // 64-row groups taken into the window at a time
+                int wn = 0;
+                const uint64_t or_raw = orv;  // union of the kept rows as read
+                uint64_t or_pe = 0;           // union of the pivots' parts above their columns
+                uint64_t or_win = 0;          // union of the window rows at or below npiv
+                // take kept rows [wn, wn + 64 MB) into the window: reduce them by
+                // the pivots so far, in order; returns the union of their words
+                auto extend = [&]() -> uint64_t {
+                    uint64_t v[MB];
+#pragma unroll
+                    for (int u = 0; u < MB; u++) {
+                        const int k = wn + 64 * u + lane;
+                        v[u] = k < nc ? cv[k] : 0ull;
+                    }
+                    for (int l = 0; l < npiv; l++) {
+                        const int ql = readlane32(my_q, l);
+                        const uint64_t pel = readlane64(my_fin, l) & above(ql);
+#pragma unroll
+                        for (int u = 0; u < MB; u++) v[u] = ((v[u] >> ql) & 1ull) ? v[u] ^ pel : v[u];
+                    }
+                    uint64_t o = 0;
+#pragma unroll
+                    for (int u = 0; u < MB; u++) {
+                        const int k = wn + 64 * u + lane;
+                        if (k < nc) cv[k] = v[u];
+                        o |= v[u];
+                    }
+                    wn = wn + 64 * MB < nc ? wn + 64 * MB : nc;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    return wave_or64(o);
+                };
+                // lowest (position, index) key of a window row in [k0, k1) at or
+                // below npiv with bit j; occ: the window row at position npiv
+                auto search = [&](const int k0, const int k1, const int j, int &occ) -> uint64_t {
+                    uint64_t key = ~0ull;
+                    for (int b0 = k0; b0 < k1; b0 += 64 * MB) {
+                        uint64_t v[MB];
+                        int p[MB];
+#pragma unroll
+                        for (int u = 0; u < MB; u++) {
+                            const int k = b0 + 64 * u + lane;
+                            v[u] = k < k1 ? cv[k] : 0ull;
+                            p[u] = k < k1 ? cp[k] : -1;
+                        }
+#pragma unroll
+                        for (int u = 0; u < MB; u++) {
+                            const int k = b0 + 64 * u + lane;
+                            const uint64_t kk = ((uint64_t)(uint32_t)p[u] << 31) | (uint64_t)(uint32_t)k;
+                            key = (p[u] >= npiv && ((v[u] >> j) & 1ull) && kk < key) ? kk : key;
+                            occ = p[u] == npiv ? k : occ;
+                        }
+                    }
+                    return wave_min64(key);
+                };
+                for (int j = 0; j < kp && npiv < rows; j++) {
+                    // a kept row at position npiv belongs in the window
+                    while (wn < nc && cp[wn] <= npiv) or_win |= extend();
+                    // a row outside the window has bit j only if read with it or
+                    // given it by a pivot
+                    const uint64_t bound = or_win | (wn < nc ? (or_raw | or_pe) : 0ull);
+                    if (!((bound >> j) & 1ull)) continue;
+                    int occ = -1;
+                    uint64_t key = search(0, wn, j, occ);
+                    while (key == ~0ull && wn < nc) {
+                        const int w0 = wn;
+                        or_win |= extend();
+                        int unused = -1;
+                        key = search(w0, wn, j, unused);
+                    }
+                    if (key == ~0ull) continue;  // column j has no pivot
+                    const int found = uni((int)(key >> 31));
+                    const int kf = uni((int)(key & 0x7fffffffull));
+                    const uint64_t om = __ballot(occ >= 0);
+                    const int ko = om ? readlane32(occ, __builtin_ctzll(om)) : -1;
+                    const uint64_t pv = cv[kf];
+                    const int pid = ci[kf];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    if (found != npiv) {
+                        if (ko >= 0) {
+                            if (lane == 0) cp[ko] = found;
+                        } else {
+                            move_zero_row(found);
+                        }
+                    }
+                    if (lane == 0) cp[kf] = npiv;
+                    my_q = writelane32(my_q, j, npiv);
+                    my_fin = writelane64(my_fin, pv, npiv);
+                    my_p = writelane32(my_p, found, npiv);
+                    my_id = writelane32(my_id, pid, npiv);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    const uint64_t pe = pv & above(j);
+                    or_pe |= pe;
+                    uint64_t o = 0;
+                    for (int b0 = 0; b0 < wn; b0 += 64 * MB) {
+                        uint64_t v[MB];
+                        int p[MB];
+#pragma unroll
+                        for (int u = 0; u < MB; u++) {
+                            const int k = b0 + 64 * u + lane;
+                            v[u] = k < wn ? cv[k] : 0ull;
+                            p[u] = k < wn ? cp[k] : -1;
+                        }
+#pragma unroll
+                        for (int u = 0; u < MB; u++) {
+                            const int k = b0 + 64 * u + lane;
+                            if (p[u] > npiv) {
+                                const bool hit = (v[u] >> j) & 1ull;
+                                if (hit) cv[k] = v[u] ^ pe;
+                                o |= hit ? v[u] ^ pe : v[u];
+                            }
+                        }
+                    }
+                    or_win = wave_or64(o);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    npiv = uni(npiv + 1);
+                }
+                // rows outside the window never moved
+                nsp = npiv;
+                for (int b0 = 0; b0 < wn; b0 += 64) {
+                    const int k = b0 + lane;
+                    const int p = k < wn ? cp[k] : -1;
+                    const int i0 = k < wn ? ci[k] : -1;
+                    const bool f = p >= npiv && p != i0;
+                    const uint64_t msk = __ballot(f);
+                    if (f) {
+                        const int idx = nsp + __popcll(msk & lt);
+                        L.dst[idx] = r + p;
+                        L.src[idx] = r + i0;
+                    }
+                    nsp += __popcll(msk);
+                }
+            }
+            // special rows: the pivots in order, then the displaced rows by
+            // position (listed above in any order, ranked here)
+            if (lane < npiv) {
+                L.dst[lane] = r + lane;
+                L.src[lane] = r + my_id;
+            }
+            {
+                const uint64_t msk = __ballot(dzp >= 0);
+                if (dzp >= 0) {
+                    const int idx = nsp + __popcll(msk & lt);
+                    L.dst[idx] = r + dzp;
+                    L.src[idx] = r + dzi;
+                }
+                nsp += __popcll(msk);
+            }
+            nspec = uni(nsp);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const int nd = nspec - npiv;  // <= npiv <= 64
+            int64_t dd = 0, ds = 0;
+            if (lane < nd) {
+                dd = L.dst[npiv + lane];
+                ds = L.src[npiv + lane];
+            }
+            const int dpos = (int)(dd - r);
+            int rank = 0;
+            for (int k = 0; k < nd; k++) rank += readlane32(dpos, k) < dpos ? 1 : 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (lane < nd) {
+                L.dst[npiv + rank] = dd;
+                L.src[npiv + rank] = ds;
+            }
         }
-        nspec = uni(base);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();

@@ -383,6 +383,9 @@ __global__ __launch_bounds__(NT) void k_m4rm_w(uint64_t *__restrict__ C, int64_t
 // other blocks take.
 // ---------------------------------------------------------------------------
 constexpr int PR_TW = 32;
+// kept rows of the slow search of the panel inside the pair update that fit
+// in the LDS beside the 128 KB of tables
+constexpr int PAIR_PANEL_ROWS = 1536;
 
 template <int BASE, int NT>
 __device__ __forceinline__ void pair_combos(uint64_t (*T)[16][PR_TW], int tid) {
@@ -436,7 +439,7 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
                                                   const PassRec *__restrict__ rect, const PassRec *__restrict__ recu,
                                                   PairPanel pp) {
     __shared__ __align__(16) uint64_t T[32][16][PR_TW];
-    __shared__ PanelLdsT<0> PL;
+    __shared__ PanelLdsT<PAIR_PANEL_ROWS> PL;
     const int tid = threadIdx.x;
     const int logical = xcd_logical(blockIdx.x, gridDim.x);
     const bool panel_here = pp.on && logical == 0;
@@ -446,7 +449,7 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
         __builtin_amdgcn_s_setprio(3);
         PanelFix f;
         f.mode = 1;
-        panel_body<2, 0>(C, m, pp.n, ldc, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank, pp.gsv, pp.gsid, PL, tid & 63, f);
+        panel_body<2, PAIR_PANEL_ROWS>(C, m, pp.n, ldc, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank, pp.gsv, pp.gsid, PL, tid & 63, f);
     };
     const int at = rect->active, au = recu->active;
     const int nbt = at ? rect->rbar : 0, nbu = au ? recu->rbar : 0;

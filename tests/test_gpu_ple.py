@@ -43,6 +43,15 @@ def test_parity_sparse(m, n, p):
     assert_same_ple(gpu_ple(A, n), oracle_ple(A, n), "%dx%d p=%g" % (m, n, p))
 
 
+@pytest.mark.parametrize("x,seed", [(0.5, 11), (3.0, 14), (20.0, 18)])
+def test_parity_density_10000(x, seed):
+    """Three points of the 10000 x 10000 sparse sweep (x non-zero entries per
+    row on average), with the seeds the sweep in bench.py uses."""
+    say("parity 10000^2 density", x)
+    A = inputs.bernoulli(10000, 10000, seed, p=x / 10000)
+    assert_same_ple(gpu_ple(A, 10000), oracle_ple(A, 10000), "10000^2 x=%g" % x)
+
+
 @pytest.mark.parametrize("m,n,rho", [(600, 600, 300), (1000, 700, 650), (700, 1000, 700), (800, 800, 800),
                                      (3000, 300, 50), (8000, 300, 100), (256, 2048, 200)])
 def test_parity_known_rank(m, n, rho):
