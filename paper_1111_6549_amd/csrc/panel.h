@@ -36,9 +36,12 @@ struct PanelLdsT {
 };
 using PanelLds = PanelLdsT<SLOW_LDS_ROWS>;
 
-// Stripe words are read past the L1 cache: with the look-ahead the panel
-// itself has just rewritten some of them (fix_deferred_rows).
-__device__ __forceinline__ uint64_t ld_stripe(const uint64_t *p) { return *(const volatile uint64_t *)p; }
+// Stripe words are read past the L1 cache (the panel itself may just have
+// rewritten some of them): a relaxed load at device scope, which, unlike a
+// volatile one, lets several loads be in flight at once.
+__device__ __forceinline__ uint64_t ld_stripe(const uint64_t *p) {
+    return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // The rows a fix wrote: lane l's entries l and 64 + l (position d, -1 if
 // none, and the new stripe word n).
@@ -531,14 +534,15 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
         } else {
             const uint64_t lt = (1ull << lane) - 1ull;
             constexpr int SB = 8;  // row loads in flight per lane
-            // kept rows: word, position now, first position
-            volatile uint64_t *cv = (volatile uint64_t *)gsv;
-            volatile int32_t *ci = (volatile int32_t *)gsid;
-            volatile int32_t *cp = (volatile int32_t *)gsid + m;
+            // kept rows: word, position now, first position (written and read
+            // by this wave only, ordered by the fences between the steps)
+            uint64_t *cv = gsv;
+            int32_t *ci = gsid;
+            int32_t *cp = gsid + m;
             if constexpr (SR > 0) {
-                cv = (volatile uint64_t *)L.sv;
-                ci = (volatile int32_t *)L.sid;
-                cp = (volatile int32_t *)L.spos;
+                cv = L.sv;
+                ci = L.sid;
+                cp = L.spos;
             }
             int nc = 0;
             uint64_t orv = 0;
@@ -547,11 +551,15 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                 orv = 0;
                 for (int64_t b0 = 0; b0 < rows; b0 += 64 * SB) {
                     uint64_t v[SB];
+                    // every lane loads (past the end: the last row, unused), so
+                    // no load sits under a branch and all SB are in flight
 #pragma unroll
                     for (int u = 0; u < SB; u++) {
                         const int64_t pos = b0 + 64 * u + lane;
-                        v[u] = pos < rows ? ld_stripe(A + (r + pos) * ldw + sw) & kmask : 0ull;
+                        v[u] = ld_stripe(A + (r + (pos < rows ? pos : rows - 1)) * ldw + sw);
                     }
+#pragma unroll
+                    for (int u = 0; u < SB; u++) v[u] = b0 + 64 * u + lane < rows ? v[u] & kmask : 0ull;
 #pragma unroll
                     for (int u = 0; u < SB; u++) {
                         const uint64_t msk = __ballot(v[u] != 0);
@@ -574,9 +582,9 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
             };
             keep(SR > 0 ? SR : INT32_MAX);
             if (SR > 0 && nc > SR) {  // more kept rows than the LDS holds
-                cv = (volatile uint64_t *)gsv;
-                ci = (volatile int32_t *)gsid;
-                cp = (volatile int32_t *)gsid + m;
+                cv = gsv;
+                ci = gsid;
+                cp = gsid + m;
                 keep(INT32_MAX);
             }
             // lane d: a row with a zero stripe word moved to position dzp (it
