@@ -50,6 +50,14 @@ struct FixOut {
     int64_t d0 = -1, d1 = -1;
 };
 
+// Order this wave's LDS accesses before and after the call: a compiler
+// barrier and a wave barrier (the LDS executes one wave's accesses in order).
+__device__ __forceinline__ void lds_order() {
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
 __device__ __forceinline__ void fix_wait() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -162,17 +170,38 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
         {
             const int64_t row0 = r + (lane < rows ? lane : rows - 1);
             const int64_t row1 = r + (64 + lane < rows ? 64 + lane : rows - 1);
+            // the fix's record entries load first (every entry, masked once
+            // the header is in), so waiting for them never waits for the
+            // stripe words behind them
+            FixOut fo;
+            int fa = 0, fnr = 0;
+            if (patch) {
+                fa = prev->active;
+                fnr = prev->nspec;
+                fo.d0 = prev->spec_dst[lane];
+                fo.d1 = prev->spec_dst[64 + lane];
+                fo.n0 = prev->spec_next[lane];
+                fo.n1 = prev->spec_next[64 + lane];
+            }
+            __builtin_amdgcn_sched_barrier(0);
             uint64_t t0 = ld_stripe(A + row0 * ldw + sw);
             uint64_t t1 = ld_stripe(A + row1 * ldw + sw);
+            __builtin_amdgcn_sched_barrier(0);
             if (patch) {
                 // the previous pass(es)' special rows in the window: their
                 // loaded words are stale, the fix's new words replace them
-                const FixOut fo = run_fix(false);
-                volatile int64_t *pf = L.src;
-                volatile uint64_t *pw = (volatile uint64_t *)L.dst;
+                // (LDS scratch of this wave: its LDS accesses execute in
+                // program order, and the compiler barriers keep that order)
+                const int fn = fa ? fnr : 0;
+                if (lane >= fn) fo.d0 = -1;
+                if (64 + lane >= fn) fo.d1 = -1;
+                if (fo.d0 >= 0) A[fo.d0 * ldw + sw] = fo.n0;
+                if (fo.d1 >= 0) A[fo.d1 * ldw + sw] = fo.n1;
+                int64_t *pf = L.src;
+                uint64_t *pw = (uint64_t *)L.dst;
                 pf[lane] = -1;
                 pf[64 + lane] = -1;
-                __builtin_amdgcn_wave_barrier();
+                lds_order();
                 if (fo.d0 >= r && fo.d0 < r + 128) {
                     pw[fo.d0 - r] = fo.n0;
                     pf[fo.d0 - r] = 1;
@@ -181,10 +210,10 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                     pw[fo.d1 - r] = fo.n1;
                     pf[fo.d1 - r] = 1;
                 }
-                __builtin_amdgcn_wave_barrier();
+                lds_order();
                 if (pf[lane] >= 0) t0 = pw[lane];
                 if (pf[64 + lane] >= 0) t1 = pw[64 + lane];
-                __builtin_amdgcn_wave_barrier();
+                lds_order();
             }
             const uint64_t v0 = lane < nmax ? (t0 & kmask) : 0ull;
             const uint64_t v1 = 64 + lane < nmax ? (t1 & kmask) : 0ull;
