@@ -43,21 +43,20 @@ template <int NT>
 __device__ __forceinline__ void batch_permute(uint64_t *__restrict__ A, int64_t m, int64_t ldw, int64_t nw, int64_t c,
                                               const PassRec *rec, uint64_t *__restrict__ coef,
                                               uint64_t *__restrict__ PB, BPermLds &L, int tid) {
-    // the record was written by wave 0 in this launch: read it with vector
-    // loads (volatile), never through the scalar cache
-    const volatile PassRec *vrec = rec;
-    const int64_t r = vrec->r;
-    const int rbar = vrec->rbar;
-    const int nspec = vrec->nspec;
+    // the record was written by wave 0 in this launch: read it with relaxed
+    // device-scope vector loads, never through the scalar cache
+    const int64_t r = ld_dev(&rec->r);
+    const int rbar = ld_dev(&rec->rbar);
+    const int nspec = ld_dev(&rec->nspec);
     const int64_t sw = c >> 6;
     const int64_t wr0 = r >> 6;
     const int sh = (int)(r & 63);
     for (int k = tid; k < nspec; k += NT) {
-        L.dst[k] = vrec->spec_dst[k];
-        L.src[k] = vrec->spec_src[k];
-        L.coef[k] = vrec->spec_coef[k];
-        L.lbits[k] = vrec->spec_lbits[k];
-        L.stripe[k] = vrec->spec_stripe[k];
+        L.dst[k] = ld_dev(&rec->spec_dst[k]);
+        L.src[k] = ld_dev(&rec->spec_src[k]);
+        L.coef[k] = ld_dev(&rec->spec_coef[k]);
+        L.lbits[k] = ld_dev(&rec->spec_lbits[k]);
+        L.stripe[k] = ld_dev(&rec->spec_stripe[k]);
     }
     for (int e = tid; e < 256; e += NT) {
         const int t = e >> 4, x = e & 15;
@@ -65,8 +64,8 @@ __device__ __forceinline__ void batch_permute(uint64_t *__restrict__ A, int64_t 
 #pragma unroll
         for (int q = 0; q < 4; q++)
             if ((x >> q) & 1) {
-                a ^= vrec->img_w[4 * t + q];
-                b ^= vrec->img_u[4 * t + q];
+                a ^= ld_dev(&rec->img_w[4 * t + q]);
+                b ^= ld_dev(&rec->img_u[4 * t + q]);
             }
         L.tw[t][x] = a;
         L.tu[t][x] = b;
@@ -215,10 +214,9 @@ __global__ __launch_bounds__(NW * 64) void k_batch(BatchArgs a) {
         for (int64_t c = 0; c < n && m > 0; c += KW) {
             if (wave == 0) panel_body<WQ, 0, BATCH_SPR>(A, m, n, ldw, c, rec, rec, P, Q, rank, gsv, gsid, PL, lane);
             __syncthreads();
-            const volatile PassRec *vrec = rec;
-            const int active = vrec->active;
-            const int64_t r = vrec->r;
-            const int rbar = vrec->rbar;
+            const int active = ld_dev(&rec->active);
+            const int64_t r = ld_dev(&rec->r);
+            const int rbar = ld_dev(&rec->rbar);
             if (active) {
                 batch_permute<NT>(A, m, ldw, nw, c, rec, coef, PB, BL, tid);
                 batch_update<NT, TB, TW, U>(A, m, ldw, nw, c, r, rbar, coef, PB, TL, tid);

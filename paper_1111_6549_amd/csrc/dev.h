@@ -32,6 +32,14 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// A relaxed device-scope load: a vector load past the L1 cache (never the
+// scalar cache), with no wait of its own, for data another wave of the
+// launch may have written.
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {

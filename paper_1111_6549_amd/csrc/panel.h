@@ -39,9 +39,7 @@ using PanelLds = PanelLdsT<SLOW_LDS_ROWS>;
 // Stripe words are read past the L1 cache (the panel itself may just have
 // rewritten some of them): a relaxed load at device scope, which, unlike a
 // volatile one, lets several loads be in flight at once.
-__device__ __forceinline__ uint64_t ld_stripe(const uint64_t *p) {
-    return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ uint64_t ld_stripe(const uint64_t *p) { return ld_dev(p); }
 
 // The rows a fix wrote: lane l's entries l and 64 + l (position d, -1 if
 // none, and the new stripe word n).
@@ -486,8 +484,8 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
         my_fin = 0;
         my_p = 0;
         if constexpr (SPR == 0) {
-            volatile uint64_t *sv = rows <= SR ? (volatile uint64_t *)L.sv : (volatile uint64_t *)gsv;
-            volatile int32_t *sid = rows <= SR ? (volatile int32_t *)L.sid : (volatile int32_t *)gsid;
+            uint64_t *sv = rows <= SR ? L.sv : gsv;
+            int32_t *sid = rows <= SR ? L.sid : gsid;
             uint64_t orv = 0;
             for (int64_t pos = lane; pos < rows; pos += 64) {
                 const uint64_t v = ld_stripe(A + (r + pos) * ldw + sw) & kmask;
