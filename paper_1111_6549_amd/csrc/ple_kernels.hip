@@ -94,15 +94,28 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
     __shared__ uint64_t sdcoef[KW];
     constexpr bool LA = MODE >= 1;
 
-    // the record's header in one scalar load, before the first branch
+    const int tid = threadIdx.x;
+    const int64_t sw = c >> 6;
+    const bool nxt = LA && sw + 1 < nw;
+    // A row block's first rows are read before the record's header is in,
+    // at the rows they take when every pass so far had full rank (the first
+    // row is then the stripe's column); they are read again if not.
+    const int64_t gfirst = (MODE == 2 ? c - KW : c) + ((int64_t)blockIdx.x - nA) * WIDE_THREADS + tid;
+    uint64_t g_sw = 0, g_nx = 0, g_ct = 0;
+    if ((int)blockIdx.x >= nA && gfirst < m) {
+        const uint64_t *row = A + gfirst * ldw;
+        g_sw = row[sw];
+        if (nxt) g_nx = row[sw + 1];
+        if (MODE == 2) g_ct = coefT[gfirst];
+    }
+    // the record's header (r < 0 never holds: the test keeps the load of r
+    // ahead of the branch, beside the others)
     const int64_t r = rec->r;
     const int rbar_rec = rec->rbar, nspec_rec = rec->nspec;
     const int active = rec->active;
-    if (MODE != 2 && !active) return;
-    const int tid = threadIdx.x;
+    if (MODE != 2 && (!active || r < 0)) return;
     const int rbar = active ? rbar_rec : 0;
     const int nspec = active ? nspec_rec : 0;
-    const int64_t sw = c >> 6;
     const int64_t wr0 = r >> 6;
     const int sh = (int)(r & 63);
 
@@ -112,13 +125,15 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         const int64_t w = (int64_t)blockIdx.x * 64 + (tid & 63);
         const int slot = tid >> 6;
         uint64_t nv[PER];
+        int64_t srcs[PER];
+#pragma unroll
+        for (int t = 0; t < PER; t++) srcs[t] = rec->spec_src[slot + SLOTS * t];  // (every entry exists)
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int k = slot + SLOTS * t;
             nv[t] = 0;
             if (k < nspec && w < ldw && !(LA && w == sw + 1)) {
-                const int64_t src = rec->spec_src[k];
-                const uint64_t old = A[src * ldw + w];
+                const uint64_t old = A[srcs[t] * ldw + w];
                 if (k < rbar && w > sw) PB[(int64_t)k * ldw + w] = old;
                 nv[t] = special_word(old, w, sw, wr0, sh, rec->spec_lbits[k], rec->spec_stripe[k]);
             }
@@ -140,7 +155,6 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
     // thread's first row, the pass maps, the pivots' next-stripe words), so
     // the launch costs about one memory round trip before the table builds.
     const int ndisp = nspec - rbar;
-    const bool nxt = LA && sw + 1 < nw;
     const int rt = (MODE == 2 && rect->active) ? rect->rbar : 0;
     const int64_t nB = (int64_t)gridDim.x - nA;
     const int64_t row0 = MODE == 2 ? rect->r : r;
@@ -148,8 +162,8 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
     const int64_t ifirst = row0 + ((int64_t)blockIdx.x - nA) * WIDE_THREADS + tid;
     // first row: special rows read here are rewritten by group A meanwhile,
     // but their values are not used (the loop skips them)
-    uint64_t f_sw = 0, f_nx = 0, f_ct = 0;
-    if (ifirst < m) {
+    uint64_t f_sw = g_sw, f_nx = g_nx, f_ct = g_ct;
+    if (ifirst != gfirst && ifirst < m) {
         const uint64_t *row = A + ifirst * ldw;
         f_sw = row[sw];
         if (nxt) f_nx = row[sw + 1];
