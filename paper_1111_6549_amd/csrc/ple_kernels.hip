@@ -88,7 +88,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
                                                           const uint64_t *__restrict__ coefT,
                                                           uint64_t *__restrict__ coefP,
                                                           const uint64_t *__restrict__ PBt) {
-    __shared__ uint64_t tw[8][256], tu[8][256], tn[8][256], tt[MODE == 2 ? 8 : 1][MODE == 2 ? 256 : 1];
+    __shared__ uint64_t tw[16][16], tu[16][16], tn[16][16], tt[MODE == 2 ? 16 : 1][16];
     __shared__ uint64_t simg_w[KW], simg_u[KW], simg_n[KW], spbt[KW];
     __shared__ int64_t sdisp[KW], sdsrc[KW], smaxdisp;
     __shared__ uint64_t sdcoef[KW];
@@ -204,55 +204,52 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         }
         if (tid == 0) smaxdisp = dv;
     }
+    // the pivots' next-stripe words as they stand (MODE 2 adds pass t's update
+    // below, once its pivots' words are in LDS)
+    if (MODE != 2 && nxt && tid < KW) simg_n[tid] = pn;
     __syncthreads();
     const int64_t maxdisp = smaxdisp;
-    if (MODE == 2) {
-        // tables of pass t's update of the next stripe word
-        for (int e = tid; e < 8 * 256; e += WIDE_THREADS) {
-            const int b = e >> 8, x = e & 255;
-            uint64_t a = 0;
-#pragma unroll
-            for (int t = 0; t < 8; t++)
-                if ((x >> t) & 1) a ^= spbt[8 * b + t];
-            tt[b][x] = a;
-        }
-        __syncthreads();
-    }
-    // the pivots' next-stripe words (in MODE 2 with pass t's update)
-    if (nxt && tid < KW) {
+    if (MODE == 2 && nxt && tid < KW) {
         uint64_t v = pn;
-        if (MODE == 2 && tid < rbar) {
-#pragma unroll
-            for (int b = 0; b < 8; b++) v ^= tt[b][(pct >> (8 * b)) & 255];
+        if (tid < rbar) {
+            for (int b = 0; b < KW; b++)
+                if ((pct >> b) & 1ull) v ^= spbt[b];
         }
         simg_n[tid] = v;
     }
-    __syncthreads();
-    for (int e = tid; e < 8 * 256; e += WIDE_THREADS) {
-        const int b = e >> 8, x = e & 255;
-        uint64_t a = 0, bb = 0, nn = 0;
+    // nibble tables, 256 threads each: the maps w and u, and pass t's update
+    // of the next stripe word (MODE 2) or this pass's (the others)
+    static_assert(WIDE_THREADS == 4 * 256, "four groups of 256 threads build the tables");
+    const int tb = (tid & 255) >> 4, tx = tid & 15;
+    auto build = [&](const uint64_t *img) {
+        uint64_t a = 0;
 #pragma unroll
-        for (int t = 0; t < 8; t++)
-            if ((x >> t) & 1) {
-                a ^= simg_w[8 * b + t];
-                bb ^= simg_u[8 * b + t];
-                if (nxt) nn ^= simg_n[8 * b + t];
-            }
-        tw[b][x] = a;
-        tu[b][x] = bb;
-        if (nxt) tn[b][x] = nn;
+        for (int t = 0; t < 4; t++)
+            if ((tx >> t) & 1) a ^= img[4 * tb + t];
+        return a;
+    };
+    if (tid < 256) tw[tb][tx] = build(simg_w);
+    else if (tid < 512) tu[tb][tx] = build(simg_u);
+    else if (tid < 768) {
+        if (MODE == 2) tt[tb][tx] = build(spbt);
+    } else if (MODE != 2 && nxt) {
+        tn[tb][tx] = build(simg_n);
     }
     __syncthreads();
+    if (MODE == 2) {
+        if (nxt && tid < 256) tn[tb][tx] = build(simg_n);
+        __syncthreads();
+    }
     if (spec_blk && tid < nspec) {
         // old word, then (MODE 2) pass t's update, then this pass's: the
         // pivots' words in tn already carry pass t's update
         uint64_t v = so;
         if (MODE == 2) {
 #pragma unroll
-            for (int b = 0; b < 8; b++) v ^= tt[b][(sct >> (8 * b)) & 255];
+            for (int b = 0; b < 16; b++) v ^= tt[b][(sct >> (4 * b)) & 15];
         }
 #pragma unroll
-        for (int b = 0; b < 8; b++) v ^= tn[b][(scf >> (8 * b)) & 255];
+        for (int b = 0; b < 16; b++) v ^= tn[b][(scf >> (4 * b)) & 15];
         rec->spec_next[tid] = v;
     }
     for (int64_t i = ifirst; i < m; i += istep) {
@@ -267,7 +264,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
                 if (nxt && ct) {
                     uint64_t acc = 0;
 #pragma unroll
-                    for (int b = 0; b < 8; b++) acc ^= tt[b][(ct >> (8 * b)) & 255];
+                    for (int b = 0; b < 16; b++) acc ^= tt[b][(ct >> (4 * b)) & 15];
                     row[sw + 1] = (first ? f_nx : row[sw + 1]) ^ acc;
                 }
                 continue;
@@ -294,8 +291,8 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         if (v) {
             uint64_t u = 0;
 #pragma unroll
-            for (int b = 0; b < 8; b++) {
-                const int x = (int)((v >> (8 * b)) & 255);
+            for (int b = 0; b < 16; b++) {
+                const int x = (int)((v >> (4 * b)) & 15);
                 wv ^= tw[b][x];
                 u ^= tu[b][x];
             }
@@ -309,10 +306,10 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         if (nxt && (wv || ct)) {
             uint64_t acc = 0;
 #pragma unroll
-            for (int b = 0; b < 8; b++) acc ^= tn[b][(wv >> (8 * b)) & 255];
+            for (int b = 0; b < 16; b++) acc ^= tn[b][(wv >> (4 * b)) & 15];
             if (MODE == 2) {
 #pragma unroll
-                for (int b = 0; b < 8; b++) acc ^= tt[b][(ct >> (8 * b)) & 255];
+                for (int b = 0; b < 16; b++) acc ^= tt[b][(ct >> (4 * b)) & 15];
             }
             row[sw + 1] = (first ? f_nx : row[sw + 1]) ^ acc;
         }
