@@ -64,7 +64,7 @@ __global__ __launch_bounds__(64) void k_panel(uint64_t *A, int64_t m, int64_t n,
 
 // ---------------------------------------------------------------------------
 // k_permute: swaps, pivot staging, coefficients, L bits.
-//   blocks [0, nA): 64 word columns each, every special row (read all, then
+//   blocks [0, nA): PERM_A_COLS word columns each, every special row (read all, then
 //                   write all, so the permutation is applied in place);
 //   blocks [nA, ..): grid-stride over the other rows.
 // MODE 0: serial pass loop.
@@ -80,6 +80,11 @@ __global__ __launch_bounds__(64) void k_panel(uint64_t *A, int64_t m, int64_t n,
 //         the next stripe word gets both passes' updates (pass u's pivots'
 //         words there first get pass t's).
 // ---------------------------------------------------------------------------
+// Word columns per special-row block: 16 (128-byte row pieces) spreads the
+// special rows over four times as many blocks as 64 would, with two rows per
+// thread instead of eight, which shortens the chain of dependent loads.
+constexpr int PERM_A_COLS = 16;
+
 template <int MODE>
 __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__ A, int64_t m, int64_t ldw, int64_t c,
                                                           PassRec *__restrict__ rec, uint64_t *__restrict__ coef,
@@ -120,10 +125,10 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
     const int sh = (int)(r & 63);
 
     if ((int)blockIdx.x < nA) {
-        constexpr int SLOTS = WIDE_THREADS / 64;         // 16
-        constexpr int PER = MAX_SPEC / SLOTS;            // 8
-        const int64_t w = (int64_t)blockIdx.x * 64 + (tid & 63);
-        const int slot = tid >> 6;
+        constexpr int SLOTS = WIDE_THREADS / PERM_A_COLS;  // 64
+        constexpr int PER = MAX_SPEC / SLOTS;              // 2
+        const int64_t w = (int64_t)blockIdx.x * PERM_A_COLS + (tid % PERM_A_COLS);
+        const int slot = tid / PERM_A_COLS;
         uint64_t nv[PER];
         int64_t srcs[PER];
 #pragma unroll
@@ -875,7 +880,7 @@ hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t 
 hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, PassRec *rec,
                           uint64_t *coef, uint64_t *PB, int mode, const PassRec *rect, const uint64_t *coefT,
                           uint64_t *coefP, const uint64_t *PBt, hipStream_t s, hipEvent_t done) {
-    const int nA = (int)((ldw + 63) / 64);
+    const int nA = (int)((ldw + PERM_A_COLS - 1) / PERM_A_COLS);
     int64_t rows_est = m - (c < m ? c : m);
     if (mode == 2) rows_est += KW;  // also the first pass's pivot rows
     if (rows_est < 1) rows_est = 1;
