@@ -23,10 +23,10 @@
 
 namespace gf2 {
 
-// Sparse-search registers of the batched kernels' panels (64 rows each): none,
-// their waves are already near the register limit, so these panels search
-// every row when their window runs out.
-constexpr int BATCH_SPR = 0;
+// The batched kernels' panels search every row in place when their window
+// runs out (no kept-row search): their waves are already near the register
+// limit.
+constexpr bool BATCH_KEPT = false;
 
 // Staged special-row lists of one pass, and the nibble tables of the maps
 // stripe word -> (w, u) for the other rows.
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(NW * 64) void k_batch(BatchArgs a) {
         __syncthreads();
         const int64_t nw = words_for(n);
         for (int64_t c = 0; c < n && m > 0; c += KW) {
-            if (wave == 0) panel_body<WQ, 0, BATCH_SPR>(A, m, n, ldw, c, rec, rec, P, Q, rank, gsv, gsid, PL, lane);
+            if (wave == 0) panel_body<WQ, 0, BATCH_KEPT>(A, m, n, ldw, c, rec, rec, P, Q, rank, gsv, gsid, PL, lane);
             __syncthreads();
             const int active = ld_dev(&rec->active);
             const int64_t r = ld_dev(&rec->r);

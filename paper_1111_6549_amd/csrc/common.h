@@ -16,9 +16,6 @@ constexpr int WIN_Q = 8;
 constexpr int MAX_SPEC = 2 * KW;
 // Rows the slow pivot search keeps in LDS; beyond this it uses workspace.
 constexpr int SLOW_LDS_ROWS = 9216;
-// Rows with a non-zero stripe word the slow search holds in registers (64 per
-// register) in the one-wave panels; with more it searches every row.
-constexpr int SPARSE_CAP = 512;
 // Pass records kept in the workspace ring: a pass's record is still read by
 // the fused update of its pair while the panel two passes later writes its own.
 constexpr int NREC = 4;

@@ -109,7 +109,7 @@ struct PairPanel {
 // pass's r; it is read before `rec` is written, so the two may be the same
 // record), `rec` receives this pass.  Writes P[r..r+rbar), Q[r..r+rbar)
 // and *rank_out = r + rbar.
-template <int WQ, int SR, int SPR = SPARSE_CAP / 64>
+template <int WQ, int SR, bool KEPT = true>
 __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c,
                                            const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
                                            int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelLdsT<SR> &L,
@@ -474,16 +474,16 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
     // those whose stripe word is not zero (word, position, first position, in
     // row order): a row with a zero stripe word is never a pivot and no
     // elimination changes it; only its position can change, when a pivot is
-    // swapped into its place.  The search then runs on the kept rows alone:
-    // held in registers when at most 64 SPR, else in LDS or workspace.  The
-    // batched kernels' panels (SPR = 0) search every row in place.
+    // swapped into its place.  The search then runs on the kept rows alone,
+    // in LDS or workspace.  The batched kernels' panels (KEPT = false) search
+    // every row in place.
     if (slow) {
         if (patch) fix_wait();  // the fix's stores, before every row is read back
         npiv = 0;
         my_q = 0;
         my_fin = 0;
         my_p = 0;
-        if constexpr (SPR == 0) {
+        if constexpr (!KEPT) {
             uint64_t *sv = rows <= SR ? L.sv : gsv;
             int32_t *sid = rows <= SR ? L.sid : gsid;
             uint64_t orv = 0;
@@ -632,227 +632,149 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
             };
             int my_id = 0;
             int nsp = 0;  // special rows listed
-            if (nc <= 64 * SPR) {
-                constexpr int R = SPR;
-                // kept row 64 q + lane: word, position now, first position
-                uint64_t ev[R];
-                int ep[R], ei[R];
+            // The kept rows are searched lazily, in row order.  Slots
+            // [0, wn) form the window, reduced by every pivot found so far;
+            // the rest are as read.  A slot's position never changes, and
+            // the active slots (position at or below npiv) are in position
+            // order: a swap exchanges the pivot's and the npiv row's word
+            // and first position between their two slots, and a pivot that
+            // takes a zero row's place is retired (position -1).  A
+            // column's pivot is then the first active slot with its bit,
+            // and only the slots after it can need the elimination.
+            constexpr int MB = 4;  // 64-slot groups taken into the window at a time
+            int wn = 0, head = 0;  // slots before head are not active
+            const uint64_t or_raw = orv;  // union of the kept rows as read
+            uint64_t or_pe = 0;           // union of the pivots' parts above their columns
+            uint64_t or_win = 0;          // contains the union of the window rows
+            // take slots [wn, wn + 64 MB) into the window: reduce them by
+            // the pivots so far, in order; returns the union of their words
+            auto extend = [&]() -> uint64_t {
+                uint64_t v[MB];
 #pragma unroll
-                for (int q = 0; q < R; q++) {
-                    const int k = 64 * q + lane;
-                    ev[q] = k < nc ? cv[k] : 0ull;
-                    ep[q] = k < nc ? ci[k] : INT32_MAX;
-                    ei[q] = ep[q];
+                for (int u = 0; u < MB; u++) {
+                    const int k = wn + 64 * u + lane;
+                    v[u] = k < nc ? cv[k] : 0ull;
                 }
-                for (int j = 0; j < kp && npiv < rows; j++) {
-                    if (!((orv >> j) & 1ull)) continue;  // no remaining row has a 1 here
-                    // pivot: the row at or below npiv with bit j at the lowest position
-                    uint64_t key = ~0ull;
+                for (int l = 0; l < npiv; l++) {
+                    const int ql = readlane32(my_q, l);
+                    const uint64_t pel = readlane64(my_fin, l) & above(ql);
 #pragma unroll
-                    for (int q = 0; q < R; q++) {
-                        const uint64_t kq = ((uint64_t)(uint32_t)ep[q] << 16) | ((uint64_t)q << 6) | (uint64_t)lane;
-                        key = (ep[q] >= npiv && ((ev[q] >> j) & 1ull) && kq < key) ? kq : key;
-                    }
-                    key = wave_min64(key);
-                    if (key == ~0ull) continue;  // unreachable: orv says a row has bit j
-                    const int found = uni((int)(key >> 16));
-                    const int fq = uni((int)((key >> 6) & 63));
-                    const int fl = uni((int)(key & 63));
-                    uint64_t pv = 0;
-                    int pid = 0;
-#pragma unroll
-                    for (int q = 0; q < R; q++)
-                        if (q == fq) {
-                            pv = readlane64(ev[q], fl);
-                            pid = readlane32(ei[q], fl);
-                        }
-                    if (found != npiv) {
-                        // the row at position npiv takes the pivot's place
-                        bool kept = false;
-#pragma unroll
-                        for (int q = 0; q < R; q++) {
-                            const bool o = ep[q] == npiv;
-                            kept = kept || __ballot(o) != 0;
-                            ep[q] = o ? found : ep[q];
-                        }
-                        if (!kept) move_zero_row(found);
-                    }
-#pragma unroll
-                    for (int q = 0; q < R; q++)
-                        if (q == fq) ep[q] = lane == fl ? npiv : ep[q];
-                    my_q = writelane32(my_q, j, npiv);
-                    my_fin = writelane64(my_fin, pv, npiv);
-                    my_p = writelane32(my_p, found, npiv);
-                    my_id = writelane32(my_id, pid, npiv);
-                    const uint64_t pe = pv & above(j);
-                    uint64_t o = 0;
-#pragma unroll
-                    for (int q = 0; q < R; q++) {
-                        if (ep[q] > npiv) {
-                            ev[q] = ((ev[q] >> j) & 1ull) ? ev[q] ^ pe : ev[q];
-                            o |= ev[q];
-                        }
-                    }
-                    orv = wave_or64(o);
-                    npiv = uni(npiv + 1);
+                    for (int u = 0; u < MB; u++) v[u] = ((v[u] >> ql) & 1ull) ? v[u] ^ pel : v[u];
                 }
-                nsp = npiv;
+                uint64_t o = 0;
 #pragma unroll
-                for (int q = 0; q < R; q++) {
-                    const bool f = ep[q] != INT32_MAX && ep[q] >= npiv && ep[q] != ei[q];
-                    const uint64_t msk = __ballot(f);
-                    if (f) {
-                        const int idx = nsp + __popcll(msk & lt);
-                        L.dst[idx] = r + ep[q];
-                        L.src[idx] = r + ei[q];
-                    }
-                    nsp += __popcll(msk);
+                for (int u = 0; u < MB; u++) {
+                    const int k = wn + 64 * u + lane;
+                    if (k < nc) cv[k] = v[u];
+                    o |= v[u];
                 }
-            } else {
-                // The kept rows are searched lazily, in row order: rows [0, wn)
-                // form the window, reduced by every pivot found so far; the rest
-                // are as read and keep their positions.  A column's search
-                // takes more rows into the window only while the window has
-                // no candidate.
-                constexpr int MB = 4;  // 64-row groups taken into the window at a time
-                int wn = 0;
-                const uint64_t or_raw = orv;  // union of the kept rows as read
-                uint64_t or_pe = 0;           // union of the pivots' parts above their columns
-                uint64_t or_win = 0;          // union of the window rows at or below npiv
-                // take kept rows [wn, wn + 64 MB) into the window: reduce them by
-                // the pivots so far, in order; returns the union of their words
-                auto extend = [&]() -> uint64_t {
+                wn = wn + 64 * MB < nc ? wn + 64 * MB : nc;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                return wave_or64(o);
+            };
+            for (int j = 0; j < kp && npiv < rows; j++) {
+                // a kept row at position npiv belongs in the window
+                while (wn < nc && cp[wn] <= npiv) or_win |= extend();
+                // a row outside the window has bit j only if read with it or
+                // given it by a pivot
+                const uint64_t bound = or_win | (wn < nc ? (or_raw | or_pe) : 0ull);
+                if (!((bound >> j) & 1ull)) continue;
+                // from head: the first active slot (h) and the first with bit j
+                int h = -1, kf = -1;
+                for (int s0 = head;; s0 += 64) {
+                    // the group [s0, s0 + 64) lies in the window, or the
+                    // window holds every kept row
+                    if (s0 + 64 > wn && wn < nc) or_win |= extend();
+                    if (s0 >= wn) break;
+                    const int k = s0 + lane;
+                    const bool in = k < wn;
+                    const int p = in ? cp[k] : -1;
+                    const uint64_t v = in ? cv[k] : 0ull;
+                    const bool act = p >= npiv;
+                    const uint64_t am = __ballot(act);
+                    if (h < 0 && am) h = s0 + (int)__builtin_ctzll(am);
+                    const uint64_t cm = __ballot(act && ((v >> j) & 1ull));
+                    if (cm) {
+                        kf = s0 + (int)__builtin_ctzll(cm);
+                        break;
+                    }
+                }
+                if (kf < 0) continue;  // column j has no pivot
+                h = uni(h);
+                kf = uni(kf);
+                const int found = cp[kf];
+                const int ph = cp[h];
+                const uint64_t pv = cv[kf];
+                const int pid = ci[kf];
+                const uint64_t vh = cv[h];
+                const int idh = ci[h];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                if (ph == npiv) {
+                    // the row at npiv is slot h: h now holds the pivot and
+                    // kf that row (kf == h: the pivot is in place)
+                    if (kf != h && lane == 0) {
+                        cv[h] = pv;
+                        ci[h] = pid;
+                        cv[kf] = vh;
+                        ci[kf] = idh;
+                    }
+                    head = h + 1;
+                } else {
+                    // a row with a zero stripe word is at npiv: it takes the
+                    // pivot's place, and the pivot's slot retires
+                    move_zero_row(found);
+                    if (lane == 0) cp[kf] = -1;
+                    if (kf == h) head = h + 1;
+                }
+                my_q = writelane32(my_q, j, npiv);
+                my_fin = writelane64(my_fin, pv, npiv);
+                my_p = writelane32(my_p, found, npiv);
+                my_id = writelane32(my_id, pid, npiv);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const uint64_t pe = pv & above(j);
+                or_pe |= pe;
+                or_win |= pe;
+                // slots before kf have no bit j; the row now in slot kf neither
+                for (int b0 = kf + 1; b0 < wn; b0 += 64 * MB) {
                     uint64_t v[MB];
+                    int p[MB];
 #pragma unroll
                     for (int u = 0; u < MB; u++) {
-                        const int k = wn + 64 * u + lane;
-                        v[u] = k < nc ? cv[k] : 0ull;
+                        const int k = b0 + 64 * u + lane;
+                        v[u] = k < wn ? cv[k] : 0ull;
+                        p[u] = k < wn ? cp[k] : -1;
                     }
-                    for (int l = 0; l < npiv; l++) {
-                        const int ql = readlane32(my_q, l);
-                        const uint64_t pel = readlane64(my_fin, l) & above(ql);
-#pragma unroll
-                        for (int u = 0; u < MB; u++) v[u] = ((v[u] >> ql) & 1ull) ? v[u] ^ pel : v[u];
-                    }
-                    uint64_t o = 0;
 #pragma unroll
                     for (int u = 0; u < MB; u++) {
-                        const int k = wn + 64 * u + lane;
-                        if (k < nc) cv[k] = v[u];
-                        o |= v[u];
+                        const int k = b0 + 64 * u + lane;
+                        if (p[u] > npiv && ((v[u] >> j) & 1ull)) cv[k] = v[u] ^ pe;
                     }
-                    wn = wn + 64 * MB < nc ? wn + 64 * MB : nc;
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                    return wave_or64(o);
-                };
-                // lowest (position, index) key of a window row in [k0, k1) at or
-                // below npiv with bit j; occ: the window row at position npiv
-                auto search = [&](const int k0, const int k1, const int j, int &occ) -> uint64_t {
-                    uint64_t key = ~0ull;
-                    for (int b0 = k0; b0 < k1; b0 += 64 * MB) {
-                        uint64_t v[MB];
-                        int p[MB];
-#pragma unroll
-                        for (int u = 0; u < MB; u++) {
-                            const int k = b0 + 64 * u + lane;
-                            v[u] = k < k1 ? cv[k] : 0ull;
-                            p[u] = k < k1 ? cp[k] : -1;
-                        }
-#pragma unroll
-                        for (int u = 0; u < MB; u++) {
-                            const int k = b0 + 64 * u + lane;
-                            const uint64_t kk = ((uint64_t)(uint32_t)p[u] << 31) | (uint64_t)(uint32_t)k;
-                            key = (p[u] >= npiv && ((v[u] >> j) & 1ull) && kk < key) ? kk : key;
-                            occ = p[u] == npiv ? k : occ;
-                        }
-                    }
-                    return wave_min64(key);
-                };
-                for (int j = 0; j < kp && npiv < rows; j++) {
-                    // a kept row at position npiv belongs in the window
-                    while (wn < nc && cp[wn] <= npiv) or_win |= extend();
-                    // a row outside the window has bit j only if read with it or
-                    // given it by a pivot
-                    const uint64_t bound = or_win | (wn < nc ? (or_raw | or_pe) : 0ull);
-                    if (!((bound >> j) & 1ull)) continue;
-                    int occ = -1;
-                    uint64_t key = search(0, wn, j, occ);
-                    while (key == ~0ull && wn < nc) {
-                        const int w0 = wn;
-                        or_win |= extend();
-                        int unused = -1;
-                        key = search(w0, wn, j, unused);
-                    }
-                    if (key == ~0ull) continue;  // column j has no pivot
-                    const int found = uni((int)(key >> 31));
-                    const int kf = uni((int)(key & 0x7fffffffull));
-                    const uint64_t om = __ballot(occ >= 0);
-                    const int ko = om ? readlane32(occ, __builtin_ctzll(om)) : -1;
-                    const uint64_t pv = cv[kf];
-                    const int pid = ci[kf];
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                    if (found != npiv) {
-                        if (ko >= 0) {
-                            if (lane == 0) cp[ko] = found;
-                        } else {
-                            move_zero_row(found);
-                        }
-                    }
-                    if (lane == 0) cp[kf] = npiv;
-                    my_q = writelane32(my_q, j, npiv);
-                    my_fin = writelane64(my_fin, pv, npiv);
-                    my_p = writelane32(my_p, found, npiv);
-                    my_id = writelane32(my_id, pid, npiv);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                    const uint64_t pe = pv & above(j);
-                    or_pe |= pe;
-                    uint64_t o = 0;
-                    for (int b0 = 0; b0 < wn; b0 += 64 * MB) {
-                        uint64_t v[MB];
-                        int p[MB];
-#pragma unroll
-                        for (int u = 0; u < MB; u++) {
-                            const int k = b0 + 64 * u + lane;
-                            v[u] = k < wn ? cv[k] : 0ull;
-                            p[u] = k < wn ? cp[k] : -1;
-                        }
-#pragma unroll
-                        for (int u = 0; u < MB; u++) {
-                            const int k = b0 + 64 * u + lane;
-                            if (p[u] > npiv) {
-                                const bool hit = (v[u] >> j) & 1ull;
-                                if (hit) cv[k] = v[u] ^ pe;
-                                o |= hit ? v[u] ^ pe : v[u];
-                            }
-                        }
-                    }
-                    or_win = wave_or64(o);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                    npiv = uni(npiv + 1);
                 }
-                // rows outside the window never moved
-                nsp = npiv;
-                for (int b0 = 0; b0 < wn; b0 += 64) {
-                    const int k = b0 + lane;
-                    const int p = k < wn ? cp[k] : -1;
-                    const int i0 = k < wn ? ci[k] : -1;
-                    const bool f = p >= npiv && p != i0;
-                    const uint64_t msk = __ballot(f);
-                    if (f) {
-                        const int idx = nsp + __popcll(msk & lt);
-                        L.dst[idx] = r + p;
-                        L.src[idx] = r + i0;
-                    }
-                    nsp += __popcll(msk);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                npiv = uni(npiv + 1);
+            }
+            // slots outside the window never moved; retired ones are pivots
+            nsp = npiv;
+            for (int b0 = 0; b0 < wn; b0 += 64) {
+                const int k = b0 + lane;
+                const int p = k < wn ? cp[k] : -1;
+                const int i0 = k < wn ? ci[k] : -1;
+                const bool f = p >= npiv && p != i0;
+                const uint64_t msk = __ballot(f);
+                if (f) {
+                    const int idx = nsp + __popcll(msk & lt);
+                    L.dst[idx] = r + p;
+                    L.src[idx] = r + i0;
                 }
+                nsp += __popcll(msk);
             }
             // special rows: the pivots in order, then the displaced rows by
             // position (listed above in any order, ranked here)

@@ -1,0 +1,130 @@
+"""CPU check of the panel's kept-row slow search, as a model (Algorithm 1's
+pivot search, Section 3.1): the kernel searches only the rows with a
+non-zero stripe word, lazily, in a window that keeps its active rows in
+position order.  This model follows the same steps and must pick the same
+pivot, at the same position, with the same reduced word, as the eager
+search over every row that Algorithm 1 describes.  It pins the design; the
+GPU parity tests pin the kernel itself."""
+import random
+
+import pytest
+
+MASK = (1 << 64) - 1
+
+
+def above(j):
+    return 0 if j >= 63 else ((~0 << (j + 1)) & MASK)
+
+
+def eager(vals, kp):
+    """Every remaining row, eliminated at once: the definition."""
+    rows = list(vals)
+    ids = list(range(len(vals)))
+    npiv, out = 0, []
+    for j in range(kp):
+        if npiv >= len(rows):
+            break
+        f = next((p for p in range(npiv, len(rows)) if (rows[p] >> j) & 1), None)
+        if f is None:
+            continue
+        rows[f], rows[npiv] = rows[npiv], rows[f]
+        ids[f], ids[npiv] = ids[npiv], ids[f]
+        pv = rows[npiv]
+        for p in range(npiv + 1, len(rows)):
+            if (rows[p] >> j) & 1:
+                rows[p] ^= pv & above(j)
+        out.append((j, f, ids[npiv], pv))
+        npiv += 1
+    return out
+
+
+def kept_lazy(vals, kp, group=4):
+    """The kernel's form: kept rows only, a window reduced by the pivots so
+    far, slot positions fixed, swaps by exchanging slot contents or retiring
+    the pivot's slot when a zero row sits at the rank position."""
+    kept = [(v, p) for p, v in enumerate(vals) if v]
+    nc = len(kept)
+    cv = [v for v, _ in kept]
+    ci = [p for _, p in kept]
+    cp = [p for _, p in kept]
+    or_raw = 0
+    for v in cv:
+        or_raw |= v
+    piv, out = [], []
+    npiv = wn = head = 0
+    or_pe = or_win = 0
+
+    def extend():
+        nonlocal wn
+        o = 0
+        for k in range(wn, min(nc, wn + 64 * group)):
+            v = cv[k]
+            for q, fin in piv:
+                if (v >> q) & 1:
+                    v ^= fin & above(q)
+            cv[k] = v
+            o |= v
+        wn = min(nc, wn + 64 * group)
+        return o
+
+    for j in range(kp):
+        if npiv >= len(vals):
+            break
+        while wn < nc and cp[wn] <= npiv:
+            or_win |= extend()
+        bound = or_win | ((or_raw | or_pe) if wn < nc else 0)
+        if not (bound >> j) & 1:
+            continue
+        h = kf = -1
+        s0 = head
+        while True:
+            if s0 + 64 > wn and wn < nc:
+                or_win |= extend()
+            if s0 >= wn:
+                break
+            for k in range(s0, min(s0 + 64, wn)):
+                act = cp[k] >= npiv
+                if h < 0 and act:
+                    h = k
+                if act and (cv[k] >> j) & 1:
+                    kf = k
+                    break
+            if kf >= 0:
+                break
+            s0 += 64
+        if kf < 0:
+            continue
+        found, pv, pid = cp[kf], cv[kf], ci[kf]
+        if cp[h] == npiv:
+            if kf != h:
+                cv[h], ci[h], cv[kf], ci[kf] = pv, pid, cv[h], ci[h]
+            head = h + 1
+        else:
+            cp[kf] = -1
+            if kf == h:
+                head = h + 1
+        piv.append((j, pv))
+        out.append((j, found, pid, pv))
+        pe = pv & above(j)
+        or_pe |= pe
+        or_win |= pe
+        for k in range(kf + 1, wn):
+            if cp[k] > npiv and (cv[k] >> j) & 1:
+                cv[k] ^= pe
+        npiv += 1
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_kept_row_search_matches_eager(seed):
+    rng = random.Random(seed)
+    for _ in range(60):
+        n = rng.choice([1, 63, 64, 65, 257, 700, 1500])
+        d = rng.choice([0.001, 0.005, 0.02, 0.08, 0.5])
+        zero_heavy = rng.random() < 0.3
+        vals = [0 if (zero_heavy and rng.random() < 0.7) else
+                sum(1 << b for b in range(64) if rng.random() < d) for _ in range(n)]
+        kp = rng.choice([64, 64, 17, 1])
+        want = eager(vals, kp)
+        for group in (1, 4):
+            assert kept_lazy(vals, kp, group) == want
