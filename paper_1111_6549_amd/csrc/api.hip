@@ -53,8 +53,9 @@ struct PleLayout {
 
 // workspace of gf2_ple: pass records (a ring of NREC) | coef[m] | coefP[m] |
 // coef2[m] | pivot block 64 x ldw | second pivot block | slow-search
-// values[m] | slow-search ids[m] and positions[m].  coefP, coef2 and the
-// second pivot block serve the fused update of a pair of passes.
+// values[m] | slow-search ids[m], positions[m] and per-64-row group counts.
+// coefP, coef2 and the second pivot block serve the fused update of a pair
+// of passes.
 PleLayout ple_layout(int64_t m, int64_t ldw) {
     PleLayout L;
     size_t off = 0;
@@ -73,7 +74,7 @@ PleLayout ple_layout(int64_t m, int64_t ldw) {
     L.gsv = off;
     off += align_up((size_t)m * 8);
     L.gsid = off;
-    off += align_up((size_t)m * 8);
+    off += align_up((size_t)m * 8 + ((size_t)m / 64 + 2) * 4);
     L.total = off;
     return L;
 }

@@ -33,6 +33,7 @@ struct PanelLdsT {
     uint64_t sv[SR > 0 ? SR : 1];
     int32_t sid[SR > 0 ? SR : 1];
     int32_t spos[SR > 0 ? SR : 1];
+    int32_t sgrp[SR > 0 ? SR / 64 + 1 : 1];
 };
 using PanelLds = PanelLdsT<SLOW_LDS_ROWS>;
 
@@ -116,10 +117,16 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                                            const int lane, PanelFix fix = PanelFix()) {
 #ifdef GF2_PANEL_TIMING
     uint64_t *dbg = gsv + (c >> 6) * 8;
+    uint64_t *dbg2 = gsv + 2048 + (c >> 6) * 8;  // phase sums of the kept-row search
 #define PANEL_STAMP(k) \
     if (lane == 0) dbg[k] = wall_clock64();
+#define PANEL_T0(t) const uint64_t t = wall_clock64();
+#define PANEL_ACC(k, t) \
+    if (lane == 0) dbg2[k] += wall_clock64() - t;
 #else
 #define PANEL_STAMP(k)
+#define PANEL_T0(t)
+#define PANEL_ACC(k, t)
 #endif
     PANEL_STAMP(0)
     const int64_t r = prev->r + prev->rbar;
@@ -566,10 +573,12 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
             uint64_t *cv = gsv;
             int32_t *ci = gsid;
             int32_t *cp = gsid + m;
+            int32_t *rg = gsid + 2 * m;  // per 64-slot group: pivots applied
             if constexpr (SR > 0) {
                 cv = L.sv;
                 ci = L.sid;
                 cp = L.spos;
+                rg = L.sgrp;
             }
             int nc = 0;
             uint64_t orv = 0;
@@ -612,6 +621,7 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                 cv = gsv;
                 ci = gsid;
                 cp = gsid + m;
+                rg = gsid + 2 * m;
                 keep(INT32_MAX);
             }
             // lane d: a row with a zero stripe word moved to position dzp (it
@@ -632,66 +642,44 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
             };
             int my_id = 0;
             int nsp = 0;  // special rows listed
-            // The kept rows are searched lazily, in row order.  Slots
-            // [0, wn) form the window, reduced by every pivot found so far;
-            // the rest are as read.  A slot's position never changes, and
-            // the active slots (position at or below npiv) are in position
-            // order: a swap exchanges the pivot's and the npiv row's word
-            // and first position between their two slots, and a pivot that
-            // takes a zero row's place is retired (position -1).  A
-            // column's pivot is then the first active slot with its bit,
-            // and only the slots after it can need the elimination.
-            constexpr int MB = 4;  // 64-slot groups taken into the window at a time
-            int wn = 0, head = 0;  // slots before head are not active
-            const uint64_t or_raw = orv;  // union of the kept rows as read
-            uint64_t or_pe = 0;           // union of the pivots' parts above their columns
-            uint64_t or_win = 0;          // contains the union of the window rows
-            // take slots [wn, wn + 64 MB) into the window: reduce them by
-            // the pivots so far, in order; returns the union of their words
-            auto extend = [&]() -> uint64_t {
-                uint64_t v[MB];
-#pragma unroll
-                for (int u = 0; u < MB; u++) {
-                    const int k = wn + 64 * u + lane;
-                    v[u] = k < nc ? cv[k] : 0ull;
-                }
-                for (int l = 0; l < npiv; l++) {
-                    const int ql = readlane32(my_q, l);
-                    const uint64_t pel = readlane64(my_fin, l) & above(ql);
-#pragma unroll
-                    for (int u = 0; u < MB; u++) v[u] = ((v[u] >> ql) & 1ull) ? v[u] ^ pel : v[u];
-                }
-                uint64_t o = 0;
-#pragma unroll
-                for (int u = 0; u < MB; u++) {
-                    const int k = wn + 64 * u + lane;
-                    if (k < nc) cv[k] = v[u];
-                    o |= v[u];
-                }
-                wn = wn + 64 * MB < nc ? wn + 64 * MB : nc;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                return wave_or64(o);
-            };
+            // The kept rows are searched in row order and reduced lazily.
+            // A slot's position never changes, and the active slots (position
+            // at or below npiv) are in position order: a swap exchanges the
+            // pivot's and the npiv row's word and first position between their
+            // two slots, and a pivot that takes a zero row's place is retired
+            // (position -1).  A column's pivot is then the first active slot
+            // with its bit.  Each 64-slot group records how many pivots have
+            // been applied to it (in order); a group is brought up to date
+            // when the search reaches it, so no elimination pass is needed.
+            // Whether a column can have a pivot at all is bounded by the union
+            // of the rows as read and the pivots' parts above their columns.
+            int head = 0;  // slots before head are not active
+            uint64_t or_pe = 0;
+            for (int g = lane; g < (nc + 63) / 64; g += 64) rg[g] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             for (int j = 0; j < kp && npiv < rows; j++) {
-                // a kept row at position npiv belongs in the window
-                while (wn < nc && cp[wn] <= npiv) or_win |= extend();
-                // a row outside the window has bit j only if read with it or
-                // given it by a pivot
-                const uint64_t bound = or_win | (wn < nc ? (or_raw | or_pe) : 0ull);
-                if (!((bound >> j) & 1ull)) continue;
+                if (!(((orv | or_pe) >> j) & 1ull)) continue;  // no row can have a 1 here
+                PANEL_T0(ts0)
                 // from head: the first active slot (h) and the first with bit j
                 int h = -1, kf = -1;
-                for (int s0 = head;; s0 += 64) {
-                    // the group [s0, s0 + 64) lies in the window, or the
-                    // window holds every kept row
-                    if (s0 + 64 > wn && wn < nc) or_win |= extend();
-                    if (s0 >= wn) break;
+                for (int s0 = head & ~63; s0 < nc; s0 += 64) {
+                    const int g = s0 >> 6;
                     const int k = s0 + lane;
-                    const bool in = k < wn;
+                    const bool in = k < nc;
+                    uint64_t v = in ? cv[k] : 0ull;
                     const int p = in ? cp[k] : -1;
-                    const uint64_t v = in ? cv[k] : 0ull;
+                    const int done = uni(rg[g]);
+                    if (done < npiv) {
+                        for (int l = done; l < npiv; l++) {
+                            const int ql = readlane32(my_q, l);
+                            const uint64_t pel = readlane64(my_fin, l) & above(ql);
+                            v = ((v >> ql) & 1ull) ? v ^ pel : v;
+                        }
+                        if (in) cv[k] = v;
+                        if (lane == 0) rg[g] = npiv;
+                    }
                     const bool act = p >= npiv;
                     const uint64_t am = __ballot(act);
                     if (h < 0 && am) h = s0 + (int)__builtin_ctzll(am);
@@ -701,7 +689,12 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                         break;
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                PANEL_ACC(1, ts0)
                 if (kf < 0) continue;  // column j has no pivot
+                PANEL_T0(tx0)
                 h = uni(h);
                 kf = uni(kf);
                 const int found = cp[kf];
@@ -714,8 +707,8 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 if (ph == npiv) {
-                    // the row at npiv is slot h: h now holds the pivot and
-                    // kf that row (kf == h: the pivot is in place)
+                    // the row at npiv is slot h: h now holds the pivot and kf
+                    // that row (kf == h: the pivot is in place)
                     if (kf != h && lane == 0) {
                         cv[h] = pv;
                         ci[h] = pid;
@@ -734,39 +727,19 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                 my_fin = writelane64(my_fin, pv, npiv);
                 my_p = writelane32(my_p, found, npiv);
                 my_id = writelane32(my_id, pid, npiv);
+                or_pe |= pv & above(j);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                const uint64_t pe = pv & above(j);
-                or_pe |= pe;
-                or_win |= pe;
-                // slots before kf have no bit j; the row now in slot kf neither
-                for (int b0 = kf + 1; b0 < wn; b0 += 64 * MB) {
-                    uint64_t v[MB];
-                    int p[MB];
-#pragma unroll
-                    for (int u = 0; u < MB; u++) {
-                        const int k = b0 + 64 * u + lane;
-                        v[u] = k < wn ? cv[k] : 0ull;
-                        p[u] = k < wn ? cp[k] : -1;
-                    }
-#pragma unroll
-                    for (int u = 0; u < MB; u++) {
-                        const int k = b0 + 64 * u + lane;
-                        if (p[u] > npiv && ((v[u] >> j) & 1ull)) cv[k] = v[u] ^ pe;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                PANEL_ACC(2, tx0)
                 npiv = uni(npiv + 1);
             }
-            // slots outside the window never moved; retired ones are pivots
+            // slots that never moved have their first position
             nsp = npiv;
-            for (int b0 = 0; b0 < wn; b0 += 64) {
+            for (int b0 = 0; b0 < nc; b0 += 64) {
                 const int k = b0 + lane;
-                const int p = k < wn ? cp[k] : -1;
-                const int i0 = k < wn ? ci[k] : -1;
+                const int p = k < nc ? cp[k] : -1;
+                const int i0 = k < nc ? ci[k] : -1;
                 const bool f = p >= npiv && p != i0;
                 const uint64_t msk = __ballot(f);
                 if (f) {
@@ -923,6 +896,8 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
     }
     PANEL_STAMP(5)
 #undef PANEL_STAMP
+#undef PANEL_T0
+#undef PANEL_ACC
 }
 
 }  // namespace gf2
