@@ -43,13 +43,22 @@ def test_parity_sparse(m, n, p):
     assert_same_ple(gpu_ple(A, n), oracle_ple(A, n), "%dx%d p=%g" % (m, n, p))
 
 
-@pytest.mark.parametrize("x,seed", [(0.5, 11), (3.0, 14), (20.0, 18)])
+@pytest.mark.parametrize("x,seed", [(0.5, 11), (3.0, 14), (8.0, 16), (20.0, 18)])
 def test_parity_density_10000(x, seed):
     """Three points of the 10000 x 10000 sparse sweep (x non-zero entries per
     row on average), with the seeds the sweep in bench.py uses."""
     say("parity 10000^2 density", x)
     A = inputs.bernoulli(10000, 10000, seed, p=x / 10000)
     assert_same_ple(gpu_ple(A, 10000), oracle_ple(A, 10000), "10000^2 x=%g" % x)
+
+
+def test_parity_sparse_tall():
+    """30000 x 1500 with about 10 non-zero entries per row: the first stripes
+    keep more than 9216 rows with a non-zero stripe word, beyond the panel's
+    LDS, so the slow search runs on its workspace copy."""
+    say("parity sparse tall 30000x1500")
+    A = inputs.bernoulli(30000, 1500, 31, p=10 / 1500)
+    assert_same_ple(gpu_ple(A, 1500), oracle_ple(A, 1500), "30000x1500 sparse")
 
 
 @pytest.mark.parametrize("m,n,rho", [(600, 600, 300), (1000, 700, 650), (700, 1000, 700), (800, 800, 800),
