@@ -37,7 +37,7 @@ hipError_t launch_padding(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, 
 hipError_t launch_make_table(const uint64_t *rows, int64_t ldr, int k, int64_t nw, uint64_t *T, int64_t ldt,
                              hipStream_t s);
 hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t j0, int64_t j1,
-                             int64_t wq0, uint64_t *coef, uint64_t *PB, hipStream_t s);
+                             int64_t wq0, int64_t q0, uint64_t *coef, uint64_t *PB, hipStream_t s);
 }  // namespace gf2
 
 using namespace gf2;
@@ -444,7 +444,12 @@ gf2_status gf2_rref_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, con
         const int64_t j0 = b * KW;
         const int64_t j1 = j0 + KW < r ? j0 + KW : r;
         const int64_t wq0 = hq[(size_t)j0] >> 6;
-        if (launch_rref_block(A, ldw, nw, Q, j0, j1, wq0, coef, PB, s) != hipSuccess) return GF2_EHIP;
+        // contiguous pivot columns (the full-rank case): their bits are one
+        // funnel shift of a row's words
+        int64_t q0 = hq[(size_t)j0];
+        for (int64_t t = j0 + 1; t < j1; t++)
+            if (hq[(size_t)t] != hq[(size_t)j0] + (t - j0)) q0 = -1;
+        if (launch_rref_block(A, ldw, nw, Q, j0, j1, wq0, q0, coef, PB, s) != hipSuccess) return GF2_EHIP;
         if (launch_m4rm(A, ldw, j1, coef, 1, PB, ldw, (int)(j1 - j0), wq0, nw, 0, 0, s) != hipSuccess) return GF2_EHIP;
     }
     return hip_status(hipGetLastError());

@@ -20,10 +20,35 @@ __device__ __forceinline__ uint64_t rl64(uint64_t v, int l) {
 
 constexpr int RREF_THREADS = 256;
 
+// A row's bits at the block's pivot columns, bit t = column Q[j0 + t].  With
+// contiguous pivot columns (q0 = the first, q0 >= 0) that is one funnel
+// shift of the two words holding them; otherwise one bit at a time.
+__device__ __forceinline__ uint64_t pivot_bits(const uint64_t *row, const int64_t *sq, int nb, int64_t q0,
+                                               int64_t nw) {
+    if (q0 >= 0) {
+        const int64_t w = q0 >> 6;
+        const int sh = (int)(q0 & 63);
+        uint64_t c = row[w] >> sh;
+        if (sh && w + 1 < nw) c |= row[w + 1] << (64 - sh);
+        return nb == 64 ? c : (c & ((1ull << nb) - 1ull));
+    }
+    int64_t cw = -1;
+    uint64_t cur = 0, c = 0;
+    for (int t = 0; t < nb; t++) {
+        const int64_t q = sq[t];
+        if ((q >> 6) != cw) {
+            cw = q >> 6;
+            cur = row[cw];
+        }
+        c |= ((cur >> (q & 63)) & 1ull) << t;
+    }
+    return c;
+}
+
 __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__restrict__ A, int64_t ldw, int64_t nw,
                                                              const int64_t *__restrict__ Q, int64_t j0, int64_t j1,
                                                              int64_t wq0, uint64_t *__restrict__ coef,
-                                                             uint64_t *__restrict__ PB, int nA) {
+                                                             uint64_t *__restrict__ PB, int nA, int64_t q0) {
     __shared__ int64_t sq[KW];
     __shared__ uint64_t sY[KW];
     __shared__ uint64_t tab[8][256];
@@ -42,19 +67,7 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
     if (tid < 64) {  // wave 0: Y = U^-1
         const int lane = tid;
         uint64_t U = 0;
-        if (lane < nb) {
-            const uint64_t *row = A + (j0 + lane) * ldw;
-            int64_t cw = -1;
-            uint64_t cur = 0;
-            for (int t = 0; t < nb; t++) {
-                const int64_t q = sq[t];
-                if ((q >> 6) != cw) {
-                    cw = q >> 6;
-                    cur = row[cw];
-                }
-                U |= ((cur >> (q & 63)) & 1ull) << t;
-            }
-        }
+        if (lane < nb) U = pivot_bits(A + (j0 + lane) * ldw, sq, nb, q0, nw);
         uint64_t Y = 1ull << lane;
         for (int t = nb - 1; t >= 0; t--) {
             const uint64_t yt = rl64(Y, t);
@@ -77,17 +90,7 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
             coef[i] = sY[i - j0] ^ (1ull << (i - j0));
             continue;
         }
-        const uint64_t *row = A + i * ldw;
-        int64_t cw = -1;
-        uint64_t cur = 0, c = 0;
-        for (int t = 0; t < nb; t++) {
-            const int64_t q = sq[t];
-            if ((q >> 6) != cw) {
-                cw = q >> 6;
-                cur = row[cw];
-            }
-            c |= ((cur >> (q & 63)) & 1ull) << t;
-        }
+        const uint64_t c = pivot_bits(A + i * ldw, sq, nb, q0, nw);
         uint64_t w = 0;
         if (c) {
 #pragma unroll
@@ -98,14 +101,14 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
 }
 
 hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t j0, int64_t j1,
-                             int64_t wq0, uint64_t *coef, uint64_t *PB, hipStream_t s) {
+                             int64_t wq0, int64_t q0, uint64_t *coef, uint64_t *PB, hipStream_t s) {
     const int nA = (int)((nw - wq0 + 63) / 64);
     int nG = (int)((j1 + RREF_THREADS - 1) / RREF_THREADS);
     if (nG > 512) nG = 512;
     if (nG < 1) nG = 1;
     ProfScope ps(KID_RREF, s);
     hipLaunchKernelGGL(k_rref_block, dim3(nA + nG), dim3(RREF_THREADS), 0, s, (const uint64_t *)A, ldw, nw, Q, j0, j1,
-                       wq0, coef, PB, nA);
+                       wq0, coef, PB, nA, q0);
     return hipGetLastError();
 }
 
