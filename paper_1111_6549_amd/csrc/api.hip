@@ -37,7 +37,11 @@ hipError_t launch_padding(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, 
 hipError_t launch_make_table(const uint64_t *rows, int64_t ldr, int k, int64_t nw, uint64_t *T, int64_t ldt,
                              hipStream_t s);
 hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t j0, int64_t j1,
-                             int64_t wq0, int64_t q0, uint64_t *coef, uint64_t *PB, hipStream_t s);
+                             int64_t ws0, int64_t q0, int64_t jz, uint64_t *coef, uint64_t *PB, PassRec *rec,
+                             hipStream_t s);
+hipError_t launch_rref_pair(uint64_t *A, int64_t ldw, int64_t m, const uint64_t *coefT, const uint64_t *coefU,
+                            const uint64_t *PBt, const uint64_t *PBu, int64_t w_begin, int64_t w_end,
+                            const PassRec *rect, const PassRec *recu, hipStream_t s);
 }  // namespace gf2
 
 using namespace gf2;
@@ -79,15 +83,20 @@ PleLayout ple_layout(int64_t m, int64_t ldw) {
     return L;
 }
 
-// workspace of gf2_rref_from_ple: coef[m] | pivot block 64 x ldw
+// workspace of gf2_rref_from_ple: coef[m] | second block's coef[m] | pivot
+// block 64 x ldw | second pivot block | two block records (a fused pair of
+// blocks per sweep)
 struct RrefLayout {
-    size_t coef, pb, total;
+    size_t coef, coef2, pb, pb2, rec, total;
 };
 RrefLayout rref_layout(int64_t m, int64_t ldw) {
     RrefLayout L;
     L.coef = 0;
-    L.pb = align_up((size_t)m * 8);
-    L.total = L.pb + align_up((size_t)KW * (size_t)ldw * 8);
+    L.coef2 = align_up((size_t)m * 8);
+    L.pb = L.coef2 + align_up((size_t)m * 8);
+    L.pb2 = L.pb + align_up((size_t)KW * (size_t)ldw * 8);
+    L.rec = L.pb2 + align_up((size_t)KW * (size_t)ldw * 8);
+    L.total = L.rec + align_up(2 * sizeof(PassRec));
     return L;
 }
 
@@ -437,20 +446,49 @@ gf2_status gf2_rref_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, con
     if (hipMemcpy(hq.data(), Q, (size_t)r * 8, hipMemcpyDeviceToHost) != hipSuccess) return GF2_EHIP;
     char *base = (char *)ws;
     uint64_t *coef = (uint64_t *)(base + L.coef);
+    uint64_t *coef2 = (uint64_t *)(base + L.coef2);
     uint64_t *PB = (uint64_t *)(base + L.pb);
+    uint64_t *PB2 = (uint64_t *)(base + L.pb2);
+    PassRec *rect = (PassRec *)(base + L.rec), *recu = rect + 1;
     const int64_t nw = words_for(n);
     const int64_t nblk = (r + KW - 1) / KW;
-    for (int64_t b = nblk - 1; b >= 0; b--) {
-        const int64_t j0 = b * KW;
-        const int64_t j1 = j0 + KW < r ? j0 + KW : r;
-        const int64_t wq0 = hq[(size_t)j0] >> 6;
-        // contiguous pivot columns (the full-rank case): their bits are one
-        // funnel shift of a row's words
+    // contiguous pivot columns (the full-rank case): their bits are one
+    // funnel shift of a row's words; -1 otherwise
+    auto first_col = [&](int64_t j0, int64_t j1) {
         int64_t q0 = hq[(size_t)j0];
         for (int64_t t = j0 + 1; t < j1; t++)
             if (hq[(size_t)t] != hq[(size_t)j0] + (t - j0)) q0 = -1;
-        if (launch_rref_block(A, ldw, nw, Q, j0, j1, wq0, q0, coef, PB, s) != hipSuccess) return GF2_EHIP;
-        if (launch_m4rm(A, ldw, j1, coef, 1, PB, ldw, (int)(j1 - j0), wq0, nw, 0, 0, s) != hipSuccess) return GF2_EHIP;
+        return q0;
+    };
+    for (int64_t b = nblk - 1; b >= 0;) {
+        const int64_t j0 = b * KW;
+        const int64_t j1 = j0 + KW < r ? j0 + KW : r;
+        const int64_t wq0 = hq[(size_t)j0] >> 6;
+        if (b >= 1) {
+            // blocks b and b - 1 in one sweep.  Block b's update leaves the
+            // bits at block b - 1's pivot columns (left of its own) as they
+            // are, so both blocks' coefficients come from the rows as they
+            // stand; block b - 1's rows first take block b's update in the
+            // sweep's table build.
+            const int64_t j0u = j0 - KW;
+            const int64_t wq0u = hq[(size_t)j0u] >> 6;
+            if (launch_rref_block(A, ldw, nw, Q, j0, j1, wq0u, first_col(j0, j1), j1, coef, PB, rect, s) !=
+                hipSuccess)
+                return GF2_EHIP;
+            if (launch_rref_block(A, ldw, nw, Q, j0u, j0, wq0u, first_col(j0u, j0), j1, coef2, PB2, recu, s) !=
+                hipSuccess)
+                return GF2_EHIP;
+            if (launch_rref_pair(A, ldw, j1, coef, coef2, PB, PB2, wq0u, nw, rect, recu, s) != hipSuccess)
+                return GF2_EHIP;
+            b -= 2;
+        } else {
+            if (launch_rref_block(A, ldw, nw, Q, j0, j1, wq0, first_col(j0, j1), j1, coef, PB, nullptr, s) !=
+                hipSuccess)
+                return GF2_EHIP;
+            if (launch_m4rm(A, ldw, j1, coef, 1, PB, ldw, (int)(j1 - j0), wq0, nw, 0, 0, s) != hipSuccess)
+                return GF2_EHIP;
+            b -= 1;
+        }
     }
     return hip_status(hipGetLastError());
 }

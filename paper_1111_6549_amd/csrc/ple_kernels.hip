@@ -921,6 +921,37 @@ hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t
 // Fused update of a pair (t, u): words [sw_t + 3, nw) of rows r_t .. m-1,
 // and with pp.on the panel of pass t + 2 (inside the same launch, or alone
 // when no word is left to update).
+// The fused two-block sweep of the back-substitution: rows [0, m) and words
+// [w_begin, w_end) get two blocks' updates at once (the second block's rows
+// first take the first's), on the pair kernel's default schedule.
+hipError_t launch_rref_pair(uint64_t *A, int64_t ldw, int64_t m, const uint64_t *coefT, const uint64_t *coefU,
+                            const uint64_t *PBt, const uint64_t *PBu, int64_t w_begin, int64_t w_end,
+                            const PassRec *rect, const PassRec *recu, hipStream_t s) {
+    if (w_begin >= w_end || m <= 0) return hipSuccess;
+    const int64_t base = w_begin & ~(int64_t)(PR_TW - 1);
+    const int nt = (int)((w_end - base + PR_TW - 1) / PR_TW);
+    const int64_t slots = device_cus();
+    int64_t maxc = m / 256;
+    if (maxc < 1) maxc = 1;
+    if (maxc > 4 * slots) maxc = 4 * slots;
+    int nchunks = 1;
+    double best_eff = -1.0;
+    for (int64_t nc = 1; nc <= maxc; nc++) {
+        const int64_t g = nt * nc;
+        const int64_t rounds = (g + slots - 1) / slots;
+        const double eff = (double)g / (double)(rounds * slots) - 0.02 * (double)(rounds - 1);
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            nchunks = (int)nc;
+        }
+    }
+    const PairPanel none;
+    ProfScope ps(KID_M4RM, s);
+    hipLaunchKernelGGL((k_m4rm_pair<1024, 1, 2, true, true>), dim3(nt * nchunks), dim3(1024), 0, s, A, ldw, m, coefT,
+                       coefU, coefT, PBt, PBu, ldw, w_begin, w_end, nt, nchunks, rect, recu, none);
+    return hipGetLastError();
+}
+
 hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t ct, const PassRec *rect,
                               const PassRec *recu, const uint64_t *coefP, const uint64_t *coefU,
                               const uint64_t *coefT, const uint64_t *PBt, const uint64_t *PBu, int m4_target,

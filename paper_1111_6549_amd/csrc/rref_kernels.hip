@@ -45,24 +45,39 @@ __device__ __forceinline__ uint64_t pivot_bits(const uint64_t *row, const int64_
     return c;
 }
 
+// Rows [j1, jz) get a zero coefficient (rows below the block that a fused
+// pair's sweep also covers).  With rec, the block is described there as a
+// pass of pivots j0 .. j1 - 1 (their rows' positions in spec_src) for the
+// fused pair update.
 __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__restrict__ A, int64_t ldw, int64_t nw,
                                                              const int64_t *__restrict__ Q, int64_t j0, int64_t j1,
-                                                             int64_t wq0, uint64_t *__restrict__ coef,
-                                                             uint64_t *__restrict__ PB, int nA, int64_t q0) {
+                                                             int64_t ws0, uint64_t *__restrict__ coef,
+                                                             uint64_t *__restrict__ PB, int nA, int64_t q0, int64_t jz,
+                                                             PassRec *rec) {
     __shared__ int64_t sq[KW];
     __shared__ uint64_t sY[KW];
     __shared__ uint64_t tab[8][256];
     const int tid = threadIdx.x;
     const int nb = (int)(j1 - j0);
 
-    if ((int)blockIdx.x < nA) {  // stage the block rows' words >= wq0
-        const int64_t w = wq0 + (int64_t)blockIdx.x * 64 + (tid & 63);
+    if ((int)blockIdx.x < nA) {  // stage the block rows' words >= ws0
+        const int64_t w = ws0 + (int64_t)blockIdx.x * 64 + (tid & 63);
         if (w >= nw) return;
         for (int k = tid >> 6; k < nb; k += RREF_THREADS / 64) PB[(int64_t)k * ldw + w] = A[(j0 + k) * ldw + w];
         return;
     }
 
     if (tid < KW) sq[tid] = tid < nb ? Q[j0 + tid] : 0;
+    if (rec && (int)blockIdx.x == nA) {
+        if (tid < nb) rec->spec_src[tid] = j0 + tid;
+        if (tid == 0) {
+            rec->r = 0;
+            rec->rbar = nb;
+            rec->nspec = nb;
+            rec->active = nb > 0;
+            rec->slow = 0;
+        }
+    }
     __syncthreads();
     if (tid < 64) {  // wave 0: Y = U^-1
         const int lane = tid;
@@ -85,7 +100,11 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
     }
     __syncthreads();
     const int64_t nG = (int64_t)gridDim.x - nA;
-    for (int64_t i = ((int64_t)blockIdx.x - nA) * RREF_THREADS + tid; i < j1; i += nG * RREF_THREADS) {
+    for (int64_t i = ((int64_t)blockIdx.x - nA) * RREF_THREADS + tid; i < jz; i += nG * RREF_THREADS) {
+        if (i >= j1) {
+            coef[i] = 0;
+            continue;
+        }
         if (i >= j0) {
             coef[i] = sY[i - j0] ^ (1ull << (i - j0));
             continue;
@@ -101,14 +120,15 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
 }
 
 hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t j0, int64_t j1,
-                             int64_t wq0, int64_t q0, uint64_t *coef, uint64_t *PB, hipStream_t s) {
-    const int nA = (int)((nw - wq0 + 63) / 64);
-    int nG = (int)((j1 + RREF_THREADS - 1) / RREF_THREADS);
+                             int64_t ws0, int64_t q0, int64_t jz, uint64_t *coef, uint64_t *PB, PassRec *rec,
+                             hipStream_t s) {
+    const int nA = (int)((nw - ws0 + 63) / 64);
+    int nG = (int)((jz + RREF_THREADS - 1) / RREF_THREADS);
     if (nG > 512) nG = 512;
     if (nG < 1) nG = 1;
     ProfScope ps(KID_RREF, s);
     hipLaunchKernelGGL(k_rref_block, dim3(nA + nG), dim3(RREF_THREADS), 0, s, (const uint64_t *)A, ldw, nw, Q, j0, j1,
-                       wq0, coef, PB, nA, q0);
+                       ws0, coef, PB, nA, q0, jz, rec);
     return hipGetLastError();
 }
 

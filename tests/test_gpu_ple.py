@@ -162,7 +162,7 @@ def test_make_table_parity():
 
 
 @pytest.mark.parametrize("m,n,kind", [(300, 500, "u"), (1000, 1000, "u"), (700, 400, "r"), (129, 2000, "u"),
-                                      (2000, 700, "r"), (600, 600, "s")])
+                                      (2000, 700, "r"), (600, 600, "s"), (4096, 4096, "u"), (3000, 2500, "r")])
 def test_echelon_and_rref_parity(m, n, kind):
     say("echelon/rref", m, n, kind)
     import oracle
