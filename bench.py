@@ -427,12 +427,13 @@ def main():
     abytes64 = alg_bytes_k64(m, n, Qh, r)
 
     # the helpers of the paper's PLE-based reductions, on this result (not in
-    # the timed step): echelon form, and the reduced echelon form from L\E
+    # the timed step): echelon form, the reduced echelon form from L\E, and
+    # the reduced echelon form of the input in the M4RI form
     helpers = None
     if not args.no_helpers:
         res = work.clone()
         hk = {}
-        for name in ("echelon", "rref_from_ple"):
+        for name in ("echelon", "rref_from_ple", "m4ri_rref"):
             times = []
             for rep in range(2):  # the first also sets up the workspace
                 work.copy_(res)
@@ -440,8 +441,13 @@ def main():
                 h0 = time.perf_counter()
                 if name == "echelon":
                     G.echelon_from_ple(work, n, rank)
-                else:
+                elif name == "rref_from_ple":
                     G.rref_from_ple(work, n, Q, rank)
+                else:  # the M4RI form on the original matrix (not on the PLE result)
+                    work.copy_(pristine)
+                    torch.cuda.synchronize()
+                    h0 = time.perf_counter()
+                    G.m4ri_rref(work, n)
                 torch.cuda.synchronize()
                 times.append((time.perf_counter() - h0) * 1000.0)
             hk[name + "_ms"] = round(min(times), 3)

@@ -135,6 +135,22 @@ size_t gf2_rref_full_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf
 gf2_status gf2_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
                     void *ws, size_t ws_bytes, const gf2_ple_opts *opts, void *stream);
 
+/* Bytes of workspace gf2_m4ri_rref needs. */
+size_t gf2_m4ri_rref_workspace_bytes(int64_t m, int64_t n, int64_t ldw);
+
+/* Reduced row echelon form in the M4RI form (Appendix, Algorithms 5-8: each
+ * block of columns is eliminated from every row, above and below its
+ * pivots): in place, A <- RREF in rows 0..r-1 and zero below.  Each 64-column
+ * block is one PLE pass (pivot search, swaps, update of the rows below)
+ * followed by the block's reduction and its elimination from the rows above,
+ * on the same table kernels.  Q[0..r) receives the pivot columns, *rank the
+ * rank (device pointers, caller-owned); ws is device workspace of at least
+ * gf2_m4ri_rref_workspace_bytes, 256-byte aligned.  Stream-ordered; one
+ * host synchronisation once the rank may have reached m.  Errors as
+ * gf2_ple. */
+gf2_status gf2_m4ri_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *Q, int64_t *rank, void *ws,
+                         size_t ws_bytes, void *stream);
+
 /*
  * C ^= A * B over GF(2): the Four-Russians product that Algorithm 2 applies
  * to the trailing block (A22 <- L21 A12 + A22; M4RM, Section 3.2), as a

@@ -38,7 +38,7 @@ hipError_t launch_make_table(const uint64_t *rows, int64_t ldr, int k, int64_t n
                              hipStream_t s);
 hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t j0, int64_t j1,
                              int64_t ws0, int64_t q0, int64_t jz, uint64_t *coef, uint64_t *PB, PassRec *rec,
-                             hipStream_t s);
+                             hipStream_t s, const PassRec *drec = nullptr);
 hipError_t launch_rref_pair(uint64_t *A, int64_t ldw, int64_t m, const uint64_t *coefT, const uint64_t *coefU,
                             const uint64_t *PBt, const uint64_t *PBu, int64_t w_begin, int64_t w_end,
                             const PassRec *rect, const PassRec *recu, hipStream_t s);
@@ -211,8 +211,17 @@ static void pass_kinds(int64_t m, int64_t n, int mode, std::vector<int8_t> &kind
 // rows), so panel(t + 1) -- which reads only that word -- runs on a second
 // stream beside the update of the words beyond; the next permute waits for
 // both.
-hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
-                       void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync) {
+// The M4RI form (Algorithms 5-8: every 64-column block eliminated from all
+// rows): after each serial pass, the block's pivot rows are brought to
+// reduced form and removed from the rows above, with the back-substitution's
+// kernels (coef[m], pivot block 64 x ldw of its own).
+struct M4riStep {
+    uint64_t *coef = nullptr;
+    uint64_t *PB = nullptr;
+};
+
+static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
+                            void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, const M4riStep *m4ri) {
     const PleLayout L = ple_layout(m, ldw);
     const int64_t mn = m < n ? m : n;
     char *base = (char *)ws;
@@ -315,6 +324,16 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
                                 nullptr)) != hipSuccess)
             return e;
         if ((e = launch_update(A, m, n, ldw, c, rec, coef, PB, 1, m4v, m4t, s)) != hipSuccess) return e;
+        if (m4ri) {
+            // rows 0 .. r + rbar - 1 lie below c + KW (r <= c)
+            const int64_t jz = c + KW < m ? c + KW : m;
+            if ((e = launch_rref_block(A, ldw, npasses, Q, 0, 0, c >> 6, -2, jz, m4ri->coef, m4ri->PB, nullptr, s,
+                                       rec)) != hipSuccess)
+                return e;
+            if ((e = launch_m4rm(A, ldw, jz, m4ri->coef, 1, m4ri->PB, ldw, KW, c >> 6, npasses, 0, 0, s)) !=
+                hipSuccess)
+                return e;
+        }
         if (t + 1 >= npasses) break;
         if (c + KW >= m && allow_sync) {
             // rank <= m: once it reaches m the remaining passes are empty
@@ -332,6 +351,11 @@ hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *
         t += 1;
     }
     return hipGetLastError();
+}
+
+hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
+                       void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync) {
+    return pass_loop(A, m, n, ldw, P, Q, rank, ws, opts, s, allow_sync, nullptr);
 }
 
 }  // namespace gf2
@@ -491,6 +515,36 @@ gf2_status gf2_rref_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, con
         }
     }
     return hip_status(hipGetLastError());
+}
+
+size_t gf2_m4ri_rref_workspace_bytes(int64_t m, int64_t n, int64_t ldw) {
+    if (!sizes_ok(m, n, ldw)) return 0;
+    return ple_layout(m, ldw).total + align_up((size_t)m * 8) + align_up((size_t)KW * (size_t)ldw * 8) +
+           align_up((size_t)m * 8);
+}
+
+gf2_status gf2_m4ri_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *Q, int64_t *rank, void *ws,
+                         size_t ws_bytes, void *stream) {
+    if (!sizes_ok(m, n, ldw)) return GF2_EINVAL;
+    const int64_t mn = m < n ? m : n;
+    if (!rank || !aligned(rank, 8)) return GF2_EINVAL;
+    if (mn > 0 && (!Q || !aligned(Q, 8))) return GF2_EINVAL;
+    if (m > 0 && ldw > 0 && (!A || !aligned(A, 8))) return GF2_EINVAL;
+    if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;
+    if (ws_bytes < gf2_m4ri_rref_workspace_bytes(m, n, ldw)) return GF2_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t ple_bytes = ple_layout(m, ldw).total;
+    char *base = (char *)ws + ple_bytes;
+    M4riStep st;
+    st.coef = (uint64_t *)base;
+    st.PB = (uint64_t *)(base + align_up((size_t)m * 8));
+    int64_t *P = (int64_t *)(base + align_up((size_t)m * 8) + align_up((size_t)KW * (size_t)ldw * 8));
+    gf2_ple_opts o{};
+    o.lookahead = 1;  // serial passes: each block's elimination follows its pass
+    hipError_t e = pass_loop(A, m, n, ldw, P, Q, rank, ws, &o, s, true, &st);
+    if (e != hipSuccess) return hip_status(e);
+    if (m == 0 || ldw == 0) return GF2_OK;
+    return hip_status(launch_echelon(A, m, ldw, rank, s));
 }
 
 size_t gf2_rref_full_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf2_ple_opts *opts) {

@@ -49,11 +49,22 @@ __device__ __forceinline__ uint64_t pivot_bits(const uint64_t *row, const int64_
 // pair's sweep also covers).  With rec, the block is described there as a
 // pass of pivots j0 .. j1 - 1 (their rows' positions in spec_src) for the
 // fused pair update.
+//
+// With drec (the forward elimination of the M4RI form), the block is that
+// pass's pivot rows, r .. r + rbar - 1, just left by a PLE pass: a pivot
+// row's columns left of its pivot column hold L bits, which are masked
+// (only its E part enters U and the staged rows), and q0 = -2 asks the
+// kernel to find out itself whether the pivot columns are contiguous.
 __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__restrict__ A, int64_t ldw, int64_t nw,
                                                              const int64_t *__restrict__ Q, int64_t j0, int64_t j1,
                                                              int64_t ws0, uint64_t *__restrict__ coef,
                                                              uint64_t *__restrict__ PB, int nA, int64_t q0, int64_t jz,
-                                                             PassRec *rec) {
+                                                             PassRec *rec, const PassRec *drec) {
+    const bool mask_l = drec != nullptr;
+    if (drec) {
+        j0 = drec->r;
+        j1 = j0 + (drec->active ? drec->rbar : 0);
+    }
     __shared__ int64_t sq[KW];
     __shared__ uint64_t sY[KW];
     __shared__ uint64_t tab[8][256];
@@ -63,10 +74,18 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
     if ((int)blockIdx.x < nA) {  // stage the block rows' words >= ws0
         const int64_t w = ws0 + (int64_t)blockIdx.x * 64 + (tid & 63);
         if (w >= nw) return;
-        for (int k = tid >> 6; k < nb; k += RREF_THREADS / 64) PB[(int64_t)k * ldw + w] = A[(j0 + k) * ldw + w];
+        for (int k = tid >> 6; k < nb; k += RREF_THREADS / 64) {
+            uint64_t v = A[(j0 + k) * ldw + w];
+            if (mask_l) {  // the row's E part: columns from its pivot column on
+                const int64_t q = Q[j0 + k], b = w * 64;
+                v = q >= b + 64 ? 0ull : (q > b ? v & ~((1ull << (q - b)) - 1ull) : v);
+            }
+            PB[(int64_t)k * ldw + w] = v;
+        }
         return;
     }
 
+    __shared__ int64_t sq0;
     if (tid < KW) sq[tid] = tid < nb ? Q[j0 + tid] : 0;
     if (rec && (int)blockIdx.x == nA) {
         if (tid < nb) rec->spec_src[tid] = j0 + tid;
@@ -79,10 +98,21 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
         }
     }
     __syncthreads();
+    if (q0 == -2) {  // contiguous pivot columns?
+        if (tid == 0) {
+            int64_t f = nb > 0 ? sq[0] : -1;
+            for (int t = 1; t < nb; t++)
+                if (sq[t] != sq[0] + t) f = -1;
+            sq0 = f;
+        }
+        __syncthreads();
+        q0 = sq0;
+    }
     if (tid < 64) {  // wave 0: Y = U^-1
         const int lane = tid;
         uint64_t U = 0;
         if (lane < nb) U = pivot_bits(A + (j0 + lane) * ldw, sq, nb, q0, nw);
+        if (mask_l) U &= ~((1ull << lane) - 1ull);  // L bits (pivot columns left of its own)
         uint64_t Y = 1ull << lane;
         for (int t = nb - 1; t >= 0; t--) {
             const uint64_t yt = rl64(Y, t);
@@ -121,14 +151,14 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
 
 hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t j0, int64_t j1,
                              int64_t ws0, int64_t q0, int64_t jz, uint64_t *coef, uint64_t *PB, PassRec *rec,
-                             hipStream_t s) {
+                             hipStream_t s, const PassRec *drec) {
     const int nA = (int)((nw - ws0 + 63) / 64);
     int nG = (int)((jz + RREF_THREADS - 1) / RREF_THREADS);
     if (nG > 512) nG = 512;
     if (nG < 1) nG = 1;
     ProfScope ps(KID_RREF, s);
     hipLaunchKernelGGL(k_rref_block, dim3(nA + nG), dim3(RREF_THREADS), 0, s, (const uint64_t *)A, ldw, nw, Q, j0, j1,
-                       ws0, coef, PB, nA, q0, jz, rec);
+                       ws0, coef, PB, nA, q0, jz, rec, drec);
     return hipGetLastError();
 }
 

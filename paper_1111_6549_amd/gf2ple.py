@@ -25,6 +25,7 @@ STATUS = {0: "GF2_OK", 1: "GF2_EINVAL", 2: "GF2_EWORKSPACE", 3: "GF2_ENOMEM", 4:
 EXPORTS = [
     "gf2_version", "gf2_status_str", "gf2_ple_workspace_bytes", "gf2_ple", "gf2_ple_schedule", "gf2_echelon_from_ple",
     "gf2_rref_workspace_bytes", "gf2_rref_from_ple", "gf2_rref_full_workspace_bytes", "gf2_rref",
+    "gf2_m4ri_rref_workspace_bytes", "gf2_m4ri_rref",
     "gf2_addmul", "gf2_make_table", "gf2_check_padding", "gf2_profile_start", "gf2_profile_stop",
     "gf2_batch_plan_create", "gf2_batch_workspace_bytes", "gf2_ple_batched", "gf2_batch_plan_info",
     "gf2_batch_plan_destroy", "gf2_batch_num_configs", "gf2_batch_config_name",
@@ -104,6 +105,8 @@ def load():
         "gf2_rref_from_ple": (st, [p, i64, i64, i64, p, p, p, sz, p]),
         "gf2_rref_full_workspace_bytes": (sz, [i64, i64, i64, p]),
         "gf2_rref": (st, [p, i64, i64, i64, p, p, p, p, sz, p, p]),
+        "gf2_m4ri_rref_workspace_bytes": (sz, [i64, i64, i64]),
+        "gf2_m4ri_rref": (st, [p, i64, i64, i64, p, p, p, sz, p]),
         "gf2_addmul": (st, [p, i64, p, i64, p, i64, i64, i64, i64, p, p]),
         "gf2_make_table": (st, [p, i64, i32, i64, p, i64, p]),
         "gf2_check_padding": (st, [p, i64, i64, i64, p]),
@@ -258,6 +261,21 @@ def rref(A, n, ws=None, update=0):
     _check(lib.gf2_rref(_ptr(A), m, n, ldw, _ptr(P), _ptr(Q), _ptr(rank), _ptr(ws), ws.numel(), ctypes.byref(o),
                         _stream()), "gf2_rref")
     return P, Q, rank
+
+
+def m4ri_rref(A, n, ws=None):
+    """In-place RREF in the M4RI form.  Returns (Q, rank)."""
+    A = _packed(A, "A")
+    m, ldw = A.shape
+    lib = load()
+    need = int(lib.gf2_m4ri_rref_workspace_bytes(m, n, ldw))
+    if ws is None:
+        ws = alloc_workspace(need, A.device)
+    Q = torch.empty(max(min(m, n), 1), dtype=torch.int64, device=A.device)
+    rank = torch.empty(1, dtype=torch.int64, device=A.device)
+    _check(lib.gf2_m4ri_rref(_ptr(A), m, n, ldw, _ptr(Q), _ptr(rank), _ptr(ws), ws.numel(), _stream()),
+           "gf2_m4ri_rref")
+    return Q, rank
 
 
 def addmul(C, A, B, k, n, update=0, m4_variant=0, m4_blocks=0):

@@ -188,6 +188,28 @@ def test_echelon_and_rref_parity(m, n, kind):
     assert np.array_equal(to_host(t), R)
 
 
+@pytest.mark.parametrize("m,n,kind", [(300, 500, "u"), (1000, 1000, "u"), (700, 400, "r"), (129, 2000, "u"),
+                                      (2000, 700, "r"), (600, 600, "s"), (4096, 4096, "u"), (3000, 2500, "r"),
+                                      (1, 1, "u"), (64, 64, "u"), (65, 130, "r")])
+def test_m4ri_rref_parity(m, n, kind):
+    """The M4RI form (every block eliminated from all rows) against the
+    oracle's RREF, which is unique; Q against its pivot columns."""
+    say("m4ri rref", m, n, kind)
+    import oracle
+    if kind == "u":
+        A = inputs.bernoulli(m, n, 41 + m)
+    elif kind == "r":
+        A = inputs.known_rank(m, n, max(1, min(m, n) // 2), 7, 8)
+    else:
+        A = inputs.bernoulli(m, n, 42 + m, p=0.01)
+    t = to_dev(A)
+    Q, rank = G.m4ri_rref(t, n)
+    R, r2, Qo = oracle.rref(A, n)
+    assert int(rank.item()) == r2
+    assert np.array_equal(to_host(t), R)
+    assert np.array_equal(Q.cpu().numpy()[:r2], np.asarray(Qo)[:r2])
+
+
 def test_check_padding():
     A = inputs.bernoulli(50, 70, 3)
     t = to_dev(A)
