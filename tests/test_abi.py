@@ -58,6 +58,18 @@ def test_argument_errors_before_launch():
     assert lib.gf2_make_table(nul, 1, 0, 10, nul, 1, nul) == 1
     assert lib.gf2_make_table(nul, 1, 9, 10, nul, 1, nul) == 1
     assert lib.gf2_echelon_from_ple(nul, 3, 3, 1, nul, nul) == 1
+    # M4RI RREF: the same checks, then the workspace size (fake aligned
+    # addresses are never dereferenced: every check precedes the first launch)
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.gf2_m4ri_rref(fake, -1, 5, 1, fake, fake, fake, 1 << 20, nul) == 1
+    assert lib.gf2_m4ri_rref(fake, 5, 200, 2, fake, fake, fake, 1 << 20, nul) == 1
+    assert lib.gf2_m4ri_rref(fake, 5, 5, 1, fake, nul, fake, 1 << 20, nul) == 1
+    assert lib.gf2_m4ri_rref(fake, 5, 5, 1, nul, fake, fake, 1 << 20, nul) == 1
+    assert lib.gf2_m4ri_rref(fake, 5, 5, 1, fake, fake, ctypes.c_void_p((1 << 20) + 8), 1 << 20, nul) == 1
+    need = lib.gf2_m4ri_rref_workspace_bytes(5, 5, 1)
+    assert need > 0 and lib.gf2_m4ri_rref_workspace_bytes(5, 65, 1) == 0
+    assert lib.gf2_m4ri_rref(fake, 5, 5, 1, fake, fake, fake, need - 1, nul) == 2
+    assert lib.gf2_rref_from_ple(fake, 5, 5, 1, fake, fake, fake, 0, nul) == 2
 
 
 def test_batch_plan_rejects_bad_descriptors():
