@@ -70,6 +70,44 @@ def alg_bytes_k64(m, n, Q, r):
     return alg_bytes_m4rm(m, n, Q, r, [0] * ((n + 63) // 64))
 
 
+def alg_bytes_rref_from_ple(n, Q, r):
+    """Algorithmic bytes of the update launches of gf2_rref_from_ple: pivot
+    blocks of 64 rows from the last to the first, two per sweep; a sweep
+    covers rows 0 .. j1-1 (j1 = end of its later block) and the words from
+    the first pivot column of its earlier block to the end, 16 B per row
+    word (one read, one write)."""
+    nw = (n + 63) // 64
+    total = 0
+    b = (r + KW - 1) // KW - 1
+    while b >= 0:
+        j0 = b * KW
+        j1 = min(j0 + KW, r)
+        if b >= 1:
+            wq = int(Q[j0 - KW]) >> 6
+            b -= 2
+        else:
+            wq = int(Q[j0]) >> 6
+            b -= 1
+        total += 16 * j1 * (nw - wq)
+    return int(total)
+
+
+def alg_bytes_m4ri_rref(m, n, Q, r):
+    """Algorithmic bytes of the update launches of gf2_m4ri_rref: the serial
+    PLE passes (as alg_bytes_k64), and after each pass with a pivot the
+    elimination from rows 0 .. min(c + 64, m) - 1 over the words from the
+    pass's stripe to the end."""
+    import numpy as np
+    nw = (n + 63) // 64
+    q = np.asarray(Q[:r], dtype=np.int64)
+    counts = np.bincount(q // KW, minlength=nw) if r else np.zeros(nw, np.int64)
+    total = alg_bytes_k64(m, n, Q, r)
+    for t in range(nw):
+        if counts[t] > 0:
+            total += 16 * min(KW * t + KW, m) * (nw - t)
+    return int(total)
+
+
 def kernel_source_hash():
     """Hash of the sources the update kernels are compiled from (the fused
     pair update also runs the next panel)."""
@@ -451,6 +489,15 @@ def main():
                 torch.cuda.synchronize()
                 times.append((time.perf_counter() - h0) * 1000.0)
             hk[name + "_ms"] = round(min(times), 3)
+        # the update launches' algorithmic bytes over the whole call's time
+        # (a lower bound on their own rate: the call also syncs once and
+        # reads Q back)
+        for name, nb in (("rref_from_ple", alg_bytes_rref_from_ple(n, Qh, r)),
+                         ("m4ri_rref", alg_bytes_m4ri_rref(m, n, Qh, r))):
+            gbps = nb / (hk[name + "_ms"] * 1e-3) / 1e9
+            hk[name + "_update_bytes"] = nb
+            hk[name + "_alg_GBps"] = round(gbps, 1)
+            hk[name + "_frac_hbm"] = round(gbps / HBM_PEAK_GBPS, 4)
         helpers = hk
         del res
         log("helpers: %s" % json.dumps(helpers))

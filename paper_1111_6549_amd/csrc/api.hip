@@ -39,6 +39,10 @@ hipError_t launch_make_table(const uint64_t *rows, int64_t ldr, int k, int64_t n
 hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t j0, int64_t j1,
                              int64_t ws0, int64_t q0, int64_t jz, uint64_t *coef, uint64_t *PB, PassRec *rec,
                              hipStream_t s, const PassRec *drec = nullptr);
+hipError_t launch_rref_block2(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t ws0, int64_t jz,
+                              int64_t j0a, int64_t j1a, int64_t q0a, uint64_t *coefa, uint64_t *PBa, PassRec *reca,
+                              int64_t j0b, int64_t j1b, int64_t q0b, uint64_t *coefb, uint64_t *PBb, PassRec *recb,
+                              hipStream_t s);
 hipError_t launch_rref_pair(uint64_t *A, int64_t ldw, int64_t m, const uint64_t *coefT, const uint64_t *coefU,
                             const uint64_t *PBt, const uint64_t *PBu, int64_t w_begin, int64_t w_end,
                             const PassRec *rect, const PassRec *recu, hipStream_t s);
@@ -496,11 +500,8 @@ gf2_status gf2_rref_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, con
             // sweep's table build.
             const int64_t j0u = j0 - KW;
             const int64_t wq0u = hq[(size_t)j0u] >> 6;
-            if (launch_rref_block(A, ldw, nw, Q, j0, j1, wq0u, first_col(j0, j1), j1, coef, PB, rect, s) !=
-                hipSuccess)
-                return GF2_EHIP;
-            if (launch_rref_block(A, ldw, nw, Q, j0u, j0, wq0u, first_col(j0u, j0), j1, coef2, PB2, recu, s) !=
-                hipSuccess)
+            if (launch_rref_block2(A, ldw, nw, Q, wq0u, j1, j0, j1, first_col(j0, j1), coef, PB, rect, j0u, j0,
+                                   first_col(j0u, j0), coef2, PB2, recu, s) != hipSuccess)
                 return GF2_EHIP;
             if (launch_rref_pair(A, ldw, j1, coef, coef2, PB, PB2, wq0u, nw, rect, recu, s) != hipSuccess)
                 return GF2_EHIP;

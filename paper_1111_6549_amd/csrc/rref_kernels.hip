@@ -55,24 +55,30 @@ __device__ __forceinline__ uint64_t pivot_bits(const uint64_t *row, const int64_
 // row's columns left of its pivot column hold L bits, which are masked
 // (only its E part enters U and the staged rows), and q0 = -2 asks the
 // kernel to find out itself whether the pivot columns are contiguous.
-__global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__restrict__ A, int64_t ldw, int64_t nw,
-                                                             const int64_t *__restrict__ Q, int64_t j0, int64_t j1,
-                                                             int64_t ws0, uint64_t *__restrict__ coef,
-                                                             uint64_t *__restrict__ PB, int nA, int64_t q0, int64_t jz,
-                                                             PassRec *rec, const PassRec *drec) {
-    const bool mask_l = drec != nullptr;
-    if (drec) {
-        j0 = drec->r;
-        j1 = j0 + (drec->active ? drec->rbar : 0);
+struct RrefBlockArgs {
+    int64_t j0, j1, ws0, q0, jz;
+    uint64_t *coef, *PB;
+    PassRec *rec;
+    const PassRec *drec;
+    int nA;  // staging workgroups; the rest of the set's nwg write coefficients
+    int nwg;
+};
+
+// One workgroup (bid of the set's nwg) of a block's job.
+__device__ __forceinline__ void rref_block_body(const uint64_t *__restrict__ A, int64_t ldw, int64_t nw,
+                                                const int64_t *__restrict__ Q, const RrefBlockArgs &a, int bid,
+                                                int64_t *sq, uint64_t *sY, uint64_t (*tab)[256], int64_t *sq0) {
+    const bool mask_l = a.drec != nullptr;
+    int64_t j0 = a.j0, j1 = a.j1, q0 = a.q0;
+    if (a.drec) {
+        j0 = a.drec->r;
+        j1 = j0 + (a.drec->active ? a.drec->rbar : 0);
     }
-    __shared__ int64_t sq[KW];
-    __shared__ uint64_t sY[KW];
-    __shared__ uint64_t tab[8][256];
     const int tid = threadIdx.x;
     const int nb = (int)(j1 - j0);
 
-    if ((int)blockIdx.x < nA) {  // stage the block rows' words >= ws0
-        const int64_t w = ws0 + (int64_t)blockIdx.x * 64 + (tid & 63);
+    if (bid < a.nA) {  // stage the block rows' words >= ws0
+        const int64_t w = a.ws0 + (int64_t)bid * 64 + (tid & 63);
         if (w >= nw) return;
         for (int k = tid >> 6; k < nb; k += RREF_THREADS / 64) {
             uint64_t v = A[(j0 + k) * ldw + w];
@@ -80,21 +86,20 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
                 const int64_t q = Q[j0 + k], b = w * 64;
                 v = q >= b + 64 ? 0ull : (q > b ? v & ~((1ull << (q - b)) - 1ull) : v);
             }
-            PB[(int64_t)k * ldw + w] = v;
+            a.PB[(int64_t)k * ldw + w] = v;
         }
         return;
     }
 
-    __shared__ int64_t sq0;
     if (tid < KW) sq[tid] = tid < nb ? Q[j0 + tid] : 0;
-    if (rec && (int)blockIdx.x == nA) {
-        if (tid < nb) rec->spec_src[tid] = j0 + tid;
+    if (a.rec && bid == a.nA) {
+        if (tid < nb) a.rec->spec_src[tid] = j0 + tid;
         if (tid == 0) {
-            rec->r = 0;
-            rec->rbar = nb;
-            rec->nspec = nb;
-            rec->active = nb > 0;
-            rec->slow = 0;
+            a.rec->r = 0;
+            a.rec->rbar = nb;
+            a.rec->nspec = nb;
+            a.rec->active = nb > 0;
+            a.rec->slow = 0;
         }
     }
     __syncthreads();
@@ -103,10 +108,10 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
             int64_t f = nb > 0 ? sq[0] : -1;
             for (int t = 1; t < nb; t++)
                 if (sq[t] != sq[0] + t) f = -1;
-            sq0 = f;
+            *sq0 = f;
         }
         __syncthreads();
-        q0 = sq0;
+        q0 = *sq0;
     }
     if (tid < 64) {  // wave 0: Y = U^-1
         const int lane = tid;
@@ -123,20 +128,20 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
     __syncthreads();
     for (int e = tid; e < 8 * 256; e += RREF_THREADS) {
         const int b = e >> 8, x = e & 255;
-        uint64_t a = 0;
+        uint64_t y = 0;
         for (int t = 0; t < 8; t++)
-            if (((x >> t) & 1) && 8 * b + t < nb) a ^= sY[8 * b + t];
-        tab[b][x] = a;
+            if (((x >> t) & 1) && 8 * b + t < nb) y ^= sY[8 * b + t];
+        tab[b][x] = y;
     }
     __syncthreads();
-    const int64_t nG = (int64_t)gridDim.x - nA;
-    for (int64_t i = ((int64_t)blockIdx.x - nA) * RREF_THREADS + tid; i < jz; i += nG * RREF_THREADS) {
+    const int64_t nG = (int64_t)a.nwg - a.nA;
+    for (int64_t i = (int64_t)(bid - a.nA) * RREF_THREADS + tid; i < a.jz; i += nG * RREF_THREADS) {
         if (i >= j1) {
-            coef[i] = 0;
+            a.coef[i] = 0;
             continue;
         }
         if (i >= j0) {
-            coef[i] = sY[i - j0] ^ (1ull << (i - j0));
+            a.coef[i] = sY[i - j0] ^ (1ull << (i - j0));
             continue;
         }
         const uint64_t c = pivot_bits(A + i * ldw, sq, nb, q0, nw);
@@ -145,20 +150,74 @@ __global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__r
 #pragma unroll
             for (int b = 0; b < 8; b++) w ^= tab[b][(c >> (8 * b)) & 255];
         }
-        coef[i] = w;
+        a.coef[i] = w;
     }
+}
+
+__global__ __launch_bounds__(RREF_THREADS) void k_rref_block(const uint64_t *__restrict__ A, int64_t ldw, int64_t nw,
+                                                             const int64_t *__restrict__ Q, RrefBlockArgs a) {
+    __shared__ int64_t sq[KW];
+    __shared__ uint64_t sY[KW];
+    __shared__ uint64_t tab[8][256];
+    __shared__ int64_t sq0;
+    rref_block_body(A, ldw, nw, Q, a, (int)blockIdx.x, sq, sY, tab, &sq0);
+}
+
+// Two blocks' jobs in one launch (the two blocks of a fused back-substitution
+// sweep read the rows as they stand and write separate outputs): workgroups
+// below a.nwg take the first, the rest the second.
+__global__ __launch_bounds__(RREF_THREADS) void k_rref_block2(const uint64_t *__restrict__ A, int64_t ldw,
+                                                              int64_t nw, const int64_t *__restrict__ Q,
+                                                              RrefBlockArgs a, RrefBlockArgs b) {
+    __shared__ int64_t sq[KW];
+    __shared__ uint64_t sY[KW];
+    __shared__ uint64_t tab[8][256];
+    __shared__ int64_t sq0;
+    const int bid = (int)blockIdx.x;
+    if (bid < a.nwg)
+        rref_block_body(A, ldw, nw, Q, a, bid, sq, sY, tab, &sq0);
+    else
+        rref_block_body(A, ldw, nw, Q, b, bid - a.nwg, sq, sY, tab, &sq0);
+}
+
+static RrefBlockArgs rref_args(int64_t nw, int64_t j0, int64_t j1, int64_t ws0, int64_t q0, int64_t jz,
+                               uint64_t *coef, uint64_t *PB, PassRec *rec, const PassRec *drec) {
+    RrefBlockArgs a;
+    a.j0 = j0;
+    a.j1 = j1;
+    a.ws0 = ws0;
+    a.q0 = q0;
+    a.jz = jz;
+    a.coef = coef;
+    a.PB = PB;
+    a.rec = rec;
+    a.drec = drec;
+    a.nA = (int)((nw - ws0 + 63) / 64);
+    int nG = (int)((jz + RREF_THREADS - 1) / RREF_THREADS);
+    if (nG > 512) nG = 512;
+    if (nG < 1) nG = 1;
+    a.nwg = a.nA + nG;
+    return a;
 }
 
 hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t j0, int64_t j1,
                              int64_t ws0, int64_t q0, int64_t jz, uint64_t *coef, uint64_t *PB, PassRec *rec,
                              hipStream_t s, const PassRec *drec) {
-    const int nA = (int)((nw - ws0 + 63) / 64);
-    int nG = (int)((jz + RREF_THREADS - 1) / RREF_THREADS);
-    if (nG > 512) nG = 512;
-    if (nG < 1) nG = 1;
+    const RrefBlockArgs a = rref_args(nw, j0, j1, ws0, q0, jz, coef, PB, rec, drec);
     ProfScope ps(KID_RREF, s);
-    hipLaunchKernelGGL(k_rref_block, dim3(nA + nG), dim3(RREF_THREADS), 0, s, (const uint64_t *)A, ldw, nw, Q, j0, j1,
-                       ws0, coef, PB, nA, q0, jz, rec, drec);
+    hipLaunchKernelGGL(k_rref_block, dim3(a.nwg), dim3(RREF_THREADS), 0, s, (const uint64_t *)A, ldw, nw, Q, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rref_block2(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t ws0, int64_t jz,
+                              int64_t j0a, int64_t j1a, int64_t q0a, uint64_t *coefa, uint64_t *PBa, PassRec *reca,
+                              int64_t j0b, int64_t j1b, int64_t q0b, uint64_t *coefb, uint64_t *PBb, PassRec *recb,
+                              hipStream_t s) {
+    const RrefBlockArgs a = rref_args(nw, j0a, j1a, ws0, q0a, jz, coefa, PBa, reca, nullptr);
+    const RrefBlockArgs b = rref_args(nw, j0b, j1b, ws0, q0b, jz, coefb, PBb, recb, nullptr);
+    ProfScope ps(KID_RREF, s);
+    hipLaunchKernelGGL(k_rref_block2, dim3(a.nwg + b.nwg), dim3(RREF_THREADS), 0, s, (const uint64_t *)A, ldw, nw, Q,
+                       a, b);
     return hipGetLastError();
 }
 
