@@ -144,7 +144,7 @@ struct LookCtx {
     int dev = -1;
     hipStream_t user = nullptr;
     hipStream_t s2 = nullptr;
-    hipEvent_t evA = nullptr, evN = nullptr;
+    hipEvent_t evA = nullptr, evN = nullptr, evM = nullptr;
 };
 
 static LookCtx *look_ctx(hipStream_t user) {
@@ -164,7 +164,10 @@ static LookCtx *look_ctx(hipStream_t user) {
     // for the host, which delays the next kernel by microseconds)
     constexpr unsigned EV_FLAGS = hipEventDisableTiming | hipEventReleaseToDevice;
     if (hipEventCreateWithFlags(&c.evA, EV_FLAGS) != hipSuccess ||
-        hipEventCreateWithFlags(&c.evN, EV_FLAGS) != hipSuccess) {
+        hipEventCreateWithFlags(&c.evN, EV_FLAGS) != hipSuccess ||
+        hipEventCreateWithFlags(&c.evM, EV_FLAGS) != hipSuccess) {
+        if (c.evA) (void)hipEventDestroy(c.evA);
+        if (c.evN) (void)hipEventDestroy(c.evN);
         (void)hipStreamDestroy(c.s2);
         return nullptr;
     }
@@ -267,6 +270,15 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
         return e;
     bool pending = false;  // this pass's panel ran on the second stream
     int64_t since_check = 0;
+    // M4RI: a block's elimination from the rows above runs on the second
+    // stream, behind the PLE passes that follow it.  It writes rows below
+    // r + rbar only (rows whose coefficient is zero are not written), which
+    // no later pass touches; it reads the pass's record, so the passes may
+    // run at most one ahead of it (the record ring holds NREC >= 2).
+    static_assert(NREC >= 2, "the M4RI elimination of a pass reads its record while the next pass writes its own");
+    LookCtx *mc = m4ri ? look_ctx(s) : nullptr;
+    hipEvent_t m4_done[2] = {mc ? mc->evN : nullptr, mc ? mc->evM : nullptr};
+    int64_t m4_last = -1;  // last pass whose elimination went to the second stream
     for (int64_t t = 0; t < npasses;) {
         const int64_t c = t * KW;
         PassRec *rec = rec_of(t), *nxt = rec_of(t + 1);
@@ -331,12 +343,21 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
         if (m4ri) {
             // rows 0 .. r + rbar - 1 lie below c + KW (r <= c)
             const int64_t jz = c + KW < m ? c + KW : m;
-            if ((e = launch_rref_block(A, ldw, npasses, Q, 0, 0, c >> 6, -2, jz, m4ri->coef, m4ri->PB, nullptr, s,
+            hipStream_t ms = mc ? mc->s2 : s;
+            if (mc) {
+                if ((e = hipEventRecord(mc->evA, s)) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(ms, mc->evA, 0)) != hipSuccess) return e;
+            }
+            if ((e = launch_rref_block(A, ldw, npasses, Q, 0, 0, c >> 6, -2, jz, m4ri->coef, m4ri->PB, nullptr, ms,
                                        rec)) != hipSuccess)
                 return e;
-            if ((e = launch_m4rm(A, ldw, jz, m4ri->coef, 1, m4ri->PB, ldw, KW, c >> 6, npasses, 0, 0, s)) !=
+            if ((e = launch_m4rm(A, ldw, jz, m4ri->coef, 1, m4ri->PB, ldw, KW, c >> 6, npasses, 0, 0, ms)) !=
                 hipSuccess)
                 return e;
+            if (mc) {
+                if ((e = hipEventRecord(m4_done[t & 1], ms)) != hipSuccess) return e;
+                m4_last = t;
+            }
         }
         if (t + 1 >= npasses) break;
         if (c + KW >= m && allow_sync) {
@@ -349,11 +370,15 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
             }
             since_check = (since_check + 1) % 8;
         }
+        // the next panel rewrites a record: the elimination of the pass
+        // before this one must be done with its own
+        if (mc && t >= 1 && (e = hipStreamWaitEvent(s, m4_done[(t - 1) & 1], 0)) != hipSuccess) return e;
         if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, PanelFix(), false, s,
                               nullptr)) != hipSuccess)
             return e;
         t += 1;
     }
+    if (mc && m4_last >= 0 && (e = hipStreamWaitEvent(s, m4_done[m4_last & 1], 0)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
