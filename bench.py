@@ -33,7 +33,7 @@ KW = 64
 # launches of one PLE and scaled by the same counters on the 512 MiB restore copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Reported only while the kernel
 # sources hash to the value the counters were taken on.
-TRAFFIC = {"source": "5d27e2232d7f65b1", "n": 65536, "seed": 5, "bytes_per_launch": 366624719}
+TRAFFIC = {"source": "04ab9aea8fe485c0", "n": 65536, "seed": 5, "bytes_per_launch": 366610682}
 
 
 def log(*a):
@@ -92,19 +92,25 @@ def alg_bytes_rref_from_ple(n, Q, r):
     return int(total)
 
 
-def alg_bytes_m4ri_rref(m, n, Q, r):
-    """Algorithmic bytes of the update launches of gf2_m4ri_rref: the serial
-    PLE passes (as alg_bytes_k64), and after each pass with a pivot the
-    elimination from rows 0 .. min(c + 64, m) - 1 over the words from the
-    pass's stripe to the end."""
+def alg_bytes_m4ri_rref(m, n, Q, r, kinds):
+    """Algorithmic bytes of the update launches of gf2_m4ri_rref on the pass
+    schedule `kinds` (gf2_ple's, with look-ahead passes run serially): the
+    passes' own updates (as alg_bytes_m4rm), and after each pass or fused
+    pair with a pivot, the elimination of its block from the rows above the
+    next pass's first row over the words from its first stripe to the end."""
     import numpy as np
     nw = (n + 63) // 64
+    kinds = [0 if k == 1 else k for k in kinds]
     q = np.asarray(Q[:r], dtype=np.int64)
     counts = np.bincount(q // KW, minlength=nw) if r else np.zeros(nw, np.int64)
-    total = alg_bytes_k64(m, n, Q, r)
-    for t in range(nw):
-        if counts[t] > 0:
-            total += 16 * min(KW * t + KW, m) * (nw - t)
+    r_at = np.concatenate([[0], np.cumsum(counts)])
+    total = alg_bytes_m4rm(m, n, Q, r, kinds)
+    t = 0
+    while t < nw:
+        np_ = 2 if kinds[t] == 2 else 1
+        if counts[t:t + np_].sum() > 0:
+            total += 16 * int(r_at[t + np_]) * (nw - t)
+        t += np_
     return int(total)
 
 
@@ -493,7 +499,7 @@ def main():
         # (a lower bound on their own rate: the call also syncs once and
         # reads Q back)
         for name, nb in (("rref_from_ple", alg_bytes_rref_from_ple(n, Qh, r)),
-                         ("m4ri_rref", alg_bytes_m4ri_rref(m, n, Qh, r))):
+                         ("m4ri_rref", alg_bytes_m4ri_rref(m, n, Qh, r, G.ple_schedule(m, n, lookahead=0)))):
             gbps = nb / (hk[name + "_ms"] * 1e-3) / 1e9
             hk[name + "_update_bytes"] = nb
             hk[name + "_alg_GBps"] = round(gbps, 1)

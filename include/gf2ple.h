@@ -140,10 +140,13 @@ size_t gf2_m4ri_rref_workspace_bytes(int64_t m, int64_t n, int64_t ldw);
 
 /* Reduced row echelon form in the M4RI form (Appendix, Algorithms 5-8: each
  * block of columns is eliminated from every row, above and below its
- * pivots): in place, A <- RREF in rows 0..r-1 and zero below.  Each 64-column
- * block is one PLE pass (pivot search, swaps, update of the rows below)
- * followed by the block's reduction and its elimination from the rows above,
- * on the same table kernels.  Q[0..r) receives the pivot columns, *rank the
+ * pivots): in place, A <- RREF in rows 0..r-1 and zero below.  The blocks
+ * are the passes of gf2_ple's default schedule (a fused pair of 64-column
+ * passes is one 128-column block: pivot search, swaps, update of the rows
+ * below); each block is then reduced and eliminated from the rows above, on
+ * the same table kernels, on a second stream of the library's own behind the
+ * passes that follow (joined into `stream` before the call's last kernel).
+ * Q[0..r) receives the pivot columns, *rank the
  * rank (device pointers, caller-owned); ws is device workspace of at least
  * gf2_m4ri_rref_workspace_bytes, 256-byte aligned.  Stream-ordered; one
  * host synchronisation once the rank may have reached m.  Errors as

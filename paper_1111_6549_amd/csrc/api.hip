@@ -3,6 +3,7 @@
 // runs in the HIP kernels of ple_kernels.hip / rref_kernels.hip.
 #include <algorithm>
 #include <mutex>
+#include <deque>
 #include <vector>
 
 #include "../../include/gf2ple.h"
@@ -42,7 +43,7 @@ hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t
 hipError_t launch_rref_block2(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t ws0, int64_t jz,
                               int64_t j0a, int64_t j1a, int64_t q0a, uint64_t *coefa, uint64_t *PBa, PassRec *reca,
                               int64_t j0b, int64_t j1b, int64_t q0b, uint64_t *coefb, uint64_t *PBb, PassRec *recb,
-                              hipStream_t s);
+                              hipStream_t s, const PassRec *dreca = nullptr, const PassRec *drecb = nullptr);
 hipError_t launch_rref_pair(uint64_t *A, int64_t ldw, int64_t m, const uint64_t *coefT, const uint64_t *coefU,
                             const uint64_t *PBt, const uint64_t *PBu, int64_t w_begin, int64_t w_end,
                             const PassRec *rect, const PassRec *recu, hipStream_t s);
@@ -144,7 +145,8 @@ struct LookCtx {
     int dev = -1;
     hipStream_t user = nullptr;
     hipStream_t s2 = nullptr;
-    hipEvent_t evA = nullptr, evN = nullptr, evM = nullptr;
+    hipEvent_t evA = nullptr, evN = nullptr;
+    hipEvent_t evJ[NREC] = {};  // M4RI: one per elimination job in flight
 };
 
 static LookCtx *look_ctx(hipStream_t user) {
@@ -163,11 +165,14 @@ static LookCtx *look_ctx(hipStream_t user) {
     // release and no timestamps (a default event also writes back the caches
     // for the host, which delays the next kernel by microseconds)
     constexpr unsigned EV_FLAGS = hipEventDisableTiming | hipEventReleaseToDevice;
-    if (hipEventCreateWithFlags(&c.evA, EV_FLAGS) != hipSuccess ||
-        hipEventCreateWithFlags(&c.evN, EV_FLAGS) != hipSuccess ||
-        hipEventCreateWithFlags(&c.evM, EV_FLAGS) != hipSuccess) {
+    bool ok = hipEventCreateWithFlags(&c.evA, EV_FLAGS) == hipSuccess &&
+              hipEventCreateWithFlags(&c.evN, EV_FLAGS) == hipSuccess;
+    for (int j = 0; ok && j < NREC; j++) ok = hipEventCreateWithFlags(&c.evJ[j], EV_FLAGS) == hipSuccess;
+    if (!ok) {
         if (c.evA) (void)hipEventDestroy(c.evA);
         if (c.evN) (void)hipEventDestroy(c.evN);
+        for (int j = 0; j < NREC; j++)
+            if (c.evJ[j]) (void)hipEventDestroy(c.evJ[j]);
         (void)hipStreamDestroy(c.s2);
         return nullptr;
     }
@@ -218,13 +223,15 @@ static void pass_kinds(int64_t m, int64_t n, int mode, std::vector<int8_t> &kind
 // rows), so panel(t + 1) -- which reads only that word -- runs on a second
 // stream beside the update of the words beyond; the next permute waits for
 // both.
-// The M4RI form (Algorithms 5-8: every 64-column block eliminated from all
-// rows): after each serial pass, the block's pivot rows are brought to
-// reduced form and removed from the rows above, with the back-substitution's
-// kernels (coef[m], pivot block 64 x ldw of its own).
+// The M4RI form (Algorithms 5-8: every column block eliminated from all
+// rows): after each pass (or fused pair of passes, a 128-column block), the
+// block's pivot rows are brought to reduced form and removed from the rows
+// above, with the back-substitution's kernels (coefficients, staged pivot
+// rows and two records of its own).
 struct M4riStep {
-    uint64_t *coef = nullptr;
-    uint64_t *PB = nullptr;
+    uint64_t *coef = nullptr, *coef2 = nullptr;
+    uint64_t *PB = nullptr, *PB2 = nullptr;
+    PassRec *rec = nullptr;  // two
 };
 
 static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
@@ -253,6 +260,10 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
     const int64_t npasses = words_for(n);
     std::vector<int8_t> kind;
     pass_kinds(m, n, mode, kind);
+    // the M4RI form keeps the second stream for its eliminations
+    if (m4ri)
+        for (auto &k : kind)
+            if (k == PK_LOOK) k = PK_SERIAL;
     // the second stream exists only for look-ahead passes; without one they
     // run serially
     LookCtx *lc = nullptr;
@@ -270,15 +281,65 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
         return e;
     bool pending = false;  // this pass's panel ran on the second stream
     int64_t since_check = 0;
-    // M4RI: a block's elimination from the rows above runs on the second
-    // stream, behind the PLE passes that follow it.  It writes rows below
-    // r + rbar only (rows whose coefficient is zero are not written), which
-    // no later pass touches; it reads the pass's record, so the passes may
-    // run at most one ahead of it (the record ring holds NREC >= 2).
-    static_assert(NREC >= 2, "the M4RI elimination of a pass reads its record while the next pass writes its own");
+    // M4RI: a block's elimination from the rows above (a job) runs on the
+    // second stream, behind the passes that follow it.  It writes only rows
+    // above the next pass's first row (rows whose coefficients are zero are
+    // not written), which no later pass touches.  It reads its passes'
+    // records, so before a kernel writes the record of pass x, every job
+    // that read the slot x shares in the ring (passes <= x - NREC) is done.
     LookCtx *mc = m4ri ? look_ctx(s) : nullptr;
-    hipEvent_t m4_done[2] = {mc ? mc->evN : nullptr, mc ? mc->evM : nullptr};
-    int64_t m4_last = -1;  // last pass whose elimination went to the second stream
+    struct M4Job {
+        int64_t first;
+        int ev;
+    };
+    std::deque<M4Job> jobs;
+    int64_t njobs = 0;
+    auto m4_guard = [&](int64_t x) -> hipError_t {
+        int ev = -1;
+        while (!jobs.empty() && jobs.front().first <= x - NREC) {
+            ev = jobs.front().ev;
+            jobs.pop_front();
+        }
+        return ev >= 0 ? hipStreamWaitEvent(s, mc->evJ[ev], 0) : hipSuccess;
+    };
+    // a job over passes [t, t + np): both blocks' reduction and removal from
+    // rows 0 .. min(c + 64 np, m) - 1 (rows r .. r + rbar - 1 of the passes
+    // lie below c + 64 np, since r <= c)
+    auto m4_job = [&](int64_t t, int np) -> hipError_t {
+        const int64_t c = t * KW;
+        const int64_t jz = c + np * KW < m ? c + np * KW : m;
+        hipStream_t ms = mc ? mc->s2 : s;
+        hipError_t err;
+        if (mc) {
+            if ((err = hipEventRecord(mc->evA, s)) != hipSuccess) return err;
+            if ((err = hipStreamWaitEvent(ms, mc->evA, 0)) != hipSuccess) return err;
+        }
+        if (np == 2) {
+            // the later block first (its update leaves the earlier block's
+            // pivot columns as they are), the earlier block's rows taking it
+            // in the sweep's table build, as in the back-substitution
+            if ((err = launch_rref_block2(A, ldw, npasses, Q, c >> 6, jz, 0, 0, -2, m4ri->coef, m4ri->PB, m4ri->rec, 0,
+                                          0, -2, m4ri->coef2, m4ri->PB2, m4ri->rec + 1, ms, rec_of(t + 1),
+                                          rec_of(t))) != hipSuccess)
+                return err;
+            if ((err = launch_rref_pair(A, ldw, jz, m4ri->coef, m4ri->coef2, m4ri->PB, m4ri->PB2, c >> 6, npasses,
+                                        m4ri->rec, m4ri->rec + 1, ms)) != hipSuccess)
+                return err;
+        } else {
+            if ((err = launch_rref_block(A, ldw, npasses, Q, 0, 0, c >> 6, -2, jz, m4ri->coef, m4ri->PB, nullptr, ms,
+                                         rec_of(t))) != hipSuccess)
+                return err;
+            if ((err = launch_m4rm(A, ldw, jz, m4ri->coef, 1, m4ri->PB, ldw, KW, c >> 6, npasses, 0, 0, ms)) !=
+                hipSuccess)
+                return err;
+        }
+        if (mc) {
+            const int ev = (int)(njobs++ % NREC);
+            if ((err = hipEventRecord(mc->evJ[ev], ms)) != hipSuccess) return err;
+            jobs.push_back({t, ev});
+        }
+        return hipSuccess;
+    };
     for (int64_t t = 0; t < npasses;) {
         const int64_t c = t * KW;
         PassRec *rec = rec_of(t), *nxt = rec_of(t + 1);
@@ -294,6 +355,7 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
                 return e;
             PanelFix f1;
             f1.mode = 1;
+            if (mc && (e = m4_guard(t + 1)) != hipSuccess) return e;
             if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, f1, false, s,
                                   nullptr)) != hipSuccess)
                 return e;
@@ -312,9 +374,11 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
             pp.rank = rank;
             pp.gsv = gsv;
             pp.gsid = gsid;
+            if (mc && (e = m4_guard(t + 2)) != hipSuccess) return e;
             if ((e = launch_update_pair(A, m, n, ldw, c, rec, nxt, coefP, coef2, coef, PB, PB2, m4t, pv, pp, s)) !=
                 hipSuccess)
                 return e;
+            if (m4ri && (e = m4_job(t, 2)) != hipSuccess) return e;
             t += 2;
             continue;
         }
@@ -340,25 +404,7 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
                                 nullptr)) != hipSuccess)
             return e;
         if ((e = launch_update(A, m, n, ldw, c, rec, coef, PB, 1, m4v, m4t, s)) != hipSuccess) return e;
-        if (m4ri) {
-            // rows 0 .. r + rbar - 1 lie below c + KW (r <= c)
-            const int64_t jz = c + KW < m ? c + KW : m;
-            hipStream_t ms = mc ? mc->s2 : s;
-            if (mc) {
-                if ((e = hipEventRecord(mc->evA, s)) != hipSuccess) return e;
-                if ((e = hipStreamWaitEvent(ms, mc->evA, 0)) != hipSuccess) return e;
-            }
-            if ((e = launch_rref_block(A, ldw, npasses, Q, 0, 0, c >> 6, -2, jz, m4ri->coef, m4ri->PB, nullptr, ms,
-                                       rec)) != hipSuccess)
-                return e;
-            if ((e = launch_m4rm(A, ldw, jz, m4ri->coef, 1, m4ri->PB, ldw, KW, c >> 6, npasses, 0, 0, ms)) !=
-                hipSuccess)
-                return e;
-            if (mc) {
-                if ((e = hipEventRecord(m4_done[t & 1], ms)) != hipSuccess) return e;
-                m4_last = t;
-            }
-        }
+        if (m4ri && (e = m4_job(t, 1)) != hipSuccess) return e;
         if (t + 1 >= npasses) break;
         if (c + KW >= m && allow_sync) {
             // rank <= m: once it reaches m the remaining passes are empty
@@ -370,15 +416,13 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
             }
             since_check = (since_check + 1) % 8;
         }
-        // the next panel rewrites a record: the elimination of the pass
-        // before this one must be done with its own
-        if (mc && t >= 1 && (e = hipStreamWaitEvent(s, m4_done[(t - 1) & 1], 0)) != hipSuccess) return e;
+        if (mc && (e = m4_guard(t + 1)) != hipSuccess) return e;
         if ((e = launch_panel(A, m, n, ldw, c + KW, rec, nxt, P, Q, rank, gsv, gsid, pr, PanelFix(), false, s,
                               nullptr)) != hipSuccess)
             return e;
         t += 1;
     }
-    if (mc && m4_last >= 0 && (e = hipStreamWaitEvent(s, m4_done[m4_last & 1], 0)) != hipSuccess) return e;
+    if (mc && !jobs.empty() && (e = hipStreamWaitEvent(s, mc->evJ[jobs.back().ev], 0)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -543,10 +587,33 @@ gf2_status gf2_rref_from_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, con
     return hip_status(hipGetLastError());
 }
 
+// workspace of gf2_m4ri_rref: that of gf2_ple | coef[m] | coef2[m] |
+// PB[64 x ldw] | PB2[64 x ldw] | two records | P[m]
+struct M4riLayout {
+    size_t coef, coef2, pb, pb2, rec, p, total;
+};
+static M4riLayout m4ri_layout(int64_t m, int64_t ldw) {
+    M4riLayout L;
+    size_t off = ple_layout(m, ldw).total;
+    L.coef = off;
+    off += align_up((size_t)m * 8);
+    L.coef2 = off;
+    off += align_up((size_t)m * 8);
+    L.pb = off;
+    off += align_up((size_t)KW * (size_t)ldw * 8);
+    L.pb2 = off;
+    off += align_up((size_t)KW * (size_t)ldw * 8);
+    L.rec = off;
+    off += align_up(2 * sizeof(PassRec));
+    L.p = off;
+    off += align_up((size_t)m * 8);
+    L.total = off;
+    return L;
+}
+
 size_t gf2_m4ri_rref_workspace_bytes(int64_t m, int64_t n, int64_t ldw) {
     if (!sizes_ok(m, n, ldw)) return 0;
-    return ple_layout(m, ldw).total + align_up((size_t)m * 8) + align_up((size_t)KW * (size_t)ldw * 8) +
-           align_up((size_t)m * 8);
+    return m4ri_layout(m, ldw).total;
 }
 
 gf2_status gf2_m4ri_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *Q, int64_t *rank, void *ws,
@@ -559,14 +626,18 @@ gf2_status gf2_m4ri_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t
     if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;
     if (ws_bytes < gf2_m4ri_rref_workspace_bytes(m, n, ldw)) return GF2_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    const size_t ple_bytes = ple_layout(m, ldw).total;
-    char *base = (char *)ws + ple_bytes;
+    const M4riLayout L = m4ri_layout(m, ldw);
+    char *base = (char *)ws;
     M4riStep st;
-    st.coef = (uint64_t *)base;
-    st.PB = (uint64_t *)(base + align_up((size_t)m * 8));
-    int64_t *P = (int64_t *)(base + align_up((size_t)m * 8) + align_up((size_t)KW * (size_t)ldw * 8));
+    st.coef = (uint64_t *)(base + L.coef);
+    st.coef2 = (uint64_t *)(base + L.coef2);
+    st.PB = (uint64_t *)(base + L.pb);
+    st.PB2 = (uint64_t *)(base + L.pb2);
+    st.rec = (PassRec *)(base + L.rec);
+    int64_t *P = (int64_t *)(base + L.p);
+    // the default schedule: fused pairs of passes, each pair's 128-column
+    // block then eliminated from the rows above in one sweep
     gf2_ple_opts o{};
-    o.lookahead = 1;  // serial passes: each block's elimination follows its pass
     hipError_t e = pass_loop(A, m, n, ldw, P, Q, rank, ws, &o, s, true, &st);
     if (e != hipSuccess) return hip_status(e);
     if (m == 0 || ldw == 0) return GF2_OK;

@@ -17,8 +17,10 @@ constexpr int MAX_SPEC = 2 * KW;
 // Rows the slow pivot search keeps in LDS; beyond this it uses workspace.
 constexpr int SLOW_LDS_ROWS = 9216;
 // Pass records kept in the workspace ring: a pass's record is still read by
-// the fused update of its pair while the panel two passes later writes its own.
-constexpr int NREC = 4;
+// the fused update of its pair while the panel two passes later writes its own,
+// and by the M4RI form's elimination from the rows above, which runs behind
+// the passes on a second stream (at most NREC passes behind).
+constexpr int NREC = 8;
 // Columns per trailing-update tile (words): 8 words = 64 B of each row.
 constexpr int TILE_W = 8;
 // Threads per block of the wide kernels.

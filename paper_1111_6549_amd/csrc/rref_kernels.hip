@@ -212,9 +212,9 @@ hipError_t launch_rref_block(uint64_t *A, int64_t ldw, int64_t nw, const int64_t
 hipError_t launch_rref_block2(uint64_t *A, int64_t ldw, int64_t nw, const int64_t *Q, int64_t ws0, int64_t jz,
                               int64_t j0a, int64_t j1a, int64_t q0a, uint64_t *coefa, uint64_t *PBa, PassRec *reca,
                               int64_t j0b, int64_t j1b, int64_t q0b, uint64_t *coefb, uint64_t *PBb, PassRec *recb,
-                              hipStream_t s) {
-    const RrefBlockArgs a = rref_args(nw, j0a, j1a, ws0, q0a, jz, coefa, PBa, reca, nullptr);
-    const RrefBlockArgs b = rref_args(nw, j0b, j1b, ws0, q0b, jz, coefb, PBb, recb, nullptr);
+                              hipStream_t s, const PassRec *dreca, const PassRec *drecb) {
+    const RrefBlockArgs a = rref_args(nw, j0a, j1a, ws0, q0a, jz, coefa, PBa, reca, dreca);
+    const RrefBlockArgs b = rref_args(nw, j0b, j1b, ws0, q0b, jz, coefb, PBb, recb, drecb);
     ProfScope ps(KID_RREF, s);
     hipLaunchKernelGGL(k_rref_block2, dim3(a.nwg + b.nwg), dim3(RREF_THREADS), 0, s, (const uint64_t *)A, ldw, nw, Q,
                        a, b);
