@@ -190,7 +190,8 @@ def test_echelon_and_rref_parity(m, n, kind):
 
 @pytest.mark.parametrize("m,n,kind", [(300, 500, "u"), (1000, 1000, "u"), (700, 400, "r"), (129, 2000, "u"),
                                       (2000, 700, "r"), (600, 600, "s"), (4096, 4096, "u"), (3000, 2500, "r"),
-                                      (1, 1, "u"), (64, 64, "u"), (65, 130, "r"), (8192, 8192, "u")])
+                                      (1, 1, "u"), (64, 64, "u"), (65, 130, "r"), (8192, 8192, "u"),
+                                      (3000, 9000, "u"), (9000, 3000, "r")])
 def test_m4ri_rref_parity(m, n, kind):
     """The M4RI form (every block eliminated from all rows) against the
     oracle's RREF, which is unique; Q against its pivot columns."""
