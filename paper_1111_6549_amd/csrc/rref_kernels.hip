@@ -20,6 +20,15 @@ __device__ __forceinline__ uint64_t rl64(uint64_t v, int l) {
 
 constexpr int RREF_THREADS = 256;
 
+// Bits q0 .. q0 + nb - 1 of a row, from its words holding column q0 (w0)
+// and the next one (w1, zero when q0 is word-aligned or the row ends).
+__device__ __forceinline__ uint64_t funnel_bits(uint64_t w0, uint64_t w1, int64_t q0, int nb) {
+    const int sh = (int)(q0 & 63);
+    uint64_t c = w0 >> sh;
+    if (sh) c |= w1 << (64 - sh);
+    return nb == 64 ? c : (c & ((1ull << nb) - 1ull));
+}
+
 // A row's bits at the block's pivot columns, bit t = column Q[j0 + t].  With
 // contiguous pivot columns (q0 = the first, q0 >= 0) that is one funnel
 // shift of the two words holding them; otherwise one bit at a time.
@@ -91,6 +100,26 @@ __device__ __forceinline__ void rref_block_body(const uint64_t *__restrict__ A, 
         return;
     }
 
+    // The words this thread will need are loaded first, on the guess that
+    // the pivot columns are contiguous from qs = Q[j0] (always so at full
+    // rank): the row it finishes (at most one per thread when the grid
+    // covers jz) and, in wave 0, its pivot row's.  They arrive while U, Y
+    // and the tables are worked out; a wrong guess falls back to pivot_bits.
+    const int64_t i0 = (int64_t)(bid - a.nA) * RREF_THREADS + tid;
+    const int64_t qs = q0 >= 0 ? q0 : (q0 == -2 && nb > 0 ? Q[j0] : -1);
+    uint64_t rw0 = 0, rw1 = 0, uw0 = 0, uw1 = 0;
+    if (qs >= 0) {
+        const int64_t w = qs >> 6;
+        const bool two = (qs & 63) && w + 1 < nw;
+        if (i0 < j0) {
+            rw0 = A[i0 * ldw + w];
+            if (two) rw1 = A[i0 * ldw + w + 1];
+        }
+        if (tid < nb) {
+            uw0 = A[(j0 + tid) * ldw + w];
+            if (two) uw1 = A[(j0 + tid) * ldw + w + 1];
+        }
+    }
     if (tid < KW) sq[tid] = tid < nb ? Q[j0 + tid] : 0;
     if (a.rec && bid == a.nA) {
         if (tid < nb) a.rec->spec_src[tid] = j0 + tid;
@@ -116,7 +145,7 @@ __device__ __forceinline__ void rref_block_body(const uint64_t *__restrict__ A, 
     if (tid < 64) {  // wave 0: Y = U^-1
         const int lane = tid;
         uint64_t U = 0;
-        if (lane < nb) U = pivot_bits(A + (j0 + lane) * ldw, sq, nb, q0, nw);
+        if (lane < nb) U = (q0 >= 0 && q0 == qs) ? funnel_bits(uw0, uw1, q0, nb) : pivot_bits(A + (j0 + lane) * ldw, sq, nb, q0, nw);
         if (mask_l) U &= ~((1ull << lane) - 1ull);  // L bits (pivot columns left of its own)
         uint64_t Y = 1ull << lane;
         for (int t = nb - 1; t >= 0; t--) {
@@ -144,7 +173,8 @@ __device__ __forceinline__ void rref_block_body(const uint64_t *__restrict__ A, 
             a.coef[i] = sY[i - j0] ^ (1ull << (i - j0));
             continue;
         }
-        const uint64_t c = pivot_bits(A + i * ldw, sq, nb, q0, nw);
+        const uint64_t c = (i == i0 && q0 >= 0 && q0 == qs) ? funnel_bits(rw0, rw1, q0, nb)
+                                                             : pivot_bits(A + i * ldw, sq, nb, q0, nw);
         uint64_t w = 0;
         if (c) {
 #pragma unroll
