@@ -3,12 +3,12 @@
 // runs in the HIP kernels of ple_kernels.hip / rref_kernels.hip.
 #include <algorithm>
 #include <mutex>
-#include <deque>
 #include <vector>
 
 #include "../../include/gf2ple.h"
 #include "batch.h"
 #include "common.h"
+#include "m4ri_jobs.h"
 #include "panel.h"
 
 namespace gf2 {
@@ -288,18 +288,9 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
     // records, so before a kernel writes the record of pass x, every job
     // that read the slot x shares in the ring (passes <= x - NREC) is done.
     LookCtx *mc = m4ri ? look_ctx(s) : nullptr;
-    struct M4Job {
-        int64_t first;
-        int ev;
-    };
-    std::deque<M4Job> jobs;
-    int64_t njobs = 0;
+    M4JobRing<NREC> jobs;
     auto m4_guard = [&](int64_t x) -> hipError_t {
-        int ev = -1;
-        while (!jobs.empty() && jobs.front().first <= x - NREC) {
-            ev = jobs.front().ev;
-            jobs.pop_front();
-        }
+        const int ev = jobs.guard(x);
         return ev >= 0 ? hipStreamWaitEvent(s, mc->evJ[ev], 0) : hipSuccess;
     };
     // a job over passes [t, t + np): both blocks' reduction and removal from
@@ -334,9 +325,9 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
                 return err;
         }
         if (mc) {
-            const int ev = (int)(njobs++ % NREC);
+            const int ev = jobs.push(t);
+            if (ev < 0) return hipErrorUnknown;  // an unguarded record write
             if ((err = hipEventRecord(mc->evJ[ev], ms)) != hipSuccess) return err;
-            jobs.push_back({t, ev});
         }
         return hipSuccess;
     };
@@ -422,7 +413,7 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
             return e;
         t += 1;
     }
-    if (mc && !jobs.empty() && (e = hipStreamWaitEvent(s, mc->evJ[jobs.back().ev], 0)) != hipSuccess) return e;
+    if (mc && jobs.last() >= 0 && (e = hipStreamWaitEvent(s, mc->evJ[jobs.last()], 0)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
