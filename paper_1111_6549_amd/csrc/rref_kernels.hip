@@ -89,13 +89,28 @@ __device__ __forceinline__ void rref_block_body(const uint64_t *__restrict__ A, 
     if (bid < a.nA) {  // stage the block rows' words >= ws0
         const int64_t w = a.ws0 + (int64_t)bid * 64 + (tid & 63);
         if (w >= nw) return;
-        for (int k = tid >> 6; k < nb; k += RREF_THREADS / 64) {
-            uint64_t v = A[(j0 + k) * ldw + w];
+        // every load before the first store (the stores could alias the
+        // rows for all the compiler knows, which would serialise the copy)
+        constexpr int RG = RREF_THREADS / 64;  // row groups
+        constexpr int PER = KW / RG;            // rows per thread
+        uint64_t v[PER];
+        int64_t q[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int k = (tid >> 6) + RG * u;
+            v[u] = k < nb ? A[(j0 + k) * ldw + w] : 0ull;
+            q[u] = (mask_l && k < nb) ? Q[j0 + k] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int k = (tid >> 6) + RG * u;
+            if (k >= nb) break;
+            uint64_t x = v[u];
             if (mask_l) {  // the row's E part: columns from its pivot column on
-                const int64_t q = Q[j0 + k], b = w * 64;
-                v = q >= b + 64 ? 0ull : (q > b ? v & ~((1ull << (q - b)) - 1ull) : v);
+                const int64_t b = w * 64;
+                x = q[u] >= b + 64 ? 0ull : (q[u] > b ? x & ~((1ull << (q[u] - b)) - 1ull) : x);
             }
-            a.PB[(int64_t)k * ldw + w] = v;
+            a.PB[(int64_t)k * ldw + w] = x;
         }
         return;
     }
