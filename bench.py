@@ -390,6 +390,54 @@ def run_serving(args, log_fn):
     return out
 
 
+def run_helpers(m, n, A, Qh, r, log_fn):
+    """The helpers of the paper's PLE-based reductions on the bench matrix (not
+    in the timed step): echelon form and the reduced echelon form from L\\E
+    (on the PLE result), and the reduced echelon form of the input in the
+    M4RI form.  Runs after the serving leg: the M4RI form's second stream
+    would otherwise change how the serving session's streams share the
+    process's hardware queues."""
+    import numpy as np
+    import torch
+    from paper_1111_6549_amd import gf2ple as G
+    pristine = torch.from_numpy(A.view(np.int64)).cuda()
+    work = pristine.clone()
+    P, Q, rank = G.ple(work, n)
+    torch.cuda.synchronize()
+    res = work.clone()
+    hk = {}
+    for name in ("echelon", "rref_from_ple", "m4ri_rref"):
+        times = []
+        for rep in range(2):  # the first also sets up the workspace
+            work.copy_(res)
+            torch.cuda.synchronize()
+            h0 = time.perf_counter()
+            if name == "echelon":
+                G.echelon_from_ple(work, n, rank)
+            elif name == "rref_from_ple":
+                G.rref_from_ple(work, n, Q, rank)
+            else:  # the M4RI form on the original matrix (not on the PLE result)
+                work.copy_(pristine)
+                torch.cuda.synchronize()
+                h0 = time.perf_counter()
+                G.m4ri_rref(work, n)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - h0) * 1000.0)
+        hk[name + "_ms"] = round(min(times), 3)
+    # the update launches' algorithmic bytes over the whole call's time (a
+    # lower bound on their own rate: the call also syncs once and reads Q back)
+    for name, nb in (("rref_from_ple", alg_bytes_rref_from_ple(n, Qh, r)),
+                     ("m4ri_rref", alg_bytes_m4ri_rref(m, n, Qh, r, G.ple_schedule(m, n, lookahead=0)))):
+        gbps = nb / (hk[name + "_ms"] * 1e-3) / 1e9
+        hk[name + "_update_bytes"] = nb
+        hk[name + "_alg_GBps"] = round(gbps, 1)
+        hk[name + "_frac_hbm"] = round(gbps / HBM_PEAK_GBPS, 4)
+    del pristine, work, res
+    torch.cuda.empty_cache()
+    log_fn("helpers: %s" % json.dumps(hk))
+    return hk
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -438,7 +486,8 @@ def main():
     log("generating %dx%d Bernoulli(0.5) seed %d" % (m, n, args.seed))
     A = inputs.bernoulli(m, n, args.seed)
     pristine = torch.from_numpy(A.view(np.int64)).cuda()
-    del A
+    if args.no_helpers:
+        del A
     work = torch.empty_like(pristine)
     ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw))
     torch.cuda.synchronize()
@@ -469,44 +518,6 @@ def main():
     kinds = G.ple_schedule(m, n, lookahead=args.lookahead)
     abytes = alg_bytes_m4rm(m, n, Qh, r, kinds)
     abytes64 = alg_bytes_k64(m, n, Qh, r)
-
-    # the helpers of the paper's PLE-based reductions, on this result (not in
-    # the timed step): echelon form, the reduced echelon form from L\E, and
-    # the reduced echelon form of the input in the M4RI form
-    helpers = None
-    if not args.no_helpers:
-        res = work.clone()
-        hk = {}
-        for name in ("echelon", "rref_from_ple", "m4ri_rref"):
-            times = []
-            for rep in range(2):  # the first also sets up the workspace
-                work.copy_(res)
-                torch.cuda.synchronize()
-                h0 = time.perf_counter()
-                if name == "echelon":
-                    G.echelon_from_ple(work, n, rank)
-                elif name == "rref_from_ple":
-                    G.rref_from_ple(work, n, Q, rank)
-                else:  # the M4RI form on the original matrix (not on the PLE result)
-                    work.copy_(pristine)
-                    torch.cuda.synchronize()
-                    h0 = time.perf_counter()
-                    G.m4ri_rref(work, n)
-                torch.cuda.synchronize()
-                times.append((time.perf_counter() - h0) * 1000.0)
-            hk[name + "_ms"] = round(min(times), 3)
-        # the update launches' algorithmic bytes over the whole call's time
-        # (a lower bound on their own rate: the call also syncs once and
-        # reads Q back)
-        for name, nb in (("rref_from_ple", alg_bytes_rref_from_ple(n, Qh, r)),
-                         ("m4ri_rref", alg_bytes_m4ri_rref(m, n, Qh, r, G.ple_schedule(m, n, lookahead=0)))):
-            gbps = nb / (hk[name + "_ms"] * 1e-3) / 1e9
-            hk[name + "_update_bytes"] = nb
-            hk[name + "_alg_GBps"] = round(gbps, 1)
-            hk[name + "_frac_hbm"] = round(gbps / HBM_PEAK_GBPS, 4)
-        helpers = hk
-        del res
-        log("helpers: %s" % json.dumps(helpers))
 
     roofline = None
     kernels = None
@@ -558,6 +569,13 @@ def main():
             del work, pristine, ws
             torch.cuda.empty_cache()
         serving = run_serving(args, log)
+    helpers = None
+    if not args.no_helpers:
+        if args.no_batched and args.no_serving:
+            del work, pristine, ws
+            torch.cuda.empty_cache()
+        helpers = run_helpers(m, n, A, Qh, r, log)
+        del A
 
     out = {
         "metric": "PLE time & HBM GB/s (% roofline), 65536² GF(2); batched matrices/s vs plain",
