@@ -118,13 +118,15 @@ bool sizes_ok(int64_t m, int64_t n, int64_t ldw) {
 
 gf2_status hip_status(hipError_t e) { return e == hipSuccess ? GF2_OK : GF2_EHIP; }
 
+// Per device: one int for the padding scan.  g_flag_mu is held for the whole
+// scan (clear, launch, read back), so concurrent scans on one device take
+// turns instead of sharing the flag.
 std::mutex g_flag_mu;
-std::vector<int *> g_flag;  // per device: one int for the padding scan
+std::vector<int *> g_flag;
 
-int *device_flag() {
+int *device_flag_locked() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    std::lock_guard<std::mutex> lk(g_flag_mu);
     if ((int)g_flag.size() <= dev) g_flag.resize(dev + 1, nullptr);
     if (!g_flag[dev]) {
         int *p = nullptr;
@@ -138,48 +140,54 @@ int *device_flag() {
 
 namespace gf2 {
 
-// Second stream and events of the look-ahead, one set per (host thread,
-// device, caller's stream) so that PLEs enqueued on different streams keep
-// their panels apart; made on first use and kept for the life of the thread.
+// The second stream of the look-ahead and of the M4RI form's eliminations:
+// one per device, made on first use and kept for the life of the process
+// (so a process holds at most one such stream per device, whatever its
+// number of host threads or calls).
+static std::mutex g_s2_mu;
+static std::vector<hipStream_t> g_s2;
+
+static hipStream_t second_stream() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_s2_mu);
+    if ((int)g_s2.size() <= dev) g_s2.resize(dev + 1, nullptr);
+    if (!g_s2[dev] && hipStreamCreateWithFlags(&g_s2[dev], hipStreamNonBlocking) != hipSuccess) g_s2[dev] = nullptr;
+    return g_s2[dev];
+}
+
+// The events that order the caller's stream and the second stream within
+// one call: made by the call and released when it returns (an event still
+// pending then is released once it completes).  Calls from different host
+// threads or on different streams share the second stream but never an
+// event, so each wait names only work its own call enqueued before it.
 struct LookCtx {
-    int dev = -1;
-    hipStream_t user = nullptr;
     hipStream_t s2 = nullptr;
     hipEvent_t evA = nullptr, evN = nullptr;
     hipEvent_t evJ[NREC] = {};  // M4RI: one per elimination job in flight
-};
-
-static LookCtx *look_ctx(hipStream_t user) {
-    constexpr size_t MAX_CTX = 32;
-    thread_local std::vector<LookCtx> ctx;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    for (auto &c : ctx)
-        if (c.dev == dev && c.user == user) return &c;
-    if (ctx.size() >= MAX_CTX) return nullptr;  // no look-ahead beyond this many streams
-    LookCtx c;
-    c.dev = dev;
-    c.user = user;
-    if (hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    // the events only order the two streams on this device: a device-scope
-    // release and no timestamps (a default event also writes back the caches
-    // for the host, which delays the next kernel by microseconds)
-    constexpr unsigned EV_FLAGS = hipEventDisableTiming | hipEventReleaseToDevice;
-    bool ok = hipEventCreateWithFlags(&c.evA, EV_FLAGS) == hipSuccess &&
-              hipEventCreateWithFlags(&c.evN, EV_FLAGS) == hipSuccess;
-    for (int j = 0; ok && j < NREC; j++) ok = hipEventCreateWithFlags(&c.evJ[j], EV_FLAGS) == hipSuccess;
-    if (!ok) {
-        if (c.evA) (void)hipEventDestroy(c.evA);
-        if (c.evN) (void)hipEventDestroy(c.evN);
+    LookCtx() = default;
+    LookCtx(const LookCtx &) = delete;
+    LookCtx &operator=(const LookCtx &) = delete;
+    ~LookCtx() {
+        if (evA) (void)hipEventDestroy(evA);
+        if (evN) (void)hipEventDestroy(evN);
         for (int j = 0; j < NREC; j++)
-            if (c.evJ[j]) (void)hipEventDestroy(c.evJ[j]);
-        (void)hipStreamDestroy(c.s2);
-        return nullptr;
+            if (evJ[j]) (void)hipEventDestroy(evJ[j]);
     }
-    ctx.reserve(MAX_CTX);  // addresses stay valid
-    ctx.push_back(c);
-    return &ctx.back();
-}
+    bool init() {
+        s2 = second_stream();
+        if (!s2) return false;
+        // the events only order the two streams on this device: a
+        // device-scope release and no timestamps (a default event also
+        // writes back the caches for the host, which delays the next kernel
+        // by microseconds)
+        constexpr unsigned EV_FLAGS = hipEventDisableTiming | hipEventReleaseToDevice;
+        bool ok = hipEventCreateWithFlags(&evA, EV_FLAGS) == hipSuccess &&
+                  hipEventCreateWithFlags(&evN, EV_FLAGS) == hipSuccess;
+        for (int j = 0; ok && j < NREC; j++) ok = hipEventCreateWithFlags(&evJ[j], EV_FLAGS) == hipSuccess;
+        return ok;
+    }
+};
 
 // Trailing blocks above this many bytes take the look-ahead in the default
 // mode when a pass is not paired: their update outlasts the next panel.
@@ -235,7 +243,8 @@ struct M4riStep {
 };
 
 static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
-                            void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, const M4riStep *m4ri) {
+                            void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, bool allow_s2,
+                            const M4riStep *m4ri) {
     const PleLayout L = ple_layout(m, ldw);
     const int64_t mn = m < n ? m : n;
     char *base = (char *)ws;
@@ -264,15 +273,16 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
     if (m4ri)
         for (auto &k : kind)
             if (k == PK_LOOK) k = PK_SERIAL;
-    // the second stream exists only for look-ahead passes; without one they
-    // run serially
-    LookCtx *lc = nullptr;
-    if (std::find(kind.begin(), kind.end(), (int8_t)PK_LOOK) != kind.end()) {
-        lc = look_ctx(s);
-        if (!lc)
-            for (auto &k : kind)
-                if (k == PK_LOOK) k = PK_SERIAL;
-    }
+    // the second stream serves look-ahead passes and the M4RI form's
+    // eliminations; without it look-ahead passes run serially and the
+    // eliminations on the caller's stream
+    LookCtx ctx;
+    const bool want_s2 = m4ri || std::find(kind.begin(), kind.end(), (int8_t)PK_LOOK) != kind.end();
+    const bool have_s2 = allow_s2 && want_s2 && ctx.init();
+    LookCtx *lc = have_s2 && !m4ri ? &ctx : nullptr;
+    if (!lc)
+        for (auto &k : kind)
+            if (k == PK_LOOK) k = PK_SERIAL;
     auto want_pair = [&](int64_t t) { return kind[t] == PK_PAIR1; };
     auto want_la = [&](int64_t t) { return kind[t] == PK_LOOK; };
     auto rec_of = [&](int64_t t) { return &recs[t % NREC]; };
@@ -287,7 +297,7 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
     // not written), which no later pass touches.  It reads its passes'
     // records, so before a kernel writes the record of pass x, every job
     // that read the slot x shares in the ring (passes <= x - NREC) is done.
-    LookCtx *mc = m4ri ? look_ctx(s) : nullptr;
+    LookCtx *mc = have_s2 && m4ri ? &ctx : nullptr;
     M4JobRing<NREC> jobs;
     auto m4_guard = [&](int64_t x) -> hipError_t {
         const int ev = jobs.guard(x);
@@ -418,8 +428,8 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
 }
 
 hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
-                       void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync) {
-    return pass_loop(A, m, n, ldw, P, Q, rank, ws, opts, s, allow_sync, nullptr);
+                       void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, bool allow_s2) {
+    return pass_loop(A, m, n, ldw, P, Q, rank, ws, opts, s, allow_sync, allow_s2, nullptr);
 }
 
 }  // namespace gf2
@@ -453,7 +463,8 @@ gf2_status gf2_check_padding(const uint64_t *A, int64_t m, int64_t n, int64_t ld
     if (m == 0 || ldw == 0) return GF2_OK;
     if (!A || !aligned(A, 8)) return GF2_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    int *flag = device_flag();
+    std::lock_guard<std::mutex> lk(g_flag_mu);
+    int *flag = device_flag_locked();
     if (!flag) return GF2_EHIP;
     if (hipMemsetAsync(flag, 0, sizeof(int), s) != hipSuccess) return GF2_EHIP;
     if (launch_padding(A, m, n, ldw, flag, s) != hipSuccess) return GF2_EHIP;
@@ -485,7 +496,7 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
         gf2_status st = gf2_check_padding(A, m, n, ldw, stream);
         if (st != GF2_OK) return st;
     }
-    return hip_status(ple_enqueue(A, m, n, ldw, P, Q, rank, ws, opts, s, true));
+    return hip_status(ple_enqueue(A, m, n, ldw, P, Q, rank, ws, opts, s, true, true));
 }
 
 int64_t gf2_ple_schedule(int64_t m, int64_t n, const gf2_ple_opts *opts, int32_t *kinds, int64_t max) {
@@ -629,7 +640,7 @@ gf2_status gf2_m4ri_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t
     // the default schedule: fused pairs of passes, each pair's 128-column
     // block then eliminated from the rows above in one sweep
     gf2_ple_opts o{};
-    hipError_t e = pass_loop(A, m, n, ldw, P, Q, rank, ws, &o, s, true, &st);
+    hipError_t e = pass_loop(A, m, n, ldw, P, Q, rank, ws, &o, s, true, true, &st);
     if (e != hipSuccess) return hip_status(e);
     if (m == 0 || ldw == 0) return GF2_OK;
     return hip_status(launch_echelon(A, m, ldw, rank, s));

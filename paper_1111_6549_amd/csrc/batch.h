@@ -35,9 +35,11 @@ int batch_occupancy(int cfg);
 int batch_default_config(int64_t max_dim);
 
 // gf2_ple after its argument checks.  allow_sync = false never waits on the
-// stream (all passes are enqueued; those past full rank exit at once).
+// stream (all passes are enqueued; those past full rank exit at once);
+// allow_s2 = false keeps every kernel on `s` (look-ahead passes run
+// serially instead of using the library's second stream).
 hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
-                       void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync);
+                       void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, bool allow_s2);
 size_t ple_workspace_total(int64_t m, int64_t ldw);
 
 }  // namespace gf2

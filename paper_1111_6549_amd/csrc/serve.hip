@@ -185,10 +185,11 @@ hipError_t gf2_serve::enqueue(Launch &L) {
     if (L.ids.size() == 1 && !reqs[L.ids[0]]->small) {
         Req &r = *reqs[L.ids[0]];
         uint8_t *p = base + r.off;
-        // the default pass schedule (fused pairs) stays on this stream
+        // the default pass schedule (fused pairs), every kernel on this
+        // stream (no look-ahead on the library's second stream)
         gf2_ple_opts o{};
         e = ple_enqueue((uint64_t *)(p + r.a_rel), r.m, r.n, r.ldw, (int64_t *)(p + r.p_rel), (int64_t *)(p + r.q_rel),
-                        (int64_t *)(p + r.r_rel), p + r.ws_rel, &o, st, false);
+                        (int64_t *)(p + r.r_rel), p + r.ws_rel, &o, st, false, false);
         if (e != hipSuccess) return e;
         n_single++;
     } else {
