@@ -30,7 +30,7 @@ def _digest(r, P, Q, A):
 
 
 @pytest.mark.parametrize("name,lookahead", [("65536x65536_seed5", 0), ("65536x65536_seed5", 1),
-                                            ("32768x131072_seed6", 0)])
+                                            ("32768x131072_seed6", 0), ("32768x131072_seed6", 1)])
 def test_full_size_digest(name, lookahead):
     want = json.load(open(GOLDEN))[name]
     m, n, seed = want["m"], want["n"], want["seed"]
@@ -46,3 +46,37 @@ def test_full_size_digest(name, lookahead):
     assert hashlib.sha256(np.ascontiguousarray(Qh, dtype="<i8").tobytes()).hexdigest() == want["q_sha256"]
     got = _digest(r, P.cpu().numpy(), Qh, t.cpu().numpy().view(np.uint64))
     assert got == want["sha256"], "L\\E/P digest differs from the oracle's"
+
+
+def _rref_digest(r, Q, A):
+    h = hashlib.sha256()
+    h.update(np.int64(r).tobytes())
+    h.update(np.ascontiguousarray(Q, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(A, dtype="<u8").tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.parametrize("form", ["rref_from_ple", "m4ri"])
+def test_full_size_rref_digest(form):
+    """Reduced echelon form of the 65536^2 seed-5 matrix, by PLE then
+    back-substitution (gf2_rref) and by the M4RI form (gf2_m4ri_rref), in the
+    launch configuration the benchmark times: the SHA-256 of (rank, Q, words)
+    must equal the oracle's.  The RREF is unique (Section 2), so both forms
+    hash alike; Q past the rank is -1 as the oracle writes it."""
+    want = json.load(open(GOLDEN))["65536x65536_seed5_rref"]
+    m, n, seed = want["m"], want["n"], want["seed"]
+    say("full size rref", form)
+    A = inputs.bernoulli(m, n, seed)
+    t = torch.from_numpy(A.view(np.int64)).cuda()
+    del A
+    if form == "rref_from_ple":
+        P, Q, rank = G.rref(t, n)
+    else:
+        Q, rank = G.m4ri_rref(t, n)
+    torch.cuda.synchronize()
+    r = int(rank.item())
+    assert r == want["rank"]
+    Qh = np.full(min(m, n), -1, dtype=np.int64)
+    Qh[:r] = Q.cpu().numpy()[:r]
+    got = _rref_digest(r, Qh, t.cpu().numpy().view(np.uint64))
+    assert got == want["sha256"], "RREF digest differs from the oracle's"

@@ -43,10 +43,13 @@ def test_parity_sparse(m, n, p):
     assert_same_ple(gpu_ple(A, n), oracle_ple(A, n), "%dx%d p=%g" % (m, n, p))
 
 
-@pytest.mark.parametrize("x,seed", [(0.5, 11), (3.0, 14), (8.0, 16), (20.0, 18)])
+DENSITY_POINTS = (0.1, 0.2, 0.5, 1.0, 2.0, 3.0, 5.0, 8.0, 12.0, 20.0)
+
+
+@pytest.mark.parametrize("x,seed", [(x, 9 + i) for i, x in enumerate(DENSITY_POINTS)])
 def test_parity_density_10000(x, seed):
-    """Three points of the 10000 x 10000 sparse sweep (x non-zero entries per
-    row on average), with the seeds the sweep in bench.py uses."""
+    """Every point of the 10000 x 10000 sparse sweep (x non-zero entries per
+    row on average), with the seeds the sweep in bench.py uses (9 + index)."""
     say("parity 10000^2 density", x)
     A = inputs.bernoulli(10000, 10000, seed, p=x / 10000)
     assert_same_ple(gpu_ple(A, 10000), oracle_ple(A, 10000), "10000^2 x=%g" % x)
