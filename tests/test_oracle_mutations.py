@@ -30,6 +30,18 @@ MUTATIONS = {
     "table_lsb_first": ("if ((x >> (k - 1 - t)) & 1)", "if ((x >> t) & 1)"),
     "no_row_swap": ("if (p != r) {                              /* swap whole rows */",
                     "if (0) {"),
+    # the pivot row rotated into place (rows r .. p-1 shift down) instead of
+    # swapped with row r: the other reading of the pivot step
+    "rotation_not_swap": ("for (int64_t w = 0; w < ldw; w++) { uint64_t t = a[w]; a[w] = b[w]; b[w] = t; }",
+                          "for (int64_t w = 0; w < ldw; w++) { uint64_t t = b[w];"
+                          " for (int64_t i = p; i > r; i--) A[i * ldw + w] = A[(i - 1) * ldw + w]; a[w] = t; }"),
+    "Q_off_by_one": ("Q[r] = c;", "Q[r] = c + 1;"),
+    "addmul_skips_last_word": ("for (int64_t w = 0; w < nw; w++) crow[w] ^= brow[w];",
+                               "for (int64_t w = 0; w + 1 < nw; w++) crow[w] ^= brow[w];"),
+    "addmul_reversed_bits": ("if (getbit(arow, t)) {", "if (getbit(arow, k - 1 - t)) {"),
+    "echelon_keeps_last_L_bit": ("int64_t lim = i < r ? i : r;", "int64_t lim = i < r ? i - 1 : r;"),
+    "echelon_keeps_rows_below": ("if (i >= r) { memset(row, 0, (size_t)ldw * 8); continue; }",
+                                 "if (i >= r) { continue; }"),
 }
 
 
@@ -48,6 +60,8 @@ def _build_mutant(name, tmpdir):
     lib.gf2o_ple.argtypes = [p, i64, i64, i64, p, p]
     lib.gf2o_rref_from_ple.argtypes = [p, i64, i64, i64, p, i64]
     lib.gf2o_make_table.argtypes = [p, i64, i64, i64, p]
+    lib.gf2o_addmul.argtypes = [p, i64, p, i64, p, i64, i64, i64, i64]
+    lib.gf2o_echelon_from_ple.argtypes = [p, i64, i64, i64, i64]
     return lib
 
 
@@ -100,6 +114,28 @@ def battery(lib):
         bits = H.unpack(Ap, n)
         r, P, Q, A = _ple(lib, bits)
         H.check_ple(bits, H.unpack(A, n), r, P, Q)
+    # echelon form: zero before each pivot, 1 at it, rows past the rank zero,
+    # and the same row space as the input (brute force)
+    for t in range(200):
+        m, n = rng.integers(1, 8, size=2)
+        bits = (rng.random((m, n)) < 0.5).astype(np.uint8)
+        rank, lead, rref_rows = H.brute_facts(bits)
+        r, P, Q, A = _ple(lib, bits)
+        lib.gf2o_echelon_from_ple(_ptr(A), m, n, A.shape[1], r)
+        E = H.unpack(A, n)
+        assert not E[r:].any()
+        for i in range(r):
+            assert not E[i, :Q[i]].any() and E[i, Q[i]] == 1
+        assert H.brute_rowspace(H.row_ints(E[:r])) == H.brute_rowspace(H.row_ints(bits))
+    # product: C ^= A B against integer matrix products mod 2 (several words)
+    for m, k, n in ((5, 70, 130), (33, 64, 65), (17, 3, 200)):
+        a = (rng.random((m, k)) < 0.5).astype(np.uint8)
+        b = (rng.random((k, n)) < 0.5).astype(np.uint8)
+        c = (rng.random((m, n)) < 0.5).astype(np.uint8)
+        Ap, Bp, Cp = H.pack(a), H.pack(b), H.pack(c)
+        lib.gf2o_addmul(_ptr(Cp), Cp.shape[1], _ptr(Ap), Ap.shape[1], _ptr(Bp), Bp.shape[1], m, k, n)
+        want = (c.astype(np.int64) + a.astype(np.int64) @ b.astype(np.int64)) % 2
+        assert np.array_equal(H.unpack(Cp, n), want.astype(np.uint8))
 
 
 def test_battery_accepts_oracle():
@@ -115,6 +151,8 @@ def test_battery_accepts_oracle():
         lib.gf2o_ple.argtypes = [p, i64, i64, i64, p, p]
         lib.gf2o_rref_from_ple.argtypes = [p, i64, i64, i64, p, i64]
         lib.gf2o_make_table.argtypes = [p, i64, i64, i64, p]
+        lib.gf2o_addmul.argtypes = [p, i64, p, i64, p, i64, i64, i64, i64]
+        lib.gf2o_echelon_from_ple.argtypes = [p, i64, i64, i64, i64]
         battery(lib)
 
 
