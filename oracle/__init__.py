@@ -40,6 +40,8 @@ def _load():
         i64, p = ctypes.c_int64, ctypes.c_void_p
         lib.gf2o_ple.restype = i64
         lib.gf2o_ple.argtypes = [p, i64, i64, i64, p, p]
+        lib.gf2o_ple_cols.restype = i64
+        lib.gf2o_ple_cols.argtypes = [p, i64, i64, i64, p, p, i64]
         lib.gf2o_echelon_from_ple.argtypes = [p, i64, i64, i64, i64]
         lib.gf2o_rref_from_ple.argtypes = [p, i64, i64, i64, p, i64]
         lib.gf2o_addmul.argtypes = [p, i64, p, i64, p, i64, i64, i64, i64]
@@ -71,6 +73,19 @@ def ple(A, n):
     P = np.empty(m, dtype=np.int64)
     Q = np.empty(min(m, n), dtype=np.int64)
     r = _load().gf2o_ple(_ptr(A), m, n, ldw, _ptr(P), _ptr(Q))
+    return int(r), P, Q
+
+
+def ple_cols(A, n, c_end):
+    """The first c_end column steps of ple() on A, in place (then L compressed
+    for the pivots found).  Returns (r, P, Q) of that partial elimination."""
+    _check_packed(A)
+    m, ldw = A.shape
+    if ldw * 64 < n:
+        raise ValueError("ldw too small for n")
+    P = np.empty(m, dtype=np.int64)
+    Q = np.empty(min(m, n), dtype=np.int64)
+    r = _load().gf2o_ple_cols(_ptr(A), m, n, ldw, _ptr(P), _ptr(Q), int(c_end))
     return int(r), P, Q
 
 

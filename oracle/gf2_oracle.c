@@ -51,14 +51,17 @@ static inline void setbit(uint64_t *row, int64_t j, int v) {
     if (v) row[j >> 6] |= mask; else row[j >> 6] &= ~mask;
 }
 
-/* PLE decomposition (Section 2 definition; pivot rule of Algorithm 1).
- * Returns the rank r.  A is m x n, ldw words per row, overwritten by L\E. */
-int64_t gf2o_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q) {
+/* The elimination of gf2o_ple over columns 0 .. c_end - 1 only (each of
+ * those steps exactly as in the whole run, rows still updated up to column
+ * n), then the compression of L for the pivots found.  With c_end = n it is
+ * gf2o_ple; a smaller c_end times a bounded share of a large elimination. */
+int64_t gf2o_ple_cols(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t c_end) {
     int64_t mn = m < n ? m : n;
     for (int64_t i = 0; i < m; i++) P[i] = i;
     for (int64_t i = 0; i < mn; i++) Q[i] = -1;
     int64_t r = 0;
-    for (int64_t c = 0; c < n && r < m; c++) {
+    if (c_end > n) c_end = n;
+    for (int64_t c = 0; c < c_end && r < m; c++) {
         /* first non-zero in column c at or below row r, current order */
         int64_t p = -1;
         for (int64_t i = r; i < m; i++)
@@ -95,6 +98,12 @@ int64_t gf2o_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int
         }
     }
     return r;
+}
+
+/* PLE decomposition (Section 2 definition; pivot rule of Algorithm 1).
+ * Returns the rank r.  A is m x n, ldw words per row, overwritten by L\E. */
+int64_t gf2o_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q) {
+    return gf2o_ple_cols(A, m, n, ldw, P, Q, n);
 }
 
 /* E from clean L\E (Section 2 definitions): clear the L part, keep E rows. */

@@ -211,3 +211,20 @@ def test_make_table_definition_and_gray_order():
         diff = T[g0] ^ T[g1]
         t = k - 1 - (g0 ^ g1).bit_length() + 1
         assert np.array_equal(diff, rows[t])
+
+
+def test_ple_cols_is_a_prefix_of_ple():
+    """gf2o_ple_cols (the bounded share the CPU baseline times) runs the same
+    steps as gf2o_ple: with c_end = n it is the whole run, and with a smaller
+    c_end it finds exactly the whole run's pivots left of c_end."""
+    A = inputs.bernoulli(300, 500, 12)
+    full = A.copy()
+    r, P, Q = oracle.ple(full, 500)
+    same = A.copy()
+    r2, P2, Q2 = oracle.ple_cols(same, 500, 500)
+    assert r2 == r and np.array_equal(P2, P) and np.array_equal(Q2, Q) and np.array_equal(same, full)
+    for c_end in (1, 64, 130, 299):
+        part = A.copy()
+        rp, Pp, Qp = oracle.ple_cols(part, 500, c_end)
+        k = int(np.sum(Q[:r] < c_end))
+        assert rp == k and np.array_equal(Qp[:k], Q[:k]) and np.array_equal(Pp[:k], P[:k])
