@@ -47,8 +47,14 @@ typedef enum gf2_status {
 /* Schedule options.  A NULL pointer or a zeroed struct selects the defaults. */
 typedef struct gf2_ple_opts {
     int32_t check_padding; /* 1: scan for set bits at columns >= n first (synchronises) */
-    int32_t update;        /* trailing update: 0 = default, 1 = XOR table (Four Russians), 2 = int8 MFMA */
-    int32_t mfma_block;    /* MFMA outer panel width in columns (multiple of 64; 0 = default 256) */
+    int32_t update;        /* 0 = default = 1: Algorithm 2, every trailing update by the Four-Russians tables;
+                              2 = Algorithm 3 (block-recursive PLE, Section 3.3): split the columns in halves
+                              (at a multiple of 64), PLE of the left half, A01 <- L00^-1 A01, then
+                              A11 <- A11 + L10 A01 as a product on the int8 matrix cores, PLE of A11, and
+                              the two halves' P, Q and L combined; rec_levels levels of splits, Algorithm 2
+                              below them.  Bit-identical to Algorithm 2.  Synchronises once per split.
+                              3 = the same recursion with its products on the Four-Russians tables */
+    int32_t rec_levels;    /* update = 2 or 3: levels of Algorithm 3 splits (0 = 1, at most 16) */
     int32_t m4_variant;    /* Four-Russians update schedule: 0 = default, 1..8 = a fixed (tile, threads, unroll) */
     int32_t m4_blocks;     /* target blocks per update launch (0 = default 512) */
     int32_t panel_regs;    /* pivot-search register window of the panel: 0 = default, 2, 4 or 8 x 64 rows */
@@ -160,13 +166,17 @@ gf2_status gf2_m4ri_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t
  * standalone call.  A is m x k (row stride lda words), B is k x n (ldb),
  * C is m x n (ldc).  For each 64-column slice of A the 64 matching rows of B
  * are tabulated 8 at a time (256-entry tables) and one table row per byte of
- * A's word is added to C.  No workspace.  opts->update = 2 selects the int8
- * matrix-core product instead (bit-identical): bits become 0/1 int8
- * operands, the int32 sums are taken mod 2; it takes stream-ordered device
- * scratch (hipMallocAsync) for the bit transpose of B, k x n bits.
+ * A's word is added to C.  opts->update = 2 selects the int8 matrix-core
+ * product instead (the product Algorithm 3 hands to matrix multiplication;
+ * bit-identical): B is bit-transposed into the workspace, the bits become
+ * 0/1 int8 operands and the int32 sums are taken mod 2.
+ *   ws  device workspace of at least gf2_addmul_workspace_bytes(m, k, n,
+ *       opts) bytes (0 for the table product, where ws may be NULL).
  */
+size_t gf2_addmul_workspace_bytes(int64_t m, int64_t k, int64_t n, const gf2_ple_opts *opts);
 gf2_status gf2_addmul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *B, int64_t ldb,
-                      int64_t m, int64_t k, int64_t n, const gf2_ple_opts *opts, void *stream);
+                      int64_t m, int64_t k, int64_t n, void *ws, size_t ws_bytes, const gf2_ple_opts *opts,
+                      void *stream);
 
 /*
  * MakeTable (Appendix A): T[x] = sum of the rows t of `rows` whose bit
@@ -268,7 +278,7 @@ const char *gf2_batch_config_name(int32_t config);
  */
 typedef struct gf2_serve_opts {
     int64_t budget_bytes;  /* device memory of the session, allocated once at create (0 = 64 GiB) */
-    int32_t streams;       /* launch streams (0 = 4, at most 16) */
+    int32_t streams;       /* launch streams (0 = 3, at most 16) */
     int32_t max_batch;     /* most requests in one batched launch (0 = 4096) */
     int32_t small_max_dim; /* max(m, n) up to which a request runs in batched launches (0 = 2048, at most 4096) */
     int32_t reserved[3];
@@ -299,7 +309,11 @@ gf2_status gf2_serve_create(const gf2_serve_opts *opts, gf2_serve **session);
 
 /* Submit an m x n packed matrix (row stride ldw words).  a_on_device = 0: A is
  * host memory, copied before the call returns.  a_on_device = 1: A is device
- * memory that must stay unchanged until the request leaves GF2_REQ_QUEUED.
+ * memory whose contents must be complete when the call is made (the stream
+ * that wrote them synchronised: the session's copy is not ordered after the
+ * caller's streams) and must stay allocated and unchanged until the request
+ * is done or failed (the copy into the session's pool runs when the request
+ * is launched, which can be after admission).
  * *ticket receives the request id.  GF2_EBUDGET if the request could never
  * fit the budget; GF2_EINVAL for bad sizes. */
 gf2_status gf2_serve_submit(gf2_serve *session, const uint64_t *A, int32_t a_on_device, int64_t m, int64_t n,
@@ -314,7 +328,8 @@ gf2_status gf2_serve_wait(gf2_serve *session, int64_t ticket, gf2_serve_info *in
 /* Copy a finished request's results out -- L\E (m rows of ldw_out words,
  * ldw_out >= ceil(n/64), extra words zero), P (m), Q (min(m, n)), rank (1);
  * any pointer may be NULL -- to host memory (to_device = 0) or device memory
- * (to_device = 1), synchronously, then release the request.  GF2_EBUSY if the
+ * (to_device = 1), synchronously (on the default stream), then release the
+ * request.  GF2_EBUSY if the
  * ticket is unknown or not done; a failed request returns its status and is
  * released. */
 gf2_status gf2_serve_fetch(gf2_serve *session, int64_t ticket, uint64_t *LE, int64_t ldw_out, int64_t *P, int64_t *Q,

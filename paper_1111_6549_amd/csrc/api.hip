@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/gf2ple.h"
+#include "alg3.h"
 #include "batch.h"
 #include "common.h"
 #include "m4ri_jobs.h"
@@ -18,7 +19,7 @@ hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t 
                         const PanelFix &fix, bool beside, hipStream_t s, hipEvent_t done);
 hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, PassRec *rec,
                           uint64_t *coef, uint64_t *PB, int mode, const PassRec *rect, const uint64_t *coefT,
-                          uint64_t *coefP, const uint64_t *PBt, hipStream_t s, hipEvent_t done);
+                          uint64_t *coefP, const uint64_t *PBt, hipStream_t s, hipEvent_t done, int64_t wlo);
 hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t ct, const PassRec *rect,
                               const PassRec *recu, const uint64_t *coefP, const uint64_t *coefU,
                               const uint64_t *coefT, const uint64_t *PBt, const uint64_t *PBu, int m4_target,
@@ -242,9 +243,12 @@ struct M4riStep {
     PassRec *rec = nullptr;  // two
 };
 
+// wlo: first word of A's rows relative to A (0, or < 0 when A points at a
+// right-hand block of a matrix): the swaps move the whole rows, words
+// [wlo, wlo + ldw), while the passes eliminate only A's n columns.
 static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
                             void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, bool allow_s2,
-                            const M4riStep *m4ri) {
+                            const M4riStep *m4ri, int64_t wlo = 0) {
     const PleLayout L = ple_layout(m, ldw);
     const int64_t mn = m < n ? m : n;
     char *base = (char *)ws;
@@ -352,7 +356,7 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
             // pass t: permute with the next stripe word updated; its bulk
             // update waits for pass t + 1
             if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 1, nullptr, nullptr, nullptr, nullptr, s,
-                                    nullptr)) != hipSuccess)
+                                    nullptr, wlo)) != hipSuccess)
                 return e;
             PanelFix f1;
             f1.mode = 1;
@@ -362,7 +366,7 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
                 return e;
             // pass u = t + 1 carries pass t's coefficients along; the pair's
             // update also runs the panel of pass t + 2 (no second stream)
-            if ((e = launch_permute(A, m, n, ldw, c + KW, nxt, coef2, PB2, 2, rec, coef, coefP, PB, s, nullptr)) !=
+            if ((e = launch_permute(A, m, n, ldw, c + KW, nxt, coef2, PB2, 2, rec, coef, coefP, PB, s, nullptr, wlo)) !=
                 hipSuccess)
                 return e;
             PairPanel pp;
@@ -388,7 +392,7 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
             // the next panel finishes the special rows' one, then searches,
             // while the update of the words beyond runs
             if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 1, nullptr, nullptr, nullptr, nullptr, s,
-                                    lc->evA)) != hipSuccess)
+                                    lc->evA, wlo)) != hipSuccess)
                 return e;
             if ((e = launch_update(A, m, n, ldw, c, rec, coef, PB, 2, m4v, m4t, s)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(lc->s2, lc->evA, 0)) != hipSuccess) return e;
@@ -402,7 +406,7 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
             continue;
         }
         if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 0, nullptr, nullptr, nullptr, nullptr, s,
-                                nullptr)) != hipSuccess)
+                                nullptr, wlo)) != hipSuccess)
             return e;
         if ((e = launch_update(A, m, n, ldw, c, rec, coef, PB, 1, m4v, m4t, s)) != hipSuccess) return e;
         if (m4ri && (e = m4_job(t, 1)) != hipSuccess) return e;
@@ -426,6 +430,32 @@ static hipError_t pass_loop(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int6
     if (mc && jobs.last() >= 0 && (e = hipStreamWaitEvent(s, mc->evJ[jobs.last()], 0)) != hipSuccess) return e;
     return hipGetLastError();
 }
+
+gf2_status ple_check_args(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, const int64_t *P, const int64_t *Q,
+                          const int64_t *rank, const gf2_ple_opts *opts) {
+    if (!sizes_ok(m, n, ldw)) return GF2_EINVAL;
+    const int64_t mn = m < n ? m : n;
+    if (!rank || !aligned(rank, 8)) return GF2_EINVAL;
+    if (m > 0 && (!P || !aligned(P, 8))) return GF2_EINVAL;
+    if (mn > 0 && (!Q || !aligned(Q, 8))) return GF2_EINVAL;
+    if (m > 0 && ldw > 0 && (!A || !aligned(A, 8))) return GF2_EINVAL;
+    if (opts && (opts->update < 0 || opts->update > 3 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
+    if (opts && (opts->rec_levels < 0 || opts->rec_levels > 16)) return GF2_EINVAL;
+    if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
+        return GF2_EINVAL;
+    if (opts && (opts->lookahead < 0 || opts->lookahead > 3)) return GF2_EINVAL;
+    if (opts && (opts->pair_variant < 0 || opts->pair_variant > 12)) return GF2_EINVAL;
+    return GF2_OK;
+}
+
+hipError_t ple_block(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
+                     const gf2_ple_opts *opts, hipStream_t s, int64_t wlo) {
+    return pass_loop(A, m, n, ldw, P, Q, rank, ws, opts, s, true, true, nullptr, wlo);
+}
+
+// update = 2 / 3: Algorithm 3 levels (matrix-core / table products)
+static bool recursive(const gf2_ple_opts *opts) { return opts && opts->update >= 2; }
+static int rec_levels(const gf2_ple_opts *opts) { return opts && opts->rec_levels > 0 ? opts->rec_levels : 1; }
 
 hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
                        void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, bool allow_s2) {
@@ -453,8 +483,9 @@ const char *gf2_status_str(gf2_status s) {
 }
 
 size_t gf2_ple_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf2_ple_opts *opts) {
-    (void)opts;
     if (!sizes_ok(m, n, ldw)) return 0;
+    if (recursive(opts))
+        return align_up(ple_layout(m, ldw).total) + alg3_extra_bytes(m, n, ldw, rec_levels(opts), opts->update == 2);
     return ple_layout(m, ldw).total;
 }
 
@@ -476,26 +507,17 @@ gf2_status gf2_check_padding(const uint64_t *A, int64_t m, int64_t n, int64_t ld
 
 gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
                    size_t ws_bytes, const gf2_ple_opts *opts, void *stream) {
-    if (!sizes_ok(m, n, ldw)) return GF2_EINVAL;
-    const int64_t mn = m < n ? m : n;
-    if (!rank || !aligned(rank, 8)) return GF2_EINVAL;
-    if (m > 0 && (!P || !aligned(P, 8))) return GF2_EINVAL;
-    if (mn > 0 && (!Q || !aligned(Q, 8))) return GF2_EINVAL;
-    if (m > 0 && ldw > 0 && (!A || !aligned(A, 8))) return GF2_EINVAL;
-    if (opts && (opts->update < 0 || opts->update > 2 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
-    if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
-        return GF2_EINVAL;
-    if (opts && (opts->lookahead < 0 || opts->lookahead > 3)) return GF2_EINVAL;
-    if (opts && (opts->pair_variant < 0 || opts->pair_variant > 12)) return GF2_EINVAL;
-    if (opts && opts->update == 2) return GF2_EINVAL;  // MFMA trailing update: see gf2_addmul
-    const PleLayout L = ple_layout(m, ldw);
+    const gf2_status chk = ple_check_args(A, m, n, ldw, P, Q, rank, opts);
+    if (chk != GF2_OK) return chk;
     if (!ws || !aligned(ws, ALIGN)) return GF2_EINVAL;
-    if (ws_bytes < L.total) return GF2_EWORKSPACE;
+    if (ws_bytes < gf2_ple_workspace_bytes(m, n, ldw, opts)) return GF2_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (opts && opts->check_padding) {
         gf2_status st = gf2_check_padding(A, m, n, ldw, stream);
         if (st != GF2_OK) return st;
     }
+    if (recursive(opts))
+        return hip_status(ple_alg3(A, m, n, ldw, P, Q, rank, ws, opts, s, rec_levels(opts), opts->update == 2));
     return hip_status(ple_enqueue(A, m, n, ldw, P, Q, rank, ws, opts, s, true, true));
 }
 
@@ -660,8 +682,15 @@ gf2_status gf2_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, 
     return gf2_rref_from_ple(A, m, n, ldw, Q, rank, ws, ws_bytes, stream);
 }
 
+size_t gf2_addmul_workspace_bytes(int64_t m, int64_t k, int64_t n, const gf2_ple_opts *opts) {
+    if (m < 0 || k < 0 || n < 0) return 0;
+    if (!opts || opts->update != 2) return 0;
+    return (size_t)words_for(n) * 64 * (size_t)words_for(k) * 8;
+}
+
 gf2_status gf2_addmul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *B, int64_t ldb,
-                      int64_t m, int64_t k, int64_t n, const gf2_ple_opts *opts, void *stream) {
+                      int64_t m, int64_t k, int64_t n, void *ws, size_t ws_bytes, const gf2_ple_opts *opts,
+                      void *stream) {
     if (m < 0 || k < 0 || n < 0) return GF2_EINVAL;
     if (ldc < words_for(n) || lda < words_for(k) || ldb < words_for(n)) return GF2_EINVAL;
     if (opts && (opts->update < 0 || opts->update > 2 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
@@ -670,14 +699,13 @@ gf2_status gf2_addmul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, 
     hipStream_t s = (hipStream_t)stream;
     const int64_t nw = words_for(n);
     if (opts && opts->update == 2) {
-        // int8 matrix cores: B transposed into stream-ordered scratch first
+        // int8 matrix cores: B bit-transposed into the caller's workspace first
         const int64_t kw = words_for(k);
-        void *bt = nullptr;
-        if (hipMallocAsync(&bt, (size_t)nw * 64 * (size_t)kw * 8, s) != hipSuccess) return GF2_EHIP;
-        hipError_t e = launch_transpose_bits(B, ldb, k, n, (uint64_t *)bt, kw, s);
-        if (e == hipSuccess) e = launch_mfma_gf2(C, ldc, A, lda, (const uint64_t *)bt, kw, m, k, n, s);
-        const hipError_t f = hipFreeAsync(bt, s);
-        return (e == hipSuccess && f == hipSuccess) ? GF2_OK : GF2_EHIP;
+        if (!ws || !aligned(ws, 8)) return GF2_EINVAL;
+        if (ws_bytes < gf2_addmul_workspace_bytes(m, k, n, opts)) return GF2_EWORKSPACE;
+        hipError_t e = launch_transpose_bits(B, ldb, k, n, (uint64_t *)ws, kw, s);
+        if (e == hipSuccess) e = launch_mfma_gf2(C, ldc, A, lda, (const uint64_t *)ws, kw, m, k, n, s);
+        return hip_status(e);
     }
     for (int64_t kb = 0; kb * KW < k; kb++) {
         const int nb = (int)(k - kb * KW < KW ? k - kb * KW : KW);

@@ -41,5 +41,9 @@ int batch_default_config(int64_t max_dim);
 hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
                        void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, bool allow_s2);
 size_t ple_workspace_total(int64_t m, int64_t ldw);
+// gf2_ple's argument checks (sizes, pointers, options), made before any
+// device call.
+gf2_status ple_check_args(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, const int64_t *P, const int64_t *Q,
+                          const int64_t *rank, const gf2_ple_opts *opts);
 
 }  // namespace gf2

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
                                                           const PassRec *__restrict__ rect,
                                                           const uint64_t *__restrict__ coefT,
                                                           uint64_t *__restrict__ coefP,
-                                                          const uint64_t *__restrict__ PBt) {
+                                                          const uint64_t *__restrict__ PBt, int64_t wlo) {
     __shared__ uint64_t tw[16][16], tu[16][16], tn[16][16], tt[MODE == 2 ? 16 : 1][16];
     __shared__ uint64_t simg_w[KW], simg_u[KW], simg_n[KW], spbt[KW];
     __shared__ int64_t sdisp[KW], sdsrc[KW], smaxdisp;
@@ -127,7 +127,10 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
     if ((int)blockIdx.x < nA) {
         constexpr int SLOTS = WIDE_THREADS / PERM_A_COLS;  // 64
         constexpr int PER = MAX_SPEC / SLOTS;              // 2
-        const int64_t w = (int64_t)blockIdx.x * PERM_A_COLS + (tid % PERM_A_COLS);
+        // the whole row moves: words [wlo, wlo + ldw) relative to A (wlo < 0
+        // when A points into a row, at a right-hand block of the matrix)
+        const int64_t w = wlo + (int64_t)blockIdx.x * PERM_A_COLS + (tid % PERM_A_COLS);
+        const int64_t wend = wlo + ldw;
         const int slot = tid / PERM_A_COLS;
         uint64_t nv[PER];
         int64_t srcs[PER];
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         for (int t = 0; t < PER; t++) {
             const int k = slot + SLOTS * t;
             nv[t] = 0;
-            if (k < nspec && w < ldw && !(LA && w == sw + 1)) {
+            if (k < nspec && w < wend && !(LA && w == sw + 1)) {
                 const uint64_t old = A[srcs[t] * ldw + w];
                 if (k < rbar && w > sw) PB[(int64_t)k * ldw + w] = old;
                 nv[t] = special_word(old, w, sw, wr0, sh, rec->spec_lbits[k], rec->spec_stripe[k]);
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int k = slot + SLOTS * t;
-            if (k < nspec && w < ldw && !(LA && w == sw + 1)) {
+            if (k < nspec && w < wend && !(LA && w == sw + 1)) {
                 const int64_t src = rec->spec_src[k], dst = rec->spec_dst[k];
                 if (dst != src || (w >= wr0 && w <= sw)) A[dst * ldw + w] = nv[t];
             }
@@ -879,7 +882,7 @@ hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t 
 
 hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c, PassRec *rec,
                           uint64_t *coef, uint64_t *PB, int mode, const PassRec *rect, const uint64_t *coefT,
-                          uint64_t *coefP, const uint64_t *PBt, hipStream_t s, hipEvent_t done) {
+                          uint64_t *coefP, const uint64_t *PBt, hipStream_t s, hipEvent_t done, int64_t wlo) {
     const int nA = (int)((ldw + PERM_A_COLS - 1) / PERM_A_COLS);
     int64_t rows_est = m - (c < m ? c : m);
     if (mode == 2) rows_est += KW;  // also the first pass's pivot rows
@@ -891,7 +894,7 @@ hipError_t launch_permute(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_
     ProfScope ps(KID_PERMUTE, s);
 #define PERMUTE_LAUNCH(MODE)                                                                                    \
     hipExtLaunchKernelGGL(k_permute<MODE>, dim3(nA + nB), dim3(WIDE_THREADS), 0, s, nullptr, done, 0, A, m, ldw, c, \
-                          rec, coef, PB, nA, nw, rect, coefT, coefP, PBt)
+                          rec, coef, PB, nA, nw, rect, coefT, coefP, PBt, wlo)
     if (mode == 0) PERMUTE_LAUNCH(0);
     else if (mode == 1) PERMUTE_LAUNCH(1);
     else PERMUTE_LAUNCH(2);
@@ -1034,7 +1037,7 @@ hipError_t launch_pass(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c
     hipError_t e =
         launch_panel(A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, panel_regs, PanelFix(), false, s, nullptr);
     if (e != hipSuccess) return e;
-    if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 0, nullptr, nullptr, nullptr, nullptr, s, nullptr)) !=
+    if ((e = launch_permute(A, m, n, ldw, c, rec, coef, PB, 0, nullptr, nullptr, nullptr, nullptr, s, nullptr, 0)) !=
         hipSuccess)
         return e;
     return launch_update(A, m, n, ldw, c, rec, coef, PB, 1, m4_variant, m4_target, s);

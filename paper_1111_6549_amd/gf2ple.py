@@ -26,7 +26,7 @@ EXPORTS = [
     "gf2_version", "gf2_status_str", "gf2_ple_workspace_bytes", "gf2_ple", "gf2_ple_schedule", "gf2_echelon_from_ple",
     "gf2_rref_workspace_bytes", "gf2_rref_from_ple", "gf2_rref_full_workspace_bytes", "gf2_rref",
     "gf2_m4ri_rref_workspace_bytes", "gf2_m4ri_rref",
-    "gf2_addmul", "gf2_make_table", "gf2_check_padding", "gf2_profile_start", "gf2_profile_stop",
+    "gf2_addmul_workspace_bytes", "gf2_addmul", "gf2_make_table", "gf2_check_padding", "gf2_profile_start", "gf2_profile_stop",
     "gf2_batch_plan_create", "gf2_batch_workspace_bytes", "gf2_ple_batched", "gf2_batch_plan_info",
     "gf2_batch_plan_destroy", "gf2_batch_num_configs", "gf2_batch_config_name",
     "gf2_serve_create", "gf2_serve_submit", "gf2_serve_poll", "gf2_serve_wait", "gf2_serve_fetch",
@@ -46,7 +46,7 @@ class KernelTime(ctypes.Structure):
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("check_padding", ctypes.c_int32), ("update", ctypes.c_int32), ("mfma_block", ctypes.c_int32),
+    _fields_ = [("check_padding", ctypes.c_int32), ("update", ctypes.c_int32), ("rec_levels", ctypes.c_int32),
                 ("m4_variant", ctypes.c_int32), ("m4_blocks", ctypes.c_int32), ("panel_regs", ctypes.c_int32),
                 ("lookahead", ctypes.c_int32), ("pair_variant", ctypes.c_int32)]
 
@@ -107,7 +107,8 @@ def load():
         "gf2_rref": (st, [p, i64, i64, i64, p, p, p, p, sz, p, p]),
         "gf2_m4ri_rref_workspace_bytes": (sz, [i64, i64, i64]),
         "gf2_m4ri_rref": (st, [p, i64, i64, i64, p, p, p, sz, p]),
-        "gf2_addmul": (st, [p, i64, p, i64, p, i64, i64, i64, i64, p, p]),
+        "gf2_addmul_workspace_bytes": (sz, [i64, i64, i64, p]),
+        "gf2_addmul": (st, [p, i64, p, i64, p, i64, i64, i64, i64, p, sz, p, p]),
         "gf2_make_table": (st, [p, i64, i32, i64, p, i64, p]),
         "gf2_check_padding": (st, [p, i64, i64, i64, p]),
         "gf2_profile_start": (st, []),
@@ -170,22 +171,22 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
 
 
-def _opts(update=0, check_padding=False, mfma_block=0, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0,
+def _opts(update=0, check_padding=False, rec_levels=0, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0,
           pair_variant=0):
     o = Opts()
     o.lookahead = int(lookahead)
     o.pair_variant = int(pair_variant)
     o.check_padding = 1 if check_padding else 0
     o.update = int(update)
-    o.mfma_block = int(mfma_block)
+    o.rec_levels = int(rec_levels)
     o.m4_variant = int(m4_variant)
     o.m4_blocks = int(m4_blocks)
     o.panel_regs = int(panel_regs)
     return o
 
 
-def workspace_bytes(m, n, ldw, update=0):
-    o = _opts(update)
+def workspace_bytes(m, n, ldw, update=0, rec_levels=0):
+    o = _opts(update, rec_levels=rec_levels)
     return int(load().gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
 
 
@@ -194,7 +195,7 @@ def alloc_workspace(nbytes, device=None):
 
 
 def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0,
-        pair_variant=0):
+        pair_variant=0, rec_levels=0):
     """In-place PLE of the packed (m, ldw) tensor A with n columns.
 
     Returns (P, Q, rank) as device tensors (int64 [m], int64 [min(m, n)],
@@ -202,8 +203,8 @@ def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0,
     A = _packed(A, "A")
     m, ldw = A.shape
     lib = load()
-    o = _opts(update, check_padding, m4_variant=m4_variant, m4_blocks=m4_blocks, panel_regs=panel_regs,
-              lookahead=lookahead, pair_variant=pair_variant)
+    o = _opts(update, check_padding, rec_levels=rec_levels, m4_variant=m4_variant, m4_blocks=m4_blocks,
+              panel_regs=panel_regs, lookahead=lookahead, pair_variant=pair_variant)
     need = int(lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
     if need == 0 and (m or n):
         raise GF2Error(1, "gf2_ple_workspace_bytes")
@@ -283,8 +284,11 @@ def addmul(C, A, B, k, n, update=0, m4_variant=0, m4_blocks=0):
     C, A, B = _packed(C, "C"), _packed(A, "A"), _packed(B, "B")
     m = C.shape[0]
     o = _opts(update, m4_variant=m4_variant, m4_blocks=m4_blocks)
-    _check(load().gf2_addmul(_ptr(C), C.shape[1], _ptr(A), A.shape[1], _ptr(B), B.shape[1], m, k, n,
-                             ctypes.byref(o), _stream()), "gf2_addmul")
+    lib = load()
+    need = int(lib.gf2_addmul_workspace_bytes(m, k, n, ctypes.byref(o)))
+    ws = alloc_workspace(need, C.device) if need else None
+    _check(lib.gf2_addmul(_ptr(C), C.shape[1], _ptr(A), A.shape[1], _ptr(B), B.shape[1], m, k, n, _ptr(ws),
+                          ws.numel() if ws is not None else 0, ctypes.byref(o), _stream()), "gf2_addmul")
 
 
 def make_table(rows, k, n, T=None):
@@ -417,7 +421,7 @@ class ServeSession:
         o.max_batch = int(max_batch)
         o.small_max_dim = int(small_max_dim)
         self._h = ctypes.c_void_p(0)
-        self._keep = {}  # device inputs referenced until admitted
+        self._keep = {}  # device inputs, referenced until their request is done or failed
         _check(load().gf2_serve_create(ctypes.byref(o), ctypes.byref(self._h)), "gf2_serve_create")
 
     def submit(self, A, n):
@@ -428,6 +432,8 @@ class ServeSession:
             m, ldw = A.shape
             if A.numel() and A.stride(0) != ldw:
                 raise ValueError("A must be contiguous")
+            # the session's copy of A is not ordered after this stream
+            torch.cuda.current_stream(A.device).synchronize()
             _check(load().gf2_serve_submit(self._h, _ptr(A), 1, m, n, ldw, ctypes.byref(t)), "gf2_serve_submit")
             self._keep[t.value] = A
         else:
@@ -441,7 +447,7 @@ class ServeSession:
     def poll(self, ticket):
         i = ServeInfo()
         _check(load().gf2_serve_poll(self._h, ticket, ctypes.byref(i)), "gf2_serve_poll")
-        if i.state != 0:
+        if i.state in (2, 3):  # done or failed: the session has read A
             self._keep.pop(ticket, None)
         return _info_dict(i)
 

@@ -54,7 +54,7 @@ def test_argument_errors_before_launch():
     assert lib.gf2_ple(nul, 5, 5, 1, nul, nul, nul, nul, 0, None, nul) == 1
     bad = G.Opts()
     bad.update = 7
-    assert lib.gf2_addmul(nul, 1, nul, 1, nul, 1, 1, 1, 1, ctypes.byref(bad), nul) == 1
+    assert lib.gf2_addmul(nul, 1, nul, 1, nul, 1, 1, 1, 1, nul, 0, ctypes.byref(bad), nul) == 1
     assert lib.gf2_make_table(nul, 1, 0, 10, nul, 1, nul) == 1
     assert lib.gf2_make_table(nul, 1, 9, 10, nul, 1, nul) == 1
     assert lib.gf2_echelon_from_ple(nul, 3, 3, 1, nul, nul) == 1
@@ -155,9 +155,39 @@ def test_schedule_options_checked_before_launch():
     ws_ptr = (ws.ctypes.data + 255) // 256 * 256
     p = lambda a: ctypes.c_void_p(a.ctypes.data)
     for field, value in (("pair_variant", 99), ("pair_variant", -1), ("lookahead", 4), ("panel_regs", 3),
-                         ("update", 2)):
+                         ("update", 4), ("update", -1), ("rec_levels", 17), ("rec_levels", -1)):
         o = G.Opts()
         setattr(o, field, value)
         st = lib.gf2_ple(p(A), m, n, ldw, p(P), p(Q), p(rank), ctypes.c_void_p(ws_ptr), ws.nbytes - 256,
                          ctypes.byref(o), ctypes.c_void_p(0))
         assert st == 1, (field, value, st)
+
+
+def test_recursive_and_product_workspaces():
+    """The Algorithm 3 schedules (update 2 and 3) need the pass loop's
+    workspace plus their own (sub-ranks; for the matrix-core products the bit
+    transpose of the largest product's right operand); the matrix-core
+    gf2_addmul needs the bit transpose of B, the table product nothing.  Too
+    small a workspace is refused before any device call."""
+    lib = G.load()
+    m = n = 4096
+    ldw = 64
+    base = lib.gf2_ple_workspace_bytes(m, n, ldw, None)
+    o2, o3 = G.Opts(), G.Opts()
+    o2.update, o3.update = 2, 3
+    w2 = lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o2))
+    w3 = lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o3))
+    assert base < w3 < w2
+    # the top product: 2048 inner bits x 2048 columns, bit-transposed
+    assert w2 - w3 >= 2048 * 2048 // 8
+    fake = ctypes.c_void_p(1 << 20)
+    nul = ctypes.c_void_p(0)
+    assert lib.gf2_ple(fake, m, n, ldw, fake, fake, fake, fake, w2 - 1, ctypes.byref(o2), nul) == 2
+    assert lib.gf2_ple(fake, m, n, ldw, fake, fake, fake, fake, w3 - 1, ctypes.byref(o3), nul) == 2
+    o1 = G.Opts()
+    o1.update = 1
+    assert lib.gf2_addmul_workspace_bytes(100, 300, 1000, ctypes.byref(o1)) == 0
+    need = lib.gf2_addmul_workspace_bytes(100, 300, 1000, ctypes.byref(o2))
+    assert need == 16 * 64 * 5 * 8
+    assert lib.gf2_addmul(fake, 16, fake, 5, fake, 16, 100, 300, 1000, fake, need - 1, ctypes.byref(o2), nul) == 2
+    assert lib.gf2_addmul(fake, 16, fake, 5, fake, 16, 100, 300, 1000, nul, 0, ctypes.byref(o2), nul) == 1

@@ -1,0 +1,146 @@
+"""CPU model of the block-recursive PLE (Algorithm 3, Section 3.3) as the
+library schedules it (update = 2 / 3): the steps in the library's order with
+its index arithmetic -- the column split at a multiple of 64, the left PLE
+whose swaps move whole rows, the triangular solve and product on the right
+block, the right PLE, the P / Q / rank combination and the word walk that
+moves the right block's L bits left -- with the oracle's PLE at the leaves.
+The result must equal the oracle's PLE of the whole matrix (its arithmetic
+is checked, not the kernels': those are compared with the oracle on the GPU).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1111_6549_amd import inputs
+from tests import helpers as H
+
+
+def _leaf(M, r0, c0, m, n, P, Q):
+    """The pass loop on the block M[r0:r0+m, c0:c0+n], swaps of whole rows."""
+    blk = H.pack(M[r0:r0 + m, c0:c0 + n])
+    r, Pb, Qb = oracle.ple(blk, n)
+    out = H.unpack(blk, n)
+    for t in range(r):  # the same swaps on the rest of each row
+        p = int(Pb[t])
+        if p != t:
+            for cols in (slice(0, c0), slice(c0 + n, M.shape[1])):
+                a = M[r0 + t, cols].copy()
+                M[r0 + t, cols] = M[r0 + p, cols]
+                M[r0 + p, cols] = a
+    M[r0:r0 + m, c0:c0 + n] = out
+    P[r0:r0 + m] = Pb
+    Q[r0:r0 + min(m, n)] = Qb
+    return r
+
+
+def _shift_words(row_words, r1, n1, nL):
+    """The library's word walk for one row (k_alg3_shift): columns
+    [n1, n1 + nL) move to [r1, r1 + nL), the columns they leave become 0."""
+    def rbits(a, b, w):
+        lo = 64 * w
+        x0, x1 = max(a, lo), min(b, lo + 64)
+        if x0 >= x1:
+            return 0
+        ln = x1 - x0
+        return (((1 << ln) - 1) << (x0 - lo)) & ((1 << 64) - 1)
+    d = n1 - r1
+    s1 = n1 + nL
+    wlast = (s1 - 1) >> 6
+    row = [int(x) for x in row_words]
+    full = (1 << 64) - 1
+    for w in range(r1 >> 6, wlast + 1):
+        md, ms = rbits(r1, r1 + nL, w), rbits(n1, s1, w)
+        v = row[w] & ~ms & ~md & full
+        if md:
+            sc = 64 * w + d
+            sw, sh = sc >> 6, sc & 63
+            assert 0 <= sw <= wlast
+            a = row[sw]
+            b = row[sw + 1] if (sh and sw + 1 <= wlast) else 0
+            sv = ((a >> sh) | (b << (64 - sh))) & full if sh else a
+            v |= sv & md
+        row[w] = v
+    return np.array(row, dtype=np.uint64)
+
+
+def _rec(M, r0, c0, m, n, P, Q, levels):
+    if levels <= 0 or n <= 64 or m == 0:
+        return _leaf(M, r0, c0, m, n, P, Q)
+    n1 = (n // 2 + 63) // 64 * 64
+    r1 = _rec(M, r0, c0, m, n1, P, Q, levels - 1)
+    N = n - n1
+    if r1 > 0:
+        # A01 <- L00^-1 A01 (forward substitution), then A11 += L10 A01
+        X = M[r0:r0 + r1, c0 + n1:c0 + n].astype(np.int64)
+        L = np.tril(M[r0:r0 + r1, c0:c0 + r1].astype(np.int64), -1)
+        for i in range(r1):
+            X[i] = (X[i] + L[i, :i] @ X[:i]) & 1
+        M[r0:r0 + r1, c0 + n1:c0 + n] = X
+        if m > r1:
+            L10 = M[r0 + r1:r0 + m, c0:c0 + r1].astype(np.int64)
+            M[r0 + r1:r0 + m, c0 + n1:c0 + n] ^= ((L10 @ X) & 1).astype(np.uint8)
+    if m <= r1:
+        return r1
+    r2 = _rec(M, r0 + r1, c0 + n1, m - r1, N, P, Q, levels - 1)
+    mn = min(m, n)
+    q_right = min(m - r1, N)
+    for i in range(r1, max(m, mn)):
+        if i < m:
+            P[r0 + i] += r1
+        if i < mn:
+            if i < r1 + q_right:
+                if Q[r0 + i] >= 0:
+                    Q[r0 + i] += n1
+            else:
+                Q[r0 + i] = -1
+    if r1 < n1:
+        for i in range(r1, m):
+            nL = min(i - r1, r2)
+            if nL <= 0:
+                continue
+            words = H.pack(M[r0 + i:r0 + i + 1, c0:c0 + n])[0]
+            M[r0 + i, c0:c0 + n] = H.unpack(_shift_words(words, r1, n1, nL)[None, :], n)[0]
+    return r1 + r2
+
+
+def model_alg3(A, n, levels):
+    m = A.shape[0]
+    M = H.unpack(A, n).copy()
+    P = np.zeros(m, np.int64)
+    Q = np.full(min(m, n), -1, np.int64)
+    r = _rec(M, 0, 0, m, n, P, Q, levels)
+    return r, P, Q, H.pack(M, A.shape[1])
+
+
+def _case(kind, m, n, seed):
+    n1 = (n // 2 + 63) // 64 * 64
+    if kind == "u":
+        return inputs.bernoulli(m, n, seed)
+    if kind == "s":
+        return inputs.bernoulli(m, n, seed, p=3.0 / n)
+    if kind == "r":
+        return inputs.known_rank(m, n, max(1, min(m, n) // 3), seed, seed + 1)
+    if kind == "deficient_left":
+        left = H.unpack(inputs.known_rank(m, n1, n1 // 2, seed, seed + 1), n1)
+        right = H.unpack(inputs.bernoulli(m, n - n1, seed + 2), n - n1)
+        return H.pack(np.concatenate([left, right], axis=1))
+    if kind == "zero_left":
+        right = H.unpack(inputs.bernoulli(m, n - n1, seed), n - n1)
+        return H.pack(np.concatenate([np.zeros((m, n1), np.uint8), right], axis=1))
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("m,n,kind,levels", [(200, 200, "u", 1), (130, 300, "u", 1), (300, 130, "u", 1),
+                                             (250, 260, "deficient_left", 1), (150, 400, "deficient_left", 2),
+                                             (400, 150, "deficient_left", 1), (200, 260, "zero_left", 1),
+                                             (300, 300, "s", 2), (280, 330, "r", 3), (65, 130, "u", 1),
+                                             (64, 65, "u", 1), (500, 700, "deficient_left", 3)])
+def test_alg3_model_equals_oracle(m, n, kind, levels):
+    A = _case(kind, m, n, 70 + m + n)
+    r, P, Q, LE = model_alg3(A, n, levels)
+    B = A.copy()
+    ro, Po, Qo = oracle.ple(B, n)
+    assert r == ro
+    assert np.array_equal(Q, Qo)
+    assert np.array_equal(P, Po)
+    assert np.array_equal(LE, B)

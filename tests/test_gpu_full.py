@@ -80,3 +80,22 @@ def test_full_size_rref_digest(form):
     Qh[:r] = Q.cpu().numpy()[:r]
     got = _rref_digest(r, Qh, t.cpu().numpy().view(np.uint64))
     assert got == want["sha256"], "RREF digest differs from the oracle's"
+
+
+@pytest.mark.parametrize("update,levels", [(2, 1), (3, 1), (2, 2)])
+def test_full_size_digest_alg3(update, levels):
+    """Algorithm 3 levels over the 65536^2 seed-5 matrix (products on the
+    matrix cores, update 2, or the tables, update 3) hash to the oracle's PLE
+    digest like Algorithm 2."""
+    want = json.load(open(GOLDEN))["65536x65536_seed5"]
+    m, n, seed = want["m"], want["n"], want["seed"]
+    say("full size alg3 update", update, "levels", levels)
+    A = inputs.bernoulli(m, n, seed)
+    t = torch.from_numpy(A.view(np.int64)).cuda()
+    del A
+    P, Q, rank = G.ple(t, n, update=update, rec_levels=levels)
+    torch.cuda.synchronize()
+    r = int(rank.item())
+    assert r == want["rank"]
+    got = _digest(r, P.cpu().numpy(), Q.cpu().numpy(), t.cpu().numpy().view(np.uint64))
+    assert got == want["sha256"], "L\\E/P digest differs from the oracle's"

@@ -314,3 +314,60 @@ def test_pair_variants(variant):
         for mode in (0, 3):
             assert_same_ple(gpu_ple(A, n, lookahead=mode, pair_variant=variant), o,
                             "%dx%d %s lookahead=%d pair_variant=%d" % (m, n, kind, mode, variant))
+
+
+# --- Algorithm 3 (block-recursive PLE, update = 2 / 3) -----------------------
+
+def _hstack_bits(left, nl, right, nr):
+    """[left | right] as one packed matrix (nl + nr columns)."""
+    return H.pack(np.concatenate([H.unpack(left, nl), H.unpack(right, nr)], axis=1))
+
+
+def _alg3_case(kind, m, n):
+    n1 = (n // 2 + 63) // 64 * 64  # the recursion's first split
+    if kind == "u":
+        return inputs.bernoulli(m, n, 500 + m + n)
+    if kind == "s":
+        return inputs.bernoulli(m, n, 501 + m + n, p=3.0 / n)
+    if kind == "r":
+        return inputs.known_rank(m, n, min(m, n) // 3, 23 + m, 29 + n)
+    if kind == "deficient_left":
+        # left block of rank n1 / 2, random right block: the right block's L
+        # bits move left across the split
+        left = inputs.known_rank(m, n1, n1 // 2, 31 + m, 37 + n)
+        right = inputs.bernoulli(m, n - n1, 502 + m)
+        return _hstack_bits(left, n1, right, n - n1)
+    if kind == "zero_left":
+        right = inputs.bernoulli(m, n - n1, 503 + m)
+        return _hstack_bits(np.zeros((m, inputs.words(n1)), np.uint64), n1, right, n - n1)
+    raise ValueError(kind)
+
+
+ALG3_CASES = [(1000, 1000, "u"), (300, 2000, "u"), (2000, 300, "u"), (1500, 1300, "u"), (2000, 2000, "s"),
+              (1200, 1100, "r"), (1000, 1000, "deficient_left"), (700, 1500, "deficient_left"),
+              (1500, 700, "deficient_left"), (900, 1000, "zero_left"), (65, 130, "u"), (64, 65, "u"),
+              (3000, 200, "r")]
+
+
+@pytest.mark.parametrize("update", [2, 3])
+@pytest.mark.parametrize("m,n,kind", ALG3_CASES)
+def test_alg3_parity(m, n, kind, update):
+    """One level of Algorithm 3 (column split in halves, TRSM, product on the
+    matrix cores (2) or the tables (3), PLE of the lower right block, P, Q and
+    L combined) gives the oracle's (rank, P, Q, L\\E) bit for bit."""
+    say("alg3", update, m, n, kind)
+    A = _alg3_case(kind, m, n)
+    assert_same_ple(gpu_ple(A, n, update=update), oracle_ple(A, n), "alg3 u%d %dx%d %s" % (update, m, n, kind))
+
+
+@pytest.mark.parametrize("update", [2, 3])
+@pytest.mark.parametrize("m,n,kind,levels", [(3000, 2500, "u", 2), (2500, 3000, "deficient_left", 3),
+                                             (4096, 4096, "u", 3), (2000, 2000, "s", 4), (8192, 8192, "u", 1)])
+def test_alg3_levels_parity(m, n, kind, levels, update):
+    """Several levels of Algorithm 3 (each half recursed again) against the
+    oracle; 8192^2 takes the matrix-core path for its products of 512 inner
+    bits and more."""
+    say("alg3 levels", update, m, n, kind, levels)
+    A = _alg3_case(kind, m, n)
+    assert_same_ple(gpu_ple(A, n, update=update, rec_levels=levels), oracle_ple(A, n),
+                    "alg3 u%d %dx%d %s levels %d" % (update, m, n, kind, levels))
