@@ -124,7 +124,6 @@ struct gf2_serve {
     SlotLayout lay{};
     int64_t slot_cap = 0;  // workgroup slots reserved per stream
     int64_t small_ldw = 0;
-    hipStream_t fetch_stream = nullptr;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -140,7 +139,9 @@ struct gf2_serve {
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
     void run();
-    hipError_t enqueue(Launch &L);
+    // Enqueue a launch without holding mu: rs are its requests (admitted and
+    // running, so no other thread changes or frees them meanwhile).
+    hipError_t enqueue(Launch &L, const std::vector<Req *> &rs, bool *single);
 };
 
 namespace {
@@ -165,12 +166,12 @@ double cost_of(const Req &r) { return (double)r.m * (double)words_for(r.n) * (do
 
 }  // namespace
 
-hipError_t gf2_serve::enqueue(Launch &L) {
+hipError_t gf2_serve::enqueue(Launch &L, const std::vector<Req *> &rs, bool *single) {
     hipStream_t st = streams[L.stream];
     hipError_t e = hipSuccess;
     int64_t maxdim = 0;
-    for (int64_t id : L.ids) {
-        Req &r = *reqs[id];
+    for (Req *rp : rs) {
+        Req &r = *rp;
         const size_t nb = (size_t)r.m * (size_t)r.ldw * 8;
         uint8_t *dst = base + r.off + r.a_rel;
         if (nb) {
@@ -182,8 +183,9 @@ hipError_t gf2_serve::enqueue(Launch &L) {
         }
         maxdim = std::max(maxdim, std::max(r.m, r.n));
     }
-    if (L.ids.size() == 1 && !reqs[L.ids[0]]->small) {
-        Req &r = *reqs[L.ids[0]];
+    *single = rs.size() == 1 && !rs[0]->small;
+    if (*single) {
+        Req &r = *rs[0];
         uint8_t *p = base + r.off;
         // the default pass schedule (fused pairs), every kernel on this
         // stream (no look-ahead on the library's second stream)
@@ -191,7 +193,6 @@ hipError_t gf2_serve::enqueue(Launch &L) {
         e = ple_enqueue((uint64_t *)(p + r.a_rel), r.m, r.n, r.ldw, (int64_t *)(p + r.p_rel), (int64_t *)(p + r.q_rel),
                         (int64_t *)(p + r.r_rel), p + r.ws_rel, &o, st, false, false);
         if (e != hipSuccess) return e;
-        n_single++;
     } else {
         const Aux &x = aux[L.stream];
         const size_t cnt = L.ids.size();
@@ -199,7 +200,7 @@ hipError_t gf2_serve::enqueue(Launch &L) {
         L.roff.resize(cnt);
         L.order.resize(cnt);
         for (size_t k = 0; k < cnt; k++) {
-            const Req &r = *reqs[L.ids[k]];
+            const Req &r = *rs[k];
             gf2_desc d;
             d.a_off = (int64_t)((r.off + r.a_rel) / 8);
             d.m = r.m;
@@ -211,9 +212,8 @@ hipError_t gf2_serve::enqueue(Launch &L) {
             L.roff[k] = (int64_t)((r.off + r.r_rel) / 8);
         }
         std::iota(L.order.begin(), L.order.end(), 0);
-        std::stable_sort(L.order.begin(), L.order.end(), [&](int32_t a, int32_t b) {
-            return cost_of(*reqs[L.ids[a]]) > cost_of(*reqs[L.ids[b]]);
-        });
+        std::stable_sort(L.order.begin(), L.order.end(),
+                         [&](int32_t a, int32_t b) { return cost_of(*rs[a]) > cost_of(*rs[b]); });
         if ((e = hipMemcpyAsync(base + x.descs, L.descs.data(), cnt * sizeof(gf2_desc), hipMemcpyHostToDevice, st)) !=
                 hipSuccess ||
             (e = hipMemcpyAsync(base + x.roff, L.roff.data(), cnt * 8, hipMemcpyHostToDevice, st)) != hipSuccess ||
@@ -237,7 +237,6 @@ hipError_t gf2_serve::enqueue(Launch &L) {
         a.slots = base + x.slots;
         a.lay = lay;
         if ((e = batch_launch(cfg, (int)grid, a, st)) != hipSuccess) return e;
-        n_batched++;
     }
     return hipEventRecord(events[L.stream], st);
 }
@@ -310,21 +309,30 @@ void gf2_serve::run() {
                 }
                 ready.swap(rest);
             }
-            const hipError_t e = enqueue(*L);
+            std::vector<Req *> rs;
+            rs.reserve(L->ids.size());
+            for (int64_t id : L->ids) rs.push_back(reqs[id].get());
+            // host inputs are copied (pageable, so the copy may wait) and the
+            // launches enqueued without the lock: submit, poll and wait go on
+            busy[s] = 1;
+            bool single = false;
+            lk.unlock();
+            const hipError_t e = enqueue(*L, rs, &single);
+            lk.lock();
             if (e != hipSuccess) {
                 // the launch could not be enqueued: fail its requests
                 (void)hipStreamSynchronize(streams[s]);
                 const double t = now();
-                for (int64_t id : L->ids) {
-                    Req &r = *reqs[id];
-                    r.state = GF2_REQ_FAILED;
-                    r.status = GF2_EHIP;
-                    r.t_done = t;
+                for (Req *r : rs) {
+                    r->state = GF2_REQ_FAILED;
+                    r->status = GF2_EHIP;
+                    r->t_done = t;
                     n_failed++;
                 }
+                busy[s] = 0;
                 cv_done.notify_all();
             } else {
-                busy[s] = 1;
+                (single ? n_single : n_batched)++;
                 inflight.push_back(std::move(L));
             }
             progress = true;
@@ -350,7 +358,9 @@ gf2_status gf2_serve_create(const gf2_serve_opts *opts, gf2_serve **session) {
         o.small_max_dim > 4096)
         return GF2_EINVAL;
     if (o.budget_bytes == 0) o.budget_bytes = (int64_t)64 << 30;
-    if (o.streams == 0) o.streams = 4;
+    // three launch streams: with the process's default stream they fit the
+    // four hardware queues a process gets by default (GPU_MAX_HW_QUEUES)
+    if (o.streams == 0) o.streams = 3;
     if (o.max_batch == 0) o.max_batch = 4096;
     if (o.small_max_dim == 0) o.small_max_dim = 2048;
 
@@ -408,8 +418,6 @@ gf2_status gf2_serve_create(const gf2_serve_opts *opts, gf2_serve **session) {
                 hipEventCreateWithFlags(&S->events[k], hipEventDisableTiming) != hipSuccess)
                 st = GF2_EHIP;
         }
-        if (st == GF2_OK && hipStreamCreateWithFlags(&S->fetch_stream, hipStreamNonBlocking) != hipSuccess)
-            st = GF2_EHIP;
     }
     if (st == GF2_OK) {
         try {
@@ -423,7 +431,6 @@ gf2_status gf2_serve_create(const gf2_serve_opts *opts, gf2_serve **session) {
             if (s) (void)hipStreamDestroy(s);
         for (auto e : S->events)
             if (e) (void)hipEventDestroy(e);
-        if (S->fetch_stream) (void)hipStreamDestroy(S->fetch_stream);
         if (S->base) (void)hipFree(S->base);
         delete S;
         return st;
@@ -528,10 +535,12 @@ gf2_status gf2_serve_fetch(gf2_serve *S, int64_t ticket, uint64_t *LE, int64_t l
         if (LE && ldw_out < words_for(r->n)) return GF2_EINVAL;
         r->fetching = true;
     }
-    // the region is not reused before the release below
+    // the region is not reused before the release below; the copies run on
+    // the default stream (no stream of the session's own, so the session's
+    // launch streams keep the hardware queues to themselves)
     const hipMemcpyKind kind = to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const uint8_t *p = S->base + r->off;
-    hipStream_t fs = S->fetch_stream;
+    hipStream_t fs = nullptr;
     hipError_t e = hipSuccess;
     const int64_t mn = std::min(r->m, r->n);
     const int64_t wcopy = LE ? std::min(ldw_out, r->ldw) : 0;
@@ -598,7 +607,6 @@ gf2_status gf2_serve_destroy(gf2_serve *S) {
     for (auto s : S->streams) (void)hipStreamSynchronize(s);
     for (auto s : S->streams) (void)hipStreamDestroy(s);
     for (auto e : S->events) (void)hipEventDestroy(e);
-    if (S->fetch_stream) (void)hipStreamDestroy(S->fetch_stream);
     if (S->base) (void)hipFree(S->base);
     delete S;
     return GF2_OK;

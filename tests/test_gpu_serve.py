@@ -124,3 +124,60 @@ def test_serve_fetch_to_device_and_release():
     with pytest.raises(G.GF2Error):
         S.poll(t2)  # released tickets are unknown
     S.close()
+
+
+SERVE_BENCH_COUNT = 3000  # the request stream bench.py serves (seed 8)
+
+
+def test_serve_bench_stream_vs_oracle():
+    """Requests of the benchmark's serving stream (inputs.serving_requests
+    with its count and seed 8, sides up to 16384, density 0.5 or 0.05): the
+    first 30, and the first two of side >= 12000 at each density, served
+    together in one session from device inputs, each equal to the oracle."""
+    reqs = inputs.serving_requests(SERVE_BENCH_COUNT, seed=8)
+    pick = list(range(30))
+    for p in (0.05, 0.5):
+        pick += [i for i, r in enumerate(reqs) if max(r["m"], r["n"]) >= 12000 and r["p"] == p and i >= 30][:2]
+    say("serve bench stream", len(pick), "requests", [(reqs[i]["m"], reqs[i]["n"], reqs[i]["p"]) for i in pick[30:]])
+    mats = [inputs.bernoulli(reqs[i]["m"], reqs[i]["n"], reqs[i]["seed"], p=reqs[i]["p"]) for i in pick]
+    S = G.ServeSession(budget_bytes=64 << 30)
+    tickets = [S.submit(torch.from_numpy(A.view(np.int64).copy()).cuda(), reqs[i]["n"]) for i, A in zip(pick, mats)]
+    out = []
+    for t, i in zip(tickets, pick):
+        info = S.wait(t)
+        assert info["state"] == "done", info
+        out.append(S.fetch(t, reqs[i]["m"], reqs[i]["n"]))
+    S.close()
+    for i, A, g in zip(pick, mats, out):
+        say("  oracle", i, reqs[i]["m"], reqs[i]["n"], reqs[i]["p"])
+        assert_same_ple(g, oracle_ple(A, reqs[i]["n"]), "bench request #%d" % i)
+
+
+def test_serve_device_input_kept_until_done():
+    """A device input is copied when its request is launched, which can be
+    after admission: with one launch stream, requests admitted behind a
+    running one wait with their inputs uncopied.  The binding keeps each
+    input tensor referenced until its request is done, so freeing the
+    caller's tensors and filling fresh ones of the same size (which the
+    caching allocator may place on the same memory) cannot change a result."""
+    say("serve device input lifetime")
+    n = 6000
+    mats = [inputs.bernoulli(n, n, 70 + k) for k in range(5)]
+    S = G.ServeSession(budget_bytes=8 << 30, streams=1, small_max_dim=1024)
+    tickets = []
+    for A in mats:
+        t = torch.from_numpy(A.view(np.int64).copy()).cuda()
+        tickets.append(S.submit(t, n))
+        del t
+    states = [S.poll(t)["state"] for t in tickets]
+    say("  states after submit", states)
+    junk = [torch.full((n, inputs.words(n)), -1, dtype=torch.int64, device="cuda") for _ in range(8)]
+    torch.cuda.synchronize()
+    out = []
+    for t in tickets:
+        assert S.wait(t)["state"] == "done"
+        out.append(S.fetch(t, n, n))
+    S.close()
+    del junk
+    for k, (A, g) in enumerate(zip(mats, out)):
+        assert_same_ple(g, oracle_ple(A, n), "device input #%d" % k)
