@@ -14,7 +14,13 @@ goes to stderr.
              second, event-timed repetition of the same steps (HIP events on
              the launch stream, recorded by the library itself)
   cpu_baseline  the CPU oracle (plain Gaussian elimination) timed on this
-             host on a bounded sample, scaled by n^3 to the full matrix
+             host on the benchmark matrix itself, over its first columns (a
+             bounded share of the elimination), scaled to the whole by the
+             expected row-word operations of the pivot sequence
+Further legs (each can be skipped): Algorithm 3 and the product comparison,
+the other configurations (1024^2, 16384^2 uniform and rank 12000,
+32768 x 131072) with the oracle beside each, the 10000^2 density sweep, the
+RREF helpers, the uneven batch and the serving stream.
 """
 import argparse
 import hashlib
@@ -127,25 +133,171 @@ def kernel_source_hash():
 DENSITY_POINTS = (0.1, 0.2, 0.5, 1.0, 2.0, 3.0, 5.0, 8.0, 12.0, 20.0)
 
 
-def cpu_baseline(n_full, sample):
-    """The oracle, untouched, on a sample x sample Bernoulli(0.5) matrix."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_work(m, n, Q, r, c_end=None):
+    """Expected row-word operations of the oracle's elimination up to column
+    c_end (all columns if None): at the pivot of column c (rank t before it)
+    every row below is tested (one word) and, for a uniformly random trailing
+    block, half of them take the pivot row's words from c on (read and write)."""
+    import numpy as np
+    nw = (n + 63) // 64
+    q = np.asarray(Q[:r], dtype=np.float64)
+    t = np.arange(r, dtype=np.float64)
+    keep = q < (n if c_end is None else c_end)
+    cost = (m - t - 1) * (1.0 + (nw - np.floor(q / 64.0)) / 2.0)
+    return float(cost[keep].sum())
+
+
+def oracle_prefix(A, n, c_end, threads, Q_full, r_full):
+    """The untouched oracle's elimination of the first c_end columns of A (a
+    copy; the whole matrix, so nothing fits a cache that the full run would
+    not), on `threads` threads; the time scaled to the whole elimination by
+    the expected row-word operations (oracle_work) of the full pivot
+    sequence.  Returns (scaled seconds, measured seconds, work fraction)."""
+    import numpy as np
     import oracle
-    from paper_1111_6549_amd import inputs
-    A = inputs.bernoulli(sample, sample, 2)
-    oracle.ple(A[:64, :1].copy(), 64)  # load/compile outside the timing
-    t0 = time.perf_counter()
-    r, _, _ = oracle.ple(A, sample)
-    dt = time.perf_counter() - t0
-    scale = (n_full / sample) ** 3
+    m = A.shape[0]
+    B = np.array(A, copy=True)
+    oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        oracle.ple_cols(B, n, c_end)
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(os.cpu_count() or 1)
+    frac = oracle_work(m, n, Q_full, r_full, c_end) / oracle_work(m, n, Q_full, r_full)
+    return dt / frac, dt, frac
+
+
+def cpu_baseline(A, n, Q, r, args, log_fn):
+    """The oracle on the benchmark matrix itself (65536^2, seed 5): its first
+    args.cpu_cols columns on every core, and its first args.cpu_cols_1core
+    columns on one core, each scaled to the whole elimination by the expected
+    row-word operations of the measured pivot sequence."""
+    import oracle
+    cores = oracle.threads()
+    full, dt, frac = oracle_prefix(A, n, args.cpu_cols, cores, Q, r)
+    log_fn("cpu baseline: first %d columns on %d threads in %.2f s (%.4f of the work)" % (args.cpu_cols, cores, dt,
+                                                                                            frac))
+    one, dt1, frac1 = oracle_prefix(A, n, args.cpu_cols_1core, 1, Q, r)
+    log_fn("cpu baseline: first %d columns on 1 thread in %.2f s (%.4f of the work)" % (args.cpu_cols_1core, dt1,
+                                                                                          frac1))
     return {
-        "value": 1.0 / (dt * scale),
+        "value": 1.0 / full,
         "unit": "matrices/s",
-        "cores": oracle.threads(),
+        "cores": cores,
         "kind": "oracle",
-        "sample": "%dx%d Bernoulli(0.5) seed 2, whole oracle PLE in %.2f s (rank %d), scaled by (%d/%d)^3; "
-                  "the sample is small enough to stay in the host's caches, so the scaled rate overstates the "
-                  "oracle on the full matrix" % (sample, sample, dt, r, n_full, sample),
+        "sample": "the benchmark matrix itself (%dx%d, seed %d): the oracle's first %d column steps on %d threads "
+                  "took %.2f s, %.4f of the whole elimination's expected row-word operations (from its pivot "
+                  "sequence), so %.1f s for the whole PLE" % (A.shape[0], n, args.seed, args.cpu_cols, cores, dt,
+                                                              frac, full),
+        "cpu_model": cpu_model(),
+        "one_core": {"value": 1.0 / one, "unit": "matrices/s", "cores": 1,
+                     "sample": "first %d column steps in %.2f s, %.5f of the work, so %.0f s for the whole PLE"
+                               % (args.cpu_cols_1core, dt1, frac1, one)},
     }
+
+
+def run_configs(args, log_fn):
+    """The other workloads of the method on one GPU, each next to the oracle:
+    1024^2 (seed 1), 16384^2 uniform (seed 2), 16384^2 of rank 12000 (X seed
+    3 times Y seed 4) and 32768 x 131072 (seed 6).  GPU: median of repeated
+    gf2_ple calls on resident input (restored from a device copy outside the
+    timing); the trailing-update launches' algorithmic bytes per launch over
+    their mean event-timed duration (the HBM fraction of the dominant
+    kernel; at these sizes the matrix fits the 256 MB Infinity Cache, so it is
+    an upper bound of the HBM share).  Oracle: whole runs (median) where they
+    take seconds, else the first columns scaled as for the headline."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1111_6549_amd import gf2ple as G
+    from paper_1111_6549_amd import inputs
+
+    cores = oracle.threads()
+    cases = [
+        ("1024x1024 Bernoulli(0.5) seed 1", 1024, 1024, lambda: inputs.bernoulli(1024, 1024, 1), 20,
+         {"all": ("whole", 20), "one": ("whole", 20)}),
+        ("16384x16384 Bernoulli(0.5) seed 2", 16384, 16384, lambda: inputs.bernoulli(16384, 16384, 2), 10,
+         {"all": ("whole", 3), "one": ("prefix", 2048)}),
+        ("16384x16384 rank 12000: X (16384x12000, seed 3) Y (12000x16384, seed 4)", 16384, 16384,
+         lambda: inputs.known_rank(16384, 16384, 12000, 3, 4, device="cuda"), 10,
+         {"all": ("whole", 3), "one": ("prefix", 2048)}),
+        ("32768x131072 Bernoulli(0.5) seed 6", 32768, 131072, lambda: inputs.bernoulli(32768, 131072, 6), 5,
+         {"all": ("prefix", 2048)}),
+    ]
+    out = []
+    for name, m, n, make, reps, cpu_plan in cases:
+        A = make()
+        ldw = inputs.words(n)
+        dev = torch.from_numpy(A.view(np.int64)).cuda()
+        work = torch.empty_like(dev)
+        ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw))
+        times = []
+        for rep in range(reps + 2):
+            work.copy_(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P, Q, rank = G.ple(work, n, ws=ws)
+            torch.cuda.synchronize()
+            if rep >= 2:
+                times.append((time.perf_counter() - t0) * 1000.0)
+        times.sort()
+        r = int(rank.item())
+        Qh = Q.cpu().numpy()
+        kinds = G.ple_schedule(m, n)
+        abytes = alg_bytes_m4rm(m, n, Qh, r, kinds)
+        G.profile_start()
+        for rep in range(3):
+            work.copy_(dev)
+            G.ple(work, n, ws=ws)
+        torch.cuda.synchronize()
+        prof = G.profile_stop()
+        pt = {"workload": name, "m": m, "n": n, "rank": r, "gpu_ms": round(times[len(times) // 2], 4),
+              "reps": reps, "update_alg_bytes": abytes}
+        k = prof.get("m4rm")
+        if k and k["launches"] and abytes:
+            per_launch = abytes / (k["launches"] / 3.0)
+            avg_ms = k["total_ms"] / k["launches"]
+            pt["update_avg_launch_ms"] = round(avg_ms, 5)
+            pt["update_alg_GBps"] = round(per_launch / (avg_ms * 1e-3) / 1e9, 1)
+            pt["update_frac_hbm"] = round(pt["update_alg_GBps"] / HBM_PEAK_GBPS, 4)
+        pt["whole_ple_alg_GBps"] = round(abytes / (pt["gpu_ms"] * 1e-3) / 1e9, 1)
+        if not args.no_cpu_baseline:
+            for which, (how, count) in cpu_plan.items():
+                th = cores if which == "all" else 1
+                if how == "whole":
+                    oracle.set_threads(th)
+                    ts = []
+                    for _ in range(count):
+                        B = np.array(A, copy=True)
+                        t0 = time.perf_counter()
+                        oracle.ple(B, n)
+                        ts.append(time.perf_counter() - t0)
+                    oracle.set_threads(os.cpu_count() or 1)
+                    ts.sort()
+                    pt["oracle_%s" % which] = {"cores": th, "ms": round(ts[len(ts) // 2] * 1e3, 2),
+                                               "sample": "whole PLE, median of %d" % count}
+                else:
+                    full, dt, frac = oracle_prefix(A, n, count, th, Qh, r)
+                    pt["oracle_%s" % which] = {"cores": th, "ms": round(full * 1e3, 1),
+                                               "sample": "first %d column steps in %.2f s, %.4f of the expected "
+                                                         "row-word operations, scaled" % (count, dt, frac)}
+        out.append(pt)
+        log_fn("config: %s" % json.dumps(pt))
+        del dev, work, ws, A
+        torch.cuda.empty_cache()
+    return {"cpu_model": cpu_model(), "points": out}
 
 
 def run_density(args, log_fn):
@@ -269,17 +421,48 @@ def run_batched(args, log_fn):
         "classes": [{"max_dim": c["max_dim"], "count": c["count"], "schedule": c["config_name"], "grid": c["grid"]}
                     for c in plan.info() if c["count"]],
     }
+    # the batch's algorithmic bytes: per matrix, 16 B per trailing row word
+    # per 64-column pass (the batched kernel runs single passes), from its
+    # own pivot columns; a weak HBM bound, most of it served from the caches
+    Qa, Ra = Q.cpu().numpy(), R.cpu().numpy()
+    bbytes = 0
+    for d, rk in zip(descs, Ra):
+        qd = Qa[d["q_off"]:d["q_off"] + min(d["m"], d["n"])]
+        bbytes += alg_bytes_m4rm(d["m"], d["n"], qd, int(rk), [0] * ((d["n"] + 63) // 64))
+    out["alg_bytes"] = int(bbytes)
+    out["alg_GBps"] = round(bbytes / batched_s / 1e9, 1)
+    out["frac_hbm"] = round(bbytes / batched_s / 1e9 / HBM_PEAK_GBPS, 4)
+    out["bound"] = "latency of the serial panels (about min(m, n)/64 per matrix) and LDS/VALU table work"
     if not args.no_cpu_baseline:
         import oracle
-        sample = list(range(0, count, max(1, count // args.batch_cpu_sample)))[:args.batch_cpu_sample]
+        from concurrent.futures import ThreadPoolExecutor
+        cores = oracle.threads()
+        host = [np.array(mt, copy=True) for mt in mats]
+
+        def one(i):
+            oracle.set_threads(1)  # this worker thread's elimination on one core
+            oracle.ple(host[i], shapes[i][1])
+
         t0 = time.perf_counter()
-        for i in sample:
-            B = np.array(mats[i], copy=True)
-            oracle.ple(B, shapes[i][1])
+        with ThreadPoolExecutor(max_workers=cores) as ex:
+            list(ex.map(one, range(count)))
         dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(len(sample) / dt, 2), "unit": "matrices/s", "cores": oracle.threads(),
-                               "kind": "oracle", "sample": "%d of the %d matrices (every %d-th), %.2f s"
-                                                            % (len(sample), count, count // len(sample), dt)}
+        sample = list(range(0, count, max(1, count // args.batch_cpu_sample)))[:args.batch_cpu_sample]
+        host1 = [np.array(mats[i], copy=True) for i in sample]
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        for i, B in zip(sample, host1):
+            oracle.ple(B, shapes[i][1])
+        dt1 = time.perf_counter() - t0
+        oracle.set_threads(os.cpu_count() or 1)
+        out["cpu_baseline"] = {"value": round(count / dt, 2), "unit": "matrices/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": "all %d matrices, one matrix per thread on %d threads, %.2f s"
+                                         % (count, cores, dt),
+                               "one_core": {"value": round(len(sample) / dt1, 2), "unit": "matrices/s", "cores": 1,
+                                            "sample": "%d of the %d matrices (every %d-th) in %.2f s"
+                                                      % (len(sample), count, count // len(sample), dt1)}}
+        log_fn("batched: oracle %.2f s on %d threads, %.2f s for %d on one" % (dt, cores, dt1, len(sample)))
     plan.close()
     return out
 
@@ -288,10 +471,12 @@ def run_serving(args, log_fn):
     """Serving: a request stream (sides log-uniform in [128, 16384], square or
     s x ceil(s/2), density 0.5 or 0.05; seed 8), inputs resident on the device.
     Plain = gf2_ple per request in arrival order on one stream.  Served = the
-    serving session (64 GiB budget) fed Poisson arrivals at 0.9x the measured
-    plain capacity (latency = arrival -> result in device memory), and the
-    same requests all at once (saturated throughput).  The plain latency at
-    the same arrivals is a FIFO replay of the measured plain service times."""
+    serving session (64 GiB budget) fed Poisson arrivals at 0.5, 0.9 and 1.5x
+    the measured plain capacity (latency = arrival -> result in device
+    memory), and the same requests all at once (saturated throughput).  The
+    plain latency at the same arrivals is a FIFO replay of the measured plain
+    service times.  The oracle serves the first requests at the 0.9x arrivals,
+    one request per core in arrival order."""
     import numpy as np
     import torch
 
@@ -300,7 +485,13 @@ def run_serving(args, log_fn):
 
     count = args.serve_count
     reqs = inputs.serving_requests(count, seed=8)
-    dev = [torch.from_numpy(inputs.bernoulli(r["m"], r["n"], r["seed"], p=r["p"]).view(np.int64)).cuda() for r in reqs]
+    dev = []
+    host_first = []
+    for k, r in enumerate(reqs):
+        A = inputs.bernoulli(r["m"], r["n"], r["seed"], p=r["p"])
+        dev.append(torch.from_numpy(A.view(np.int64)).cuda())
+        if k < args.serve_cpu_sample:
+            host_first.append(A)
     torch.cuda.synchronize()
     log_fn("serving: %d requests resident (%.2f GB)" % (count, sum(t.numel() for t in dev) * 8 / 1e9))
 
@@ -346,47 +537,155 @@ def run_serving(args, log_fn):
         span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
         return lat, span, st
 
-    rate = 0.9 * capacity
+    def fifo(arrivals, service_s, servers=1):
+        """Completion latencies of a FIFO queue with `servers` servers."""
+        free = [0.0] * servers
+        lat = np.empty(len(arrivals))
+        for i, at in enumerate(arrivals):
+            k = int(np.argmin(free))
+            fin = max(at, free[k]) + service_s[i]
+            free[k] = fin
+            lat[i] = fin - at
+        return lat
+
+    pct = lambda x, q: round(float(np.percentile(x, q)) * 1e3, 3)
     rng = np.random.Generator(np.random.PCG64(8))
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
-    arrivals -= arrivals[0]
-    lat, span, st = serve(arrivals)
-    # FIFO replay of the plain service times at the same arrivals
-    fin = 0.0
-    plain_lat = np.empty(count)
-    for i in range(count):
-        fin = max(arrivals[i], fin) + service[i]
-        plain_lat[i] = fin - arrivals[i]
-    log_fn("serving: poisson %.1f req/s: p50 %.2f ms p99 %.2f ms" % (rate, np.median(lat) * 1e3,
-                                                                     np.percentile(lat, 99) * 1e3))
+    unit_gaps = rng.exponential(1.0, size=count)  # one draw, scaled per rate
+    poisson = []
+    arrivals_09 = None
+    for mult in (0.5, 0.9, 1.5):
+        rate = mult * capacity
+        arrivals = np.cumsum(unit_gaps / rate)
+        arrivals -= arrivals[0]
+        if mult == 0.9:
+            arrivals_09 = arrivals
+        lat, span, st = serve(arrivals)
+        plain_lat = fifo(arrivals, service)
+        pt = {"load": mult, "rate_per_s": round(rate, 1), "served_p50_ms": pct(lat, 50), "served_p99_ms": pct(lat, 99),
+              "served_matrices_per_s": round(count / span, 1), "plain_fifo_p50_ms": pct(plain_lat, 50),
+              "plain_fifo_p99_ms": pct(plain_lat, 99),
+              "launches": {"batched": st["launches_batched"], "single": st["launches_single"]}}
+        poisson.append(pt)
+        log_fn("serving: poisson %s" % json.dumps(pt))
     lat_sat, span_sat, st_sat = serve(np.zeros(count))
     log_fn("serving: saturated %.3f s for %d requests" % (span_sat, count))
-    pct = lambda x, q: round(float(np.percentile(x, q)) * 1e3, 3)
     out = {
         "workload": "%d requests, sides log-uniform in [128, 16384], square or s x ceil(s/2), density 0.5 or 0.05, "
                     "seed 8, inputs resident on the device, 64 GiB budget" % count,
         "plain_capacity_per_s": round(capacity, 1),
-        "poisson": {"rate_per_s": round(rate, 1), "served_p50_ms": pct(lat, 50), "served_p99_ms": pct(lat, 99),
-                    "served_matrices_per_s": round(count / span, 1), "plain_fifo_p50_ms": pct(plain_lat, 50),
-                    "plain_fifo_p99_ms": pct(plain_lat, 99),
-                    "launches": {"batched": st["launches_batched"], "single": st["launches_single"]}},
+        "poisson": poisson,
         "saturated": {"served_matrices_per_s": round(count / span_sat, 1),
                       "plain_matrices_per_s": round(capacity, 1),
                       "speedup_vs_plain": round((count / span_sat) / capacity, 2),
                       "served_p50_ms": pct(lat_sat, 50), "served_p99_ms": pct(lat_sat, 99),
                       "launches": {"batched": st_sat["launches_batched"], "single": st_sat["launches_single"]}},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and host_first:
+        import queue
+        import threading
+
         import oracle
-        sample = [i for i in range(count) if max(reqs[i]["m"], reqs[i]["n"]) <= 8192][:args.serve_cpu_sample]
-        t0 = time.perf_counter()
-        for i in sample:
-            B = dev[i].cpu().numpy().view(np.uint64).copy()
-            oracle.ple(B, reqs[i]["n"])
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(len(sample) / dt, 2), "unit": "matrices/s", "cores": oracle.threads(),
-                               "kind": "oracle", "sample": "the first %d requests with sides <= 8192, in order, "
-                                                           "%.2f s" % (len(sample), dt)}
+        cores = oracle.threads()
+        K = len(host_first)
+        arr = arrivals_09[:K]
+        fin = np.zeros(K)
+        q = queue.Queue()
+
+        def worker():
+            oracle.set_threads(1)
+            while True:
+                k = q.get()
+                if k is None:
+                    return
+                B = np.array(host_first[k], copy=True)
+                oracle.ple(B, reqs[k]["n"])
+                fin[k] = time.perf_counter()
+
+        ths = [threading.Thread(target=worker) for _ in range(cores)]
+        for t in ths:
+            t.start()
+        start = time.perf_counter()
+        for k in range(K):
+            while time.perf_counter() - start < arr[k]:
+                time.sleep(0.0002)
+            q.put(k)
+        for _ in ths:
+            q.put(None)
+        for t in ths:
+            t.join()
+        oracle.set_threads(os.cpu_count() or 1)
+        lat = fin - start - arr
+        span = fin.max() - start
+        out["cpu_baseline"] = {"value": round(K / span, 2), "unit": "matrices/s", "cores": cores, "kind": "oracle",
+                               "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                               "sample": "the first %d requests at the 0.9x Poisson arrivals, one request per "
+                                         "thread on %d threads in arrival order, %.2f s" % (K, cores, span)}
+        log_fn("serving: oracle %s" % json.dumps(out["cpu_baseline"]))
+    return out
+
+
+def run_alg3(args, m, n, pristine, work, log_fn):
+    """Algorithm 3 (block-recursive PLE) against Algorithm 2 on the bench
+    matrix: gf2_ple with update = 2 (products on the int8 matrix cores) and
+    update = 3 (products on the Four-Russians tables), one and two levels of
+    column splits; each the best of two calls after one untimed call.  Then
+    the product on its own, C ^= A B for 65536 x k x 65536 at k = 256, 512,
+    1024, on the tables and on the matrix cores: time, the tables' HBM rate
+    (16 bytes per row word of C per 64 inner bits) and the matrix cores'
+    int8 rate (2 m k n operations) against the 5.0 POPS dense int8 peak."""
+    import torch
+    from paper_1111_6549_amd import gf2ple as G
+    from paper_1111_6549_amd import inputs
+    ldw = inputs.words(n)
+    out = {"ple": []}
+    for update, levels in ((3, 1), (2, 1), (2, 2)):
+        ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw, update=update, rec_levels=levels))
+        times = []
+        for rep in range(3):
+            work.copy_(pristine)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P, Q, rank = G.ple(work, n, ws=ws, update=update, rec_levels=levels)
+            torch.cuda.synchronize()
+            if rep:
+                times.append((time.perf_counter() - t0) * 1000.0)
+        pt = {"update": update, "products": "int8 matrix cores" if update == 2 else "Four-Russians tables",
+              "levels": levels, "ms": round(min(times), 3), "rank": int(rank.item())}
+        out["ple"].append(pt)
+        log_fn("alg3: %s" % json.dumps(pt))
+        del ws
+    torch.cuda.empty_cache()
+    prod = []
+    mm = nn = 65536
+    C = torch.zeros((mm, nn // 64), dtype=torch.int64, device="cuda")
+    for k in (256, 512, 1024):
+        Ak = torch.from_numpy(inputs.bernoulli(mm, k, 60 + k).view("int64")).cuda()
+        Bk = torch.from_numpy(inputs.bernoulli(k, nn, 61 + k).view("int64")).cuda()
+        row = {"k": k}
+        for update in (1, 2):
+            times = []
+            for rep in range(4):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                G.addmul(C, Ak, Bk, k, nn, update=update)
+                torch.cuda.synchronize()
+                if rep:
+                    times.append((time.perf_counter() - t0) * 1000.0)
+            t = min(times)
+            if update == 1:
+                row["tables_ms"] = round(t, 3)
+                row["tables_alg_GBps"] = round(16.0 * mm * (nn // 64) * (k // 64) / (t * 1e-3) / 1e9, 1)
+            else:
+                pops = 2.0 * mm * k * nn / (t * 1e-3) / 1e15
+                row["mfma_ms"] = round(t, 3)
+                row["mfma_int8_POPS"] = round(pops, 3)
+                row["mfma_frac_int8_peak"] = round(pops / 5.0, 4)
+        prod.append(row)
+        log_fn("product: %s" % json.dumps(row))
+        del Ak, Bk
+    del C
+    torch.cuda.empty_cache()
+    out["product_65536_k_65536"] = prod
     return out
 
 
@@ -394,9 +693,7 @@ def run_helpers(m, n, A, Qh, r, log_fn):
     """The helpers of the paper's PLE-based reductions on the bench matrix (not
     in the timed step): echelon form and the reduced echelon form from L\\E
     (on the PLE result), and the reduced echelon form of the input in the
-    M4RI form.  Runs after the serving leg: the M4RI form's second stream
-    would otherwise change how the serving session's streams share the
-    process's hardware queues."""
+    M4RI form."""
     import numpy as np
     import torch
     from paper_1111_6549_amd import gf2ple as G
@@ -445,7 +742,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--cpu-cols", type=int, default=4096,
+                    help="columns of the oracle's elimination timed on all cores for the CPU baseline")
+    ap.add_argument("--cpu-cols-1core", type=int, default=256,
+                    help="columns of the oracle's elimination timed on one core")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 1024^2 / 16384^2 / 32768x131072 legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-helpers", action="store_true", help="skip timing the echelon / RREF helpers")
@@ -455,14 +756,15 @@ def main():
     ap.add_argument("--lookahead", type=int, default=0,
                     help="0 = library default, 1 = serial passes, 2 = look-ahead only, 3 = pairs everywhere")
     ap.add_argument("--pair-variant", type=int, default=0, help="fused pair update schedule 1..12 (0 = default)")
+    ap.add_argument("--no-alg3", action="store_true", help="skip Algorithm 3 and the product comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--batch-cpu-sample", type=int, default=512)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-density", action="store_true", help="skip the 10000^2 density sweep")
-    ap.add_argument("--serve-count", type=int, default=600)
-    ap.add_argument("--serve-cpu-sample", type=int, default=60)
+    ap.add_argument("--serve-count", type=int, default=3000)
+    ap.add_argument("--serve-cpu-sample", type=int, default=40)
     ap.add_argument("--serve-small-max", type=int, default=0,
                     help="largest side served by batched launches (0 = library default)")
     args = ap.parse_args()
@@ -486,8 +788,6 @@ def main():
     log("generating %dx%d Bernoulli(0.5) seed %d" % (m, n, args.seed))
     A = inputs.bernoulli(m, n, args.seed)
     pristine = torch.from_numpy(A.view(np.int64)).cuda()
-    if args.no_helpers:
-        del A
     work = torch.empty_like(pristine)
     ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw))
     torch.cuda.synchronize()
@@ -548,34 +848,36 @@ def main():
             }
         log("profiled: %s" % json.dumps(kernels))
 
+    alg3 = None
+    if not args.no_alg3:
+        alg3 = run_alg3(args, m, n, pristine, work, log)
+
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on %d^2" % args.cpu_sample)
-        cpu = cpu_baseline(n, args.cpu_sample)
-        log("cpu baseline done: %s" % cpu["sample"])
+        cpu = cpu_baseline(A, n, Qh, r, args, log)
+
+    configs = None
+    if not args.no_configs:
+        configs = run_configs(args, log)
 
     density = None
     if not args.no_density:
         density = run_density(args, log)
 
+    # the helpers (whose M4RI form makes the library's second stream) run
+    # before the serving session: its throughput must not depend on that
+    del work, pristine, ws
+    torch.cuda.empty_cache()
+    helpers = None
+    if not args.no_helpers:
+        helpers = run_helpers(m, n, A, Qh, r, log)
+    del A
     batched = None
     if not args.no_batched:
-        del work, pristine, ws
-        torch.cuda.empty_cache()
         batched = run_batched(args, log)
     serving = None
     if not args.no_serving:
-        if args.no_batched:
-            del work, pristine, ws
-            torch.cuda.empty_cache()
         serving = run_serving(args, log)
-    helpers = None
-    if not args.no_helpers:
-        if args.no_batched and args.no_serving:
-            del work, pristine, ws
-            torch.cuda.empty_cache()
-        helpers = run_helpers(m, n, A, Qh, r, log)
-        del A
 
     out = {
         "metric": "PLE time & HBM GB/s (% roofline), 65536² GF(2); batched matrices/s vs plain",
@@ -604,7 +906,9 @@ def main():
         "k64_alg_GBps_whole_ple": round(abytes64 / (ms_per_step * 1e-3) / 1e9, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "configs": configs,
         "helpers": helpers,
+        "alg3": alg3,
         "density_sweep": density,
         "batched": batched,
         "serving": serving,
