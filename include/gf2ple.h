@@ -105,6 +105,27 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
                    void *ws, size_t ws_bytes, const gf2_ple_opts *opts, void *stream);
 
 /*
+ * gf2_ple without caller workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as gf2_ple, except:
+ *   - the workspace is a static device array of the library, one per GPU,
+ *     gf2_ple_noalloc_max_workspace() bytes (16 MiB), held from the first
+ *     call on that GPU until the process ends; GF2_EWORKSPACE when
+ *     gf2_ple_workspace_bytes(m, n, ldw) exceeds it (e.g. m = 65536 with
+ *     ldw = 1024 needs about 4 MiB);
+ *   - every call on one GPU shares that array, so calls that overlap on one
+ *     GPU (on different streams, or from different host threads without
+ *     ordering) race and give undefined results: order them on one stream;
+ *   - it never waits on the stream and never uses a second stream (the
+ *     passes past full rank are enqueued and exit at once);
+ *   - opts->check_padding and opts->update >= 2 are rejected (GF2_EINVAL).
+ * It calls no hipMalloc / hipFree.
+ */
+size_t gf2_ple_noalloc_max_workspace(void);
+gf2_status gf2_ple_noalloc(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
+                           const gf2_ple_opts *opts, void *stream);
+
+/*
  * The pass schedule gf2_ple follows for an m x n matrix with these options
  * (host only, no device call): kinds[t] for each 64-column pass t of
  * Algorithm 2, for up to max passes:

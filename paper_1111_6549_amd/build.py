@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libgf2ple.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "ple_kernels.hip", "rref_kernels.hip", "prof.hip", "batch.hip", "serve.hip", "mfma.hip", "alg3.hip"]
+SOURCES = ["api.hip", "ple_kernels.hip", "rref_kernels.hip", "prof.hip", "batch.hip", "serve.hip", "mfma.hip", "noalloc.hip", "alg3.hip"]
 HEADERS = ["common.h"]
 
 HIP_FLAGS = [

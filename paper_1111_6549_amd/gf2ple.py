@@ -31,6 +31,7 @@ EXPORTS = [
     "gf2_batch_plan_destroy", "gf2_batch_num_configs", "gf2_batch_config_name",
     "gf2_serve_create", "gf2_serve_submit", "gf2_serve_poll", "gf2_serve_wait", "gf2_serve_fetch",
     "gf2_serve_release", "gf2_serve_stats_get", "gf2_serve_destroy",
+    "gf2_ple_noalloc_max_workspace", "gf2_ple_noalloc",
 ]
 
 
@@ -128,6 +129,8 @@ def load():
         "gf2_serve_release": (st, [p, i64]),
         "gf2_serve_stats_get": (st, [p, p]),
         "gf2_serve_destroy": (st, [p]),
+        "gf2_ple_noalloc_max_workspace": (sz, []),
+        "gf2_ple_noalloc": (st, [p, i64, i64, i64, p, p, p, p, p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -215,6 +218,21 @@ def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0,
     rank = torch.empty(1, dtype=torch.int64, device=A.device)
     _check(lib.gf2_ple(_ptr(A), m, n, ldw, _ptr(P), _ptr(Q), _ptr(rank), _ptr(ws), ws.numel(),
                        ctypes.byref(o), _stream()), "gf2_ple")
+    return P, Q, rank
+
+
+def ple_noalloc(A, n, lookahead=0, panel_regs=0):
+    """In-place PLE of the packed (m, ldw) tensor A through gf2_ple_noalloc
+    (the library's static device workspace instead of a caller buffer).
+    Returns (P, Q, rank) as device tensors."""
+    A = _packed(A, "A")
+    m, ldw = A.shape
+    o = _opts(panel_regs=panel_regs, lookahead=lookahead)
+    P = torch.empty(m, dtype=torch.int64, device=A.device)
+    Q = torch.empty(min(m, n), dtype=torch.int64, device=A.device)
+    rank = torch.empty(1, dtype=torch.int64, device=A.device)
+    _check(load().gf2_ple_noalloc(_ptr(A), m, n, ldw, _ptr(P), _ptr(Q), _ptr(rank), ctypes.byref(o), _stream()),
+           "gf2_ple_noalloc")
     return P, Q, rank
 
 

@@ -163,6 +163,24 @@ def test_schedule_options_checked_before_launch():
         assert st == 1, (field, value, st)
 
 
+def test_noalloc_checks_before_any_device_call():
+    """gf2_ple_noalloc: argument errors, check_padding and a workspace beyond
+    its static array are refused before any device call."""
+    lib = G.load()
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced on these paths
+    limit = int(lib.gf2_ple_noalloc_max_workspace())
+    assert limit == 16 << 20
+    assert lib.gf2_ple_noalloc(nul, -1, 5, 1, nul, nul, nul, None, nul) == 1
+    assert lib.gf2_ple_noalloc(fake, 5, 200, 2, fake, fake, fake, None, nul) == 1
+    o = G.Opts()
+    o.check_padding = 1
+    assert lib.gf2_ple_noalloc(fake, 5, 5, 1, fake, fake, fake, ctypes.byref(o), nul) == 1
+    m, n = 1_000_000, 64
+    assert lib.gf2_ple_workspace_bytes(m, n, 1, None) > limit
+    assert lib.gf2_ple_noalloc(fake, m, n, 1, fake, fake, fake, None, nul) == 2
+
+
 def test_recursive_and_product_workspaces():
     """The Algorithm 3 schedules (update 2 and 3) need the pass loop's
     workspace plus their own (sub-ranks; for the matrix-core products the bit
@@ -191,3 +209,5 @@ def test_recursive_and_product_workspaces():
     assert need == 16 * 64 * 5 * 8
     assert lib.gf2_addmul(fake, 16, fake, 5, fake, 16, 100, 300, 1000, fake, need - 1, ctypes.byref(o2), nul) == 2
     assert lib.gf2_addmul(fake, 16, fake, 5, fake, 16, 100, 300, 1000, nul, 0, ctypes.byref(o2), nul) == 1
+    # the no-allocation call takes no recursive schedule
+    assert lib.gf2_ple_noalloc(fake, m, n, ldw, fake, fake, fake, ctypes.byref(o2), nul) == 1
