@@ -50,10 +50,12 @@ typedef struct gf2_ple_opts {
     int32_t update;        /* 0 = default = 1: Algorithm 2, every trailing update by the Four-Russians tables;
                               2 = Algorithm 3 (block-recursive PLE, Section 3.3): split the columns in halves
                               (at a multiple of 64), PLE of the left half, A01 <- L00^-1 A01, then
-                              A11 <- A11 + L10 A01 as a product on the int8 matrix cores, PLE of A11, and
+                              A11 <- A11 + L10 A01 as a product on the fp4 matrix cores, PLE of A11, and
                               the two halves' P, Q and L combined; rec_levels levels of splits, Algorithm 2
                               below them.  Bit-identical to Algorithm 2.  Synchronises once per split.
-                              3 = the same recursion with its products on the Four-Russians tables */
+                              3 = the same recursion with its products on the Four-Russians tables;
+                              4 = the same recursion with its products on the int8 matrix cores.
+                              gf2_addmul: 2 = fp4 matrix cores, 4 = int8 matrix cores, else tables */
     int32_t rec_levels;    /* update = 2 or 3: levels of Algorithm 3 splits (0 = 1, at most 16) */
     int32_t m4_variant;    /* Four-Russians update schedule: 0 = default, 1..8 = a fixed (tile, threads, unroll) */
     int32_t m4_blocks;     /* target blocks per update launch (0 = default 512) */
@@ -187,10 +189,11 @@ gf2_status gf2_m4ri_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t
  * standalone call.  A is m x k (row stride lda words), B is k x n (ldb),
  * C is m x n (ldc).  For each 64-column slice of A the 64 matching rows of B
  * are tabulated 8 at a time (256-entry tables) and one table row per byte of
- * A's word is added to C.  opts->update = 2 selects the int8 matrix-core
- * product instead (the product Algorithm 3 hands to matrix multiplication;
+ * A's word is added to C.  opts->update = 2 selects the matrix-core product
+ * instead (the product Algorithm 3 hands to matrix multiplication;
  * bit-identical): B is bit-transposed into the workspace, the bits become
- * 0/1 int8 operands and the int32 sums are taken mod 2.
+ * fp4 (e2m1) operands 0.0 / 1.0 and the exact fp32 sums are taken mod 2;
+ * opts->update = 4 does the same with int8 operands and int32 sums.
  *   ws  device workspace of at least gf2_addmul_workspace_bytes(m, k, n,
  *       opts) bytes (0 for the table product, where ws may be NULL).
  */

@@ -20,10 +20,10 @@ size_t ple_workspace_total(int64_t m, int64_t ldw);
 size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma);
 
 // Algorithm 3 with `levels` levels of column splits (then Algorithm 2):
-// products on the int8 matrix cores (mfma) or the Four-Russians tables.
-// Synchronises the stream once per split (to size the products by the left
-// block's rank).
+// products on the Four-Russians tables (products = 0), the fp4 matrix cores
+// (1) or the int8 matrix cores (2).  Synchronises the stream once per split
+// (to size the products by the left block's rank).
 hipError_t ple_alg3(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
-                    const gf2_ple_opts *opts, hipStream_t s, int levels, bool mfma);
+                    const gf2_ple_opts *opts, hipStream_t s, int levels, int products);
 
 }  // namespace gf2

@@ -1,7 +1,7 @@
 // Block-recursive PLE (Algorithm 3, Section 3.3) on top of the
 // block-iterative pass loop (Algorithm 2), for gf2_ple with update = 2
-// (products on the int8 matrix cores) or update = 3 (products on the
-// Four-Russians tables).
+// (products on the fp4 matrix cores), 3 (products on the Four-Russians
+// tables) or 4 (products on the int8 matrix cores).
 //
 // One level on the m x n block A, split at column n1 (a multiple of 64):
 //   1. PLE of the left block [A0 A1]'s first n1 columns; its swaps move whole
@@ -31,7 +31,7 @@ hipError_t launch_m4rm(uint64_t *C, int64_t ldc, int64_t m, const uint64_t *coef
 hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int64_t n, uint64_t *Bt, int64_t ldbt,
                                  hipStream_t s);
 hipError_t launch_mfma_gf2(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *Bt, int64_t ldbt,
-                           int64_t m, int64_t k, int64_t n, hipStream_t s);
+                           int64_t m, int64_t k, int64_t n, hipStream_t s, int fmt);
 
 // X <- L^-1 X on one diagonal block of nb <= 64 rows (the leaves of step 2):
 // rows j0 .. j0 + nb - 1 of A, whose L bits below the diagonal sit in word
@@ -133,6 +133,7 @@ struct Ctx {
     const gf2_ple_opts *opts;
     hipStream_t s;
     bool mfma;
+    int fmt;              // matrix-core operands: 0 fp4, 1 int8
     int64_t *rank_slots;  // device, MAX_DEPTH
     uint64_t *bt;         // bit transpose of a product's right operand
     size_t bt_bytes;
@@ -149,7 +150,8 @@ hipError_t product(Ctx &c, uint64_t *A, int64_t crow0, int64_t M, int64_t kw0, i
         if ((size_t)words_for(N) * 64 * (size_t)ldbt * 8 > c.bt_bytes) return hipErrorInvalidValue;
         hipError_t e = launch_transpose_bits(A + brow0 * ldw + xw0, ldw, K, N, c.bt, ldbt, c.s);
         if (e != hipSuccess) return e;
-        return launch_mfma_gf2(A + crow0 * ldw + xw0, ldw, A + crow0 * ldw + kw0, ldw, c.bt, ldbt, M, K, N, c.s);
+        return launch_mfma_gf2(A + crow0 * ldw + xw0, ldw, A + crow0 * ldw + kw0, ldw, c.bt, ldbt, M, K, N, c.s,
+                               c.fmt);
     }
     for (int64_t kb = 0; kb * 64 < K; kb++) {
         const int nb = (int)(K - kb * 64 < 64 ? K - kb * 64 : 64);
@@ -246,13 +248,15 @@ size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma
 }
 
 hipError_t ple_alg3(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
-                    const gf2_ple_opts *opts, hipStream_t s, int levels, bool mfma) {
+                    const gf2_ple_opts *opts, hipStream_t s, int levels, int products) {
+    const bool mfma = products != 0;
     Ctx c;
     c.ldw = ldw;
     c.ws = ws;
     c.opts = opts;
     c.s = s;
     c.mfma = mfma;
+    c.fmt = products == 2 ? 1 : 0;
     char *extra = (char *)ws + al(ple_workspace_total(m, ldw));
     c.rank_slots = (int64_t *)extra;
     c.bt = (uint64_t *)(extra + al((size_t)MAX_DEPTH * 8));

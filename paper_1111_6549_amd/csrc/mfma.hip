@@ -11,6 +11,7 @@
 // 8 (i / 4) + 4 (l / 32) + i % 4.
 #include "common.h"
 #include "dev.h"
+#include "m4rm.h"
 
 namespace gf2 {
 
@@ -196,6 +197,154 @@ __global__ __launch_bounds__(256) void k_mfma_gf2t(uint64_t *__restrict__ C, int
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same product on the fp4 matrix cores (v_mfma_scale_f32_32x32x64_f8f6f4
+// with e2m1 operands, unit scales): a bit becomes the fp4 value 0.0 or 1.0
+// (nibble 0b0000 / 0b0010), the fp32 sums are exact integers (at most k),
+// and their low bit is the GF(2) sum.
+//
+// A block computes 256 rows x 256 columns of C (4 output words) with four
+// waves in 2 x 2, each 128 x 128 as 4 x 4 tiles of 32 x 32 (256 fp32
+// accumulators per lane).  K advances one 64-bit word a step: each thread
+// expands one word of A (its row) and one word of Bt (its column) into fp4
+// in LDS -- once per block instead of once per wave -- and the waves read
+// their operands from there.  LDS is double-buffered, so the next step's
+// expansion overlaps this step's matrix-core work; the words themselves are
+// loaded two steps ahead.
+// ---------------------------------------------------------------------------
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// 8 bits -> 8 fp4 values in one dword: nibble j = 0b0010 (1.0) if bit j is set
+__device__ __forceinline__ uint32_t byte_to_fp4x8(uint32_t x) {
+    x &= 0xFFu;
+    x = (x | (x << 12)) & 0x000F000Fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    x = (x | (x << 3)) & 0x11111111u;
+    return x << 1;
+}
+
+__device__ __forceinline__ uint4 word_half_to_fp4(uint64_t w, int half) {
+    const uint32_t v = (uint32_t)(w >> (32 * half));
+    uint4 r;
+    r.x = byte_to_fp4x8(v);
+    r.y = byte_to_fp4x8(v >> 8);
+    r.z = byte_to_fp4x8(v >> 16);
+    r.w = byte_to_fp4x8(v >> 24);
+    return r;
+}
+
+constexpr int F4_BM = 256, F4_BN = 256, F4_CH = 1;  // block rows, block columns, words per load chunk
+
+__global__ __launch_bounds__(256) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, int64_t ldc,
+                                                      const uint64_t *__restrict__ A, int64_t lda,
+                                                      const uint64_t *__restrict__ Bt, int64_t ldbt, int64_t m,
+                                                      int64_t kw, int64_t nw, int64_t gcols, int64_t grows) {
+    // [buffer][K half][row or column]: 32 fp4 values (one K half of a word)
+    __shared__ uint4 sA[2][2][F4_BM];
+    __shared__ uint4 sB[2][2][F4_BN];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // blocks of one XCD take a contiguous range: neighbouring column blocks
+    // of the same rows share that XCD's L2
+    const int64_t logical = xcd_logical((int)blockIdx.x, (int)gridDim.x);
+    const int64_t bc = logical % gcols, br = logical / gcols;
+    if (br >= grows) return;  // (the grid is exactly gcols x grows)
+    const int64_t r0 = br * F4_BM, w0 = bc * (F4_BN / 64);
+    const int64_t ra = r0 + tid;
+    const bool va = ra < m;
+    const uint64_t *pa = A + (va ? ra : 0) * lda;
+    const int64_t cb = w0 * 64 + tid;  // Bt has nw * 64 rows (zero past n)
+    const bool vb = cb < nw * 64;
+    const uint64_t *pb = Bt + (vb ? cb : 0) * ldbt;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 31, kh = lane >> 5;
+
+    uint64_t ca[F4_CH], cbw[F4_CH], na[F4_CH], nbw[F4_CH];
+    auto load = [&](uint64_t(&xa)[F4_CH], uint64_t(&xb)[F4_CH], int64_t chunk) {
+#pragma unroll
+        for (int s = 0; s < F4_CH; s++) {
+            const int64_t kk = chunk * F4_CH + s;
+            xa[s] = (va && kk < kw) ? pa[kk] : 0ull;
+            xb[s] = (vb && kk < kw) ? pb[kk] : 0ull;
+        }
+    };
+    auto store = [&](int buf, uint64_t x, uint64_t y) {
+        sA[buf][0][tid] = word_half_to_fp4(x, 0);
+        sA[buf][1][tid] = word_half_to_fp4(x, 1);
+        sB[buf][0][tid] = word_half_to_fp4(y, 0);
+        sB[buf][1][tid] = word_half_to_fp4(y, 1);
+    };
+    auto frag = [](const uint4 &t) { return v8i{(int)t.x, (int)t.y, (int)t.z, (int)t.w, 0, 0, 0, 0}; };
+    const int64_t nchunk = (kw + F4_CH - 1) / F4_CH;
+    load(ca, cbw, 0);
+    if (nchunk > 1) load(na, nbw, 1);
+    v16f acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = v16f{};
+    store(0, ca[0], cbw[0]);
+    __syncthreads();
+    for (int64_t c = 0; c < nchunk; c++) {
+#pragma unroll
+        for (int s = 0; s < F4_CH; s++) {
+            const int64_t kk = c * F4_CH + s;
+            if (kk >= kw) break;
+            const int buf = (int)(kk & 1);
+            v8i b[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) b[j] = frag(sB[buf][kh][wc * 128 + 32 * j + lr]);
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const v8i a = frag(sA[buf][kh][wr * 128 + 32 * i + lr]);
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[j], acc[i][j], 4, 4, 0, 127, 0,
+                                                                               127);
+            }
+            if (kk + 1 < kw) {
+                const uint64_t x = s + 1 < F4_CH ? ca[(s + 1) % F4_CH] : na[0];
+                const uint64_t y = s + 1 < F4_CH ? cbw[(s + 1) % F4_CH] : nbw[0];
+                store(buf ^ 1, x, y);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int s = 0; s < F4_CH; s++) {
+            ca[s] = na[s];
+            cbw[s] = nbw[s];
+        }
+        if (c + 2 < nchunk) load(na, nbw, c + 2);
+    }
+    // sums mod 2 -> bits; lane L collects rows L and 64 + L of the wave's
+    // 128, words d = 0, 1 of its 128 columns
+    uint64_t out[2][2] = {{0, 0}, {0, 0}};
+    const uint64_t lo32 = 0xFFFFFFFFull;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+            const int q = 32 * i + (e >> 2) * 8 + (e & 3);  // rows q (lanes < 32) and q + 4 (lanes >= 32)
+#pragma unroll
+            for (int d = 0; d < 2; d++) {
+                const uint64_t b0 = __ballot(((int)acc[i][2 * d][e]) & 1);
+                const uint64_t b1 = __ballot(((int)acc[i][2 * d + 1][e]) & 1);
+                out[q >> 6][d] = lane == (q & 63) ? ((b0 & lo32) | (b1 << 32)) : out[q >> 6][d];
+                out[(q + 4) >> 6][d] = lane == ((q + 4) & 63) ? ((b0 >> 32) | (b1 & ~lo32)) : out[(q + 4) >> 6][d];
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; p++) {
+        const int64_t row = r0 + wr * 128 + 64 * p + lane;
+#pragma unroll
+        for (int d = 0; d < 2; d++) {
+            const int64_t w = w0 + wc * 2 + d;
+            if (row < m && w < nw && out[p][d]) C[row * ldc + w] ^= out[p][d];
+        }
+    }
+}
+
 hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int64_t n, uint64_t *Bt, int64_t ldbt,
                                  hipStream_t s) {
     const int64_t blocks = (words_for(k) * words_for(n) + 3) / 4;
@@ -205,8 +354,18 @@ hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int6
     return hipGetLastError();
 }
 
+// fmt 0: fp4 matrix cores; 1: int8 matrix cores
 hipError_t launch_mfma_gf2(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *Bt, int64_t ldbt,
-                           int64_t m, int64_t k, int64_t n, hipStream_t s) {
+                           int64_t m, int64_t k, int64_t n, hipStream_t s, int fmt) {
+    if (fmt == 0) {
+        const int64_t nw = words_for(n), kw = words_for(k);
+        const int64_t gcols = (nw + F4_BN / 64 - 1) / (F4_BN / 64), grows = (m + F4_BM - 1) / F4_BM;
+        if (gcols <= 0 || grows <= 0 || kw <= 0) return hipSuccess;
+        ProfScope ps(KID_MFMA, s);
+        hipLaunchKernelGGL(k_mfma_gf2_fp4, dim3((unsigned)(gcols * grows)), dim3(256), 0, s, C, ldc, A, lda, Bt, ldbt,
+                           m, kw, nw, gcols, grows);
+        return hipGetLastError();
+    }
     if (k >= 128) {
         // 128 x 128 per wave, four waves side by side
         constexpr int TR = 4, TC = 4;

@@ -82,11 +82,11 @@ def test_full_size_rref_digest(form):
     assert got == want["sha256"], "RREF digest differs from the oracle's"
 
 
-@pytest.mark.parametrize("update,levels", [(2, 1), (3, 1), (2, 2)])
+@pytest.mark.parametrize("update,levels", [(2, 1), (3, 1), (2, 2), (4, 1)])
 def test_full_size_digest_alg3(update, levels):
-    """Algorithm 3 levels over the 65536^2 seed-5 matrix (products on the
-    matrix cores, update 2, or the tables, update 3) hash to the oracle's PLE
-    digest like Algorithm 2."""
+    """Algorithm 3 levels over the 65536^2 seed-5 matrix (products on the fp4
+    matrix cores, update 2, the tables, update 3, or the int8 matrix cores,
+    update 4) hash to the oracle's PLE digest like Algorithm 2."""
     want = json.load(open(GOLDEN))["65536x65536_seed5"]
     m, n, seed = want["m"], want["n"], want["seed"]
     say("full size alg3 update", update, "levels", levels)

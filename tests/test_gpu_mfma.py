@@ -1,6 +1,7 @@
-"""GPU parity of the int8 matrix-core GF(2) product (gf2_addmul with
-update = 2) against the oracle's product by definition, on ragged shapes that
-span several 64 x 64 wave tiles, partial words in every dimension, and k
+"""GPU parity of the matrix-core GF(2) products (gf2_addmul with update = 2,
+fp4 operands, and update = 4, int8 operands) against the oracle's product by
+definition, on ragged shapes that span several block tiles (256 x 256 for
+fp4, 128 x 128 wave tiles for int8), partial words in every dimension, and k
 from 1 to a few thousand; and agreement with the XOR-table product."""
 import numpy as np
 import pytest
@@ -13,7 +14,8 @@ from tests.gpu_util import say, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(1, 1, 1), (1, 64, 1), (64, 1, 64), (33, 17, 65), (100, 64, 70), (128, 128, 128), (300, 150, 900),
-          (700, 1000, 130), (129, 33, 4097), (2048, 512, 2048), (1000, 2049, 300), (4100, 96, 640)]
+          (700, 1000, 130), (129, 33, 4097), (2048, 512, 2048), (1000, 2049, 300), (4100, 96, 640),
+          (257, 4096, 513), (3000, 1100, 2500)]
 
 
 @pytest.mark.parametrize("m,k,n", SHAPES)
@@ -24,7 +26,7 @@ def test_mfma_addmul_matches_oracle(m, k, n):
     B = inputs.bernoulli(k, n, 13 + n)
     want = C.copy()
     oracle.addmul(want, A, B, k, n)
-    for update in (2, 1):
+    for update in (2, 4, 1):
         tC = to_dev(C)
         G.addmul(tC, to_dev(A), to_dev(B), k, n, update=update)
         got = to_host(tC)
@@ -41,6 +43,7 @@ def test_mfma_addmul_sparse_and_strided():
     B = inputs.bernoulli(k, n, 23, p=0.05, ldw=inputs.words(n) + 2)
     want = C.copy()
     oracle.addmul(want, A, B, k, n)
-    tC = to_dev(C)
-    G.addmul(tC, to_dev(A), to_dev(B), k, n, update=2)
-    assert np.array_equal(to_host(tC), want)
+    for update in (2, 4):
+        tC = to_dev(C)
+        G.addmul(tC, to_dev(A), to_dev(B), k, n, update=update)
+        assert np.array_equal(to_host(tC), want), "update=%d" % update

@@ -353,20 +353,21 @@ ALG3_CASES = [(1000, 1000, "u"), (300, 2000, "u"), (2000, 300, "u"), (1500, 1300
 @pytest.mark.parametrize("m,n,kind", ALG3_CASES)
 def test_alg3_parity(m, n, kind, update):
     """One level of Algorithm 3 (column split in halves, TRSM, product on the
-    matrix cores (2) or the tables (3), PLE of the lower right block, P, Q and
-    L combined) gives the oracle's (rank, P, Q, L\\E) bit for bit."""
+    fp4 matrix cores (2) or the tables (3), PLE of the lower right block, P, Q
+    and L combined) gives the oracle's (rank, P, Q, L\\E) bit for bit."""
     say("alg3", update, m, n, kind)
     A = _alg3_case(kind, m, n)
     assert_same_ple(gpu_ple(A, n, update=update), oracle_ple(A, n), "alg3 u%d %dx%d %s" % (update, m, n, kind))
 
 
-@pytest.mark.parametrize("update", [2, 3])
+@pytest.mark.parametrize("update", [2, 3, 4])
 @pytest.mark.parametrize("m,n,kind,levels", [(3000, 2500, "u", 2), (2500, 3000, "deficient_left", 3),
                                              (4096, 4096, "u", 3), (2000, 2000, "s", 4), (8192, 8192, "u", 1)])
 def test_alg3_levels_parity(m, n, kind, levels, update):
     """Several levels of Algorithm 3 (each half recursed again) against the
-    oracle; 8192^2 takes the matrix-core path for its products of 512 inner
-    bits and more."""
+    oracle, with fp4 (2) and int8 (4) matrix-core products and table products
+    (3); 8192^2 takes the matrix-core path for its products of 512 inner bits
+    and more."""
     say("alg3 levels", update, m, n, kind, levels)
     A = _alg3_case(kind, m, n)
     assert_same_ple(gpu_ple(A, n, update=update, rec_levels=levels), oracle_ple(A, n),
