@@ -521,7 +521,7 @@ def run_serving(args, log_fn):
     del scratch, wsp
 
     def serve(arrivals):
-        S = G.ServeSession(budget_bytes=64 << 30, small_max_dim=args.serve_small_max)
+        S = G.ServeSession(budget_bytes=64 << 30, small_max_dim=args.serve_small_max, streams=args.serve_streams)
         tickets = []
         start = time.perf_counter()
         for r, t, at in zip(reqs, dev, arrivals):
@@ -626,19 +626,20 @@ def run_serving(args, log_fn):
 
 def run_alg3(args, m, n, pristine, work, log_fn):
     """Algorithm 3 (block-recursive PLE) against Algorithm 2 on the bench
-    matrix: gf2_ple with update = 2 (products on the int8 matrix cores) and
-    update = 3 (products on the Four-Russians tables), one and two levels of
-    column splits; each the best of two calls after one untimed call.  Then
-    the product on its own, C ^= A B for 65536 x k x 65536 at k = 256, 512,
-    1024, on the tables and on the matrix cores: time, the tables' HBM rate
-    (16 bytes per row word of C per 64 inner bits) and the matrix cores'
-    int8 rate (2 m k n operations) against the 5.0 POPS dense int8 peak."""
+    matrix: gf2_ple with update = 2 (products on the fp4 matrix cores), 3 (on
+    the Four-Russians tables) and 4 (on the int8 matrix cores), one and two
+    levels of column splits; each the best of two calls after one untimed
+    call.  Then the product on its own, C ^= A B for 65536 x k x 65536 at
+    k = 256, 512, 1024, on the tables and both matrix-core forms: time, the
+    tables' HBM rate (16 bytes per row word of C per 64 inner bits) and the
+    matrix cores' rate (2 m k n operations) against the dense peaks (fp4
+    10.1 PFLOP/s, int8 5.0 POPS)."""
     import torch
     from paper_1111_6549_amd import gf2ple as G
     from paper_1111_6549_amd import inputs
     ldw = inputs.words(n)
     out = {"ple": []}
-    for update, levels in ((3, 1), (2, 1), (2, 2)):
+    for update, levels in ((3, 1), (2, 1), (2, 2), (4, 1)):
         ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw, update=update, rec_levels=levels))
         times = []
         for rep in range(3):
@@ -649,7 +650,8 @@ def run_alg3(args, m, n, pristine, work, log_fn):
             torch.cuda.synchronize()
             if rep:
                 times.append((time.perf_counter() - t0) * 1000.0)
-        pt = {"update": update, "products": "int8 matrix cores" if update == 2 else "Four-Russians tables",
+        pt = {"update": update, "products": {2: "fp4 matrix cores", 3: "Four-Russians tables",
+                                             4: "int8 matrix cores"}[update],
               "levels": levels, "ms": round(min(times), 3), "rank": int(rank.item())}
         out["ple"].append(pt)
         log_fn("alg3: %s" % json.dumps(pt))
@@ -662,7 +664,7 @@ def run_alg3(args, m, n, pristine, work, log_fn):
         Ak = torch.from_numpy(inputs.bernoulli(mm, k, 60 + k).view("int64")).cuda()
         Bk = torch.from_numpy(inputs.bernoulli(k, nn, 61 + k).view("int64")).cuda()
         row = {"k": k}
-        for update in (1, 2):
+        for update in (1, 2, 4):
             times = []
             for rep in range(4):
                 torch.cuda.synchronize()
@@ -675,11 +677,16 @@ def run_alg3(args, m, n, pristine, work, log_fn):
             if update == 1:
                 row["tables_ms"] = round(t, 3)
                 row["tables_alg_GBps"] = round(16.0 * mm * (nn // 64) * (k // 64) / (t * 1e-3) / 1e9, 1)
+            elif update == 2:
+                pf = 2.0 * mm * k * nn / (t * 1e-3) / 1e15
+                row["fp4_ms"] = round(t, 3)
+                row["fp4_PFLOPs"] = round(pf, 3)
+                row["fp4_frac_peak"] = round(pf / 10.1, 4)
             else:
                 pops = 2.0 * mm * k * nn / (t * 1e-3) / 1e15
-                row["mfma_ms"] = round(t, 3)
-                row["mfma_int8_POPS"] = round(pops, 3)
-                row["mfma_frac_int8_peak"] = round(pops / 5.0, 4)
+                row["int8_ms"] = round(t, 3)
+                row["int8_POPS"] = round(pops, 3)
+                row["int8_frac_peak"] = round(pops / 5.0, 4)
         prod.append(row)
         log_fn("product: %s" % json.dumps(row))
         del Ak, Bk
@@ -765,6 +772,7 @@ def main():
     ap.add_argument("--no-density", action="store_true", help="skip the 10000^2 density sweep")
     ap.add_argument("--serve-count", type=int, default=3000)
     ap.add_argument("--serve-cpu-sample", type=int, default=40)
+    ap.add_argument("--serve-streams", type=int, default=0, help="serving launch streams (0 = library default)")
     ap.add_argument("--serve-small-max", type=int, default=0,
                     help="largest side served by batched launches (0 = library default)")
     args = ap.parse_args()

@@ -30,7 +30,7 @@ hipError_t launch_update(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t
 hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int64_t n, uint64_t *Bt, int64_t ldbt,
                                  hipStream_t s);
 hipError_t launch_mfma_gf2(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *Bt, int64_t ldbt,
-                           int64_t m, int64_t k, int64_t n, hipStream_t s);
+                           int64_t m, int64_t k, int64_t n, hipStream_t s, int fmt);
 hipError_t launch_m4rm(uint64_t *C, int64_t ldc, int64_t m, const uint64_t *coef, int64_t coef_ld, const uint64_t *B,
                        int64_t ldb, int nbits, int64_t w_begin, int64_t w_end, int m4_variant, int m4_target,
                        hipStream_t s);
@@ -141,27 +141,13 @@ int *device_flag_locked() {
 
 namespace gf2 {
 
-// The second stream of the look-ahead and of the M4RI form's eliminations:
-// one per device, made on first use and kept for the life of the process
-// (so a process holds at most one such stream per device, whatever its
-// number of host threads or calls).
-static std::mutex g_s2_mu;
-static std::vector<hipStream_t> g_s2;
-
-static hipStream_t second_stream() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    std::lock_guard<std::mutex> lk(g_s2_mu);
-    if ((int)g_s2.size() <= dev) g_s2.resize(dev + 1, nullptr);
-    if (!g_s2[dev] && hipStreamCreateWithFlags(&g_s2[dev], hipStreamNonBlocking) != hipSuccess) g_s2[dev] = nullptr;
-    return g_s2[dev];
-}
-
-// The events that order the caller's stream and the second stream within
-// one call: made by the call and released when it returns (an event still
-// pending then is released once it completes).  Calls from different host
-// threads or on different streams share the second stream but never an
-// event, so each wait names only work its own call enqueued before it.
+// The second stream of the look-ahead and of the M4RI form's eliminations,
+// and the events that order it against the caller's stream: made by the
+// call that needs them and released when it returns (a stream or event
+// still in use then is released once its work completes).  No stream of
+// the library outlives a call, so a process's later streams (a serving
+// session's, say) get the hardware queues as if the call had not run, and
+// calls from different host threads share nothing.
 struct LookCtx {
     hipStream_t s2 = nullptr;
     hipEvent_t evA = nullptr, evN = nullptr;
@@ -174,10 +160,13 @@ struct LookCtx {
         if (evN) (void)hipEventDestroy(evN);
         for (int j = 0; j < NREC; j++)
             if (evJ[j]) (void)hipEventDestroy(evJ[j]);
+        if (s2) (void)hipStreamDestroy(s2);
     }
     bool init() {
-        s2 = second_stream();
-        if (!s2) return false;
+        if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
+            s2 = nullptr;
+            return false;
+        }
         // the events only order the two streams on this device: a
         // device-scope release and no timestamps (a default event also
         // writes back the caches for the host, which delays the next kernel
@@ -439,7 +428,7 @@ gf2_status ple_check_args(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, 
     if (m > 0 && (!P || !aligned(P, 8))) return GF2_EINVAL;
     if (mn > 0 && (!Q || !aligned(Q, 8))) return GF2_EINVAL;
     if (m > 0 && ldw > 0 && (!A || !aligned(A, 8))) return GF2_EINVAL;
-    if (opts && (opts->update < 0 || opts->update > 3 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
+    if (opts && (opts->update < 0 || opts->update > 4 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
     if (opts && (opts->rec_levels < 0 || opts->rec_levels > 16)) return GF2_EINVAL;
     if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
         return GF2_EINVAL;
@@ -453,9 +442,11 @@ hipError_t ple_block(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P,
     return pass_loop(A, m, n, ldw, P, Q, rank, ws, opts, s, true, true, nullptr, wlo);
 }
 
-// update = 2 / 3: Algorithm 3 levels (matrix-core / table products)
+// update = 2 / 3 / 4: Algorithm 3 levels (fp4 matrix-core / table / int8
+// matrix-core products)
 static bool recursive(const gf2_ple_opts *opts) { return opts && opts->update >= 2; }
 static int rec_levels(const gf2_ple_opts *opts) { return opts && opts->rec_levels > 0 ? opts->rec_levels : 1; }
+static int rec_products(const gf2_ple_opts *opts) { return opts->update == 2 ? 1 : (opts->update == 4 ? 2 : 0); }
 
 hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
                        void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, bool allow_s2) {
@@ -485,7 +476,8 @@ const char *gf2_status_str(gf2_status s) {
 size_t gf2_ple_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf2_ple_opts *opts) {
     if (!sizes_ok(m, n, ldw)) return 0;
     if (recursive(opts))
-        return align_up(ple_layout(m, ldw).total) + alg3_extra_bytes(m, n, ldw, rec_levels(opts), opts->update == 2);
+        return align_up(ple_layout(m, ldw).total) +
+               alg3_extra_bytes(m, n, ldw, rec_levels(opts), rec_products(opts) != 0);
     return ple_layout(m, ldw).total;
 }
 
@@ -517,7 +509,7 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
         if (st != GF2_OK) return st;
     }
     if (recursive(opts))
-        return hip_status(ple_alg3(A, m, n, ldw, P, Q, rank, ws, opts, s, rec_levels(opts), opts->update == 2));
+        return hip_status(ple_alg3(A, m, n, ldw, P, Q, rank, ws, opts, s, rec_levels(opts), rec_products(opts)));
     return hip_status(ple_enqueue(A, m, n, ldw, P, Q, rank, ws, opts, s, true, true));
 }
 
@@ -682,9 +674,12 @@ gf2_status gf2_rref(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, 
     return gf2_rref_from_ple(A, m, n, ldw, Q, rank, ws, ws_bytes, stream);
 }
 
+// update 2: fp4 matrix cores; 4: int8 matrix cores; 0, 1, 3: tables
+static bool addmul_mfma(const gf2_ple_opts *opts) { return opts && (opts->update == 2 || opts->update == 4); }
+
 size_t gf2_addmul_workspace_bytes(int64_t m, int64_t k, int64_t n, const gf2_ple_opts *opts) {
     if (m < 0 || k < 0 || n < 0) return 0;
-    if (!opts || opts->update != 2) return 0;
+    if (!addmul_mfma(opts)) return 0;
     return (size_t)words_for(n) * 64 * (size_t)words_for(k) * 8;
 }
 
@@ -693,18 +688,19 @@ gf2_status gf2_addmul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, 
                       void *stream) {
     if (m < 0 || k < 0 || n < 0) return GF2_EINVAL;
     if (ldc < words_for(n) || lda < words_for(k) || ldb < words_for(n)) return GF2_EINVAL;
-    if (opts && (opts->update < 0 || opts->update > 2 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
+    if (opts && (opts->update < 0 || opts->update > 4 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
     if (m == 0 || n == 0 || k == 0) return GF2_OK;
     if (!C || !A || !B || !aligned(C, 8) || !aligned(A, 8) || !aligned(B, 8)) return GF2_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const int64_t nw = words_for(n);
-    if (opts && opts->update == 2) {
-        // int8 matrix cores: B bit-transposed into the caller's workspace first
+    if (addmul_mfma(opts)) {
+        // matrix cores: B bit-transposed into the caller's workspace first
         const int64_t kw = words_for(k);
         if (!ws || !aligned(ws, 8)) return GF2_EINVAL;
         if (ws_bytes < gf2_addmul_workspace_bytes(m, k, n, opts)) return GF2_EWORKSPACE;
         hipError_t e = launch_transpose_bits(B, ldb, k, n, (uint64_t *)ws, kw, s);
-        if (e == hipSuccess) e = launch_mfma_gf2(C, ldc, A, lda, (const uint64_t *)ws, kw, m, k, n, s);
+        if (e == hipSuccess)
+            e = launch_mfma_gf2(C, ldc, A, lda, (const uint64_t *)ws, kw, m, k, n, s, opts->update == 4 ? 1 : 0);
         return hip_status(e);
     }
     for (int64_t kb = 0; kb * KW < k; kb++) {
