@@ -39,7 +39,7 @@ KW = 64
 # launches of one PLE and scaled by the same counters on the 512 MiB restore copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Reported only while the kernel
 # sources hash to the value the counters were taken on.
-TRAFFIC = {"source": "04ab9aea8fe485c0", "n": 65536, "seed": 5, "bytes_per_launch": 366610682}
+TRAFFIC = {"source": "91d4ef490062b617", "n": 65536, "seed": 5, "bytes_per_launch": 366621923}
 
 
 def log(*a):
@@ -624,6 +624,51 @@ def run_serving(args, log_fn):
     return out
 
 
+def run_products(log_fn, shapes=((65536, 256, 65536), (65536, 512, 65536), (65536, 1024, 65536))):
+    """C ^= A B over GF(2) on the tables (update 1) and on the fp4 (2) and
+    int8 (4) matrix cores, for m x k x n at each shape: the best of three
+    calls after one untimed call; the tables' algorithmic HBM rate (16 bytes
+    per row word of C per 64 inner bits) and the matrix cores' rate
+    (2 m k n operations) against their dense peaks."""
+    import torch
+    from paper_1111_6549_amd import gf2ple as G
+    from paper_1111_6549_amd import inputs
+    prod = []
+    for mm, k, nn in shapes:
+        C = torch.zeros((mm, (nn + 63) // 64), dtype=torch.int64, device="cuda")
+        Ak = torch.from_numpy(inputs.bernoulli(mm, k, 60 + k).view("int64")).cuda()
+        Bk = torch.from_numpy(inputs.bernoulli(k, nn, 61 + k).view("int64")).cuda()
+        row = {"m": mm, "k": k, "n": nn}
+        for update in (1, 2, 4):
+            times = []
+            for rep in range(4):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                G.addmul(C, Ak, Bk, k, nn, update=update)
+                torch.cuda.synchronize()
+                if rep:
+                    times.append((time.perf_counter() - t0) * 1000.0)
+            t = min(times)
+            if update == 1:
+                row["tables_ms"] = round(t, 3)
+                row["tables_alg_GBps"] = round(16.0 * mm * ((nn + 63) // 64) * (k / 64.0) / (t * 1e-3) / 1e9, 1)
+            elif update == 2:
+                pf = 2.0 * mm * k * nn / (t * 1e-3) / 1e15
+                row["fp4_ms"] = round(t, 3)
+                row["fp4_PFLOPs"] = round(pf, 3)
+                row["fp4_frac_peak"] = round(pf / 10.1, 4)
+            else:
+                pops = 2.0 * mm * k * nn / (t * 1e-3) / 1e15
+                row["int8_ms"] = round(t, 3)
+                row["int8_POPS"] = round(pops, 3)
+                row["int8_frac_peak"] = round(pops / 5.0, 4)
+        prod.append(row)
+        log_fn("product: %s" % json.dumps(row))
+        del Ak, Bk, C
+        torch.cuda.empty_cache()
+    return prod
+
+
 def run_alg3(args, m, n, pristine, work, log_fn):
     """Algorithm 3 (block-recursive PLE) against Algorithm 2 on the bench
     matrix: gf2_ple with update = 2 (products on the fp4 matrix cores), 3 (on
@@ -657,42 +702,8 @@ def run_alg3(args, m, n, pristine, work, log_fn):
         log_fn("alg3: %s" % json.dumps(pt))
         del ws
     torch.cuda.empty_cache()
-    prod = []
-    mm = nn = 65536
-    C = torch.zeros((mm, nn // 64), dtype=torch.int64, device="cuda")
-    for k in (256, 512, 1024):
-        Ak = torch.from_numpy(inputs.bernoulli(mm, k, 60 + k).view("int64")).cuda()
-        Bk = torch.from_numpy(inputs.bernoulli(k, nn, 61 + k).view("int64")).cuda()
-        row = {"k": k}
-        for update in (1, 2, 4):
-            times = []
-            for rep in range(4):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                G.addmul(C, Ak, Bk, k, nn, update=update)
-                torch.cuda.synchronize()
-                if rep:
-                    times.append((time.perf_counter() - t0) * 1000.0)
-            t = min(times)
-            if update == 1:
-                row["tables_ms"] = round(t, 3)
-                row["tables_alg_GBps"] = round(16.0 * mm * (nn // 64) * (k // 64) / (t * 1e-3) / 1e9, 1)
-            elif update == 2:
-                pf = 2.0 * mm * k * nn / (t * 1e-3) / 1e15
-                row["fp4_ms"] = round(t, 3)
-                row["fp4_PFLOPs"] = round(pf, 3)
-                row["fp4_frac_peak"] = round(pf / 10.1, 4)
-            else:
-                pops = 2.0 * mm * k * nn / (t * 1e-3) / 1e15
-                row["int8_ms"] = round(t, 3)
-                row["int8_POPS"] = round(pops, 3)
-                row["int8_frac_peak"] = round(pops / 5.0, 4)
-        prod.append(row)
-        log_fn("product: %s" % json.dumps(row))
-        del Ak, Bk
-    del C
-    torch.cuda.empty_cache()
-    out["product_65536_k_65536"] = prod
+    prod = run_products(log_fn)
+    out["products"] = prod
     return out
 
 
@@ -764,6 +775,8 @@ def main():
                     help="0 = library default, 1 = serial passes, 2 = look-ahead only, 3 = pairs everywhere")
     ap.add_argument("--pair-variant", type=int, default=0, help="fused pair update schedule 1..12 (0 = default)")
     ap.add_argument("--no-alg3", action="store_true", help="skip Algorithm 3 and the product comparison")
+    ap.add_argument("--only-products", action="store_true",
+                    help="run only the product comparison (tables, fp4 and int8 matrix cores) and exit")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -791,6 +804,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     G.load()
+    if args.only_products:
+        # the product on its own: the shapes of the comparison and the top
+        # product of one Algorithm 3 level on 65536^2 (32768 x 32768 x 32768)
+        prod = run_products(log, ((65536, 1024, 65536), (32768, 32768, 32768)))
+        print(json.dumps({"metric": "GF(2) product C ^= A B: tables vs fp4 / int8 matrix cores", "products": prod}))
+        return
     m = n = args.n
     ldw = inputs.words(n)
     log("generating %dx%d Bernoulli(0.5) seed %d" % (m, n, args.seed))
