@@ -207,34 +207,29 @@ __global__ __launch_bounds__(256) void k_mfma_gf2t(uint64_t *__restrict__ C, int
 // waves in 2 x 2, each 128 x 128 as 4 x 4 tiles of 32 x 32 (256 fp32
 // accumulators per lane).  K advances one 64-bit word a step: each thread
 // expands one word of A (its row) and one word of Bt (its column) into fp4
-// in LDS -- once per block instead of once per wave -- and the waves read
-// their operands from there.  LDS is double-buffered, so the next step's
+// in LDS -- once per block instead of once per wave, four shift-and-mask
+// steps per 32 bits -- and the waves read their operands from there.  LDS is double-buffered, so the next step's
 // expansion overlaps this step's matrix-core work; the words themselves are
-// loaded two steps ahead.
+// loaded four steps ahead.
 // ---------------------------------------------------------------------------
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// 8 bits -> 8 fp4 values in one dword: nibble j = 0b0010 (1.0) if bit j is set
-__device__ __forceinline__ uint32_t byte_to_fp4x8(uint32_t x) {
-    x &= 0xFFu;
-    x = (x | (x << 12)) & 0x000F000Fu;
-    x = (x | (x << 6)) & 0x03030303u;
-    x = (x | (x << 3)) & 0x11111111u;
-    return x << 1;
-}
-
+// 32 bits -> 32 fp4 values 0.0 / 1.0 (nibble 0b0010 = 1.0) in four dwords.
+// The K order inside an operand is free as long as A and B share it, so
+// bit 4s + d of v goes to nibble s of dword d: each dword is one shift and
+// one mask of v.
 __device__ __forceinline__ uint4 word_half_to_fp4(uint64_t w, int half) {
     const uint32_t v = (uint32_t)(w >> (32 * half));
     uint4 r;
-    r.x = byte_to_fp4x8(v);
-    r.y = byte_to_fp4x8(v >> 8);
-    r.z = byte_to_fp4x8(v >> 16);
-    r.w = byte_to_fp4x8(v >> 24);
+    r.x = (v << 1) & 0x22222222u;
+    r.y = v & 0x22222222u;
+    r.z = (v >> 1) & 0x22222222u;
+    r.w = (v >> 2) & 0x22222222u;
     return r;
 }
 
-constexpr int F4_BM = 256, F4_BN = 256, F4_CH = 1;  // block rows, block columns, words per load chunk
+constexpr int F4_BM = 256, F4_BN = 256, F4_AHEAD = 4;  // block rows, block columns, words loaded ahead
 
 __global__ __launch_bounds__(256) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, int64_t ldc,
                                                       const uint64_t *__restrict__ A, int64_t lda,
@@ -259,15 +254,8 @@ __global__ __launch_bounds__(256) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, 
     const int wr = wave >> 1, wc = wave & 1;
     const int lr = lane & 31, kh = lane >> 5;
 
-    uint64_t ca[F4_CH], cbw[F4_CH], na[F4_CH], nbw[F4_CH];
-    auto load = [&](uint64_t(&xa)[F4_CH], uint64_t(&xb)[F4_CH], int64_t chunk) {
-#pragma unroll
-        for (int s = 0; s < F4_CH; s++) {
-            const int64_t kk = chunk * F4_CH + s;
-            xa[s] = (va && kk < kw) ? pa[kk] : 0ull;
-            xb[s] = (vb && kk < kw) ? pb[kk] : 0ull;
-        }
-    };
+    auto ldA = [&](int64_t kk) { return (va && kk < kw) ? pa[kk] : 0ull; };
+    auto ldB = [&](int64_t kk) { return (vb && kk < kw) ? pb[kk] : 0ull; };
     auto store = [&](int buf, uint64_t x, uint64_t y) {
         sA[buf][0][tid] = word_half_to_fp4(x, 0);
         sA[buf][1][tid] = word_half_to_fp4(x, 1);
@@ -275,46 +263,65 @@ __global__ __launch_bounds__(256) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, 
         sB[buf][1][tid] = word_half_to_fp4(y, 1);
     };
     auto frag = [](const uint4 &t) { return v8i{(int)t.x, (int)t.y, (int)t.z, (int)t.w, 0, 0, 0, 0}; };
-    const int64_t nchunk = (kw + F4_CH - 1) / F4_CH;
-    load(ca, cbw, 0);
-    if (nchunk > 1) load(na, nbw, 1);
+    // xa[i], xb[i]: the words of step kk + 1 + i, in flight
+    uint64_t xa[F4_AHEAD], xb[F4_AHEAD];
+#pragma unroll
+    for (int i = 0; i < F4_AHEAD; i++) {
+        xa[i] = ldA(1 + i);
+        xb[i] = ldB(1 + i);
+    }
     v16f acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = v16f{};
-    store(0, ca[0], cbw[0]);
+    // step kk's operands come from buffer kk & 1: written (expanded) during
+    // step kk - 1, read into registers right after the barrier that ends it,
+    // so each step's matrix-core work overlaps the next step's expansion
+    store(0, ldA(0), ldB(0));
     __syncthreads();
-    for (int64_t c = 0; c < nchunk; c++) {
+    v8i fa[4], fb[4];
 #pragma unroll
-        for (int s = 0; s < F4_CH; s++) {
-            const int64_t kk = c * F4_CH + s;
-            if (kk >= kw) break;
-            const int buf = (int)(kk & 1);
-            v8i b[4];
+    for (int i = 0; i < 4; i++) {
+        fa[i] = frag(sA[0][kh][wr * 128 + 32 * i + lr]);
+        fb[i] = frag(sB[0][kh][wc * 128 + 32 * i + lr]);
+    }
+    for (int64_t kk = 0; kk < kw; kk++) {
+        const int nxt = (int)((kk + 1) & 1);
+        // buffer nxt was last read for step kk - 1, before the barrier that
+        // ended it; past the last step this store is unused
+        store(nxt, xa[0], xb[0]);
 #pragma unroll
-            for (int j = 0; j < 4; j++) b[j] = frag(sB[buf][kh][wc * 128 + 32 * j + lr]);
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j], 4, 4, 0, 127, 0,
+                                                                           127);
+#pragma unroll
+        for (int i = 0; i + 1 < F4_AHEAD; i++) {
+            xa[i] = xa[i + 1];
+            xb[i] = xb[i + 1];
+        }
+        xa[F4_AHEAD - 1] = ldA(kk + 1 + F4_AHEAD);
+        xb[F4_AHEAD - 1] = ldB(kk + 1 + F4_AHEAD);
+        // issue order: the expansion's ALU work and LDS stores between the
+        // matrix-core instructions (32 cycles each), and all of it before the
+        // barrier
+#pragma unroll
+        for (int g = 0; g < 16; g++) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two VALU
+            if (g % 4 == 3) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // one LDS store
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
+        if (kk + 1 < kw) {
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                const v8i a = frag(sA[buf][kh][wr * 128 + 32 * i + lr]);
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[j], acc[i][j], 4, 4, 0, 127, 0,
-                                                                               127);
+                fa[i] = frag(sA[nxt][kh][wr * 128 + 32 * i + lr]);
+                fb[i] = frag(sB[nxt][kh][wc * 128 + 32 * i + lr]);
             }
-            if (kk + 1 < kw) {
-                const uint64_t x = s + 1 < F4_CH ? ca[(s + 1) % F4_CH] : na[0];
-                const uint64_t y = s + 1 < F4_CH ? cbw[(s + 1) % F4_CH] : nbw[0];
-                store(buf ^ 1, x, y);
-            }
-            __syncthreads();
         }
-#pragma unroll
-        for (int s = 0; s < F4_CH; s++) {
-            ca[s] = na[s];
-            cbw[s] = nbw[s];
-        }
-        if (c + 2 < nchunk) load(na, nbw, c + 2);
     }
     // sums mod 2 -> bits; lane L collects rows L and 64 + L of the wave's
     // 128, words d = 0, 1 of its 128 columns
