@@ -507,18 +507,25 @@ def run_serving(args, log_fn):
         G.ple(w, r["n"], ws=wsp)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    outs = []
     for (r, t), (a, b) in zip(zip(reqs, dev), ev):
         w = scratch[:t.numel()].view(t.shape)
         w.copy_(t)
         a.record()
-        G.ple(w, r["n"], ws=wsp)
+        outs.append(G.ple(w, r["n"], ws=wsp))
         b.record()
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     service = np.array([a.elapsed_time(b) * 1e-3 for a, b in ev])
     capacity = count / plain_s
     log_fn("serving: plain %.3f s (%.1f req/s)" % (plain_s, capacity))
-    del scratch, wsp
+    # the stream's algorithmic bytes: per request, 16 B per trailing row word
+    # per 64-column pass (a schedule-independent count), from its pivots
+    sbytes = 0
+    for r, (P, Q, rank) in zip(reqs, outs):
+        rk = int(rank.item())
+        sbytes += alg_bytes_k64(r["m"], r["n"], Q.cpu().numpy(), rk)
+    del scratch, wsp, outs
 
     def serve(arrivals):
         S = G.ServeSession(budget_bytes=64 << 30, small_max_dim=args.serve_small_max, streams=args.serve_streams)
@@ -569,10 +576,16 @@ def run_serving(args, log_fn):
         log_fn("serving: poisson %s" % json.dumps(pt))
     lat_sat, span_sat, st_sat = serve(np.zeros(count))
     log_fn("serving: saturated %.3f s for %d requests" % (span_sat, count))
+    frac_sat = round(sbytes / span_sat / 1e9 / HBM_PEAK_GBPS, 4)
     out = {
         "workload": "%d requests, sides log-uniform in [128, 16384], square or s x ceil(s/2), density 0.5 or 0.05, "
                     "seed 8, inputs resident on the device, 64 GiB budget" % count,
         "plain_capacity_per_s": round(capacity, 1),
+        "k64_alg_bytes": int(sbytes),
+        "plain_frac_hbm": round(sbytes / plain_s / 1e9 / HBM_PEAK_GBPS, 4),
+        "saturated_frac_hbm": frac_sat,
+        "bound": "latency of the requests' serial panels (small requests in batched launches, large ones in "
+                 "their own pass loops, three at a time)",
         "poisson": poisson,
         "saturated": {"served_matrices_per_s": round(count / span_sat, 1),
                       "plain_matrices_per_s": round(capacity, 1),

@@ -225,6 +225,34 @@ def test_check_padding():
         G.ple(to_dev(A2), 70, check_padding=True)
 
 
+def test_check_padding_concurrent_streams():
+    """Padding scans from two host threads on two streams at once: each
+    reports its own matrix (the scan's device flag is not shared between
+    concurrent calls)."""
+    import threading
+    say("check_padding from two threads")
+    clean = to_dev(inputs.bernoulli(4000, 70, 8))
+    dirty_h = inputs.bernoulli(4000, 70, 9)
+    dirty_h[3999, 1] |= np.uint64(1) << np.uint64(63)
+    dirty = to_dev(dirty_h)
+    torch.cuda.synchronize()
+    results = {"clean": [], "dirty": []}
+
+    def worker(name, t):
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            for _ in range(50):
+                results[name].append(G.check_padding(t, 70))
+
+    ths = [threading.Thread(target=worker, args=("clean", clean)), threading.Thread(target=worker, args=("dirty", dirty))]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    assert results["clean"] == [0] * 50
+    assert results["dirty"] == [6] * 50
+
+
 @pytest.mark.parametrize("variant", list(range(0, 13)))
 def test_schedule_invariance(variant):
     """Every update schedule (tile width, threads, unroll, grid size) gives
