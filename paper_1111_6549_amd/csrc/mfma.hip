@@ -203,41 +203,73 @@ __global__ __launch_bounds__(256) void k_mfma_gf2t(uint64_t *__restrict__ C, int
 // (nibble 0b0000 / 0b0010), the fp32 sums are exact integers (at most k),
 // and their low bit is the GF(2) sum.
 //
-// A block computes 256 rows x 256 columns of C (4 output words) with four
-// waves in 2 x 2, each 128 x 128 as 4 x 4 tiles of 32 x 32 (256 fp32
-// accumulators per lane).  K advances one 64-bit word a step: each thread
-// expands one word of A (its row) and one word of Bt (its column) into fp4
-// in LDS -- once per block instead of once per wave, four shift-and-mask
-// steps per 32 bits -- and the waves read their operands from there.  LDS is double-buffered, so the next step's
-// expansion overlaps this step's matrix-core work; the words themselves are
-// loaded four steps ahead.
+// A block of eight waves (two per SIMD) computes 256 rows x 256 columns of C
+// (4 output words); the waves sit 4 x 2, each 64 rows x 128 columns as 2 x 4
+// tiles of 32 x 32 (128 fp32 accumulators per lane).  K advances F4_KS
+// 64-bit words per barrier.  The block's 512 operand rows (256 rows of A,
+// 256 rows of Bt) are loaded one row per thread, F4_KS words ahead, and
+// stored into double-buffered LDS as raw 32-bit halves; each wave reads the
+// halves of its own 2 + 4 operand tiles and expands them into fp4 in
+// registers just before its matrix-core instructions.  LDS holds bits rather
+// than fp4 nibbles, which cuts its traffic four-fold; the expansion (seven
+// ALU instructions per operand and word) runs on one wave of a SIMD while
+// the other's matrix-core instructions execute.
 // ---------------------------------------------------------------------------
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// 32 bits -> 32 fp4 values 0.0 / 1.0 (nibble 0b0010 = 1.0) in four dwords.
-// The K order inside an operand is free as long as A and B share it, so
-// bit 4s + d of v goes to nibble s of dword d: each dword is one shift and
-// one mask of v.
-__device__ __forceinline__ uint4 word_half_to_fp4(uint64_t w, int half) {
-    const uint32_t v = (uint32_t)(w >> (32 * half));
-    uint4 r;
-    r.x = (v << 1) & 0x22222222u;
-    r.y = v & 0x22222222u;
-    r.z = (v >> 1) & 0x22222222u;
-    r.w = (v >> 2) & 0x22222222u;
-    return r;
+// 32 bits -> 32 fp4 values 0.0 / 1.0 (nibble 0b0010 = 1.0) in four dwords
+// (the upper four operand dwords are unused by e2m1).  The K order inside an
+// operand is free as long as A and B share it, so bit 4s + d of v goes to
+// nibble s of dword d: each dword is one shift and one mask of v.
+__device__ __forceinline__ v8i half_to_fp4(uint32_t v) {
+    return v8i{(int)((v << 1) & 0x22222222u), (int)(v & 0x22222222u), (int)((v >> 1) & 0x22222222u),
+               (int)((v >> 2) & 0x22222222u), 0, 0, 0, 0};
 }
 
-constexpr int F4_BM = 256, F4_BN = 256, F4_AHEAD = 4;  // block rows, block columns, words loaded ahead
+constexpr int F4_BM = 256, F4_BN = 256;  // block rows, block columns
+constexpr int F4_KS = 8;                 // words of K per barrier
 
-__global__ __launch_bounds__(256) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, int64_t ldc,
+// One step's KS words of an operand row, zero past kw.  ld_full: the step
+// lies inside [0, kw), loads without conditions (16-byte parts when VEC);
+// ld_tail: word by word with bounds checks.
+template <bool VEC>
+__device__ __forceinline__ void f4_ld_full(const uint64_t *__restrict__ p, uint64_t *x) {
+#pragma unroll
+    for (int q = 0; q < F4_KS; q += (VEC ? 2 : 1)) {
+        if constexpr (VEC) {
+            const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(p + q);
+            x[q] = v.x;
+            x[q + 1] = v.y;
+        } else {
+            x[q] = p[q];
+        }
+    }
+}
+__device__ __forceinline__ void f4_ld_tail(const uint64_t *__restrict__ p, int64_t w0, int64_t kw, uint64_t *x) {
+#pragma unroll
+    for (int q = 0; q < F4_KS; q++) x[q] = w0 + q < kw ? p[q] : 0ull;
+}
+
+// VEC: rows are read in 16-byte parts (A and Bt 16-byte aligned, lda and
+// ldbt even); otherwise word by word.
+//
+// Step kk, for each wave: store step kk + 1's words (loaded during step
+// kk - 1) into LDS buffer (kk + 1) & 1; read the rest of step kk's operand
+// halves from buffer kk & 1; issue the loads of step kk + 2; barrier; read
+// the first operand halves of step kk + 1; then step kk's matrix-core
+// instructions, which use registers only.  A buffer is rewritten only after
+// the barrier that follows its last read, and the matrix-core work sits
+// between barriers, where one wave's instructions overlap the other's loads,
+// stores and expansion.
+template <bool VEC>
+__global__ __launch_bounds__(512) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, int64_t ldc,
                                                       const uint64_t *__restrict__ A, int64_t lda,
                                                       const uint64_t *__restrict__ Bt, int64_t ldbt, int64_t m,
                                                       int64_t kw, int64_t nw, int64_t gcols, int64_t grows) {
-    // [buffer][K half][row or column]: 32 fp4 values (one K half of a word)
-    __shared__ uint4 sA[2][2][F4_BM];
-    __shared__ uint4 sB[2][2][F4_BN];
+    constexpr int KS = F4_KS, WC = 2, TI = 2, TJ = 4, CH = KS / 4;  // CH chunks of 4 words per step
+    // [buffer][operand row: A rows, then Bt rows][low halves of the KS words, then high halves]
+    __shared__ __align__(16) uint32_t sP[2][F4_BM + F4_BN][2 * KS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // blocks of one XCD take a contiguous range: neighbouring column blocks
     // of the same rows share that XCD's L2
@@ -245,90 +277,102 @@ __global__ __launch_bounds__(256) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, 
     const int64_t bc = logical % gcols, br = logical / gcols;
     if (br >= grows) return;  // (the grid is exactly gcols x grows)
     const int64_t r0 = br * F4_BM, w0 = bc * (F4_BN / 64);
-    const int64_t ra = r0 + tid;
-    const bool va = ra < m;
-    const uint64_t *pa = A + (va ? ra : 0) * lda;
-    const int64_t cb = w0 * 64 + tid;  // Bt has nw * 64 rows (zero past n)
-    const bool vb = cb < nw * 64;
-    const uint64_t *pb = Bt + (vb ? cb : 0) * ldbt;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / WC, wc = wave % WC;
     const int lr = lane & 31, kh = lane >> 5;
-
-    auto ldA = [&](int64_t kk) { return (va && kk < kw) ? pa[kk] : 0ull; };
-    auto ldB = [&](int64_t kk) { return (vb && kk < kw) ? pb[kk] : 0ull; };
-    auto store = [&](int buf, uint64_t x, uint64_t y) {
-        sA[buf][0][tid] = word_half_to_fp4(x, 0);
-        sA[buf][1][tid] = word_half_to_fp4(x, 1);
-        sB[buf][0][tid] = word_half_to_fp4(y, 0);
-        sB[buf][1][tid] = word_half_to_fp4(y, 1);
+    // this thread's operand row (Bt has nw * 64 rows, zero past n); a row
+    // past the end reads row 0 and stores zeros
+    const int64_t g = tid < F4_BM ? r0 + tid : w0 * 64 + (tid - F4_BM);
+    const bool valid = tid < F4_BM ? g < m : g < nw * 64;
+    const uint64_t *src = tid < F4_BM ? A + (valid ? g : 0) * lda : Bt + (valid ? g : 0) * ldbt;
+    const int64_t steps = (kw + KS - 1) / KS, full = kw / KS;
+    auto ld = [&](int64_t kk, uint64_t *x) {
+        if (kk < full)
+            f4_ld_full<VEC>(src + kk * KS, x);
+        else
+            f4_ld_tail(src + kk * KS, kk * KS, kw, x);
     };
-    auto frag = [](const uint4 &t) { return v8i{(int)t.x, (int)t.y, (int)t.z, (int)t.w, 0, 0, 0, 0}; };
-    // xa[i], xb[i]: the words of step kk + 1 + i, in flight
-    uint64_t xa[F4_AHEAD], xb[F4_AHEAD];
+    auto put = [&](int buf, const uint64_t *x) {
+        uint4 *d = reinterpret_cast<uint4 *>(&sP[buf][tid][0]);
+        const uint64_t z = valid ? ~0ull : 0ull;
 #pragma unroll
-    for (int i = 0; i < F4_AHEAD; i++) {
-        xa[i] = ldA(1 + i);
-        xb[i] = ldB(1 + i);
+        for (int h = 0; h < KS / 4; h++) {
+            const uint64_t a = x[4 * h] & z, b = x[4 * h + 1] & z, c = x[4 * h + 2] & z, e = x[4 * h + 3] & z;
+            d[h] = uint4{(uint32_t)a, (uint32_t)b, (uint32_t)c, (uint32_t)e};
+            d[KS / 4 + h] = uint4{(uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), (uint32_t)(e >> 32)};
+        }
+    };
+    // the lane's raw operand halves (half kh of its rows) for chunk h of a step
+    auto fetch = [&](int buf, int h, uint32_t (*ra)[4], uint32_t (*rb)[4]) {
+#pragma unroll
+        for (int i = 0; i < TI; i++) {
+            const uint4 v = reinterpret_cast<const uint4 *>(&sP[buf][wr * TI * 32 + 32 * i + lr][kh * KS])[h];
+            ra[i][0] = v.x, ra[i][1] = v.y, ra[i][2] = v.z, ra[i][3] = v.w;
+        }
+#pragma unroll
+        for (int j = 0; j < TJ; j++) {
+            const uint4 v = reinterpret_cast<const uint4 *>(&sP[buf][F4_BM + wc * TJ * 32 + 32 * j + lr][kh * KS])[h];
+            rb[j][0] = v.x, rb[j][1] = v.y, rb[j][2] = v.z, rb[j][3] = v.w;
+        }
+    };
+    v16f acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; i++)
+#pragma unroll
+        for (int j = 0; j < TJ; j++) acc[i][j] = v16f{};
+    auto mma = [&](const uint32_t (*ra)[4], const uint32_t (*rb)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            v8i fa[TI], fb[TJ];
+#pragma unroll
+            for (int i = 0; i < TI; i++) fa[i] = half_to_fp4(ra[i][q]);
+#pragma unroll
+            for (int j = 0; j < TJ; j++) fb[j] = half_to_fp4(rb[j][q]);
+#pragma unroll
+            for (int i = 0; i < TI; i++)
+#pragma unroll
+                for (int j = 0; j < TJ; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j], 4, 4, 0, 127,
+                                                                               0, 127);
+        }
+    };
+    uint64_t xs[KS];  // step kk + 1's words during step kk
+    {
+        uint64_t x0[KS];
+        ld(0, x0);
+        ld(1, xs);
+        put(0, x0);
     }
-    v16f acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = v16f{};
-    // step kk's operands come from buffer kk & 1: written (expanded) during
-    // step kk - 1, read into registers right after the barrier that ends it,
-    // so each step's matrix-core work overlaps the next step's expansion
-    store(0, ldA(0), ldB(0));
     __syncthreads();
-    v8i fa[4], fb[4];
+    uint32_t ca[TI][4], cb[TJ][4];  // chunk 0 of the current step
+    fetch(0, 0, ca, cb);
+    for (int64_t kk = 0; kk < steps; kk++) {
+        const int cur = (int)(kk & 1), nxt = cur ^ 1;
+        put(nxt, xs);
+        uint32_t da[CH - 1][TI][4], db[CH - 1][TJ][4];  // chunks 1.. of the current step
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-        fa[i] = frag(sA[0][kh][wr * 128 + 32 * i + lr]);
-        fb[i] = frag(sB[0][kh][wc * 128 + 32 * i + lr]);
-    }
-    for (int64_t kk = 0; kk < kw; kk++) {
-        const int nxt = (int)((kk + 1) & 1);
-        // buffer nxt was last read for step kk - 1, before the barrier that
-        // ended it; past the last step this store is unused
-        store(nxt, xa[0], xb[0]);
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j], 4, 4, 0, 127, 0,
-                                                                           127);
-#pragma unroll
-        for (int i = 0; i + 1 < F4_AHEAD; i++) {
-            xa[i] = xa[i + 1];
-            xb[i] = xb[i + 1];
-        }
-        xa[F4_AHEAD - 1] = ldA(kk + 1 + F4_AHEAD);
-        xb[F4_AHEAD - 1] = ldB(kk + 1 + F4_AHEAD);
-        // issue order: the expansion's ALU work and LDS stores between the
-        // matrix-core instructions (32 cycles each), and all of it before the
-        // barrier
-#pragma unroll
-        for (int g = 0; g < 16; g++) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
-            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two VALU
-            if (g % 4 == 3) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // one LDS store
-        }
-        __builtin_amdgcn_sched_barrier(0);
+        for (int h = 1; h < CH; h++) fetch(cur, h, da[h - 1], db[h - 1]);
+        ld(kk + 2, xs);
         __syncthreads();
-        if (kk + 1 < kw) {
+        uint32_t na[TI][4], nb[TJ][4];
+        if (kk + 1 < steps) fetch(nxt, 0, na, nb);
+        mma(ca, cb);
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                fa[i] = frag(sA[nxt][kh][wr * 128 + 32 * i + lr]);
-                fb[i] = frag(sB[nxt][kh][wc * 128 + 32 * i + lr]);
-            }
-        }
+        for (int h = 1; h < CH; h++) mma(da[h - 1], db[h - 1]);
+#pragma unroll
+        for (int i = 0; i < TI; i++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) ca[i][q] = na[i][q];
+#pragma unroll
+        for (int j = 0; j < TJ; j++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) cb[j][q] = nb[j][q];
     }
-    // sums mod 2 -> bits; lane L collects rows L and 64 + L of the wave's
-    // 128, words d = 0, 1 of its 128 columns
-    uint64_t out[2][2] = {{0, 0}, {0, 0}};
+    // sums mod 2 -> bits; lane L collects row L of the wave's 64, words
+    // d = 0, 1 of its 128 columns
+    uint64_t out[2] = {0, 0};
     const uint64_t lo32 = 0xFFFFFFFFull;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < TI; i++) {
 #pragma unroll
         for (int e = 0; e < 16; e++) {
             const int q = 32 * i + (e >> 2) * 8 + (e & 3);  // rows q (lanes < 32) and q + 4 (lanes >= 32)
@@ -336,19 +380,16 @@ __global__ __launch_bounds__(256) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, 
             for (int d = 0; d < 2; d++) {
                 const uint64_t b0 = __ballot(((int)acc[i][2 * d][e]) & 1);
                 const uint64_t b1 = __ballot(((int)acc[i][2 * d + 1][e]) & 1);
-                out[q >> 6][d] = lane == (q & 63) ? ((b0 & lo32) | (b1 << 32)) : out[q >> 6][d];
-                out[(q + 4) >> 6][d] = lane == ((q + 4) & 63) ? ((b0 >> 32) | (b1 & ~lo32)) : out[(q + 4) >> 6][d];
+                out[d] = lane == q ? ((b0 & lo32) | (b1 << 32)) : out[d];
+                out[d] = lane == q + 4 ? ((b0 >> 32) | (b1 & ~lo32)) : out[d];
             }
         }
     }
+    const int64_t row = r0 + wr * TI * 32 + lane;
 #pragma unroll
-    for (int p = 0; p < 2; p++) {
-        const int64_t row = r0 + wr * 128 + 64 * p + lane;
-#pragma unroll
-        for (int d = 0; d < 2; d++) {
-            const int64_t w = w0 + wc * 2 + d;
-            if (row < m && w < nw && out[p][d]) C[row * ldc + w] ^= out[p][d];
-        }
+    for (int d = 0; d < 2; d++) {
+        const int64_t w = w0 + wc * 2 + d;
+        if (row < m && w < nw && out[d]) C[row * ldc + w] ^= out[d];
     }
 }
 
@@ -368,9 +409,14 @@ hipError_t launch_mfma_gf2(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t 
         const int64_t nw = words_for(n), kw = words_for(k);
         const int64_t gcols = (nw + F4_BN / 64 - 1) / (F4_BN / 64), grows = (m + F4_BM - 1) / F4_BM;
         if (gcols <= 0 || grows <= 0 || kw <= 0) return hipSuccess;
+        const bool vec = (uintptr_t)A % 16 == 0 && (uintptr_t)Bt % 16 == 0 && lda % 2 == 0 && ldbt % 2 == 0;
         ProfScope ps(KID_MFMA, s);
-        hipLaunchKernelGGL(k_mfma_gf2_fp4, dim3((unsigned)(gcols * grows)), dim3(256), 0, s, C, ldc, A, lda, Bt, ldbt,
-                           m, kw, nw, gcols, grows);
+        if (vec)
+            hipLaunchKernelGGL(k_mfma_gf2_fp4<true>, dim3((unsigned)(gcols * grows)), dim3(512), 0, s, C, ldc, A, lda,
+                               Bt, ldbt, m, kw, nw, gcols, grows);
+        else
+            hipLaunchKernelGGL(k_mfma_gf2_fp4<false>, dim3((unsigned)(gcols * grows)), dim3(512), 0, s, C, ldc, A, lda,
+                               Bt, ldbt, m, kw, nw, gcols, grows);
         return hipGetLastError();
     }
     if (k >= 128) {

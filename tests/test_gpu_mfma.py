@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [(1, 1, 1), (1, 64, 1), (64, 1, 64), (33, 17, 65), (100, 64, 70), (128, 128, 128), (300, 150, 900),
           (700, 1000, 130), (129, 33, 4097), (2048, 512, 2048), (1000, 2049, 300), (4100, 96, 640),
-          (257, 4096, 513), (3000, 1100, 2500)]
+          (257, 4096, 513), (3000, 1100, 2500), (1500, 640, 1200), (600, 1400, 520)]
 
 
 @pytest.mark.parametrize("m,k,n", SHAPES)
