@@ -6,9 +6,9 @@
 // One level on the m x n block A, split at column n1 (a multiple of 64):
 //   1. PLE of the left block [A0 A1]'s first n1 columns; its swaps move whole
 //      rows, so the right block A1 ends up with its rows permuted (P1^T A1);
-//   2. A01 <- L00^-1 A01 on the first r1 rows of A1 (triangular solve, by
-//      recursion on halves: each half's solve, then the product that removes
-//      it from the other half);
+//   2. A01 <- L00^-1 A01 on the first r1 rows of A1 (triangular solve, in
+//      blocks of 128 rows: each block's own forward substitution, then one
+//      Four-Russians sweep that removes the block from every row below it);
 //   3. A11 <- A11 + L10 A01 (the product that Algorithm 3 hands to matrix
 //      multiplication);
 //   4. PLE of A11 (rows r1.., columns n1..), again moving whole rows, so the
@@ -22,6 +22,7 @@
 
 #include "alg3.h"
 #include "dev.h"
+#include "m4rm.h"
 
 namespace gf2 {
 
@@ -32,27 +33,164 @@ hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int6
                                  hipStream_t s);
 hipError_t launch_mfma_gf2(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *Bt, int64_t ldbt,
                            int64_t m, int64_t k, int64_t n, hipStream_t s, int fmt);
+int device_cu_count();
 
-// X <- L^-1 X on one diagonal block of nb <= 64 rows (the leaves of step 2):
-// rows j0 .. j0 + nb - 1 of A, whose L bits below the diagonal sit in word
-// lw (row j0 + i: bits 0 .. i - 1), and X = their words [xw0, xw1).  One
-// wave per word of X, lane i holding row j0 + i; once row j is final its
-// word goes to every lane i > j with L[i][j] = 1 (forward substitution).
-__global__ __launch_bounds__(256) void k_trsm64(uint64_t *__restrict__ A, int64_t ldw, int64_t j0, int nb, int64_t lw,
-                                                int64_t xw0, int64_t xw1) {
+// X <- L^-1 X on one diagonal block of nb <= 128 rows (step 2): rows
+// j0 .. j0 + nb - 1 of A, whose L bits left of the diagonal inside the block
+// sit in words lw, lw + 1, and X = their words [xw0, xw1).  One wave per
+// word of X, two rows per lane: row j0 + l (L bits: word lw, bits < l) and
+// row j0 + 64 + l (all of word lw, then word lw + 1, bits < l).  Forward
+// substitution: once row j is final its word goes by readlane to every lane
+// whose row has L[.][j] = 1; the first 64 rows are final after 64 steps, and
+// by then their words are folded into the second half too.
+__global__ __launch_bounds__(256) void k_trsm128(uint64_t *__restrict__ A, int64_t ldw, int64_t j0, int nb, int64_t lw,
+                                                 int64_t xw0, int64_t xw1) {
     const int lane = threadIdx.x & 63;
     const int64_t w = xw0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= xw1) return;  // w is the same for the whole wave
-    const bool on = lane < nb;
-    uint64_t *row = A + (j0 + (on ? lane : 0)) * ldw;
-    uint64_t x = on ? row[w] : 0ull;
+    const bool on0 = lane < nb, on1 = 64 + lane < nb;
+    uint64_t *row0 = A + (j0 + (on0 ? lane : 0)) * ldw;
+    uint64_t *row1 = A + (j0 + (on1 ? 64 + lane : 0)) * ldw;
+    uint64_t x0 = on0 ? row0[w] : 0ull, x1 = on1 ? row1[w] : 0ull;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t l = on ? (row[lw] & below) : 0ull;
-    for (int j = 0; j + 1 < nb; j++) {
-        const uint64_t xj = readlane64(x, j);
-        x ^= ((l >> j) & 1ull) ? xj : 0ull;
+    const uint64_t l0 = on0 ? (row0[lw] & below) : 0ull;
+    const uint64_t l1a = on1 ? row1[lw] : 0ull;
+    const uint64_t l1b = on1 ? (row1[lw + 1] & below) : 0ull;
+    // every step runs (rows past nb are zero with zero L bits); with j a
+    // constant, bit j of an L word becomes an all-ones or zero 32-bit mask in
+    // one signed bit-field extract (the builtin's result type is unsigned:
+    // the mask is applied to each half of the row word, never widened)
+    auto bitmask = [](uint64_t l, int j) -> uint32_t {
+        const uint32_t h = (uint32_t)(j < 32 ? l : (l >> 32));
+        return __builtin_amdgcn_sbfe(h, (unsigned)(j & 31), 1u);
+    };
+    // x ^= xj & mask, one v_bitop3 per half: S1 ^ (S0 & S2) with S0 = xj,
+    // S1 = x, S2 = mask (truth table 0x6C; the function is symmetric in S0
+    // and S2, so the table does not depend on which operand is the high
+    // index bit)
+    auto apply = [](uint64_t x, uint64_t xj, uint32_t msk) -> uint64_t {
+        const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)xj, (uint32_t)x, msk, 0x6C);
+        const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(xj >> 32), (uint32_t)(x >> 32), msk, 0x6C);
+        return ((uint64_t)hi << 32) | lo;
+    };
+#pragma unroll
+    for (int j = 0; j < 64; j++) {
+        const uint64_t xj = readlane64(x0, j);
+        x0 = apply(x0, xj, bitmask(l0, j));
+        x1 = apply(x1, xj, bitmask(l1a, j));
     }
-    if (on) row[w] = x;
+#pragma unroll
+    for (int j = 0; j < 63; j++) {
+        const uint64_t xj = readlane64(x1, j);
+        x1 = apply(x1, xj, bitmask(l1b, j));
+    }
+    if (on0) row0[w] = x0;
+    if (on1) row1[w] = x1;
+}
+
+// One sweep of the blocked triangular solve: rows [rb_all, re_all) of
+// X = A[.][xw0, xw1) lose the solved rows j0 .. j0 + nb - 1 (nb <= 128):
+//   X[i] ^= sum_j L[i][j0 + j] X[j0 + j],
+// the coefficient bits being row i's L bits in words lw, lw + 1 (all of them
+// L bits, as every row below the block is past its columns).  Thirty-two
+// 16-entry tables of 4-row sums per 32-word tile in LDS (rows past nb are
+// zero, so every table is read and a row's 32 reads carry no branch); 16
+// lanes per row, two words per lane, the next row's words loaded during
+// this row's lookups.  Blocks: (tile, row chunk), tiles fastest.
+constexpr int TP_TW = 32;
+__global__ __launch_bounds__(1024) void k_trsm_pair(uint64_t *__restrict__ A, int64_t ldw, int64_t j0, int nb,
+                                                    int64_t lw, int64_t rb_all, int64_t re_all, int64_t xw0,
+                                                    int64_t xw1, int ntiles, int nchunks) {
+    constexpr int NT = 1024, LPR = TP_TW / 2, RS = NT / LPR;
+    __shared__ __align__(16) uint64_t T[32][16][TP_TW];
+    const int tid = threadIdx.x;
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    const int tile = logical % ntiles, chunk = logical / ntiles;
+    if (chunk >= nchunks) return;
+    const int64_t per = (re_all - rb_all + nchunks - 1) / nchunks;
+    const int64_t rb = rb_all + (int64_t)chunk * per;
+    const int64_t re = rb + per < re_all ? rb + per : re_all;
+    if (rb >= re) return;
+    const int64_t wt0 = (xw0 & ~(int64_t)(TP_TW - 1)) + (int64_t)tile * TP_TW;
+    // single-row entries and the zero entries
+    for (int e = tid; e < 128 * TP_TW; e += NT) {
+        const int k = e / TP_TW, wl = e % TP_TW;
+        const int64_t w = wt0 + wl;
+        const int q = k >> 2, b = k & 3;
+        T[q][1 << b][wl] = (k < nb && w >= xw0 && w < xw1) ? A[(j0 + k) * ldw + w] : 0ull;
+        if (b == 0) T[q][0][wl] = 0ull;
+    }
+    __syncthreads();
+    for (int e = tid; e < 32 * 16 * TP_TW; e += NT) {
+        const int wl = e % TP_TW;
+        const int x = (e / TP_TW) & 15;
+        const int q = e / (TP_TW * 16);
+        if (__popc(x) < 2) continue;
+        uint64_t acc = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+            if ((x >> b) & 1) acc ^= T[q][1 << b][wl];
+        T[q][x][wl] = acc;
+    }
+    __syncthreads();
+    const int wp = tid % LPR, rs = tid / LPR;
+    const int64_t w2 = wt0 + 2 * wp;
+    const bool ok0 = w2 >= xw0 && w2 < xw1, ok1 = w2 + 1 >= xw0 && w2 + 1 < xw1;
+    const uint32_t tbase = (uint32_t)(2 * wp) * 8u;  // byte offset of this lane's pair of words
+    // a lane's two words move as one 16-byte access when the row stride is
+    // even and the base 16-byte aligned (tiles start at even words)
+    const bool wide = (ldw & 1) == 0 && ((uintptr_t)A & 15) == 0 && ok0 && ok1;
+    auto load = [&](int64_t i, uint64_t &c0, uint64_t &c1, uint64_t &v0, uint64_t &v1) {
+        if (i < re) {
+            const uint64_t *row = A + i * ldw;
+            c0 = row[lw];
+            c1 = row[lw + 1];
+            if (wide) {
+                const ulonglong2 v = *(const ulonglong2 *)(row + w2);
+                v0 = v.x;
+                v1 = v.y;
+            } else {
+                v0 = ok0 ? row[w2] : 0ull;
+                v1 = ok1 ? row[w2 + 1] : 0ull;
+            }
+        } else {
+            c0 = c1 = v0 = v1 = 0ull;
+        }
+    };
+    int64_t i = rb + rs;
+    uint64_t nc0, nc1, nv0, nv1;
+    load(i, nc0, nc1, nv0, nv1);
+    for (; i < re; i += RS) {
+        const uint64_t c0 = nc0, c1 = nc1, x0 = nv0, x1 = nv1;
+        load(i + RS, nc0, nc1, nv0, nv1);
+        const uint32_t h[4] = {(uint32_t)c0, (uint32_t)(c0 >> 32), (uint32_t)c1, (uint32_t)(c1 >> 32)};
+        uint64_t a0 = 0, a1 = 0;
+#pragma unroll
+        for (int g = 0; g < 32; g += 2) {
+            ulonglong2 t[2];
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                const int q = g + j;
+                const uint32_t nib = (h[q >> 3] >> (4 * (q & 7))) & 15u;
+                t[j] = *(const ulonglong2 *)((const char *)&T[0][0][0] + tbase +
+                                             ((uint32_t)q * 16u + nib) * (uint32_t)(TP_TW * 8));
+            }
+            a0 = xor3_64(a0, t[0].x, t[1].x);
+            a1 = xor3_64(a1, t[0].y, t[1].y);
+        }
+        if (c0 | c1) {
+            uint64_t *row = A + i * ldw;
+            if (wide) {
+                ulonglong2 v;
+                v.x = x0 ^ a0;
+                v.y = x1 ^ a1;
+                *(ulonglong2 *)(row + w2) = v;
+            } else {
+                if (ok0) row[w2] = x0 ^ a0;
+                if (ok1) row[w2 + 1] = x1 ^ a1;
+            }
+        }
+    }
 }
 
 // Step 5, the permutation and rank: the right block's P and Q entries
@@ -162,33 +300,52 @@ hipError_t product(Ctx &c, uint64_t *A, int64_t crow0, int64_t M, int64_t kw0, i
     return hipSuccess;
 }
 
-hipError_t trsm64(Ctx &c, uint64_t *A, int64_t j0, int nb, int64_t xw0, int64_t xw1) {
+hipError_t trsm128(Ctx &c, uint64_t *A, int64_t j0, int nb, int64_t xw0, int64_t xw1) {
     const int64_t blocks = (xw1 - xw0 + 3) / 4;
     if (blocks <= 0 || nb <= 0) return hipSuccess;
     ProfScope ps(KID_M4RM, c.s);
-    hipLaunchKernelGGL(k_trsm64, dim3((unsigned)blocks), dim3(256), 0, c.s, A, c.ldw, j0, nb, j0 >> 6, xw0, xw1);
+    hipLaunchKernelGGL(k_trsm128, dim3((unsigned)blocks), dim3(256), 0, c.s, A, c.ldw, j0, nb, j0 >> 6, xw0, xw1);
     return hipGetLastError();
 }
 
-// rows [j0, j1) of X = A[.][xw0, xw1) <- L^-1 X, with L the unit lower
-// triangle of A[j0 .. j1)[j0 .. j1) (j0 a multiple of 64)
-hipError_t trsm(Ctx &c, uint64_t *A, int64_t j0, int64_t j1, int64_t xw0, int64_t xw1, int64_t N) {
-    if (j1 - j0 <= 64) return trsm64(c, A, j0, (int)(j1 - j0), xw0, xw1);
-    hipError_t e;
-    if (!c.mfma) {
-        // tables: one 64-row block at a time, each removed from the rows below
-        for (int64_t b = j0; b < j1; b += 64) {
-            const int nb = (int)(j1 - b < 64 ? j1 - b : 64);
-            if ((e = trsm64(c, A, b, nb, xw0, xw1)) != hipSuccess) return e;
-            if (b + 64 < j1 && (e = product(c, A, b + 64, j1 - b - 64, b >> 6, 64, b, xw0, xw1, N)) != hipSuccess)
-                return e;
+// rows [rb, re) of X lose the solved rows j0 .. j0 + nb - 1; the grid is
+// whole rounds of one block per CU (at least 256 rows per chunk)
+hipError_t trsm_sweep(Ctx &c, uint64_t *A, int64_t j0, int nb, int64_t rb, int64_t re, int64_t xw0, int64_t xw1) {
+    if (rb >= re || xw0 >= xw1) return hipSuccess;
+    const int64_t base = xw0 & ~(int64_t)(TP_TW - 1);
+    const int nt = (int)((xw1 - base + TP_TW - 1) / TP_TW);
+    const int64_t slots = device_cu_count();
+    int64_t maxc = (re - rb) / 256;
+    if (maxc < 1) maxc = 1;
+    if (maxc > 4 * slots) maxc = 4 * slots;
+    int nchunks = 1;
+    double best = -1.0;
+    for (int64_t nc = 1; nc <= maxc; nc++) {
+        const int64_t g = nt * nc;
+        const int64_t rounds = (g + slots - 1) / slots;
+        const double eff = (double)g / (double)(rounds * slots) - 0.02 * (double)(rounds - 1);
+        if (eff > best + 1e-9) {
+            best = eff;
+            nchunks = (int)nc;
         }
-        return hipSuccess;
     }
-    const int64_t h = ((j1 - j0) / 2 + 63) & ~(int64_t)63;
-    if ((e = trsm(c, A, j0, j0 + h, xw0, xw1, N)) != hipSuccess) return e;
-    if ((e = product(c, A, j0 + h, j1 - j0 - h, j0 >> 6, h, j0, xw0, xw1, N)) != hipSuccess) return e;
-    return trsm(c, A, j0 + h, j1, xw0, xw1, N);
+    ProfScope ps(KID_M4RM, c.s);
+    hipLaunchKernelGGL(k_trsm_pair, dim3((unsigned)(nt * nchunks)), dim3(1024), 0, c.s, A, c.ldw, j0, nb, j0 >> 6, rb,
+                       re, xw0, xw1, nt, nchunks);
+    return hipGetLastError();
+}
+
+// rows [0, r) of X = A[.][xw0, xw1) <- L^-1 X, with L the unit lower
+// triangle of A[0 .. r)[0 .. r): 128-row blocks in order, each solved on its
+// own and then removed from the rows below it in one sweep
+hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1) {
+    hipError_t e;
+    for (int64_t b = 0; b < r; b += 128) {
+        const int nb = (int)(r - b < 128 ? r - b : 128);
+        if ((e = trsm128(c, A, b, nb, xw0, xw1)) != hipSuccess) return e;
+        if ((e = trsm_sweep(c, A, b, nb, b + nb, r, xw0, xw1)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t ple_rec(Ctx &c, uint64_t *A, int64_t m, int64_t n, int64_t *P, int64_t *Q, int64_t *rank, int levels,
@@ -204,7 +361,7 @@ hipError_t ple_rec(Ctx &c, uint64_t *A, int64_t m, int64_t n, int64_t *P, int64_
     if ((e = hipStreamSynchronize(c.s)) != hipSuccess) return e;
     const int64_t xw0 = n1 >> 6, xw1 = words_for(n), N = n - n1;
     if (r1 > 0) {
-        if ((e = trsm(c, A, 0, r1, xw0, xw1, N)) != hipSuccess) return e;
+        if ((e = trsm(c, A, r1, xw0, xw1)) != hipSuccess) return e;
         if ((e = product(c, A, r1, m - r1, 0, r1, 0, xw0, xw1, N)) != hipSuccess) return e;
     }
     if (m <= r1) return hipSuccess;  // then min(m, n) = r1: P and Q are complete

@@ -758,6 +758,8 @@ static int device_cus() {
     return g_cus;
 }
 
+int device_cu_count() { return device_cus(); }
+
 static void m4_grid(int v, int64_t rows_est, int64_t w_begin, int64_t w_end, int target, int *ntiles, int *nchunks) {
     const int tw = kM4Variants[v].tw;
     const int64_t base = w_begin & ~(int64_t)(tw - 1);

@@ -144,3 +144,72 @@ def test_alg3_model_equals_oracle(m, n, kind, levels):
     assert np.array_equal(Q, Qo)
     assert np.array_equal(P, Po)
     assert np.array_equal(LE, B)
+
+
+def _trsm_blocked_words(W, r, xw0, xw1):
+    """The triangular solve as the library runs it, on packed words W (rows
+    x words, the L bits of row i in its words left of column i): 128-row
+    blocks in order; in each, the two-rows-per-lane forward substitution
+    (first half from word lw's bits below the lane, second half from all of
+    word lw then word lw + 1's bits below the lane), then the rows below the
+    block take the block's rows selected by their words lw, lw + 1."""
+    W = W.copy()
+    one = np.uint64(1)
+    for b in range(0, r, 128):
+        nb = min(128, r - b)
+        lw = b // 64
+        for w in range(xw0, xw1):
+            x0 = [W[b + l, w] if l < nb else np.uint64(0) for l in range(64)]
+            x1 = [W[b + 64 + l, w] if 64 + l < nb else np.uint64(0) for l in range(64)]
+            below = [np.uint64(0) if l == 0 else np.uint64((1 << l) - 1) for l in range(64)]
+            l0 = [W[b + l, lw] & below[l] if l < nb else np.uint64(0) for l in range(64)]
+            l1a = [W[b + 64 + l, lw] if 64 + l < nb else np.uint64(0) for l in range(64)]
+            l1b = [W[b + 64 + l, lw + 1] & below[l] if 64 + l < nb else np.uint64(0) for l in range(64)]
+            for j in range(min(nb, 64)):
+                xj = x0[j]
+                for l in range(64):
+                    if (l0[l] >> np.uint64(j)) & one:
+                        x0[l] ^= xj
+                    if (l1a[l] >> np.uint64(j)) & one:
+                        x1[l] ^= xj
+            for j in range(max(0, nb - 64 - 1)):
+                xj = x1[j]
+                for l in range(64):
+                    if (l1b[l] >> np.uint64(j)) & one:
+                        x1[l] ^= xj
+            for l in range(64):
+                if l < nb:
+                    W[b + l, w] = x0[l]
+                if 64 + l < nb:
+                    W[b + 64 + l, w] = x1[l]
+        for i in range(b + nb, r):
+            c = [W[i, lw], W[i, lw + 1]]
+            for j in range(nb):
+                if (c[j >> 6] >> np.uint64(j & 63)) & one:
+                    W[i, xw0:xw1] ^= W[b + j, xw0:xw1]
+    return W
+
+
+@pytest.mark.parametrize("r,ncols,seed", [(300, 200, 1), (128, 70, 2), (129, 64, 3), (256, 130, 4), (64, 64, 5),
+                                          (20, 100, 6)])
+def test_blocked_trsm_words_equal_forward_substitution(r, ncols, seed):
+    """The library's blocked solve (its word indices and masks) equals plain
+    forward substitution X <- L^-1 X for a random unit lower triangular L.
+    The bits on and right of the diagonal of the L block (the E part of those
+    rows in L\\E) are random too: the solve must not read them."""
+    rng = np.random.default_rng(seed)
+    nl = (r + 63) // 64 * 64
+    Lb = np.tril(rng.integers(0, 2, (r, r), dtype=np.uint8), -1)
+    Eb = np.triu(rng.integers(0, 2, (r, nl), dtype=np.uint8))
+    Xb = rng.integers(0, 2, (r, ncols), dtype=np.uint8)
+    M = np.zeros((r, nl + ncols), np.uint8)
+    M[:, :nl] = Eb
+    M[:, :r] |= Lb
+    M[:, nl:] = Xb
+    W = H.pack(M)
+    xw0 = nl // 64
+    got = H.unpack(_trsm_blocked_words(W, r, xw0, W.shape[1]), nl + ncols)[:, nl:]
+    X = Xb.astype(np.int64)
+    for i in range(r):
+        X[i] = (X[i] + Lb[i, :i].astype(np.int64) @ X[:i]) & 1
+    assert np.array_equal(got, X.astype(np.uint8))
