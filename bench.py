@@ -687,7 +687,8 @@ def run_alg3(args, m, n, pristine, work, log_fn):
     matrix: gf2_ple with update = 2 (products on the fp4 matrix cores), 3 (on
     the Four-Russians tables) and 4 (on the int8 matrix cores), one and two
     levels of column splits; each the best of two calls after one untimed
-    call.  Then the product on its own, C ^= A B for 65536 x k x 65536 at
+    call; and left strips of 8192 to 24576 columns with the splits going on
+    in the right block (rec_split).  Then the product on its own, C ^= A B for 65536 x k x 65536 at
     k = 256, 512, 1024, on the tables and both matrix-core forms: time, the
     tables' HBM rate (16 bytes per row word of C per 64 inner bits) and the
     matrix cores' rate (2 m k n operations) against the dense peaks (fp4
@@ -697,20 +698,22 @@ def run_alg3(args, m, n, pristine, work, log_fn):
     from paper_1111_6549_amd import inputs
     ldw = inputs.words(n)
     out = {"ple": []}
-    for update, levels in ((3, 1), (2, 1), (2, 2), (4, 1)):
-        ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw, update=update, rec_levels=levels))
+    cfgs = [(3, 1, 0), (2, 1, 0), (2, 2, 0), (4, 1, 0)]
+    cfgs += [(2, 16, s) for s in (8192, 12288, 16384, 24576) if s < n]
+    for update, levels, split in cfgs:
+        ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw, update=update, rec_levels=levels, rec_split=split))
         times = []
         for rep in range(3):
             work.copy_(pristine)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            P, Q, rank = G.ple(work, n, ws=ws, update=update, rec_levels=levels)
+            P, Q, rank = G.ple(work, n, ws=ws, update=update, rec_levels=levels, rec_split=split)
             torch.cuda.synchronize()
             if rep:
                 times.append((time.perf_counter() - t0) * 1000.0)
         pt = {"update": update, "products": {2: "fp4 matrix cores", 3: "Four-Russians tables",
                                              4: "int8 matrix cores"}[update],
-              "levels": levels, "ms": round(min(times), 3), "rank": int(rank.item())}
+              "levels": levels, "split": split or "halves", "ms": round(min(times), 3), "rank": int(rank.item())}
         out["ple"].append(pt)
         log_fn("alg3: %s" % json.dumps(pt))
         del ws

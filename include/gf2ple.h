@@ -48,11 +48,12 @@ typedef enum gf2_status {
 typedef struct gf2_ple_opts {
     int32_t check_padding; /* 1: scan for set bits at columns >= n first (synchronises) */
     int32_t update;        /* 0 = default = 1: Algorithm 2, every trailing update by the Four-Russians tables;
-                              2 = Algorithm 3 (block-recursive PLE, Section 3.3): split the columns in halves
-                              (at a multiple of 64), PLE of the left half, A01 <- L00^-1 A01, then
-                              A11 <- A11 + L10 A01 as a product on the fp4 matrix cores, PLE of A11, and
-                              the two halves' P, Q and L combined; rec_levels levels of splits, Algorithm 2
-                              below them.  Bit-identical to Algorithm 2.  Synchronises once per split.
+                              2 = Algorithm 3 (block-recursive PLE, Section 3.3): split the columns (in
+                              halves, or a left strip of rec_split columns), PLE of the left block,
+                              A01 <- L00^-1 A01, then A11 <- A11 + L10 A01 as a product on the fp4 matrix
+                              cores, PLE of A11, and the two blocks' P, Q and L combined; rec_levels levels
+                              of splits, Algorithm 2 below them.  Bit-identical to Algorithm 2.
+                              Synchronises once per split.
                               3 = the same recursion with its products on the Four-Russians tables;
                               4 = the same recursion with its products on the int8 matrix cores.
                               gf2_addmul: 2 = fp4 matrix cores, 4 = int8 matrix cores, else tables */
@@ -66,6 +67,10 @@ typedef struct gf2_ple_opts {
                               stream beside the update), no pairs; 3 = pairs on every pass */
     int32_t pair_variant;  /* schedule of the fused pair update: 0 = default; 1..12 = a fixed (threads, rows in
                               flight, table reads per group, coefficient prefetch) */
+    int32_t rec_split;     /* update = 2, 3 or 4: 0 = split each block's columns in halves (both halves
+                              recurse); > 0 (a multiple of 64) = the left block of every split is a strip of
+                              rec_split columns done by Algorithm 2, and the splits go on in the right block
+                              while levels remain and it is wider than rec_split */
 } gf2_ple_opts;
 
 /* Library version string, e.g. "gf2ple 0.1.0 gfx950". */

@@ -17,13 +17,15 @@ size_t ple_workspace_total(int64_t m, int64_t ldw);
 // Extra workspace of the recursion beyond the pass loop's, for an m x n
 // matrix: the sub-ranks and, with matrix-core products, the bit transpose of
 // the largest product's right operand.
-size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma);
+size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma, int64_t split);
 
 // Algorithm 3 with `levels` levels of column splits (then Algorithm 2):
 // products on the Four-Russians tables (products = 0), the fp4 matrix cores
-// (1) or the int8 matrix cores (2).  Synchronises the stream once per split
-// (to size the products by the left block's rank).
+// (1) or the int8 matrix cores (2).  split = 0: halves, both recursing;
+// split > 0: a left strip of `split` columns (a leaf) and the recursion in
+// the right block.  Synchronises the stream once per split (to size the
+// products by the left block's rank).
 hipError_t ple_alg3(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
-                    const gf2_ple_opts *opts, hipStream_t s, int levels, int products);
+                    const gf2_ple_opts *opts, hipStream_t s, int levels, int products, int64_t split);
 
 }  // namespace gf2

@@ -275,7 +275,13 @@ struct Ctx {
     int64_t *rank_slots;  // device, MAX_DEPTH
     uint64_t *bt;         // bit transpose of a product's right operand
     size_t bt_bytes;
+    int64_t split;        // 0: halves; > 0: left strips of this many columns
 };
+
+// the left block's columns of a split of n columns
+int64_t split_cols(int64_t n, int64_t split) {
+    return split > 0 ? (split < n ? split : n) : ((n / 2 + 63) & ~(int64_t)63);
+}
 
 // A[crow0 .. crow0 + M)[xw0, xw1) ^= (bits [64 kw0, 64 kw0 + K) of those rows)
 //                                    x A[brow0 .. brow0 + K)[xw0, xw1)
@@ -350,11 +356,12 @@ hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1) {
 
 hipError_t ple_rec(Ctx &c, uint64_t *A, int64_t m, int64_t n, int64_t *P, int64_t *Q, int64_t *rank, int levels,
                    int64_t wlo, int depth) {
-    if (levels <= 0 || n <= 64 || m == 0 || depth >= MAX_DEPTH)
+    if (levels <= 0 || n <= 64 || m == 0 || depth >= MAX_DEPTH || (c.split > 0 && n <= c.split))
         return ple_block(A, m, n, c.ldw, P, Q, rank, c.ws, c.opts, c.s, wlo);
     const int64_t ldw = c.ldw;
-    const int64_t n1 = (n / 2 + 63) & ~(int64_t)63;
-    hipError_t e = ple_rec(c, A, m, n1, P, Q, rank, levels - 1, wlo, depth + 1);
+    const int64_t n1 = split_cols(n, c.split);
+    // a strip is a leaf; halves recurse on both sides
+    hipError_t e = ple_rec(c, A, m, n1, P, Q, rank, c.split > 0 ? 0 : levels - 1, wlo, depth + 1);
     if (e != hipSuccess) return e;
     int64_t r1 = 0;
     if ((e = hipMemcpyAsync(&r1, rank, 8, hipMemcpyDeviceToHost, c.s)) != hipSuccess) return e;
@@ -392,12 +399,13 @@ hipError_t ple_rec(Ctx &c, uint64_t *A, int64_t m, int64_t n, int64_t *P, int64_
 
 }  // namespace
 
-size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma) {
+size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma, int64_t split) {
     (void)ldw;
     size_t b = al((size_t)MAX_DEPTH * 8);
-    if (mfma && levels > 0 && n > 64) {
-        // the largest product: inner size at most min(m, n1), n - n1 columns
-        const int64_t n1 = (n / 2 + 63) & ~(int64_t)63;
+    if (mfma && levels > 0 && n > 64 && !(split > 0 && n <= split)) {
+        // the largest product is the first split's: inner size at most
+        // min(m, n1), n - n1 columns
+        const int64_t n1 = split_cols(n, split);
         const int64_t k = m < n1 ? m : n1;
         b += al((size_t)words_for(n - n1) * 64 * (size_t)words_for(k) * 8);
     }
@@ -405,7 +413,7 @@ size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma
 }
 
 hipError_t ple_alg3(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
-                    const gf2_ple_opts *opts, hipStream_t s, int levels, int products) {
+                    const gf2_ple_opts *opts, hipStream_t s, int levels, int products, int64_t split) {
     const bool mfma = products != 0;
     Ctx c;
     c.ldw = ldw;
@@ -417,7 +425,8 @@ hipError_t ple_alg3(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, 
     char *extra = (char *)ws + al(ple_workspace_total(m, ldw));
     c.rank_slots = (int64_t *)extra;
     c.bt = (uint64_t *)(extra + al((size_t)MAX_DEPTH * 8));
-    c.bt_bytes = alg3_extra_bytes(m, n, ldw, levels, mfma) - al((size_t)MAX_DEPTH * 8);
+    c.split = split;
+    c.bt_bytes = alg3_extra_bytes(m, n, ldw, levels, mfma, split) - al((size_t)MAX_DEPTH * 8);
     return ple_rec(c, A, m, n, P, Q, rank, levels, 0, 0);
 }
 

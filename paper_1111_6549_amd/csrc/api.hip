@@ -430,6 +430,7 @@ gf2_status ple_check_args(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, 
     if (m > 0 && ldw > 0 && (!A || !aligned(A, 8))) return GF2_EINVAL;
     if (opts && (opts->update < 0 || opts->update > 4 || opts->m4_variant < 0 || opts->m4_blocks < 0)) return GF2_EINVAL;
     if (opts && (opts->rec_levels < 0 || opts->rec_levels > 16)) return GF2_EINVAL;
+    if (opts && (opts->rec_split < 0 || opts->rec_split % 64 != 0)) return GF2_EINVAL;
     if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
         return GF2_EINVAL;
     if (opts && (opts->lookahead < 0 || opts->lookahead > 3)) return GF2_EINVAL;
@@ -447,6 +448,7 @@ hipError_t ple_block(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P,
 static bool recursive(const gf2_ple_opts *opts) { return opts && opts->update >= 2; }
 static int rec_levels(const gf2_ple_opts *opts) { return opts && opts->rec_levels > 0 ? opts->rec_levels : 1; }
 static int rec_products(const gf2_ple_opts *opts) { return opts->update == 2 ? 1 : (opts->update == 4 ? 2 : 0); }
+static int64_t rec_split(const gf2_ple_opts *opts) { return opts ? opts->rec_split : 0; }
 
 hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
                        void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, bool allow_s2) {
@@ -477,7 +479,7 @@ size_t gf2_ple_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf2_ple_
     if (!sizes_ok(m, n, ldw)) return 0;
     if (recursive(opts))
         return align_up(ple_layout(m, ldw).total) +
-               alg3_extra_bytes(m, n, ldw, rec_levels(opts), rec_products(opts) != 0);
+               alg3_extra_bytes(m, n, ldw, rec_levels(opts), rec_products(opts) != 0, rec_split(opts));
     return ple_layout(m, ldw).total;
 }
 
@@ -509,7 +511,8 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
         if (st != GF2_OK) return st;
     }
     if (recursive(opts))
-        return hip_status(ple_alg3(A, m, n, ldw, P, Q, rank, ws, opts, s, rec_levels(opts), rec_products(opts)));
+        return hip_status(
+            ple_alg3(A, m, n, ldw, P, Q, rank, ws, opts, s, rec_levels(opts), rec_products(opts), rec_split(opts)));
     return hip_status(ple_enqueue(A, m, n, ldw, P, Q, rank, ws, opts, s, true, true));
 }
 

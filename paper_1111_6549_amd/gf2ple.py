@@ -49,7 +49,7 @@ class KernelTime(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("check_padding", ctypes.c_int32), ("update", ctypes.c_int32), ("rec_levels", ctypes.c_int32),
                 ("m4_variant", ctypes.c_int32), ("m4_blocks", ctypes.c_int32), ("panel_regs", ctypes.c_int32),
-                ("lookahead", ctypes.c_int32), ("pair_variant", ctypes.c_int32)]
+                ("lookahead", ctypes.c_int32), ("pair_variant", ctypes.c_int32), ("rec_split", ctypes.c_int32)]
 
 
 class Desc(ctypes.Structure):
@@ -175,8 +175,9 @@ def _ptr(t):
 
 
 def _opts(update=0, check_padding=False, rec_levels=0, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0,
-          pair_variant=0):
+          pair_variant=0, rec_split=0):
     o = Opts()
+    o.rec_split = int(rec_split)
     o.lookahead = int(lookahead)
     o.pair_variant = int(pair_variant)
     o.check_padding = 1 if check_padding else 0
@@ -188,8 +189,8 @@ def _opts(update=0, check_padding=False, rec_levels=0, m4_variant=0, m4_blocks=0
     return o
 
 
-def workspace_bytes(m, n, ldw, update=0, rec_levels=0):
-    o = _opts(update, rec_levels=rec_levels)
+def workspace_bytes(m, n, ldw, update=0, rec_levels=0, rec_split=0):
+    o = _opts(update, rec_levels=rec_levels, rec_split=rec_split)
     return int(load().gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
 
 
@@ -198,7 +199,7 @@ def alloc_workspace(nbytes, device=None):
 
 
 def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0,
-        pair_variant=0, rec_levels=0):
+        pair_variant=0, rec_levels=0, rec_split=0):
     """In-place PLE of the packed (m, ldw) tensor A with n columns.
 
     Returns (P, Q, rank) as device tensors (int64 [m], int64 [min(m, n)],
@@ -207,7 +208,7 @@ def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0,
     m, ldw = A.shape
     lib = load()
     o = _opts(update, check_padding, rec_levels=rec_levels, m4_variant=m4_variant, m4_blocks=m4_blocks,
-              panel_regs=panel_regs, lookahead=lookahead, pair_variant=pair_variant)
+              panel_regs=panel_regs, lookahead=lookahead, pair_variant=pair_variant, rec_split=rec_split)
     need = int(lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
     if need == 0 and (m or n):
         raise GF2Error(1, "gf2_ple_workspace_bytes")

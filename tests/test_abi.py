@@ -155,7 +155,8 @@ def test_schedule_options_checked_before_launch():
     ws_ptr = (ws.ctypes.data + 255) // 256 * 256
     p = lambda a: ctypes.c_void_p(a.ctypes.data)
     for field, value in (("pair_variant", 99), ("pair_variant", -1), ("lookahead", 4), ("panel_regs", 3),
-                         ("update", 5), ("update", -1), ("rec_levels", 17), ("rec_levels", -1)):
+                         ("update", 5), ("update", -1), ("rec_levels", 17), ("rec_levels", -1),
+                         ("rec_split", -64), ("rec_split", 100)):
         o = G.Opts()
         setattr(o, field, value)
         st = lib.gf2_ple(p(A), m, n, ldw, p(P), p(Q), p(rank), ctypes.c_void_p(ws_ptr), ws.nbytes - 256,
@@ -198,6 +199,14 @@ def test_recursive_and_product_workspaces():
     assert base < w3 < w2
     # the top product: 2048 inner bits x 2048 columns, bit-transposed
     assert w2 - w3 >= 2048 * 2048 // 8
+    # left strips of 1024 columns: the first product is 1024 inner bits x
+    # 3072 columns; a strip as wide as the matrix is no split at all
+    o2.rec_split = 1024
+    w2s = lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o2))
+    assert w2s - w3 >= 1024 * 3072 // 8 and w2s < w2
+    o2.rec_split = 4096
+    assert lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o2)) == w3
+    o2.rec_split = 0
     fake = ctypes.c_void_p(1 << 20)
     nul = ctypes.c_void_p(0)
     assert lib.gf2_ple(fake, m, n, ldw, fake, fake, fake, fake, w2 - 1, ctypes.byref(o2), nul) == 2
@@ -211,3 +220,36 @@ def test_recursive_and_product_workspaces():
     assert lib.gf2_addmul(fake, 16, fake, 5, fake, 16, 100, 300, 1000, nul, 0, ctypes.byref(o2), nul) == 1
     # the no-allocation call takes no recursive schedule
     assert lib.gf2_ple_noalloc(fake, m, n, ldw, fake, fake, fake, ctypes.byref(o2), nul) == 1
+
+
+def _header_struct_fields(name):
+    """(type, field, array length) of a typedef struct in include/gf2ple.h, in order."""
+    text = open(os.path.join(os.path.dirname(__file__), "..", "include", "gf2ple.h")).read()
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        for nm in names.split(","):
+            m = re.match(r"(\w+)(\[(\d+)\])?$", nm.strip())
+            assert m, decl
+            out.append((ctype, m.group(1), int(m.group(3)) if m.group(3) else None))
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("gf2_ple_opts", "Opts"), ("gf2_desc", "Desc"),
+                                          ("gf2_batch_opts", "BatchOpts"), ("gf2_batch_class", "BatchClass"),
+                                          ("gf2_serve_opts", "ServeOpts")])
+def test_binding_structs_match_header(cname, pyname):
+    """The ctypes structures of the binding list the header's fields in the
+    header's order with the same widths."""
+    width = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
+    want = _header_struct_fields(cname)
+    got = getattr(G, pyname)._fields_
+    assert [f for _, f, _ in want] == [f for f, _ in got]
+    for (ctype, f, count), (_, pytype) in zip(want, got):
+        exp = width[ctype] * count if count else width[ctype]
+        assert ctypes.sizeof(pytype) == ctypes.sizeof(exp), f

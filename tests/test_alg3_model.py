@@ -63,11 +63,12 @@ def _shift_words(row_words, r1, n1, nL):
     return np.array(row, dtype=np.uint64)
 
 
-def _rec(M, r0, c0, m, n, P, Q, levels):
-    if levels <= 0 or n <= 64 or m == 0:
+def _rec(M, r0, c0, m, n, P, Q, levels, split=0):
+    if levels <= 0 or n <= 64 or m == 0 or (split > 0 and n <= split):
         return _leaf(M, r0, c0, m, n, P, Q)
-    n1 = (n // 2 + 63) // 64 * 64
-    r1 = _rec(M, r0, c0, m, n1, P, Q, levels - 1)
+    # halves (both recursing) or a left strip of `split` columns (a leaf)
+    n1 = min(split, n) if split > 0 else (n // 2 + 63) // 64 * 64
+    r1 = _rec(M, r0, c0, m, n1, P, Q, 0 if split > 0 else levels - 1, split)
     N = n - n1
     if r1 > 0:
         # A01 <- L00^-1 A01 (forward substitution), then A11 += L10 A01
@@ -81,7 +82,7 @@ def _rec(M, r0, c0, m, n, P, Q, levels):
             M[r0 + r1:r0 + m, c0 + n1:c0 + n] ^= ((L10 @ X) & 1).astype(np.uint8)
     if m <= r1:
         return r1
-    r2 = _rec(M, r0 + r1, c0 + n1, m - r1, N, P, Q, levels - 1)
+    r2 = _rec(M, r0 + r1, c0 + n1, m - r1, N, P, Q, levels - 1, split)
     mn = min(m, n)
     q_right = min(m - r1, N)
     for i in range(r1, max(m, mn)):
@@ -103,12 +104,12 @@ def _rec(M, r0, c0, m, n, P, Q, levels):
     return r1 + r2
 
 
-def model_alg3(A, n, levels):
+def model_alg3(A, n, levels, split=0):
     m = A.shape[0]
     M = H.unpack(A, n).copy()
     P = np.zeros(m, np.int64)
     Q = np.full(min(m, n), -1, np.int64)
-    r = _rec(M, 0, 0, m, n, P, Q, levels)
+    r = _rec(M, 0, 0, m, n, P, Q, levels, split)
     return r, P, Q, H.pack(M, A.shape[1])
 
 
@@ -138,6 +139,23 @@ def _case(kind, m, n, seed):
 def test_alg3_model_equals_oracle(m, n, kind, levels):
     A = _case(kind, m, n, 70 + m + n)
     r, P, Q, LE = model_alg3(A, n, levels)
+    B = A.copy()
+    ro, Po, Qo = oracle.ple(B, n)
+    assert r == ro
+    assert np.array_equal(Q, Qo)
+    assert np.array_equal(P, Po)
+    assert np.array_equal(LE, B)
+
+
+@pytest.mark.parametrize("m,n,kind,levels,split", [(300, 300, "u", 16, 64), (400, 260, "deficient_left", 16, 128),
+                                                   (200, 500, "u", 3, 128), (260, 400, "zero_left", 16, 64),
+                                                   (350, 330, "r", 2, 192), (200, 640, "deficient_left", 16, 64),
+                                                   (500, 700, "s", 16, 256)])
+def test_alg3_strips_model_equals_oracle(m, n, kind, levels, split):
+    """Left strips of `split` columns, the recursion going on in the right
+    block (update = 2 / 3 / 4 with rec_split > 0)."""
+    A = _case(kind, m, n, 90 + m + n)
+    r, P, Q, LE = model_alg3(A, n, levels, split)
     B = A.copy()
     ro, Po, Qo = oracle.ple(B, n)
     assert r == ro

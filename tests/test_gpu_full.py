@@ -82,18 +82,20 @@ def test_full_size_rref_digest(form):
     assert got == want["sha256"], "RREF digest differs from the oracle's"
 
 
-@pytest.mark.parametrize("update,levels", [(2, 1), (3, 1), (2, 2), (4, 1)])
-def test_full_size_digest_alg3(update, levels):
+@pytest.mark.parametrize("update,levels,split", [(2, 1, 0), (3, 1, 0), (2, 2, 0), (4, 1, 0), (2, 16, 16384),
+                                                 (2, 16, 8192)])
+def test_full_size_digest_alg3(update, levels, split):
     """Algorithm 3 levels over the 65536^2 seed-5 matrix (products on the fp4
     matrix cores, update 2, the tables, update 3, or the int8 matrix cores,
-    update 4) hash to the oracle's PLE digest like Algorithm 2."""
+    update 4; halves, or left strips of `split` columns) hash to the oracle's
+    PLE digest like Algorithm 2."""
     want = json.load(open(GOLDEN))["65536x65536_seed5"]
     m, n, seed = want["m"], want["n"], want["seed"]
-    say("full size alg3 update", update, "levels", levels)
+    say("full size alg3 update", update, "levels", levels, "split", split)
     A = inputs.bernoulli(m, n, seed)
     t = torch.from_numpy(A.view(np.int64)).cuda()
     del A
-    P, Q, rank = G.ple(t, n, update=update, rec_levels=levels)
+    P, Q, rank = G.ple(t, n, update=update, rec_levels=levels, rec_split=split)
     torch.cuda.synchronize()
     r = int(rank.item())
     assert r == want["rank"]

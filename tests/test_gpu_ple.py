@@ -400,3 +400,19 @@ def test_alg3_levels_parity(m, n, kind, levels, update):
     A = _alg3_case(kind, m, n)
     assert_same_ple(gpu_ple(A, n, update=update, rec_levels=levels), oracle_ple(A, n),
                     "alg3 u%d %dx%d %s levels %d" % (update, m, n, kind, levels))
+
+
+@pytest.mark.parametrize("update", [2, 3, 4])
+@pytest.mark.parametrize("m,n,kind,levels,split", [(3000, 2500, "u", 16, 512), (2500, 3000, "deficient_left", 16, 640),
+                                                   (4096, 4096, "u", 3, 1024), (2000, 2000, "s", 16, 256),
+                                                   (1500, 4000, "zero_left", 16, 768), (6000, 6000, "u", 16, 1536),
+                                                   (1200, 1100, "r", 2, 320)])
+def test_alg3_strips_parity(m, n, kind, levels, split, update):
+    """Algorithm 3 with left strips of `split` columns (each a leaf), the
+    splits going on in the right block while levels remain, against the
+    oracle; products on the fp4 (2) or int8 (4) matrix cores or the tables
+    (3)."""
+    say("alg3 strips", update, m, n, kind, levels, split)
+    A = _alg3_case(kind, m, n)
+    assert_same_ple(gpu_ple(A, n, update=update, rec_levels=levels, rec_split=split), oracle_ple(A, n),
+                    "alg3 u%d %dx%d %s levels %d split %d" % (update, m, n, kind, levels, split))
