@@ -199,9 +199,10 @@ __global__ __launch_bounds__(256) void k_mfma_gf2t(uint64_t *__restrict__ C, int
 
 // ---------------------------------------------------------------------------
 // The same product on the fp4 matrix cores (v_mfma_scale_f32_32x32x64_f8f6f4
-// with e2m1 operands, unit scales): a bit becomes the fp4 value 0.0 or 1.0
-// (nibble 0b0000 / 0b0010), the fp32 sums are exact integers (at most k),
-// and their low bit is the GF(2) sum.
+// with e2m1 operands, unit scales): a clear bit becomes 0.0, a set bit a
+// power of two whose product with the other operand's is exactly 1, so the
+// fp32 sums are exact integers (at most k) and their low bit is the GF(2)
+// sum.
 //
 // A block of eight waves (two per SIMD) computes 256 rows x 256 columns of C
 // (4 output words); the waves sit 4 x 2, each 64 rows x 128 columns as 2 x 4
@@ -211,20 +212,30 @@ __global__ __launch_bounds__(256) void k_mfma_gf2t(uint64_t *__restrict__ C, int
 // stored into double-buffered LDS as raw 32-bit halves; each wave reads the
 // halves of its own 2 + 4 operand tiles and expands them into fp4 in
 // registers just before its matrix-core instructions.  LDS holds bits rather
-// than fp4 nibbles, which cuts its traffic four-fold; the expansion (seven
-// ALU instructions per operand and word) runs on one wave of a SIMD while
-// the other's matrix-core instructions execute.
+// than fp4 nibbles, which cuts its traffic four-fold; the expansion (five or
+// seven ALU instructions per operand and word) runs on one wave of a SIMD
+// while the other's matrix-core instructions execute.
 // ---------------------------------------------------------------------------
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// 32 bits -> 32 fp4 values 0.0 / 1.0 (nibble 0b0010 = 1.0) in four dwords
-// (the upper four operand dwords are unused by e2m1).  The K order inside an
-// operand is free as long as A and B share it, so bit 4s + d of v goes to
-// nibble s of dword d: each dword is one shift and one mask of v.
-__device__ __forceinline__ v8i half_to_fp4(uint32_t v) {
-    return v8i{(int)((v << 1) & 0x22222222u), (int)(v & 0x22222222u), (int)((v >> 1) & 0x22222222u),
-               (int)((v >> 2) & 0x22222222u), 0, 0, 0, 0};
+// 32 bits -> 32 fp4 values in four dwords (the upper four operand dwords
+// are unused by e2m1).  The K order inside an operand is free as long as A
+// and B share it: bit 4s + d of v goes to nibble s of dword d.  The two
+// operands use reciprocal values, so each product of two set bits is exactly
+// 1 while each dword costs at most one shift and one mask:
+//   half_to_fp4_x: a set bit is 0.5, 1, 2, 2 in dwords 0..3 (nibble bits
+//                  0, 1, 2 -- a mask alone -- and bit 2 again for d = 3);
+//   half_to_fp4_y: a set bit is 2, 1, 0.5, 0.5 (nibble bits 2, 1, 0, 0).
+// (e2m1: 0b0001 = 0.5, 0b0010 = 1.0, 0b0100 = 2.0.)  Five and seven ALU
+// instructions; the operand with more tiles per wave takes the cheaper one.
+__device__ __forceinline__ v8i half_to_fp4_x(uint32_t v) {
+    return v8i{(int)(v & 0x11111111u), (int)(v & 0x22222222u), (int)(v & 0x44444444u), (int)((v >> 1) & 0x44444444u),
+               0, 0, 0, 0};
+}
+__device__ __forceinline__ v8i half_to_fp4_y(uint32_t v) {
+    return v8i{(int)((v << 2) & 0x44444444u), (int)(v & 0x22222222u), (int)((v >> 2) & 0x11111111u),
+               (int)((v >> 3) & 0x11111111u), 0, 0, 0, 0};
 }
 
 constexpr int F4_BM = 256, F4_BN = 256;  // block rows, block columns
@@ -324,9 +335,9 @@ __global__ __launch_bounds__(512) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, 
         for (int q = 0; q < 4; q++) {
             v8i fa[TI], fb[TJ];
 #pragma unroll
-            for (int i = 0; i < TI; i++) fa[i] = half_to_fp4(ra[i][q]);
+            for (int i = 0; i < TI; i++) fa[i] = half_to_fp4_y(ra[i][q]);
 #pragma unroll
-            for (int j = 0; j < TJ; j++) fb[j] = half_to_fp4(rb[j][q]);
+            for (int j = 0; j < TJ; j++) fb[j] = half_to_fp4_x(rb[j][q]);
 #pragma unroll
             for (int i = 0; i < TI; i++)
 #pragma unroll
