@@ -2,17 +2,22 @@
 """Benchmark: PLE decomposition of a dense 65536 x 65536 GF(2) matrix on one
 MI355X through the C ABI (gf2_ple).
 
-One step = one full PLE (every pass of Algorithm 2: panel, permute, trailing
-update) of the resident matrix.  Before each step the input is restored from
-a pristine device copy (a 512 MiB device-to-device copy, inside the timed
-region, about 0.1 ms of a step).  Prints ONE JSON line on stdout; progress
-goes to stderr.
+One step = one full PLE of the resident matrix by Algorithm 3 with one
+column split (Section 3.3; --alg 2 times Algorithm 2 alone): the left block
+(3/8 of the columns) by the pass loop of Algorithm 2 (panel, permute,
+trailing update), the triangular solve of the right block's top rows, the
+Schur product on the fp4 matrix cores, and the lower-right block by the pass
+loop again.  Before each step the input is restored from a pristine device
+copy (a 512 MiB device-to-device copy, inside the timed region, about 0.1 ms
+of a step).  Prints ONE JSON line on stdout; progress goes to stderr.
 
   value      whole-job throughput in PLE decompositions per second
-  roofline   the dominant kernel (the Four-Russians trailing update k_m4rm):
-             algorithmic bytes per launch / average launch time, both from a
-             second, event-timed repetition of the same steps (HIP events on
-             the launch stream, recorded by the library itself)
+  roofline   the dominant kernel (the Four-Russians trailing update k_m4rm
+             of the two pass loops): algorithmic bytes per launch / average
+             launch time, both from a second, event-timed repetition of the
+             same steps (HIP events on the launch stream, recorded by the
+             library itself); roofline_product and roofline_trsm give the
+             same for the matrix-core product and the triangular solve
   cpu_baseline  the CPU oracle (plain Gaussian elimination) timed on this
              host on the benchmark matrix itself, over its first columns (a
              bounded share of the elimination), scaled to the whole by the
@@ -33,13 +38,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+FP4_PEAK_TFLOPS = 10100.0
 KW = 64
-# HBM bytes per trailing-update launch on the 65536^2 seed-5 workload:
+# HBM bytes per trailing-update launch on the 65536^2 seed-5 workload (the
+# default timed path: Algorithm 3 with one split at column 24576):
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE, averaged over the update
-# launches of one PLE and scaled by the same counters on the 512 MiB restore copy
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Reported only while the kernel
-# sources hash to the value the counters were taken on.
-TRAFFIC = {"source": "91d4ef490062b617", "n": 65536, "seed": 5, "bytes_per_launch": 366621923}
+# launches of one PLE and scaled by the same counters on the 512 MiB restore
+# copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Reported only for that
+# configuration and while the kernel sources hash to the value the counters
+# were taken on.
+TRAFFIC = {"source": "8fe153e24a951129", "n": 65536, "seed": 5, "split": 24576, "bytes_per_launch": 158691695}
 
 
 def log(*a):
@@ -687,8 +695,10 @@ def run_alg3(args, m, n, pristine, work, log_fn):
     matrix: gf2_ple with update = 2 (products on the fp4 matrix cores), 3 (on
     the Four-Russians tables) and 4 (on the int8 matrix cores), one and two
     levels of column splits; each the best of two calls after one untimed
-    call; and left strips of 8192 to 24576 columns with the splits going on
-    in the right block (rec_split).  Then the product on its own, C ^= A B for 65536 x k x 65536 at
+    call; one uneven split (a left block of 20480 to 28672 columns,
+    rec_split with one level), and left strips of 16384 columns with the
+    splits going on in the right block; Algorithm 2 beside them.  Then the
+    product on its own, C ^= A B for 65536 x k x 65536 at
     k = 256, 512, 1024, on the tables and both matrix-core forms: time, the
     tables' HBM rate (16 bytes per row word of C per 64 inner bits) and the
     matrix cores' rate (2 m k n operations) against the dense peaks (fp4
@@ -698,7 +708,8 @@ def run_alg3(args, m, n, pristine, work, log_fn):
     from paper_1111_6549_amd import inputs
     ldw = inputs.words(n)
     out = {"ple": []}
-    cfgs = [(3, 1, 0), (2, 1, 0), (2, 2, 0), (4, 1, 0)]
+    cfgs = [(1, 0, 0), (3, 1, 0), (2, 1, 0), (2, 2, 0), (4, 1, 0), (2, 1, 20480), (2, 1, 24576), (2, 1, 28672),
+            (2, 16, 16384)]
     cfgs += [(2, 16, s) for s in (8192, 12288, 16384, 24576) if s < n]
     for update, levels, split in cfgs:
         ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw, update=update, rec_levels=levels, rec_split=split))
@@ -711,8 +722,8 @@ def run_alg3(args, m, n, pristine, work, log_fn):
             torch.cuda.synchronize()
             if rep:
                 times.append((time.perf_counter() - t0) * 1000.0)
-        pt = {"update": update, "products": {2: "fp4 matrix cores", 3: "Four-Russians tables",
-                                             4: "int8 matrix cores"}[update],
+        pt = {"update": update, "products": {1: "none (Algorithm 2)", 2: "fp4 matrix cores",
+                                             3: "Four-Russians tables", 4: "int8 matrix cores"}[update],
               "levels": levels, "split": split or "halves", "ms": round(min(times), 3), "rank": int(rank.item())}
         out["ple"].append(pt)
         log_fn("alg3: %s" % json.dumps(pt))
@@ -790,6 +801,11 @@ def main():
     ap.add_argument("--lookahead", type=int, default=0,
                     help="0 = library default, 1 = serial passes, 2 = look-ahead only, 3 = pairs everywhere")
     ap.add_argument("--pair-variant", type=int, default=0, help="fused pair update schedule 1..12 (0 = default)")
+    ap.add_argument("--alg", type=int, default=3, choices=(2, 3),
+                    help="timed path: 3 = Algorithm 3 with one column split (default), 2 = Algorithm 2 alone "
+                         "(the gf2_ple default)")
+    ap.add_argument("--rec-split", type=int, default=0,
+                    help="Algorithm 3's left block in columns (a multiple of 64; 0 = 3/8 of n)")
     ap.add_argument("--no-alg3", action="store_true", help="skip Algorithm 3 and the product comparison")
     ap.add_argument("--only-products", action="store_true",
                     help="run only the product comparison (tables, fp4 and int8 matrix cores) and exit")
@@ -832,15 +848,20 @@ def main():
     A = inputs.bernoulli(m, n, args.seed)
     pristine = torch.from_numpy(A.view(np.int64)).cuda()
     work = torch.empty_like(pristine)
-    ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw))
-    torch.cuda.synchronize()
-
     sched = dict(m4_variant=args.m4_variant, m4_blocks=args.m4_blocks, panel_regs=args.panel_regs,
                  lookahead=args.lookahead, pair_variant=args.pair_variant)
+    # Algorithm 3 with one split: the left block of `split` columns and the
+    # lower-right block by Algorithm 2, the triangular solve and the Schur
+    # product (fp4 matrix cores) between them
+    split = (args.rec_split or (3 * n // 8)) // 64 * 64
+    use_alg3 = args.alg == 3 and 64 <= split < n
+    rec = dict(update=2, rec_levels=1, rec_split=split) if use_alg3 else {}
+    ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw, **rec))
+    torch.cuda.synchronize()
 
     def step():
         work.copy_(pristine)
-        return G.ple(work, n, ws=ws, **sched)
+        return G.ple(work, n, ws=ws, **sched, **rec)
 
     for i in range(args.warmup):
         step()
@@ -858,11 +879,28 @@ def main():
     log("timed %d steps: %.3f ms/step, rank %d" % (args.steps, ms_per_step, r))
 
     Qh = Q.cpu().numpy()
-    kinds = G.ple_schedule(m, n, lookahead=args.lookahead)
-    abytes = alg_bytes_m4rm(m, n, Qh, r, kinds)
     abytes64 = alg_bytes_k64(m, n, Qh, r)
+    trsm_bytes = prod_flops = r1 = None
+    if use_alg3:
+        # the two Algorithm 2 blocks' update launches, the solve's sweeps
+        # (rows below each 128-row block, 16 B per row word of the right
+        # block) and the product's 2 M K N operations
+        import numpy as np
+        r1 = int(np.count_nonzero(Qh[:r] < split))
+        N = n - split
+        kinds_l = G.ple_schedule(m, split, lookahead=args.lookahead)
+        kinds_r = G.ple_schedule(m - r1, N, lookahead=args.lookahead)
+        abytes = (alg_bytes_m4rm(m, split, Qh[:r1], r1, kinds_l) +
+                  alg_bytes_m4rm(m - r1, N, Qh[r1:r] - split, r - r1, kinds_r))
+        kinds = kinds_l + kinds_r
+        nwr = (N + 63) // 64
+        trsm_bytes = int(sum(16 * (r1 - b - 128) * nwr for b in range(0, r1, 128) if b + 128 < r1))
+        prod_flops = 2 * (m - r1) * r1 * N
+    else:
+        kinds = G.ple_schedule(m, n, lookahead=args.lookahead)
+        abytes = alg_bytes_m4rm(m, n, Qh, r, kinds)
 
-    roofline = None
+    roofline = roofline_product = roofline_trsm = None
     kernels = None
     if not args.no_profile:
         G.profile_start()
@@ -878,8 +916,9 @@ def main():
             achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
             traffic = None
             if (TRAFFIC and TRAFFIC.get("source") == kernel_source_hash() and TRAFFIC.get("n") == args.n
-                    and TRAFFIC.get("seed") == args.seed and not args.m4_variant and not args.m4_blocks
-                    and not args.pair_variant and not args.lookahead):
+                    and TRAFFIC.get("seed") == args.seed and TRAFFIC.get("split") == (split if use_alg3 else 0)
+                    and not args.m4_variant and not args.m4_blocks and not args.pair_variant
+                    and not args.lookahead):
                 traffic = TRAFFIC["bytes_per_launch"]
             roofline = {
                 "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -889,7 +928,59 @@ def main():
                 "launches_per_step": launches_per_step,
                 "alg_bytes_per_launch": round(bytes_per_launch), "avg_launch_ms": round(avg_ms, 5),
             }
+        if use_alg3:
+            kp, kt = kernels.get("mfma"), kernels.get("trsm")
+            if kp and kp["total_ms"] > 0:
+                tf = prod_flops * kp["launches"] / args.steps / (kp["total_ms"] / args.steps * 1e-3) / 1e12
+                roofline_product = {"kernel": "k_mfma_gf2_fp4 (the Schur product, %d x %d x %d)" % (m - r1, r1, n - split),
+                                    "bound": "mfma", "achieved": round(tf, 1), "peak": FP4_PEAK_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": round(tf / FP4_PEAK_TFLOPS, 4),
+                                    "ms_per_step": round(kp["total_ms"] / args.steps, 3)}
+            if kt and kt["total_ms"] > 0:
+                gb = trsm_bytes / (kt["total_ms"] / args.steps * 1e-3) / 1e9
+                roofline_trsm = {"kernel": "k_trsm_pair sweeps with the k_trsm128 block solves", "bound": "hbm",
+                                 "achieved": round(gb, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                 "frac": round(gb / HBM_PEAK_GBPS, 4), "alg_bytes_per_step": trsm_bytes,
+                                 "ms_per_step": round(kt["total_ms"] / args.steps, 3)}
         log("profiled: %s" % json.dumps(kernels))
+
+    # Algorithm 2 alone on the same matrix in the same run: time and the
+    # update kernel's rate (the gf2_ple default, for comparison)
+    alg2 = None
+    if use_alg3:
+        ws2 = G.alloc_workspace(G.workspace_bytes(m, n, ldw))
+
+        def step2():
+            work.copy_(pristine)
+            return G.ple(work, n, ws=ws2, **sched)
+
+        step2()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            P2, Q2, rank2 = step2()
+        torch.cuda.synchronize()
+        ms2 = (time.perf_counter() - t0) * 1000.0 / args.steps
+        alg2 = {"ms_per_step": round(ms2, 3), "rank": int(rank2.item())}
+        log("Algorithm 2 alone: %d steps, %.3f ms/step" % (args.steps, ms2))
+        if not args.no_profile:
+            kinds2 = G.ple_schedule(m, n, lookahead=args.lookahead)
+            ab2 = alg_bytes_m4rm(m, n, Qh, r, kinds2)
+            G.profile_start()
+            for i in range(args.steps):
+                step2()
+            torch.cuda.synchronize()
+            k2 = G.profile_stop()
+            k = k2.get("m4rm")
+            if k and k["total_ms"] > 0:
+                lps = k["launches"] / args.steps
+                avg = k["total_ms"] / k["launches"]
+                ach = ab2 / lps / (avg * 1e-3) / 1e9
+                alg2["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                    "frac": round(ach / HBM_PEAK_GBPS, 4), "launches_per_step": lps,
+                                    "alg_bytes_per_launch": round(ab2 / lps), "avg_launch_ms": round(avg, 5)}
+            alg2["kernels_ms_per_step"] = {kk: round(v["total_ms"] / args.steps, 3) for kk, v in k2.items()}
+        del ws2
 
     alg3 = None
     if not args.no_alg3:
@@ -937,10 +1028,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "PLE of a dense %dx%d GF(2) matrix, Bernoulli(0.5), seed %d, uint64 row words"
                                % (m, n, args.seed),
-                   "m": m, "n": n, "pass_width_K": KW, "update": "xor-table",
+                   "m": m, "n": n, "pass_width_K": KW,
+                   "algorithm": ("Algorithm 3, one column split at %d: Algorithm 2 on the left block and on the "
+                                 "lower-right block, the triangular solve in 128-row blocks between them, the "
+                                 "Schur product on the fp4 matrix cores" % split) if use_alg3 else "Algorithm 2",
+                   "update": "xor-table",
                    "update_schedule": "pairs of passes: one sweep with 32 nibble tables x 32-word tiles, "
                                       "the next panel inside it; single passes past the last pair",
-                   "schedule": sched},
+                   "schedule": dict(sched, **rec)},
         "rank": r,
         "schedule": {"passes": len(kinds), "serial": kinds.count(0), "lookahead": kinds.count(1),
                      "fused_pairs": kinds.count(3)},
@@ -948,6 +1043,10 @@ def main():
         "k64_alg_bytes_per_step": abytes64,
         "k64_alg_GBps_whole_ple": round(abytes64 / (ms_per_step * 1e-3) / 1e9, 1),
         "roofline": roofline,
+        "roofline_product": roofline_product,
+        "roofline_trsm": roofline_trsm,
+        "left_rank": r1,
+        "alg2_same_run": alg2,
         "cpu_baseline": cpu,
         "configs": configs,
         "helpers": helpers,

@@ -381,7 +381,10 @@ gf2_status gf2_serve_destroy(gf2_serve *session);
  * the recorded events and writes up to max_entries per-kernel totals
  * (launch count, summed/min/max elapsed milliseconds) to `out` (host memory),
  * and the number of kernels seen to *count.  Process-wide; not for
- * concurrent use from several host threads.
+ * concurrent use from several host threads.  Names: "panel", "permute",
+ * "m4rm" (the Four-Russians updates), "init", "rref_block", "echelon",
+ * "mfma" (matrix-core products), "batch", "trsm" (Algorithm 3's triangular
+ * solve) and "transpose" (bit transpose of a product's right operand).
  */
 typedef struct gf2_kernel_time {
     char name[32];

@@ -309,7 +309,7 @@ hipError_t product(Ctx &c, uint64_t *A, int64_t crow0, int64_t M, int64_t kw0, i
 hipError_t trsm128(Ctx &c, uint64_t *A, int64_t j0, int nb, int64_t xw0, int64_t xw1) {
     const int64_t blocks = (xw1 - xw0 + 3) / 4;
     if (blocks <= 0 || nb <= 0) return hipSuccess;
-    ProfScope ps(KID_M4RM, c.s);
+    ProfScope ps(KID_TRSM, c.s);
     hipLaunchKernelGGL(k_trsm128, dim3((unsigned)blocks), dim3(256), 0, c.s, A, c.ldw, j0, nb, j0 >> 6, xw0, xw1);
     return hipGetLastError();
 }
@@ -335,7 +335,7 @@ hipError_t trsm_sweep(Ctx &c, uint64_t *A, int64_t j0, int nb, int64_t rb, int64
             nchunks = (int)nc;
         }
     }
-    ProfScope ps(KID_M4RM, c.s);
+    ProfScope ps(KID_TRSM, c.s);
     hipLaunchKernelGGL(k_trsm_pair, dim3((unsigned)(nt * nchunks)), dim3(1024), 0, c.s, A, c.ldw, j0, nb, j0 >> 6, rb,
                        re, xw0, xw1, nt, nchunks);
     return hipGetLastError();

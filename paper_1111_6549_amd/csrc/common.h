@@ -52,7 +52,19 @@ __host__ __device__ inline int64_t words_for(int64_t n) { return (n + 63) >> 6; 
 
 // Kernel timing: when enabled (gf2_profile_start), every launch site brackets
 // its kernel with HIP events on the launch stream.
-enum KernelId { KID_PANEL = 0, KID_PERMUTE, KID_M4RM, KID_INIT, KID_RREF, KID_ECHELON, KID_MFMA, KID_BATCH, KID_COUNT };
+enum KernelId {
+    KID_PANEL = 0,
+    KID_PERMUTE,
+    KID_M4RM,
+    KID_INIT,
+    KID_RREF,
+    KID_ECHELON,
+    KID_MFMA,
+    KID_BATCH,
+    KID_TRSM,
+    KID_TRANSPOSE,
+    KID_COUNT
+};
 bool prof_enabled();
 void prof_mark(int kid, hipStream_t s, bool begin);
 

@@ -408,7 +408,7 @@ hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int6
                                  hipStream_t s) {
     const int64_t blocks = (words_for(k) * words_for(n) + 3) / 4;
     if (blocks <= 0) return hipSuccess;
-    ProfScope ps(KID_MFMA, s);
+    ProfScope ps(KID_TRANSPOSE, s);
     hipLaunchKernelGGL(k_transpose_bits, dim3((unsigned)blocks), dim3(256), 0, s, B, ldb, k, n, Bt, ldbt);
     return hipGetLastError();
 }

@@ -23,7 +23,8 @@ std::atomic<bool> g_on{false};
 std::vector<Mark> g_marks;
 std::vector<hipEvent_t> g_pool;
 
-const char *kNames[KID_COUNT] = {"panel", "permute", "m4rm", "init", "rref_block", "echelon", "mfma", "batch"};
+const char *kNames[KID_COUNT] = {"panel", "permute", "m4rm",  "init",     "rref_block",
+                                 "echelon", "mfma",  "batch", "trsm", "transpose"};
 
 hipEvent_t take_event() {
     if (!g_pool.empty()) {
