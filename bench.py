@@ -710,7 +710,6 @@ def run_alg3(args, m, n, pristine, work, log_fn):
     out = {"ple": []}
     cfgs = [(1, 0, 0), (3, 1, 0), (2, 1, 0), (2, 2, 0), (4, 1, 0), (2, 1, 20480), (2, 1, 24576), (2, 1, 28672),
             (2, 16, 16384)]
-    cfgs += [(2, 16, s) for s in (8192, 12288, 16384, 24576) if s < n]
     for update, levels, split in cfgs:
         ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw, update=update, rec_levels=levels, rec_split=split))
         times = []
