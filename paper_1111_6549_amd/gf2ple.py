@@ -160,14 +160,26 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _packed(t, name):
+def _packed(t, name, whole_rows=False):
+    """Check a packed operand.  whole_rows: the call works on whole rows of
+    ldw words in place (the PLE family), so the tensor's rows must be its
+    memory rows (no view of a column block)."""
     if not isinstance(t, torch.Tensor) or t.dim() != 2 or t.dtype not in (torch.int64, torch.uint64):
         raise TypeError("%s must be a 2-D int64/uint64 tensor of packed rows" % name)
     if not t.is_cuda:
         raise ValueError("%s must be on the GPU" % name)
     if t.numel() and t.stride(1) != 1:
         raise ValueError("%s rows must be contiguous" % name)
+    if t.numel() and t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+        raise ValueError("%s rows overlap" % name)
+    if whole_rows and t.numel() and t.shape[0] > 1 and t.stride(0) != t.shape[1]:
+        raise ValueError("%s must be contiguous (the call works on whole rows of ldw words)" % name)
     return t
+
+
+def _ld(t):
+    """Row stride in words: the leading dimension the C ABI takes."""
+    return t.stride(0) if t.shape[0] > 1 else t.shape[1]
 
 
 def _ptr(t):
@@ -204,7 +216,7 @@ def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0,
 
     Returns (P, Q, rank) as device tensors (int64 [m], int64 [min(m, n)],
     int64 [1]).  A holds the clean L\\E afterwards."""
-    A = _packed(A, "A")
+    A = _packed(A, "A", whole_rows=True)
     m, ldw = A.shape
     lib = load()
     o = _opts(update, check_padding, rec_levels=rec_levels, m4_variant=m4_variant, m4_blocks=m4_blocks,
@@ -226,7 +238,7 @@ def ple_noalloc(A, n, lookahead=0, panel_regs=0):
     """In-place PLE of the packed (m, ldw) tensor A through gf2_ple_noalloc
     (the library's static device workspace instead of a caller buffer).
     Returns (P, Q, rank) as device tensors."""
-    A = _packed(A, "A")
+    A = _packed(A, "A", whole_rows=True)
     m, ldw = A.shape
     o = _opts(panel_regs=panel_regs, lookahead=lookahead)
     P = torch.empty(m, dtype=torch.int64, device=A.device)
@@ -250,13 +262,13 @@ def ple_schedule(m, n, lookahead=0):
 
 
 def echelon_from_ple(A, n, rank):
-    A = _packed(A, "A")
+    A = _packed(A, "A", whole_rows=True)
     m, ldw = A.shape
     _check(load().gf2_echelon_from_ple(_ptr(A), m, n, ldw, _ptr(rank), _stream()), "gf2_echelon_from_ple")
 
 
 def rref_from_ple(A, n, Q, rank, ws=None):
-    A = _packed(A, "A")
+    A = _packed(A, "A", whole_rows=True)
     m, ldw = A.shape
     lib = load()
     need = int(lib.gf2_rref_workspace_bytes(m, n, ldw))
@@ -268,7 +280,7 @@ def rref_from_ple(A, n, Q, rank, ws=None):
 
 def rref(A, n, ws=None, update=0):
     """In-place RREF (via PLE).  Returns (P, Q, rank)."""
-    A = _packed(A, "A")
+    A = _packed(A, "A", whole_rows=True)
     m, ldw = A.shape
     lib = load()
     o = _opts(update)
@@ -285,7 +297,7 @@ def rref(A, n, ws=None, update=0):
 
 def m4ri_rref(A, n, ws=None):
     """In-place RREF in the M4RI form.  Returns (Q, rank)."""
-    A = _packed(A, "A")
+    A = _packed(A, "A", whole_rows=True)
     m, ldw = A.shape
     lib = load()
     need = int(lib.gf2_m4ri_rref_workspace_bytes(m, n, ldw))
@@ -299,14 +311,16 @@ def m4ri_rref(A, n, ws=None):
 
 
 def addmul(C, A, B, k, n, update=0, m4_variant=0, m4_blocks=0):
-    """C ^= A * B over GF(2); A is m x k, B is k x n, all packed on the GPU."""
+    """C ^= A * B over GF(2); A is m x k, B is k x n, all packed on the GPU.
+    Each may be a view of a column block of a wider matrix (rows contiguous,
+    its row stride passed as the leading dimension)."""
     C, A, B = _packed(C, "C"), _packed(A, "A"), _packed(B, "B")
     m = C.shape[0]
     o = _opts(update, m4_variant=m4_variant, m4_blocks=m4_blocks)
     lib = load()
     need = int(lib.gf2_addmul_workspace_bytes(m, k, n, ctypes.byref(o)))
     ws = alloc_workspace(need, C.device) if need else None
-    _check(lib.gf2_addmul(_ptr(C), C.shape[1], _ptr(A), A.shape[1], _ptr(B), B.shape[1], m, k, n, _ptr(ws),
+    _check(lib.gf2_addmul(_ptr(C), _ld(C), _ptr(A), _ld(A), _ptr(B), _ld(B), m, k, n, _ptr(ws),
                           ws.numel() if ws is not None else 0, ctypes.byref(o), _stream()), "gf2_addmul")
 
 
@@ -315,12 +329,12 @@ def make_table(rows, k, n, T=None):
     rows = _packed(rows, "rows")
     if T is None:
         T = torch.empty((1 << k, rows.shape[1]), dtype=rows.dtype, device=rows.device)
-    _check(load().gf2_make_table(_ptr(rows), rows.shape[1], k, n, _ptr(T), T.shape[1], _stream()), "gf2_make_table")
+    _check(load().gf2_make_table(_ptr(rows), _ld(rows), k, n, _ptr(T), _ld(T), _stream()), "gf2_make_table")
     return T
 
 
 def check_padding(A, n):
-    A = _packed(A, "A")
+    A = _packed(A, "A", whole_rows=True)
     m, ldw = A.shape
     return int(load().gf2_check_padding(_ptr(A), m, n, ldw, _stream()))
 

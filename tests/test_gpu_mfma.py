@@ -47,3 +47,35 @@ def test_mfma_addmul_sparse_and_strided():
         tC = to_dev(C)
         G.addmul(tC, to_dev(A), to_dev(B), k, n, update=update)
         assert np.array_equal(to_host(tC), want), "update=%d" % update
+
+
+@pytest.mark.parametrize("off,ld_extra", [(3, 0), (4, 7), (4, 640)])
+def test_addmul_on_column_block_views(off, ld_extra):
+    """C, A and B as views of column blocks of wider matrices (row strides
+    of the wider matrices, even and odd; the view 16-byte aligned or not):
+    the product reads and writes only the views' words, for every product
+    kind."""
+    import torch
+    say("mfma addmul views", off, ld_extra)
+    m, k, n = 1500, 1100, 900
+    kw, nw = inputs.words(k), inputs.words(n)
+    C = inputs.bernoulli(m, n, 31)
+    A = inputs.bernoulli(m, k, 32)
+    B = inputs.bernoulli(k, n, 33)
+    want = C.copy()
+    oracle.addmul(want, A, B, k, n)
+    for update in (2, 4, 1):
+        # each operand sits at word offset `off` of a wider matrix filled with a marker
+        def wide(X, words):
+            W = np.full((X.shape[0], words + off + ld_extra), 0x5A5A5A5A5A5A5A5A, np.uint64)
+            W[:, off:off + X.shape[1]] = X
+            return to_dev(W)
+        tC, tA, tB = wide(C, nw), wide(A, kw), wide(B, nw)
+        G.addmul(tC[:, off:off + nw], tA[:, off:off + kw], tB[:, off:off + nw], k, n, update=update)
+        got = to_host(tC)
+        assert np.array_equal(got[:, off:off + nw], want), "update=%d" % update
+        assert np.all(got[:, :off] == 0x5A5A5A5A5A5A5A5A) and np.all(got[:, off + nw:] == 0x5A5A5A5A5A5A5A5A)
+        torch.cuda.synchronize()
+    # the in-place PLE works on whole rows: a column-block view is refused
+    with pytest.raises(ValueError):
+        G.ple(tC[:, off:off + nw], n)
