@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 FP4_PEAK_TFLOPS = 10100.0
+TRSM_BLOCK = 4096  # Algorithm 3's diagonal blocks of the solve with fp4 products (csrc/alg3.hip)
 KW = 64
 # HBM bytes per trailing-update launch on the 65536^2 seed-5 workload (the
 # default timed path: Algorithm 3 with one split at column 24576):
@@ -892,9 +893,18 @@ def main():
         abytes = (alg_bytes_m4rm(m, split, Qh[:r1], r1, kinds_l) +
                   alg_bytes_m4rm(m - r1, N, Qh[r1:r] - split, r - r1, kinds_r))
         kinds = kinds_l + kinds_r
+        # the solve as the library runs it with fp4 products: diagonal blocks
+        # of TRSM_BLOCK rows, each swept in 128-row blocks and then removed
+        # from the rows below by one product
         nwr = (N + 63) // 64
-        trsm_bytes = int(sum(16 * (r1 - b - 128) * nwr for b in range(0, r1, 128) if b + 128 < r1))
+        trsm_bytes = 0
         prod_flops = 2 * (m - r1) * r1 * N
+        for d0 in range(0, r1, TRSM_BLOCK):
+            d1 = min(r1, d0 + TRSM_BLOCK)
+            trsm_bytes += sum(16 * (d1 - b - 128) * nwr for b in range(d0, d1, 128) if b + 128 < d1)
+            if d1 < r1:
+                prod_flops += 2 * (r1 - d1) * (d1 - d0) * N
+        trsm_bytes = int(trsm_bytes)
     else:
         kinds = G.ple_schedule(m, n, lookahead=args.lookahead)
         abytes = alg_bytes_m4rm(m, n, Qh, r, kinds)
@@ -930,14 +940,17 @@ def main():
         if use_alg3:
             kp, kt = kernels.get("mfma"), kernels.get("trsm")
             if kp and kp["total_ms"] > 0:
-                tf = prod_flops * kp["launches"] / args.steps / (kp["total_ms"] / args.steps * 1e-3) / 1e12
-                roofline_product = {"kernel": "k_mfma_gf2_fp4 (the Schur product, %d x %d x %d)" % (m - r1, r1, n - split),
+                tf = prod_flops / (kp["total_ms"] / args.steps * 1e-3) / 1e12  # every product of a step
+                roofline_product = {"kernel": "k_mfma_gf2_fp4 (the Schur product, %d x %d x %d, and the solve's "
+                                              "products between its diagonal blocks)" % (m - r1, r1, n - split),
                                     "bound": "mfma", "achieved": round(tf, 1), "peak": FP4_PEAK_TFLOPS,
                                     "unit": "TFLOP/s", "frac": round(tf / FP4_PEAK_TFLOPS, 4),
+                                    "launches_per_step": kp["launches"] / args.steps, "flops_per_step": prod_flops,
                                     "ms_per_step": round(kp["total_ms"] / args.steps, 3)}
             if kt and kt["total_ms"] > 0:
                 gb = trsm_bytes / (kt["total_ms"] / args.steps * 1e-3) / 1e9
-                roofline_trsm = {"kernel": "k_trsm_pair sweeps with the k_trsm128 block solves", "bound": "hbm",
+                roofline_trsm = {"kernel": "k_trsm_pair sweeps inside the diagonal blocks, with the k_trsm128 "
+                                           "block solves", "bound": "hbm",
                                  "achieved": round(gb, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                                  "frac": round(gb / HBM_PEAK_GBPS, 4), "alg_bytes_per_step": trsm_bytes,
                                  "ms_per_step": round(kt["total_ms"] / args.steps, 3)}

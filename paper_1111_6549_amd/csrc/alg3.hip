@@ -8,7 +8,9 @@
 //      rows, so the right block A1 ends up with its rows permuted (P1^T A1);
 //   2. A01 <- L00^-1 A01 on the first r1 rows of A1 (triangular solve, in
 //      blocks of 128 rows: each block's own forward substitution, then one
-//      Four-Russians sweep that removes the block from every row below it);
+//      Four-Russians sweep that removes the block from every row below it;
+//      with fp4 products, in diagonal blocks of 4096 rows solved that way,
+//      each removed from the rows below by one product);
 //   3. A11 <- A11 + L10 A01 (the product that Algorithm 3 hands to matrix
 //      multiplication);
 //   4. PLE of A11 (rows r1.., columns n1..), again moving whole rows, so the
@@ -341,15 +343,35 @@ hipError_t trsm_sweep(Ctx &c, uint64_t *A, int64_t j0, int nb, int64_t rb, int64
     return hipGetLastError();
 }
 
-// rows [0, r) of X = A[.][xw0, xw1) <- L^-1 X, with L the unit lower
-// triangle of A[0 .. r)[0 .. r): 128-row blocks in order, each solved on its
-// own and then removed from the rows below it in one sweep
-hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1) {
+// rows [d0, d1) of X = A[.][xw0, xw1) <- L^-1 X, with L the unit lower
+// triangle of A[d0 .. d1)[d0 .. d1) (d0 a multiple of 128): 128-row blocks
+// in order, each solved on its own and then removed from the rows below it
+// (up to d1) in one sweep
+hipError_t trsm_diag(Ctx &c, uint64_t *A, int64_t d0, int64_t d1, int64_t xw0, int64_t xw1) {
     hipError_t e;
-    for (int64_t b = 0; b < r; b += 128) {
-        const int nb = (int)(r - b < 128 ? r - b : 128);
+    for (int64_t b = d0; b < d1; b += 128) {
+        const int nb = (int)(d1 - b < 128 ? d1 - b : 128);
         if ((e = trsm128(c, A, b, nb, xw0, xw1)) != hipSuccess) return e;
-        if ((e = trsm_sweep(c, A, b, nb, b + nb, r, xw0, xw1)) != hipSuccess) return e;
+        if ((e = trsm_sweep(c, A, b, nb, b + nb, d1, xw0, xw1)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// With fp4 products, diagonal blocks of this many rows: each is solved by
+// the sweeps above, then removed from every row below it by one product
+// (inner size TRSM_BLOCK) instead of TRSM_BLOCK / 128 sweeps.  (The int8
+// product is too slow at this inner size to gain from it.)
+constexpr int64_t TRSM_BLOCK = 4096;
+
+// rows [0, r) of X = A[.][xw0, xw1) <- L^-1 X, with L the unit lower
+// triangle of A[0 .. r)[0 .. r)
+hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1, int64_t N) {
+    if (!c.mfma || c.fmt != 0) return trsm_diag(c, A, 0, r, xw0, xw1);
+    hipError_t e;
+    for (int64_t d0 = 0; d0 < r; d0 += TRSM_BLOCK) {
+        const int64_t d1 = r - d0 < TRSM_BLOCK ? r : d0 + TRSM_BLOCK;
+        if ((e = trsm_diag(c, A, d0, d1, xw0, xw1)) != hipSuccess) return e;
+        if (d1 < r && (e = product(c, A, d1, r - d1, d0 >> 6, d1 - d0, d0, xw0, xw1, N)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -368,7 +390,7 @@ hipError_t ple_rec(Ctx &c, uint64_t *A, int64_t m, int64_t n, int64_t *P, int64_
     if ((e = hipStreamSynchronize(c.s)) != hipSuccess) return e;
     const int64_t xw0 = n1 >> 6, xw1 = words_for(n), N = n - n1;
     if (r1 > 0) {
-        if ((e = trsm(c, A, r1, xw0, xw1)) != hipSuccess) return e;
+        if ((e = trsm(c, A, r1, xw0, xw1, N)) != hipSuccess) return e;
         if ((e = product(c, A, r1, m - r1, 0, r1, 0, xw0, xw1, N)) != hipSuccess) return e;
     }
     if (m <= r1) return hipSuccess;  // then min(m, n) = r1: P and Q are complete

@@ -390,12 +390,14 @@ def test_alg3_parity(m, n, kind, update):
 
 @pytest.mark.parametrize("update", [2, 3, 4])
 @pytest.mark.parametrize("m,n,kind,levels", [(3000, 2500, "u", 2), (2500, 3000, "deficient_left", 3),
-                                             (4096, 4096, "u", 3), (2000, 2000, "s", 4), (8192, 8192, "u", 1)])
+                                             (4096, 4096, "u", 3), (2000, 2000, "s", 4), (8192, 8192, "u", 1),
+                                             (12000, 12000, "u", 1)])
 def test_alg3_levels_parity(m, n, kind, levels, update):
     """Several levels of Algorithm 3 (each half recursed again) against the
     oracle, with fp4 (2) and int8 (4) matrix-core products and table products
     (3); 8192^2 takes the matrix-core path for its products of 512 inner bits
-    and more."""
+    and more; 12000^2 (left rank 6016) solves in two diagonal blocks, the
+    first removed from the second by a product."""
     say("alg3 levels", update, m, n, kind, levels)
     A = _alg3_case(kind, m, n)
     assert_same_ple(gpu_ple(A, n, update=update, rec_levels=levels), oracle_ple(A, n),
@@ -406,7 +408,7 @@ def test_alg3_levels_parity(m, n, kind, levels, update):
 @pytest.mark.parametrize("m,n,kind,levels,split", [(3000, 2500, "u", 16, 512), (2500, 3000, "deficient_left", 16, 640),
                                                    (4096, 4096, "u", 3, 1024), (2000, 2000, "s", 16, 256),
                                                    (1500, 4000, "zero_left", 16, 768), (6000, 6000, "u", 16, 1536),
-                                                   (1200, 1100, "r", 2, 320)])
+                                                   (1200, 1100, "r", 2, 320), (12000, 11000, "u", 1, 5120)])
 def test_alg3_strips_parity(m, n, kind, levels, split, update):
     """Algorithm 3 with left strips of `split` columns (each a leaf), the
     splits going on in the right block while levels remain, against the
