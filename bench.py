@@ -804,6 +804,8 @@ def main():
     ap.add_argument("--alg", type=int, default=3, choices=(2, 3),
                     help="timed path: 3 = Algorithm 3 with one column split (default), 2 = Algorithm 2 alone "
                          "(the gf2_ple default)")
+    ap.add_argument("--no-alg2", action="store_true",
+                    help="skip timing Algorithm 2 alone beside the Algorithm 3 path (for profiler runs)")
     ap.add_argument("--rec-split", type=int, default=0,
                     help="Algorithm 3's left block in columns (a multiple of 64; 0 = 3/8 of n)")
     ap.add_argument("--no-alg3", action="store_true", help="skip Algorithm 3 and the product comparison")
@@ -959,7 +961,7 @@ def main():
     # Algorithm 2 alone on the same matrix in the same run: time and the
     # update kernel's rate (the gf2_ple default, for comparison)
     alg2 = None
-    if use_alg3:
+    if use_alg3 and not args.no_alg2:
         ws2 = G.alloc_workspace(G.workspace_bytes(m, n, ldw))
 
         def step2():
