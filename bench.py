@@ -800,7 +800,7 @@ def main():
     ap.add_argument("--panel-regs", type=int, default=0, help="panel register window 2/4/8 (0 = default)")
     ap.add_argument("--lookahead", type=int, default=0,
                     help="0 = library default, 1 = serial passes, 2 = look-ahead only, 3 = pairs everywhere")
-    ap.add_argument("--pair-variant", type=int, default=0, help="fused pair update schedule 1..12 (0 = default)")
+    ap.add_argument("--pair-variant", type=int, default=0, help="fused pair update schedule 1..14 (0 = default)")
     ap.add_argument("--alg", type=int, default=3, choices=(2, 3),
                     help="timed path: 3 = Algorithm 3 with one column split (default), 2 = Algorithm 2 alone "
                          "(the gf2_ple default)")

@@ -66,7 +66,9 @@ typedef struct gf2_ple_opts {
                               1 = serial passes only; 2 = look-ahead on every pass (next panel on a second
                               stream beside the update), no pairs; 3 = pairs on every pass */
     int32_t pair_variant;  /* schedule of the fused pair update: 0 = default; 1..12 = a fixed (threads, rows in
-                              flight, table reads per group, coefficient prefetch) */
+                              flight, table reads per group, coefficient prefetch); 13 / 14 = the default
+                              schedule with the next panel always / never in a block of its own (the
+                              default gives it one when the sweep is short) */
     int32_t rec_split;     /* update = 2, 3 or 4: 0 = split each block's columns in halves (both halves
                               recurse); > 0 (a multiple of 64) = the left block of every split is a strip of
                               rec_split columns done by Algorithm 2, and the splits go on in the right block

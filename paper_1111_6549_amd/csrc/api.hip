@@ -434,7 +434,7 @@ gf2_status ple_check_args(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, 
     if (opts && opts->panel_regs != 0 && opts->panel_regs != 2 && opts->panel_regs != 4 && opts->panel_regs != 8)
         return GF2_EINVAL;
     if (opts && (opts->lookahead < 0 || opts->lookahead > 3)) return GF2_EINVAL;
-    if (opts && (opts->pair_variant < 0 || opts->pair_variant > 12)) return GF2_EINVAL;
+    if (opts && (opts->pair_variant < 0 || opts->pair_variant > 14)) return GF2_EINVAL;
     return GF2_OK;
 }
 

@@ -394,17 +394,19 @@ __global__ __launch_bounds__(NT) void k_m4rm_w(uint64_t *__restrict__ C, int64_t
 // Tiles of 32 words; 16 lanes per row, two words per lane, 128-bit table
 // reads; 128 KB of tables per block.
 //
-// The panel of pass t + 2 runs inside the same launch, on the last wave of
-// block 0 (raised priority), once the block's tables are built: its stripe
-// word lies left of the words this sweep writes, so the two are independent,
-// and no event between two streams is needed to order them.  That block's
-// row chunk is shortened to the share its other waves can do in the time the
-// other blocks take.
+// The panel of pass t + 2 runs inside the same launch: its stripe word lies
+// left of the words this sweep writes, so the two are independent, and no
+// event between two streams is needed to order them.  It runs either on the
+// last wave of block 0 (raised priority), once the block's tables are built,
+// that block's row chunk shortened to the share its other waves can do in
+// the time the other blocks take, or (pp.share < 0) in a block of its own.
 // ---------------------------------------------------------------------------
 constexpr int PR_TW = 32;
 // kept rows of the slow search of the panel inside the pair update that fit
 // in the LDS beside the 128 KB of tables
 constexpr int PAIR_PANEL_ROWS = 1536;
+// sweeps estimated shorter than this (us) give the panel a block of its own
+constexpr double PAIR_OWN_PANEL_US = 30.0;
 
 template <int BASE, int NT>
 __device__ __forceinline__ void pair_combos(uint64_t (*T)[16][PR_TW], int tid) {
@@ -460,8 +462,11 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
     __shared__ __align__(16) uint64_t T[32][16][PR_TW];
     __shared__ PanelLdsT<PAIR_PANEL_ROWS> PL;
     const int tid = threadIdx.x;
-    const int logical = xcd_logical(blockIdx.x, gridDim.x);
-    const bool panel_here = pp.on && logical == 0;
+    // share < 0: the panel has a block of its own (logical block 0, one
+    // extra block in the grid), and the sweep's blocks are the rest
+    const bool own = pp.on && pp.share < 0;
+    const int logical = xcd_logical(blockIdx.x, gridDim.x) - (own ? 1 : 0);
+    const bool panel_here = pp.on && logical == (own ? -1 : 0);
     // pass t + 2's panel: the pair's special rows' words in its stripe come
     // from the second pass's record
     auto run_panel = [&]() {
@@ -470,12 +475,16 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
         f.mode = 1;
         panel_body<2, PAIR_PANEL_ROWS>(C, m, pp.n, ldc, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank, pp.gsv, pp.gsid, PL, tid & 63, f);
     };
+    if (own && panel_here) {
+        if (tid < 64) run_panel();
+        return;
+    }
     const int at = rect->active, au = recu->active;
     const int nbt = at ? rect->rbar : 0, nbu = au ? recu->rbar : 0;
     int tile = 0;
     int64_t rb = 0, re = 0;
     const bool rows_here =
-        (at || au) && pair_block_rows(m, rect->r, ntiles, nchunks, logical, pp.on, pp.share, &tile, &rb, &re);
+        (at || au) && pair_block_rows(m, rect->r, ntiles, nchunks, logical, pp.on && !own, pp.share, &tile, &rb, &re);
     if (!rows_here) {
         if (panel_here && tid < 64) run_panel();
         return;
@@ -974,12 +983,18 @@ hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, in
     if (rows_est < 1) rows_est = 1;
     const int64_t base = tw0 & ~(int64_t)(PR_TW - 1);
     const int nt = (int)((nw - base + PR_TW - 1) / PR_TW);
+    // The next panel gets a block (a CU) of its own when the sweep is short:
+    // the panel then starts at once, alone on its CU, instead of after block
+    // 0's tables and beside its sweep (about 25 us there), which is most of
+    // such a launch.  Variants 13 and 14 force the two forms.
+    const double upd_us = (double)rows_est * (double)(nw - tw0) * 16.0 / 3.3e6;
+    const bool own = pp.on && (pair_variant == 13 || (pair_variant != 14 && upd_us < PAIR_OWN_PANEL_US));
     int nchunks = 1;
     if (m4_target > 0) {
         nchunks = (m4_target + nt - 1) / nt;
     } else {
-        // whole rounds of one block per CU
-        const int64_t slots = device_cus();
+        // whole rounds of one block per CU (less the panel's)
+        const int64_t slots = device_cus() - (own ? 1 : 0);
         int64_t maxc = rows_est / 256;
         if (maxc < 1) maxc = 1;
         if (maxc > 4 * slots) maxc = 4 * slots;
@@ -999,18 +1014,20 @@ hipError_t launch_update_pair(uint64_t *A, int64_t m, int64_t n, int64_t ldw, in
     // chunk is the rest (about 25 us of panel against an update streaming
     // its bytes at about 3.3 TB/s)
     PairPanel ppl = pp;
-    if (pp.on) {
-        const double upd_us = (double)rows_est * (double)(nw - tw0) * 16.0 / 3.3e6;
+    if (own) {
+        ppl.share = -1;
+    } else if (pp.on) {
         const double busy = upd_us > 0.0 ? (25.0 / upd_us < 1.0 ? 25.0 / upd_us : 1.0) : 1.0;
         ppl.share = (int)(65536.0 * (16.0 - busy) / 16.0);
     }
+    const unsigned grid = (unsigned)(nt * nchunks + (own ? 1 : 0));
     ProfScope ps(KID_M4RM, s);
 #define PAIR_LAUNCH(NT, U, G, PF)                                                                                 \
-    hipLaunchKernelGGL((k_m4rm_pair<NT, U, G, PF>), dim3(nt * nchunks), dim3(NT), 0, s, A, ldw, m, coefP, coefU,    \
-                       coefT, PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu, ppl)
+    hipLaunchKernelGGL((k_m4rm_pair<NT, U, G, PF>), dim3(grid), dim3(NT), 0, s, A, ldw, m, coefP, coefU, coefT,     \
+                       PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu, ppl)
 #define PAIR_LAUNCH_RP(NT, G)                                                                                     \
-    hipLaunchKernelGGL((k_m4rm_pair<NT, 1, G, true, true>), dim3(nt * nchunks), dim3(NT), 0, s, A, ldw, m, coefP,   \
-                       coefU, coefT, PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu, ppl)
+    hipLaunchKernelGGL((k_m4rm_pair<NT, 1, G, true, true>), dim3(grid), dim3(NT), 0, s, A, ldw, m, coefP, coefU,    \
+                       coefT, PBt, PBu, ldw, tw0, nw, nt, nchunks, rect, recu, ppl)
     // (threads, rows in flight per thread, table reads per group, coefficient
     // prefetch[, row prefetch]); the default was the fastest on MI355X for the
     // 65536^2 PLE

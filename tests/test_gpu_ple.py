@@ -322,13 +322,13 @@ def test_lookahead_16384_seed2():
         assert_same_ple(gpu_ple(A, 16384, lookahead=mode), serial, "lookahead=%d" % mode)
 
 
-@pytest.mark.parametrize("variant", list(range(0, 13)))
+@pytest.mark.parametrize("variant", list(range(0, 15)))
 def test_pair_variants(variant):
     """Every schedule of the fused pair update (threads, rows in flight,
     reads per group, coefficient prefetch; the next panel inside the same
-    launch) gives the oracle's bits, with pairs forced on every pass, on
-    full-rank, rank-deficient and ragged (n not a multiple of the tile)
-    inputs."""
+    launch, beside the sweep or in a block of its own) gives the oracle's
+    bits, with pairs forced on every pass, on full-rank, rank-deficient and
+    ragged (n not a multiple of the tile) inputs."""
     say("pair variant", variant)
     cases = [(1500, 1300, "u"), (2100, 2100, "r"), (700, 2000, "u"), (3000, 1111, "s")]
     for m, n, kind in cases:
