@@ -709,22 +709,28 @@ def run_alg3(args, m, n, pristine, work, log_fn):
     from paper_1111_6549_amd import inputs
     ldw = inputs.words(n)
     out = {"ple": []}
-    cfgs = [(1, 0, 0), (3, 1, 0), (2, 1, 0), (2, 2, 0), (4, 1, 0), (2, 1, 20480), (2, 1, 24576), (2, 1, 28672),
-            (2, 16, 16384)]
-    for update, levels, split in cfgs:
-        ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw, update=update, rec_levels=levels, rec_split=split))
+    # (update, levels, split, Strassen's split of the fp4 products: 0 default, -1 none)
+    cfgs = [(1, 0, 0, 0), (3, 1, 0, 0), (2, 1, 0, 0), (2, 2, 0, 0), (4, 1, 0, 0), (2, 1, 20480, 0), (2, 1, 24576, 0),
+            (2, 1, 24576, -1), (2, 1, 28672, 0), (2, 16, 16384, 0)]
+    for update, levels, split, psplit in cfgs:
+        ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw, update=update, rec_levels=levels, rec_split=split,
+                                                 product_split=psplit))
         times = []
         for rep in range(3):
             work.copy_(pristine)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            P, Q, rank = G.ple(work, n, ws=ws, update=update, rec_levels=levels, rec_split=split)
+            P, Q, rank = G.ple(work, n, ws=ws, update=update, rec_levels=levels, rec_split=split,
+                               product_split=psplit)
             torch.cuda.synchronize()
             if rep:
                 times.append((time.perf_counter() - t0) * 1000.0)
         pt = {"update": update, "products": {1: "none (Algorithm 2)", 2: "fp4 matrix cores",
                                              3: "Four-Russians tables", 4: "int8 matrix cores"}[update],
               "levels": levels, "split": split or "halves", "ms": round(min(times), 3), "rank": int(rank.item())}
+        if update == 2:
+            pt["product_split"] = {0: "default (one Strassen level on products of at least 8192 bits a side)",
+                                   -1: "none"}[psplit]
         out["ple"].append(pt)
         log_fn("alg3: %s" % json.dumps(pt))
         del ws
@@ -806,6 +812,8 @@ def main():
                          "(the gf2_ple default)")
     ap.add_argument("--no-alg2", action="store_true",
                     help="skip timing Algorithm 2 alone beside the Algorithm 3 path (for profiler runs)")
+    ap.add_argument("--product-split", type=int, default=0, choices=(-1, 0, 1),
+                    help="Strassen's split of the fp4 products on the timed path (0 = library default)")
     ap.add_argument("--rec-split", type=int, default=0,
                     help="Algorithm 3's left block in columns (a multiple of 64; 0 = 3/8 of n)")
     ap.add_argument("--no-alg3", action="store_true", help="skip Algorithm 3 and the product comparison")
@@ -857,7 +865,7 @@ def main():
     # product (fp4 matrix cores) between them
     split = (args.rec_split or (3 * n // 8)) // 64 * 64
     use_alg3 = args.alg == 3 and 64 <= split < n
-    rec = dict(update=2, rec_levels=1, rec_split=split) if use_alg3 else {}
+    rec = dict(update=2, rec_levels=1, rec_split=split, product_split=args.product_split) if use_alg3 else {}
     ws = G.alloc_workspace(G.workspace_bytes(m, n, ldw, **rec))
     torch.cuda.synchronize()
 
@@ -900,12 +908,20 @@ def main():
         # from the rows below by one product
         nwr = (N + 63) // 64
         trsm_bytes = 0
-        prod_flops = 2 * (m - r1) * r1 * N
+        # each product's 2 M K N operations, and those the matrix cores run
+        # by the library's plan for it (seven half-size products when it
+        # takes Strassen's split)
+        prod_list = [(m - r1, r1)]
         for d0 in range(0, r1, TRSM_BLOCK):
             d1 = min(r1, d0 + TRSM_BLOCK)
             trsm_bytes += sum(16 * (d1 - b - 128) * nwr for b in range(d0, d1, 128) if b + 128 < d1)
             if d1 < r1:
-                prod_flops += 2 * (r1 - d1) * (d1 - d0) * N
+                prod_list.append((r1 - d1, d1 - d0))
+        prod_flops = sum(2 * M * K * N for M, K in prod_list)
+        prod_mfma_flops = 0
+        for M, K in prod_list:
+            steps_, _ = G.product_plan(M, K, 64 * nwr, args.product_split)
+            prod_mfma_flops += sum(2 * b[0][4] * b[0][5] * b[1][4] for kind, b in steps_ if kind == 1)
         trsm_bytes = int(trsm_bytes)
     else:
         kinds = G.ple_schedule(m, n, lookahead=args.lookahead)
@@ -942,12 +958,16 @@ def main():
         if use_alg3:
             kp, kt = kernels.get("mfma"), kernels.get("trsm")
             if kp and kp["total_ms"] > 0:
-                tf = prod_flops / (kp["total_ms"] / args.steps * 1e-3) / 1e12  # every product of a step
+                sec = kp["total_ms"] / args.steps * 1e-3  # every product of a step
+                tf = prod_mfma_flops / sec / 1e12
                 roofline_product = {"kernel": "k_mfma_gf2_fp4 (the Schur product, %d x %d x %d, and the solve's "
                                               "products between its diagonal blocks)" % (m - r1, r1, n - split),
                                     "bound": "mfma", "achieved": round(tf, 1), "peak": FP4_PEAK_TFLOPS,
                                     "unit": "TFLOP/s", "frac": round(tf / FP4_PEAK_TFLOPS, 4),
-                                    "launches_per_step": kp["launches"] / args.steps, "flops_per_step": prod_flops,
+                                    "launches_per_step": kp["launches"] / args.steps,
+                                    "flops_per_step": prod_mfma_flops,
+                                    "classical_flops_per_step": prod_flops,
+                                    "classical_equivalent_tflops": round(prod_flops / sec / 1e12, 1),
                                     "ms_per_step": round(kp["total_ms"] / args.steps, 3)}
             if kt and kt["total_ms"] > 0:
                 gb = trsm_bytes / (kt["total_ms"] / args.steps * 1e-3) / 1e9

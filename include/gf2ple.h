@@ -73,6 +73,9 @@ typedef struct gf2_ple_opts {
                               recurse); > 0 (a multiple of 64) = the left block of every split is a strip of
                               rec_split columns done by Algorithm 2, and the splits go on in the right block
                               while levels remain and it is wider than rec_split */
+    int32_t product_split; /* update = 2: Strassen's split of the fp4 products (see gf2_product_plan):
+                              0 = default (one level on products whose three sizes are all at least
+                              GF2_PLAN_MIN_BITS), 1 = one level on every product the split allows, -1 = none */
 } gf2_ple_opts;
 
 /* Library version string, e.g. "gf2ple 0.1.0 gfx950". */
@@ -149,6 +152,42 @@ gf2_status gf2_ple_noalloc(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64
  * serially instead.)
  */
 int64_t gf2_ple_schedule(int64_t m, int64_t n, const gf2_ple_opts *opts, int32_t *kinds, int64_t max);
+
+/* A block of a product plan step: rows [row0, row0 + rows) and bits [0, bits) starting at word word0 of
+ * a buffer whose rows are ld words apart.  buf: 0 = the left operand A, 1 = the bit transpose of the
+ * right operand B (one row per column of B, zero past the inner size), 2 = the result C, 3 = the
+ * plan's workspace (row0 = 0, word0 = the block's offset in words).  rows = 0: no block. */
+typedef struct {
+    int64_t buf, row0, word0, ld, rows, bits;
+} gf2_plan_block;
+
+/* A step.  kind 0, a sum: b[0] = b[1] ^ b[2] over b[0]'s rows and bits, b[1] and b[2] read as zero
+ * outside their own rows and bits.  kind 1, a product: the product of b[0] (rows x inner size
+ * b[0].bits) and the matrix whose bit transpose is b[1] (b[1].rows columns) is added to b[2] and,
+ * if b[3].rows > 0, to b[3], each over its own rows and bits (at most the product's). */
+typedef struct {
+    int64_t kind;
+    gf2_plan_block b[4];
+} gf2_plan_step;
+
+#define GF2_PLAN_MIN_BITS 8192
+#define GF2_PLAN_MAX_STEPS 17
+
+/*
+ * The plan by which gf2_ple (update = 2, Algorithm 3 of Section 3.3) adds a product C (m x n) ^= A (m x k)
+ * * B (k x n) on the fp4 matrix cores (host only, no device call).  Section 3.3 notes that the paper's
+ * implementation multiplies by Strassen-Winograd; with split = 1 (or 0 and all three sizes at least
+ * GF2_PLAN_MIN_BITS, and n a multiple of 64) the plan is one level of Strassen's split: C, A and B in
+ * 2 x 2 blocks (rows of A and C split at a multiple of 256 near the middle, the inner size at an even
+ * number of words, the columns at a multiple of 256 bits), ten block sums in the workspace, then
+ * seven products of half size, each added to one or two blocks of C.  Over GF(2) every sign of
+ * Strassen's formulas is a plus.  Otherwise (split = -1, or sizes too small to split) the plan is one
+ * product.  lda, ldbt, ldc fill the ld of the blocks in buffers 0, 1, 2.  Writes up to max steps
+ * (at most GF2_PLAN_MAX_STEPS) and *ws_words (the workspace in 8-byte words); returns the number of
+ * steps, or -1 for invalid arguments.
+ */
+int64_t gf2_product_plan(int64_t m, int64_t k, int64_t n, int32_t split, int64_t lda, int64_t ldbt, int64_t ldc,
+                         gf2_plan_step *steps, int64_t max, int64_t *ws_words);
 
 /* Echelon form from a PLE result (Section 2, row echelon form): in place,
  * A <- E: rows i < r keep columns >= i (their L part is cleared), rows
@@ -386,7 +425,8 @@ gf2_status gf2_serve_destroy(gf2_serve *session);
  * concurrent use from several host threads.  Names: "panel", "permute",
  * "m4rm" (the Four-Russians updates), "init", "rref_block", "echelon",
  * "mfma" (matrix-core products), "batch", "trsm" (Algorithm 3's triangular
- * solve) and "transpose" (bit transpose of a product's right operand).
+ * solve), "transpose" (bit transpose of a product's right operand) and "sums" (the block sums of
+ * Strassen's split of a product).
  */
 typedef struct gf2_kernel_time {
     char name[32];

@@ -17,7 +17,7 @@ size_t ple_workspace_total(int64_t m, int64_t ldw);
 // Extra workspace of the recursion beyond the pass loop's, for an m x n
 // matrix: the sub-ranks and, with matrix-core products, the bit transpose of
 // the largest product's right operand.
-size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma, int64_t split);
+size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma, int64_t split, int psplit);
 
 // Algorithm 3 with `levels` levels of column splits (then Algorithm 2):
 // products on the Four-Russians tables (products = 0), the fp4 matrix cores
@@ -25,7 +25,14 @@ size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma
 // split > 0: a left strip of `split` columns (a leaf) and the recursion in
 // the right block.  Synchronises the stream once per split (to size the
 // products by the left block's rank).
+// psplit: Strassen's split of the fp4 products (gf2_ple_opts.product_split).
 hipError_t ple_alg3(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
-                    const gf2_ple_opts *opts, hipStream_t s, int levels, int products, int64_t split);
+                    const gf2_ple_opts *opts, hipStream_t s, int levels, int products, int64_t split, int psplit);
+
+// The steps of an m x k x n product C ^= A B on the fp4 matrix cores: one
+// product, or one level of Strassen's split (gf2_product_plan).
+int64_t product_plan(int64_t m, int64_t k, int64_t n, int split, int64_t lda, int64_t ldbt, int64_t ldc,
+                     gf2_plan_step *st, int64_t max, int64_t *ws_words);
+int64_t product_plan_ws_bound(int64_t m, int64_t k, int64_t n);
 
 }  // namespace gf2

@@ -35,7 +35,161 @@ hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int6
                                  hipStream_t s);
 hipError_t launch_mfma_gf2(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *Bt, int64_t ldbt,
                            int64_t m, int64_t k, int64_t n, hipStream_t s, int fmt);
+hipError_t launch_fp4_product2(uint64_t *C0, int64_t ldc0, int64_t rows0, int64_t words0, uint64_t *C1, int64_t ldc1,
+                               int64_t rows1, int64_t words1, const uint64_t *A, int64_t lda, const uint64_t *Bt,
+                               int64_t ldbt, int64_t m, int64_t k, int64_t n, hipStream_t s);
 int device_cu_count();
+
+// ---------------------------------------------------------------------------
+// Strassen's split of a product (the paper's implementation multiplies by
+// Strassen-Winograd, Section 3.3).  Over GF(2) every sign in Strassen's
+// seven products is a plus:
+//   P1 = (A11 + A22)(B11 + B22) -> C11, C22     P5 = (A11 + A12) B22 -> C11, C12
+//   P2 = (A21 + A22) B11        -> C21, C22     P6 = (A21 + A11)(B11 + B12) -> C22
+//   P3 = A11 (B12 + B22)        -> C12, C22     P7 = (A12 + A22)(B21 + B22) -> C11
+//   P4 = A22 (B21 + B11)        -> C11, C21
+// The blocks need not be equal: the second row / inner / column part may be
+// smaller, and reads as zero where it is shorter (A12, A22 and B21, B22 have
+// K2 < K1 inner bits; A21, A22 have m2 <= m1 rows; B12, B22 have N2 <= N1
+// columns).  A product then runs over the sizes its outputs need: P4 over
+// the m2 rows and K2 inner bits of A22 (so B21 + B11 is cut to K2 bits, the
+// A row's bits past K2 meeting zeros), P5 and P7 over K2 bits, P6 over the
+// m2 x N2 block of C22 only.
+// ---------------------------------------------------------------------------
+namespace {
+gf2_plan_block pblk(int64_t buf, int64_t row0, int64_t word0, int64_t ld, int64_t rows, int64_t bits) {
+    gf2_plan_block b;
+    b.buf = buf;
+    b.row0 = row0;
+    b.word0 = word0;
+    b.ld = ld;
+    b.rows = rows;
+    b.bits = bits;
+    return b;
+}
+const gf2_plan_block NO_BLOCK = pblk(0, 0, 0, 0, 0, 0);
+}  // namespace
+
+int64_t product_plan(int64_t m, int64_t k, int64_t n, int split, int64_t lda, int64_t ldbt, int64_t ldc,
+                     gf2_plan_step *st, int64_t max, int64_t *ws_words) {
+    if (m < 0 || k < 0 || n < 0 || split < -1 || split > 1 || lda < 0 || ldbt < 0 || ldc < 0 || max < 0 ||
+        (max > 0 && !st))
+        return -1;
+    const int64_t kw = words_for(k), nw = words_for(n);
+    bool halve = n % 64 == 0 && m >= 2 && kw >= 4 && nw >= 2;
+    if (split < 0 || (split == 0 && (m < GF2_PLAN_MIN_BITS || k < GF2_PLAN_MIN_BITS || n < GF2_PLAN_MIN_BITS)))
+        halve = false;
+    int64_t ns = 0, ws = 0;
+    auto put = [&](int64_t kind, gf2_plan_block b0, gf2_plan_block b1, gf2_plan_block b2, gf2_plan_block b3) {
+        if (ns < max) {
+            st[ns].kind = kind;
+            st[ns].b[0] = b0;
+            st[ns].b[1] = b1;
+            st[ns].b[2] = b2;
+            st[ns].b[3] = b3;
+        }
+        ns++;
+    };
+    if (!halve) {
+        put(1, pblk(0, 0, 0, lda, m, k), pblk(1, 0, 0, ldbt, n, k), pblk(2, 0, 0, ldc, m, n), NO_BLOCK);
+        if (ws_words) *ws_words = 0;
+        return ns;
+    }
+    // rows at a multiple of 256 (the product's block rows), the inner size at
+    // an even number of words (16-byte operand loads), columns at a multiple
+    // of 256 bits; each first part at least as large as the second
+    int64_t m1 = (((m + 1) / 2) + 255) & ~(int64_t)255;
+    if (m1 >= m) m1 = (m + 1) / 2;
+    const int64_t m2 = m - m1;
+    const int64_t kw1 = (((kw + 1) / 2) + 1) & ~(int64_t)1;
+    const int64_t K1 = 64 * kw1, K2 = k - K1;
+    int64_t nw1 = (((nw + 1) / 2) + 3) & ~(int64_t)3;
+    if (nw1 >= nw) nw1 = (nw + 1) / 2;
+    const int64_t N1 = 64 * nw1, N2 = n - N1;
+    const gf2_plan_block A11 = pblk(0, 0, 0, lda, m1, K1), A12 = pblk(0, 0, kw1, lda, m1, K2),
+                         A21 = pblk(0, m1, 0, lda, m2, K1), A22 = pblk(0, m1, kw1, lda, m2, K2);
+    const gf2_plan_block B11 = pblk(1, 0, 0, ldbt, N1, K1), B12 = pblk(1, N1, 0, ldbt, N2, K1),
+                         B21 = pblk(1, 0, kw1, ldbt, N1, K2), B22 = pblk(1, N1, kw1, ldbt, N2, K2);
+    const gf2_plan_block C11 = pblk(2, 0, 0, ldc, m1, N1), C12 = pblk(2, 0, nw1, ldc, m1, N2),
+                         C21 = pblk(2, m1, 0, ldc, m2, N1), C22 = pblk(2, m1, nw1, ldc, m2, N2);
+    // a workspace block: even row stride, 256-byte aligned
+    auto wsb = [&](int64_t rows, int64_t bits) {
+        const int64_t ld = (words_for(bits) + 1) & ~(int64_t)1;
+        const gf2_plan_block b = pblk(3, 0, ws, ld, rows, bits);
+        ws += (rows * ld + 31) & ~(int64_t)31;
+        return b;
+    };
+    const gf2_plan_block S1 = wsb(m1, K1), S2 = wsb(m2, K1), S5 = wsb(m1, K2), S6 = wsb(m2, K1), S7 = wsb(m1, K2);
+    const gf2_plan_block T1 = wsb(N1, K1), T3 = wsb(N2, K1), T4 = wsb(N1, K2), T6 = wsb(N2, K1), T7 = wsb(N1, K2);
+    put(0, S1, A11, A22, NO_BLOCK);
+    put(0, S2, A21, A22, NO_BLOCK);
+    put(0, S5, A11, A12, NO_BLOCK);
+    put(0, S6, A21, A11, NO_BLOCK);
+    put(0, S7, A12, A22, NO_BLOCK);
+    put(0, T1, B11, B22, NO_BLOCK);
+    put(0, T3, B12, B22, NO_BLOCK);
+    put(0, T4, B21, B11, NO_BLOCK);
+    put(0, T6, B11, B12, NO_BLOCK);
+    put(0, T7, B21, B22, NO_BLOCK);
+    put(1, S1, T1, C11, C22);
+    put(1, S2, B11, C21, C22);
+    put(1, A11, T3, C12, C22);
+    put(1, A22, T4, C21, pblk(2, 0, 0, ldc, m2, N1));  // C11's first m2 rows
+    put(1, S5, B22, C12, pblk(2, 0, 0, ldc, m1, N2));  // C11's first N2 columns
+    put(1, S6, T6, C22, NO_BLOCK);
+    put(1, S7, T7, C11, NO_BLOCK);
+    if (ws_words) *ws_words = ws;
+    return ns;
+}
+
+// A bound on product_plan's workspace for products of at most m x k x n
+// bits: ten blocks of at most m / 2 + 256 rows (or n / 2 + 256) and
+// kw / 2 + 3 words, each rounded to 32 words.
+int64_t product_plan_ws_bound(int64_t m, int64_t k, int64_t n) {
+    const int64_t kl = words_for(k) / 2 + 3;
+    return 5 * ((m / 2 + 256) * kl + 32) + 5 * ((n / 2 + 256) * kl + 32);
+}
+
+namespace {
+
+constexpr int PLAN_MAX_SUMS = 10;
+struct PlanSum {
+    uint64_t *d;
+    const uint64_t *x, *y;
+    int64_t ldd, ldx, ldy;
+    int32_t rows, words, xrows, xwords, yrows, ywords;
+    uint64_t dmask, xmask, ymask;  // the last word's valid bits of d, x, y
+};
+struct PlanSums {
+    PlanSum s[PLAN_MAX_SUMS];
+};
+
+// sum blockIdx.y of the plan: d = x ^ y, element by element over d's rows and
+// words; x and y read as zero outside their own rows and words, and each
+// last word masked to its bits
+__global__ __launch_bounds__(256) void k_plan_sums(PlanSums ps) {
+    const PlanSum &q = ps.s[blockIdx.y];
+    const uint32_t words = (uint32_t)q.words, total = (uint32_t)q.rows * words;
+    for (uint32_t e = blockIdx.x * 256u + threadIdx.x; e < total; e += gridDim.x * 256u) {
+        const uint32_t i = e / words, w = e - i * words;
+        uint64_t x = 0, y = 0;
+        if ((int32_t)i < q.xrows && (int32_t)w < q.xwords) {
+            x = q.x[(int64_t)i * q.ldx + w];
+            if ((int32_t)w == q.xwords - 1) x &= q.xmask;
+        }
+        if ((int32_t)i < q.yrows && (int32_t)w < q.ywords) {
+            y = q.y[(int64_t)i * q.ldy + w];
+            if ((int32_t)w == q.ywords - 1) y &= q.ymask;
+        }
+        uint64_t v = x ^ y;
+        if (w == words - 1) v &= q.dmask;
+        q.d[(int64_t)i * q.ldd + w] = v;
+    }
+}
+
+uint64_t last_mask(int64_t bits) { return (bits & 63) ? (1ull << (bits & 63)) - 1 : ~0ull; }
+
+}  // namespace
 
 // X <- L^-1 X on one diagonal block of nb <= 128 rows (step 2): rows
 // j0 .. j0 + nb - 1 of A, whose L bits left of the diagonal inside the block
@@ -278,6 +432,9 @@ struct Ctx {
     uint64_t *bt;         // bit transpose of a product's right operand
     size_t bt_bytes;
     int64_t split;        // 0: halves; > 0: left strips of this many columns
+    int psplit;           // Strassen's split of the fp4 products (product_plan)
+    uint64_t *plan_ws;    // the plan's sums
+    size_t plan_bytes;
 };
 
 // the left block's columns of a split of n columns
@@ -287,6 +444,61 @@ int64_t split_cols(int64_t n, int64_t split) {
 
 // A[crow0 .. crow0 + M)[xw0, xw1) ^= (bits [64 kw0, 64 kw0 + K) of those rows)
 //                                    x A[brow0 .. brow0 + K)[xw0, xw1)
+// The fp4 product C ^= Aop * B (Bt its bit transpose), by product_plan's
+// steps: the sums in one launch, then the products in order.
+hipError_t run_plan(Ctx &c, uint64_t *C, int64_t ldc, const uint64_t *Aop, int64_t lda, const uint64_t *Bt,
+                    int64_t ldbt, int64_t M, int64_t K, int64_t N) {
+    gf2_plan_step st[GF2_PLAN_MAX_STEPS];
+    int64_t wsw = 0;
+    const int64_t ns = product_plan(M, K, N, c.psplit, lda, ldbt, ldc, st, GF2_PLAN_MAX_STEPS, &wsw);
+    if (ns < 1 || ns > GF2_PLAN_MAX_STEPS || (size_t)wsw * 8 > c.plan_bytes) return hipErrorInvalidValue;
+    auto addr = [&](const gf2_plan_block &b) -> uint64_t * {
+        uint64_t *base = b.buf == 0 ? (uint64_t *)Aop : b.buf == 1 ? (uint64_t *)Bt : b.buf == 2 ? C : c.plan_ws;
+        return base + b.row0 * b.ld + b.word0;
+    };
+    PlanSums sums;
+    int nsum = 0;
+    int64_t most = 0;
+    for (int64_t i = 0; i < ns; i++) {
+        if (st[i].kind != 0) continue;
+        const gf2_plan_block &d = st[i].b[0], &x = st[i].b[1], &y = st[i].b[2];
+        if (nsum >= PLAN_MAX_SUMS || d.rows * words_for(d.bits) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+        PlanSum &q = sums.s[nsum++];
+        q.d = addr(d);
+        q.x = addr(x);
+        q.y = addr(y);
+        q.ldd = d.ld;
+        q.ldx = x.ld;
+        q.ldy = y.ld;
+        q.rows = (int32_t)d.rows;
+        q.words = (int32_t)words_for(d.bits);
+        q.xrows = (int32_t)x.rows;
+        q.xwords = (int32_t)words_for(x.bits);
+        q.yrows = (int32_t)y.rows;
+        q.ywords = (int32_t)words_for(y.bits);
+        q.dmask = last_mask(d.bits);
+        q.xmask = last_mask(x.bits);
+        q.ymask = last_mask(y.bits);
+        most = std::max(most, d.rows * words_for(d.bits));
+    }
+    hipError_t e;
+    if (nsum > 0 && most > 0) {
+        const int64_t bx = std::min<int64_t>((most + 255) / 256, 2048);
+        ProfScope ps(KID_SUMS, c.s);
+        hipLaunchKernelGGL(k_plan_sums, dim3((unsigned)bx, (unsigned)nsum), dim3(256), 0, c.s, sums);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    for (int64_t i = 0; i < ns; i++) {
+        if (st[i].kind != 1) continue;
+        const gf2_plan_block &a = st[i].b[0], &b = st[i].b[1], &o0 = st[i].b[2], &o1 = st[i].b[3];
+        if ((e = launch_fp4_product2(addr(o0), o0.ld, o0.rows, words_for(o0.bits), o1.rows > 0 ? addr(o1) : nullptr,
+                                     o1.ld, o1.rows, words_for(o1.bits), addr(a), a.ld, addr(b), b.ld, a.rows, a.bits,
+                                     b.rows, c.s)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t product(Ctx &c, uint64_t *A, int64_t crow0, int64_t M, int64_t kw0, int64_t K, int64_t brow0, int64_t xw0,
                    int64_t xw1, int64_t N) {
     if (M <= 0 || K <= 0 || N <= 0) return hipSuccess;
@@ -296,6 +508,10 @@ hipError_t product(Ctx &c, uint64_t *A, int64_t crow0, int64_t M, int64_t kw0, i
         if ((size_t)words_for(N) * 64 * (size_t)ldbt * 8 > c.bt_bytes) return hipErrorInvalidValue;
         hipError_t e = launch_transpose_bits(A + brow0 * ldw + xw0, ldw, K, N, c.bt, ldbt, c.s);
         if (e != hipSuccess) return e;
+        // (the plan takes whole words of columns: Bt's rows past N are zero)
+        if (c.fmt == 0)
+            return run_plan(c, A + crow0 * ldw + xw0, ldw, A + crow0 * ldw + kw0, ldw, c.bt, ldbt, M, K,
+                            64 * words_for(N));
         return launch_mfma_gf2(A + crow0 * ldw + xw0, ldw, A + crow0 * ldw + kw0, ldw, c.bt, ldbt, M, K, N, c.s,
                                c.fmt);
     }
@@ -421,21 +637,31 @@ hipError_t ple_rec(Ctx &c, uint64_t *A, int64_t m, int64_t n, int64_t *P, int64_
 
 }  // namespace
 
-size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma, int64_t split) {
+namespace {
+// the largest product is the first split's: at most m rows, inner size at
+// most min(m, n1), n - n1 columns
+size_t bt_bytes_for(int64_t m, int64_t n, int levels, bool mfma, int64_t split) {
+    if (!(mfma && levels > 0 && n > 64 && !(split > 0 && n <= split))) return 0;
+    const int64_t n1 = split_cols(n, split);
+    const int64_t k = m < n1 ? m : n1;
+    return al((size_t)words_for(n - n1) * 64 * (size_t)words_for(k) * 8);
+}
+size_t plan_bytes_for(int64_t m, int64_t n, int levels, bool mfma, int64_t split, int psplit) {
+    if (psplit < 0 || !(mfma && levels > 0 && n > 64 && !(split > 0 && n <= split))) return 0;
+    const int64_t n1 = split_cols(n, split);
+    const int64_t k = m < n1 ? m : n1;
+    return al((size_t)product_plan_ws_bound(m, k, n - n1) * 8);
+}
+}  // namespace
+
+size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma, int64_t split, int psplit) {
     (void)ldw;
-    size_t b = al((size_t)MAX_DEPTH * 8);
-    if (mfma && levels > 0 && n > 64 && !(split > 0 && n <= split)) {
-        // the largest product is the first split's: inner size at most
-        // min(m, n1), n - n1 columns
-        const int64_t n1 = split_cols(n, split);
-        const int64_t k = m < n1 ? m : n1;
-        b += al((size_t)words_for(n - n1) * 64 * (size_t)words_for(k) * 8);
-    }
-    return b;
+    return al((size_t)MAX_DEPTH * 8) + bt_bytes_for(m, n, levels, mfma, split) +
+           plan_bytes_for(m, n, levels, mfma, split, psplit);
 }
 
 hipError_t ple_alg3(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
-                    const gf2_ple_opts *opts, hipStream_t s, int levels, int products, int64_t split) {
+                    const gf2_ple_opts *opts, hipStream_t s, int levels, int products, int64_t split, int psplit) {
     const bool mfma = products != 0;
     Ctx c;
     c.ldw = ldw;
@@ -448,7 +674,10 @@ hipError_t ple_alg3(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, 
     c.rank_slots = (int64_t *)extra;
     c.bt = (uint64_t *)(extra + al((size_t)MAX_DEPTH * 8));
     c.split = split;
-    c.bt_bytes = alg3_extra_bytes(m, n, ldw, levels, mfma, split) - al((size_t)MAX_DEPTH * 8);
+    c.bt_bytes = bt_bytes_for(m, n, levels, mfma, split);
+    c.psplit = products == 1 ? psplit : -1;
+    c.plan_ws = (uint64_t *)((char *)c.bt + c.bt_bytes);
+    c.plan_bytes = plan_bytes_for(m, n, levels, mfma, split, c.psplit);
     return ple_rec(c, A, m, n, P, Q, rank, levels, 0, 0);
 }
 

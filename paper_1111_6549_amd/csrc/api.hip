@@ -435,6 +435,7 @@ gf2_status ple_check_args(const uint64_t *A, int64_t m, int64_t n, int64_t ldw, 
         return GF2_EINVAL;
     if (opts && (opts->lookahead < 0 || opts->lookahead > 3)) return GF2_EINVAL;
     if (opts && (opts->pair_variant < 0 || opts->pair_variant > 14)) return GF2_EINVAL;
+    if (opts && (opts->product_split < -1 || opts->product_split > 1)) return GF2_EINVAL;
     return GF2_OK;
 }
 
@@ -449,6 +450,8 @@ static bool recursive(const gf2_ple_opts *opts) { return opts && opts->update >=
 static int rec_levels(const gf2_ple_opts *opts) { return opts && opts->rec_levels > 0 ? opts->rec_levels : 1; }
 static int rec_products(const gf2_ple_opts *opts) { return opts->update == 2 ? 1 : (opts->update == 4 ? 2 : 0); }
 static int64_t rec_split(const gf2_ple_opts *opts) { return opts ? opts->rec_split : 0; }
+// Strassen's split applies to the fp4 products only
+static int prod_split(const gf2_ple_opts *opts) { return rec_products(opts) == 1 ? opts->product_split : -1; }
 
 hipError_t ple_enqueue(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank,
                        void *ws, const gf2_ple_opts *opts, hipStream_t s, bool allow_sync, bool allow_s2) {
@@ -479,7 +482,8 @@ size_t gf2_ple_workspace_bytes(int64_t m, int64_t n, int64_t ldw, const gf2_ple_
     if (!sizes_ok(m, n, ldw)) return 0;
     if (recursive(opts))
         return align_up(ple_layout(m, ldw).total) +
-               alg3_extra_bytes(m, n, ldw, rec_levels(opts), rec_products(opts) != 0, rec_split(opts));
+               alg3_extra_bytes(m, n, ldw, rec_levels(opts), rec_products(opts) != 0, rec_split(opts),
+                                prod_split(opts));
     return ple_layout(m, ldw).total;
 }
 
@@ -512,8 +516,14 @@ gf2_status gf2_ple(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, i
     }
     if (recursive(opts))
         return hip_status(
-            ple_alg3(A, m, n, ldw, P, Q, rank, ws, opts, s, rec_levels(opts), rec_products(opts), rec_split(opts)));
+            ple_alg3(A, m, n, ldw, P, Q, rank, ws, opts, s, rec_levels(opts), rec_products(opts), rec_split(opts),
+                     prod_split(opts)));
     return hip_status(ple_enqueue(A, m, n, ldw, P, Q, rank, ws, opts, s, true, true));
+}
+
+int64_t gf2_product_plan(int64_t m, int64_t k, int64_t n, int32_t split, int64_t lda, int64_t ldbt, int64_t ldc,
+                         gf2_plan_step *steps, int64_t max, int64_t *ws_words) {
+    return product_plan(m, k, n, split, lda, ldbt, ldc, steps, max, ws_words);
 }
 
 int64_t gf2_ple_schedule(int64_t m, int64_t n, const gf2_ple_opts *opts, int32_t *kinds, int64_t max) {

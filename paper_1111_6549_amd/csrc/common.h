@@ -63,6 +63,7 @@ enum KernelId {
     KID_BATCH,
     KID_TRSM,
     KID_TRANSPOSE,
+    KID_SUMS,
     KID_COUNT
 };
 bool prof_enabled();

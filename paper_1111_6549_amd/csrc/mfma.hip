@@ -239,6 +239,10 @@ __device__ __forceinline__ v8i half_to_fp4_y(uint32_t v) {
 }
 
 constexpr int F4_BM = 256, F4_BN = 256;  // block rows, block columns
+struct F4Out {                            // a destination of the fp4 product
+    uint64_t *C;
+    int64_t ldc, rows, words;
+};
 constexpr int F4_KS = 8;                 // words of K per barrier
 
 // One step's KS words of an operand row, zero past kw.  ld_full: the step
@@ -273,11 +277,14 @@ __device__ __forceinline__ void f4_ld_tail(const uint64_t *__restrict__ p, int64
 // the barrier that follows its last read, and the matrix-core work sits
 // between barriers, where one wave's instructions overlap the other's loads,
 // stores and expansion.
+//
+// The product (m x 64 nw bits) is added to o0 and, when o1.C is set, to o1,
+// each over its own rows and words (at most the product's).
 template <bool VEC>
-__global__ __launch_bounds__(512) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, int64_t ldc,
-                                                      const uint64_t *__restrict__ A, int64_t lda,
-                                                      const uint64_t *__restrict__ Bt, int64_t ldbt, int64_t m,
-                                                      int64_t kw, int64_t nw, int64_t gcols, int64_t grows) {
+__global__ __launch_bounds__(512) void k_mfma_gf2_fp4(F4Out o0, F4Out o1, const uint64_t *__restrict__ A,
+                                                      int64_t lda, const uint64_t *__restrict__ Bt, int64_t ldbt,
+                                                      int64_t m, int64_t kw, int64_t nw, int64_t gcols,
+                                                      int64_t grows) {
     constexpr int KS = F4_KS, WC = 2, TI = 2, TJ = 4, CH = KS / 4;  // CH chunks of 4 words per step
     // [buffer][operand row: A rows, then Bt rows][low halves of the KS words, then high halves]
     __shared__ __align__(16) uint32_t sP[2][F4_BM + F4_BN][2 * KS];
@@ -400,7 +407,9 @@ __global__ __launch_bounds__(512) void k_mfma_gf2_fp4(uint64_t *__restrict__ C, 
 #pragma unroll
     for (int d = 0; d < 2; d++) {
         const int64_t w = w0 + wc * 2 + d;
-        if (row < m && w < nw && out[d]) C[row * ldc + w] ^= out[d];
+        if (!out[d]) continue;
+        if (row < o0.rows && w < o0.words) o0.C[row * o0.ldc + w] ^= out[d];
+        if (o1.C && row < o1.rows && w < o1.words) o1.C[row * o1.ldc + w] ^= out[d];
     }
 }
 
@@ -413,23 +422,33 @@ hipError_t launch_transpose_bits(const uint64_t *B, int64_t ldb, int64_t k, int6
     return hipGetLastError();
 }
 
+// C0 (rows0 x words0) ^= A (m x k) * B and, with C1, C1 (rows1 x words1) ^=
+// the same product, on the fp4 matrix cores; Bt is B's bit transpose (n rows
+// of ldbt words, zero past k).  rows0, rows1 <= m; words0, words1 <= the
+// words of n.
+hipError_t launch_fp4_product2(uint64_t *C0, int64_t ldc0, int64_t rows0, int64_t words0, uint64_t *C1, int64_t ldc1,
+                               int64_t rows1, int64_t words1, const uint64_t *A, int64_t lda, const uint64_t *Bt,
+                               int64_t ldbt, int64_t m, int64_t k, int64_t n, hipStream_t s) {
+    const int64_t nw = words_for(n), kw = words_for(k);
+    const int64_t gcols = (nw + F4_BN / 64 - 1) / (F4_BN / 64), grows = (m + F4_BM - 1) / F4_BM;
+    if (gcols <= 0 || grows <= 0 || kw <= 0) return hipSuccess;
+    if (rows0 > m || words0 > nw || (C1 && (rows1 > m || words1 > nw))) return hipErrorInvalidValue;
+    const F4Out o0{C0, ldc0, rows0, words0}, o1{C1, ldc1, C1 ? rows1 : 0, C1 ? words1 : 0};
+    const bool vec = (uintptr_t)A % 16 == 0 && (uintptr_t)Bt % 16 == 0 && lda % 2 == 0 && ldbt % 2 == 0;
+    ProfScope ps(KID_MFMA, s);
+    if (vec)
+        hipLaunchKernelGGL(k_mfma_gf2_fp4<true>, dim3((unsigned)(gcols * grows)), dim3(512), 0, s, o0, o1, A, lda, Bt,
+                           ldbt, m, kw, nw, gcols, grows);
+    else
+        hipLaunchKernelGGL(k_mfma_gf2_fp4<false>, dim3((unsigned)(gcols * grows)), dim3(512), 0, s, o0, o1, A, lda,
+                           Bt, ldbt, m, kw, nw, gcols, grows);
+    return hipGetLastError();
+}
+
 // fmt 0: fp4 matrix cores; 1: int8 matrix cores
 hipError_t launch_mfma_gf2(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda, const uint64_t *Bt, int64_t ldbt,
                            int64_t m, int64_t k, int64_t n, hipStream_t s, int fmt) {
-    if (fmt == 0) {
-        const int64_t nw = words_for(n), kw = words_for(k);
-        const int64_t gcols = (nw + F4_BN / 64 - 1) / (F4_BN / 64), grows = (m + F4_BM - 1) / F4_BM;
-        if (gcols <= 0 || grows <= 0 || kw <= 0) return hipSuccess;
-        const bool vec = (uintptr_t)A % 16 == 0 && (uintptr_t)Bt % 16 == 0 && lda % 2 == 0 && ldbt % 2 == 0;
-        ProfScope ps(KID_MFMA, s);
-        if (vec)
-            hipLaunchKernelGGL(k_mfma_gf2_fp4<true>, dim3((unsigned)(gcols * grows)), dim3(512), 0, s, C, ldc, A, lda,
-                               Bt, ldbt, m, kw, nw, gcols, grows);
-        else
-            hipLaunchKernelGGL(k_mfma_gf2_fp4<false>, dim3((unsigned)(gcols * grows)), dim3(512), 0, s, C, ldc, A, lda,
-                               Bt, ldbt, m, kw, nw, gcols, grows);
-        return hipGetLastError();
-    }
+    if (fmt == 0) return launch_fp4_product2(C, ldc, m, words_for(n), nullptr, 0, 0, 0, A, lda, Bt, ldbt, m, k, n, s);
     if (k >= 128) {
         // 128 x 128 per wave, four waves side by side
         constexpr int TR = 4, TC = 4;

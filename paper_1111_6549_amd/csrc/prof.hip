@@ -24,7 +24,7 @@ std::vector<Mark> g_marks;
 std::vector<hipEvent_t> g_pool;
 
 const char *kNames[KID_COUNT] = {"panel", "permute", "m4rm",  "init",     "rref_block",
-                                 "echelon", "mfma",  "batch", "trsm", "transpose"};
+                                 "echelon", "mfma",  "batch", "trsm", "transpose", "sums"};
 
 hipEvent_t take_event() {
     if (!g_pool.empty()) {

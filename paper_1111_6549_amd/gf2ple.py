@@ -23,7 +23,8 @@ STATUS = {0: "GF2_OK", 1: "GF2_EINVAL", 2: "GF2_EWORKSPACE", 3: "GF2_ENOMEM", 4:
 
 # every symbol include/gf2ple.h declares
 EXPORTS = [
-    "gf2_version", "gf2_status_str", "gf2_ple_workspace_bytes", "gf2_ple", "gf2_ple_schedule", "gf2_echelon_from_ple",
+    "gf2_version", "gf2_status_str", "gf2_ple_workspace_bytes", "gf2_ple", "gf2_ple_schedule", "gf2_product_plan",
+    "gf2_echelon_from_ple",
     "gf2_rref_workspace_bytes", "gf2_rref_from_ple", "gf2_rref_full_workspace_bytes", "gf2_rref",
     "gf2_m4ri_rref_workspace_bytes", "gf2_m4ri_rref",
     "gf2_addmul_workspace_bytes", "gf2_addmul", "gf2_make_table", "gf2_check_padding", "gf2_profile_start", "gf2_profile_stop",
@@ -49,7 +50,17 @@ class KernelTime(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("check_padding", ctypes.c_int32), ("update", ctypes.c_int32), ("rec_levels", ctypes.c_int32),
                 ("m4_variant", ctypes.c_int32), ("m4_blocks", ctypes.c_int32), ("panel_regs", ctypes.c_int32),
-                ("lookahead", ctypes.c_int32), ("pair_variant", ctypes.c_int32), ("rec_split", ctypes.c_int32)]
+                ("lookahead", ctypes.c_int32), ("pair_variant", ctypes.c_int32), ("rec_split", ctypes.c_int32),
+                ("product_split", ctypes.c_int32)]
+
+
+class PlanBlock(ctypes.Structure):
+    _fields_ = [("buf", ctypes.c_int64), ("row0", ctypes.c_int64), ("word0", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("rows", ctypes.c_int64), ("bits", ctypes.c_int64)]
+
+
+class PlanStep(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int64), ("b", PlanBlock * 4)]
 
 
 class Desc(ctypes.Structure):
@@ -102,6 +113,7 @@ def load():
         "gf2_ple": (st, [p, i64, i64, i64, p, p, p, p, sz, p, p]),
         "gf2_echelon_from_ple": (st, [p, i64, i64, i64, p, p]),
         "gf2_ple_schedule": (i64, [i64, i64, p, p, i64]),
+        "gf2_product_plan": (i64, [i64, i64, i64, ctypes.c_int32, i64, i64, i64, p, i64, p]),
         "gf2_rref_workspace_bytes": (sz, [i64, i64, i64]),
         "gf2_rref_from_ple": (st, [p, i64, i64, i64, p, p, p, sz, p]),
         "gf2_rref_full_workspace_bytes": (sz, [i64, i64, i64, p]),
@@ -187,9 +199,10 @@ def _ptr(t):
 
 
 def _opts(update=0, check_padding=False, rec_levels=0, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0,
-          pair_variant=0, rec_split=0):
+          pair_variant=0, rec_split=0, product_split=0):
     o = Opts()
     o.rec_split = int(rec_split)
+    o.product_split = int(product_split)
     o.lookahead = int(lookahead)
     o.pair_variant = int(pair_variant)
     o.check_padding = 1 if check_padding else 0
@@ -201,8 +214,8 @@ def _opts(update=0, check_padding=False, rec_levels=0, m4_variant=0, m4_blocks=0
     return o
 
 
-def workspace_bytes(m, n, ldw, update=0, rec_levels=0, rec_split=0):
-    o = _opts(update, rec_levels=rec_levels, rec_split=rec_split)
+def workspace_bytes(m, n, ldw, update=0, rec_levels=0, rec_split=0, product_split=0):
+    o = _opts(update, rec_levels=rec_levels, rec_split=rec_split, product_split=product_split)
     return int(load().gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
 
 
@@ -211,7 +224,7 @@ def alloc_workspace(nbytes, device=None):
 
 
 def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0, panel_regs=0, lookahead=0,
-        pair_variant=0, rec_levels=0, rec_split=0):
+        pair_variant=0, rec_levels=0, rec_split=0, product_split=0):
     """In-place PLE of the packed (m, ldw) tensor A with n columns.
 
     Returns (P, Q, rank) as device tensors (int64 [m], int64 [min(m, n)],
@@ -220,7 +233,8 @@ def ple(A, n, ws=None, update=0, check_padding=False, m4_variant=0, m4_blocks=0,
     m, ldw = A.shape
     lib = load()
     o = _opts(update, check_padding, rec_levels=rec_levels, m4_variant=m4_variant, m4_blocks=m4_blocks,
-              panel_regs=panel_regs, lookahead=lookahead, pair_variant=pair_variant, rec_split=rec_split)
+              panel_regs=panel_regs, lookahead=lookahead, pair_variant=pair_variant, rec_split=rec_split,
+              product_split=product_split)
     need = int(lib.gf2_ple_workspace_bytes(m, n, ldw, ctypes.byref(o)))
     if need == 0 and (m or n):
         raise GF2Error(1, "gf2_ple_workspace_bytes")
@@ -247,6 +261,22 @@ def ple_noalloc(A, n, lookahead=0, panel_regs=0):
     _check(load().gf2_ple_noalloc(_ptr(A), m, n, ldw, _ptr(P), _ptr(Q), _ptr(rank), ctypes.byref(o), _stream()),
            "gf2_ple_noalloc")
     return P, Q, rank
+
+
+def product_plan(m, k, n, split=0, lda=0, ldbt=0, ldc=0):
+    """The steps by which Algorithm 3 adds an m x k x n product on the fp4
+    matrix cores (gf2_product_plan): (steps, workspace words), each step
+    (kind, [(buf, row0, word0, ld, rows, bits)] * 4)."""
+    steps = (PlanStep * 17)()
+    ws = ctypes.c_int64(0)
+    ns = int(load().gf2_product_plan(m, k, n, split, lda, ldbt, ldc, steps, 17, ctypes.byref(ws)))
+    if ns < 0:
+        raise GF2Error(1, "gf2_product_plan")
+    out = []
+    for i in range(ns):
+        st = steps[i]
+        out.append((int(st.kind), [(b.buf, b.row0, b.word0, b.ld, b.rows, b.bits) for b in st.b]))
+    return out, int(ws.value)
 
 
 def ple_schedule(m, n, lookahead=0):

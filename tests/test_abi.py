@@ -156,7 +156,8 @@ def test_schedule_options_checked_before_launch():
     p = lambda a: ctypes.c_void_p(a.ctypes.data)
     for field, value in (("pair_variant", 99), ("pair_variant", -1), ("lookahead", 4), ("panel_regs", 3),
                          ("update", 5), ("update", -1), ("rec_levels", 17), ("rec_levels", -1),
-                         ("rec_split", -64), ("rec_split", 100)):
+                         ("rec_split", -64), ("rec_split", 100), ("pair_variant", 15), ("product_split", 2),
+                         ("product_split", -2)):
         o = G.Opts()
         setattr(o, field, value)
         st = lib.gf2_ple(p(A), m, n, ldw, p(P), p(Q), p(rank), ctypes.c_void_p(ws_ptr), ws.nbytes - 256,

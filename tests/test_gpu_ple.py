@@ -404,6 +404,22 @@ def test_alg3_levels_parity(m, n, kind, levels, update):
                     "alg3 u%d %dx%d %s levels %d" % (update, m, n, kind, levels))
 
 
+@pytest.mark.parametrize("psplit", [1, -1])
+@pytest.mark.parametrize("m,n,kind,levels,split", [(3000, 2500, "u", 2, 0), (2500, 3000, "deficient_left", 3, 0),
+                                                   (4096, 4096, "u", 3, 0), (2000, 2000, "s", 4, 0),
+                                                   (1200, 1100, "r", 2, 0), (1500, 4000, "zero_left", 16, 768),
+                                                   (12000, 11000, "u", 1, 5120), (12000, 12000, "u", 1, 0),
+                                                   (9000, 7000, "deficient_left", 1, 0)])
+def test_alg3_product_split_parity(m, n, kind, levels, split, psplit):
+    """Algorithm 3 with fp4 products, each by one level of Strassen's split
+    (psplit 1: ten block sums, seven half-size products into one or two
+    blocks of the result) or by one product (-1), against the oracle."""
+    say("alg3 product split", psplit, m, n, kind, levels, split)
+    A = _alg3_case(kind, m, n)
+    assert_same_ple(gpu_ple(A, n, update=2, rec_levels=levels, rec_split=split, product_split=psplit),
+                    oracle_ple(A, n), "alg3 %dx%d %s levels %d split %d psplit %d" % (m, n, kind, levels, split, psplit))
+
+
 @pytest.mark.parametrize("update", [2, 3, 4])
 @pytest.mark.parametrize("m,n,kind,levels,split", [(3000, 2500, "u", 16, 512), (2500, 3000, "deficient_left", 16, 640),
                                                    (4096, 4096, "u", 3, 1024), (2000, 2000, "s", 16, 256),
