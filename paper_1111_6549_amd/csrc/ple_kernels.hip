@@ -490,6 +490,20 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
         return;
     }
     const int64_t wt0 = (w_begin & ~(int64_t)(PR_TW - 1)) + (int64_t)tile * PR_TW;
+    // every global read of the table build first: pass u's staged pivot
+    // words and their pass-t coefficients (two dependent loads) then travel
+    // beside pass t's words and the first table build
+    constexpr int IT = (KW * PR_TW + NT - 1) / NT;
+    uint64_t pbu[IT], ctu[IT];
+#pragma unroll
+    for (int it = 0; it < IT; it++) {
+        const int e = tid + it * NT;
+        const int k = e / PR_TW;
+        const int64_t w = wt0 + e % PR_TW;
+        const bool on = e < KW * PR_TW && k < nbu && w >= w_begin && w < w_end;
+        pbu[it] = on ? PBu[(int64_t)k * ldb + w] : 0ull;
+        ctu[it] = on && nbt ? coefT[recu->spec_src[k]] : 0ull;
+    }
     for (int e = tid; e < KW * PR_TW; e += NT) {
         const int k = e / PR_TW, wl = e % PR_TW;
         const int64_t w = wt0 + wl;
@@ -500,19 +514,16 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
     __syncthreads();
     pair_combos<0, NT>(T, tid);
     __syncthreads();
-    for (int e = tid; e < KW * PR_TW; e += NT) {
-        const int k = e / PR_TW, wl = e % PR_TW;
-        const int64_t w = wt0 + wl;
-        const int q = k >> 2, b = k & 3;
-        uint64_t v = 0;
-        if (k < nbu && w >= w_begin && w < w_end) {
-            v = PBu[(int64_t)k * ldb + w];
-            if (nbt) {
-                const uint64_t ct = coefT[recu->spec_src[k]];
 #pragma unroll
-                for (int qq = 0; qq < 16; qq++) v ^= T[qq][(ct >> (4 * qq)) & 15][wl];
-            }
-        }
+    for (int it = 0; it < IT; it++) {
+        const int e = tid + it * NT;
+        if (e >= KW * PR_TW) break;
+        const int k = e / PR_TW, wl = e % PR_TW;
+        const int q = k >> 2, b = k & 3;
+        uint64_t v = pbu[it];
+        const uint64_t ct = ctu[it];
+#pragma unroll
+        for (int qq = 0; qq < 16; qq++) v ^= T[qq][(ct >> (4 * qq)) & 15][wl];
         T[16 + q][1 << b][wl] = v;
         if (b == 0) T[16 + q][0][wl] = 0ull;
     }
