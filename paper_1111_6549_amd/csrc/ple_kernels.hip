@@ -95,8 +95,8 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
                                                           const uint64_t *__restrict__ PBt, int64_t wlo) {
     __shared__ uint64_t tw[16][16], tu[16][16], tn[16][16], tt[MODE == 2 ? 16 : 1][16];
     __shared__ uint64_t simg_w[KW], simg_u[KW], simg_n[KW], spbt[KW];
-    __shared__ int64_t sdisp[KW], sdsrc[KW], smaxdisp;
-    __shared__ uint64_t sdcoef[KW];
+    __shared__ int64_t sp_dst[MAX_SPEC], sp_src[MAX_SPEC], smaxdisp;
+    __shared__ uint64_t sp_coef[MAX_SPEC];
     constexpr bool LA = MODE >= 1;
 
     const int tid = threadIdx.x;
@@ -112,6 +112,16 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         g_sw = row[sw];
         if (nxt) g_nx = row[sw + 1];
         if (MODE == 2) g_ct = coefT[gfirst];
+    }
+    // the row blocks read the record's special-row entries beside its header
+    // (every entry exists), so the loads that take a special row's position
+    // wait for one round trip, not two
+    int64_t s_src = 0, s_dst = 0;
+    uint64_t s_coef = 0;
+    if ((int)blockIdx.x >= nA && tid < MAX_SPEC) {
+        s_src = rec->spec_src[tid];
+        s_dst = rec->spec_dst[tid];
+        s_coef = rec->spec_coef[tid];
     }
     // the record's header (r < 0 never holds: the test keeps the load of r
     // ahead of the branch, beside the others)
@@ -182,10 +192,14 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
     const bool spec_blk = nxt && (int)blockIdx.x == nA;
     uint64_t so = 0, sct = 0, scf = 0;  // special row tid: old next-stripe word, pass t and own coefficients
     if (spec_blk && tid < nspec) {
-        const int64_t src = rec->spec_src[tid];
-        so = A[src * ldw + sw + 1];
-        if (MODE == 2) sct = coefT[src];
-        scf = rec->spec_coef[tid];
+        so = A[s_src * ldw + sw + 1];
+        if (MODE == 2) sct = coefT[s_src];
+        scf = s_coef;
+    }
+    if (tid < MAX_SPEC) {
+        sp_dst[tid] = s_dst;
+        sp_src[tid] = s_src;
+        sp_coef[tid] = s_coef;
     }
     if (tid < KW) {
         simg_w[tid] = active ? rec->img_w[tid] : 0ull;
@@ -194,17 +208,18 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         // group A leaves the next stripe word of the special rows alone, so
         // these are the pivots' words there as they stand at the pass start
         if (nxt && tid < rbar) {
-            const int64_t src = rec->spec_src[tid];
-            pn = A[src * ldw + sw + 1];
-            if (MODE == 2) pct = coefT[src];
+            pn = A[s_src * ldw + sw + 1];
+            if (MODE == 2) pct = coefT[s_src];
         }
-        int64_t dv = -1;
-        if (tid < ndisp) {
-            dv = rec->spec_dst[rbar + tid];
-            sdisp[tid] = dv;
-            sdsrc[tid] = rec->spec_src[rbar + tid];
-            sdcoef[tid] = rec->spec_coef[rbar + tid];
-        }
+    }
+    // the pivots' next-stripe words as they stand (MODE 2 adds pass t's update
+    // below, once its pivots' words are in LDS)
+    if (MODE != 2 && nxt && tid < KW) simg_n[tid] = pn;
+    __syncthreads();
+    // the displaced rows are entries rbar .. nspec - 1: the largest position
+    // they take (read after the tables' barrier)
+    if (tid < 64) {
+        int64_t dv = tid < ndisp ? sp_dst[rbar + tid] : -1;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             const int64_t ov = __shfl_xor(dv, o);
@@ -212,11 +227,6 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         }
         if (tid == 0) smaxdisp = dv;
     }
-    // the pivots' next-stripe words as they stand (MODE 2 adds pass t's update
-    // below, once its pivots' words are in LDS)
-    if (MODE != 2 && nxt && tid < KW) simg_n[tid] = pn;
-    __syncthreads();
-    const int64_t maxdisp = smaxdisp;
     if (MODE == 2 && nxt && tid < KW) {
         uint64_t v = pn;
         if (tid < rbar) {
@@ -244,6 +254,7 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
         tn[tb][tx] = build(simg_n);
     }
     __syncthreads();
+    const int64_t maxdisp = smaxdisp;
     if (MODE == 2) {
         if (nxt && tid < 256) tn[tb][tx] = build(simg_n);
         __syncthreads();
@@ -279,17 +290,17 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_permute(uint64_t *__restrict__
             }
         }
         if (i < r + rbar) {
-            coef[i] = rec->spec_coef[i - r];
-            if (MODE == 2) coefP[i] = coefT[rec->spec_src[i - r]];
+            coef[i] = sp_coef[i - r];
+            if (MODE == 2) coefP[i] = coefT[sp_src[i - r]];
             continue;
         }
         if (i <= maxdisp) {
             // no early exit, so the compares' LDS reads can all be in flight
             int hit = -1;
-            for (int d = 0; d < ndisp; d++) hit = sdisp[d] == i ? d : hit;
+            for (int d = 0; d < ndisp; d++) hit = sp_dst[rbar + d] == i ? rbar + d : hit;
             if (hit >= 0) {
-                coef[i] = sdcoef[hit];
-                if (MODE == 2) coefP[i] = coefT[sdsrc[hit]];
+                coef[i] = sp_coef[hit];
+                if (MODE == 2) coefP[i] = coefT[sp_src[hit]];
                 continue;
             }
         }
