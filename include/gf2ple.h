@@ -178,9 +178,10 @@ typedef struct {
  * * B (k x n) on the fp4 matrix cores (host only, no device call).  Section 3.3 notes that the paper's
  * implementation multiplies by Strassen-Winograd; with split = 1 (or 0 and all three sizes at least
  * GF2_PLAN_MIN_BITS, and n a multiple of 64) the plan is one level of Strassen's split: C, A and B in
- * 2 x 2 blocks (rows of A and C split at a multiple of 256 near the middle, the inner size at an even
- * number of words, the columns at a multiple of 256 bits), ten block sums in the workspace, then
- * seven products of half size, each added to one or two blocks of C.  Over GF(2) every sign of
+ * 2 x 2 blocks (the rows of A and C split at their middle rounded up to a multiple of 256, the inner
+ * size at its middle rounded up to an even number of words, the columns at their middle rounded up to
+ * a multiple of 256 bits; where that rounding leaves no second part, at the middle itself), ten block
+ * sums in the workspace, then seven products of half size, each added to one or two blocks of C.  Over GF(2) every sign of
  * Strassen's formulas is a plus.  Otherwise (split = -1, or sizes too small to split) the plan is one
  * product.  lda, ldbt, ldc fill the ld of the blocks in buffers 0, 1, 2.  Writes up to max steps
  * (at most GF2_PLAN_MAX_STEPS) and *ws_words (the workspace in 8-byte words); returns the number of
