@@ -199,19 +199,35 @@ uint64_t last_mask(int64_t bits) { return (bits & 63) ? (1ull << (bits & 63)) - 
 // substitution: once row j is final its word goes by readlane to every lane
 // whose row has L[.][j] = 1; the first 64 rows are final after 64 steps, and
 // by then their words are folded into the second half too.
-__global__ __launch_bounds__(256) void k_trsm128(uint64_t *__restrict__ A, int64_t ldw, int64_t j0, int nb, int64_t lw,
-                                                 int64_t xw0, int64_t xw1) {
+//
+// The L bits are row i's words of L (row stride ldl), X row i is at X + i ldx
+// (the same rows as L's when X = L, or another matrix with a row per L row).
+// rblk > 0 (several diagonal blocks at once): blockIdx.y = y takes the block
+// of rows [y rblk, min(rend, (y + 1) rblk)), j0 is relative to its start and
+// the block's rows past its end are not there.
+__global__ __launch_bounds__(256) void k_trsm128(const uint64_t *__restrict__ L, int64_t ldl, uint64_t *__restrict__ X,
+                                                 int64_t ldx, int64_t j0, int nb, int64_t xw0, int64_t xw1,
+                                                 int64_t rblk, int64_t rend) {
     const int lane = threadIdx.x & 63;
     const int64_t w = xw0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= xw1) return;  // w is the same for the whole wave
+    if (rblk > 0) {
+        const int64_t y0 = (int64_t)blockIdx.y * rblk, y1 = y0 + rblk < rend ? y0 + rblk : rend;
+        j0 += y0;
+        if (y1 - j0 < nb) nb = (int)(y1 - j0);
+        if (nb <= 0) return;
+    }
+    const int64_t lw = j0 >> 6;
     const bool on0 = lane < nb, on1 = 64 + lane < nb;
-    uint64_t *row0 = A + (j0 + (on0 ? lane : 0)) * ldw;
-    uint64_t *row1 = A + (j0 + (on1 ? 64 + lane : 0)) * ldw;
+    const uint64_t *lrow0 = L + (j0 + (on0 ? lane : 0)) * ldl;
+    const uint64_t *lrow1 = L + (j0 + (on1 ? 64 + lane : 0)) * ldl;
+    uint64_t *row0 = X + (j0 + (on0 ? lane : 0)) * ldx;
+    uint64_t *row1 = X + (j0 + (on1 ? 64 + lane : 0)) * ldx;
     uint64_t x0 = on0 ? row0[w] : 0ull, x1 = on1 ? row1[w] : 0ull;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t l0 = on0 ? (row0[lw] & below) : 0ull;
-    const uint64_t l1a = on1 ? row1[lw] : 0ull;
-    const uint64_t l1b = on1 ? (row1[lw + 1] & below) : 0ull;
+    const uint64_t l0 = on0 ? (lrow0[lw] & below) : 0ull;
+    const uint64_t l1a = on1 ? lrow1[lw] : 0ull;
+    const uint64_t l1b = on1 ? (lrow1[lw + 1] & below) : 0ull;
     // every step runs (rows past nb are zero with zero L bits); with j a
     // constant, bit j of an L word becomes an all-ones or zero 32-bit mask in
     // one signed bit-field extract (the builtin's result type is unsigned:
@@ -254,15 +270,27 @@ __global__ __launch_bounds__(256) void k_trsm128(uint64_t *__restrict__ A, int64
 // lanes per row, two words per lane, the next row's words loaded during
 // this row's lookups.  Blocks: (tile, row chunk), tiles fastest.
 constexpr int TP_TW = 32;
-__global__ __launch_bounds__(1024) void k_trsm_pair(uint64_t *__restrict__ A, int64_t ldw, int64_t j0, int nb,
-                                                    int64_t lw, int64_t rb_all, int64_t re_all, int64_t xw0,
-                                                    int64_t xw1, int ntiles, int nchunks) {
+// L, X, rblk and rend as for k_trsm128: with rblk > 0, j0, rb_all are
+// relative to the start of block y's rows and re_all is its end.
+__global__ __launch_bounds__(1024) void k_trsm_pair(const uint64_t *__restrict__ L, int64_t ldl,
+                                                    uint64_t *__restrict__ X, int64_t ldx, int64_t j0, int nb,
+                                                    int64_t rb_all, int64_t re_all, int64_t xw0, int64_t xw1,
+                                                    int ntiles, int nchunks, int64_t rblk, int64_t rend) {
     constexpr int NT = 1024, LPR = TP_TW / 2, RS = NT / LPR;
     __shared__ __align__(16) uint64_t T[32][16][TP_TW];
     const int tid = threadIdx.x;
     const int logical = xcd_logical(blockIdx.x, gridDim.x);
     const int tile = logical % ntiles, chunk = logical / ntiles;
     if (chunk >= nchunks) return;
+    if (rblk > 0) {
+        const int64_t y0 = (int64_t)blockIdx.y * rblk;
+        j0 += y0;
+        rb_all += y0;
+        re_all = y0 + rblk < rend ? y0 + rblk : rend;
+        if (re_all - j0 < nb) nb = (int)(re_all - j0);
+        if (nb <= 0) return;
+    }
+    const int64_t lw = j0 >> 6;
     const int64_t per = (re_all - rb_all + nchunks - 1) / nchunks;
     const int64_t rb = rb_all + (int64_t)chunk * per;
     const int64_t re = rb + per < re_all ? rb + per : re_all;
@@ -273,7 +301,7 @@ __global__ __launch_bounds__(1024) void k_trsm_pair(uint64_t *__restrict__ A, in
         const int k = e / TP_TW, wl = e % TP_TW;
         const int64_t w = wt0 + wl;
         const int q = k >> 2, b = k & 3;
-        T[q][1 << b][wl] = (k < nb && w >= xw0 && w < xw1) ? A[(j0 + k) * ldw + w] : 0ull;
+        T[q][1 << b][wl] = (k < nb && w >= xw0 && w < xw1) ? X[(j0 + k) * ldx + w] : 0ull;
         if (b == 0) T[q][0][wl] = 0ull;
     }
     __syncthreads();
@@ -295,12 +323,13 @@ __global__ __launch_bounds__(1024) void k_trsm_pair(uint64_t *__restrict__ A, in
     const uint32_t tbase = (uint32_t)(2 * wp) * 8u;  // byte offset of this lane's pair of words
     // a lane's two words move as one 16-byte access when the row stride is
     // even and the base 16-byte aligned (tiles start at even words)
-    const bool wide = (ldw & 1) == 0 && ((uintptr_t)A & 15) == 0 && ok0 && ok1;
+    const bool wide = (ldx & 1) == 0 && ((uintptr_t)X & 15) == 0 && ok0 && ok1;
     auto load = [&](int64_t i, uint64_t &c0, uint64_t &c1, uint64_t &v0, uint64_t &v1) {
         if (i < re) {
-            const uint64_t *row = A + i * ldw;
-            c0 = row[lw];
-            c1 = row[lw + 1];
+            const uint64_t *lrow = L + i * ldl;
+            c0 = lrow[lw];
+            c1 = lrow[lw + 1];
+            const uint64_t *row = X + i * ldx;
             if (wide) {
                 const ulonglong2 v = *(const ulonglong2 *)(row + w2);
                 v0 = v.x;
@@ -335,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_trsm_pair(uint64_t *__restrict__ A, in
             a1 = xor3_64(a1, t[0].y, t[1].y);
         }
         if (c0 | c1) {
-            uint64_t *row = A + i * ldw;
+            uint64_t *row = X + i * ldx;
             if (wide) {
                 ulonglong2 v;
                 v.x = x0 ^ a0;
@@ -347,6 +376,24 @@ __global__ __launch_bounds__(1024) void k_trsm_pair(uint64_t *__restrict__ A, in
             }
         }
     }
+}
+
+// The diagonal blocks' identities in Y (rows [0, r), ldy words, the block of
+// row i starting at row i - i mod blk, columns relative to it): Y[i] = e_(i mod
+// blk) (flip = 0, one thread per word) or Y[i] ^= e_(i mod blk) (flip = 1,
+// one thread per row).
+__global__ void k_block_ident(uint64_t *__restrict__ Y, int64_t ldy, int64_t r, int64_t blk, int flip) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (flip) {
+        if (e >= r) return;
+        const int64_t rel = e % blk;
+        Y[e * ldy + (rel >> 6)] ^= 1ull << (rel & 63);
+        return;
+    }
+    const int64_t i = e / ldy, w = e % ldy;
+    if (i >= r) return;
+    const int64_t rel = i % blk;
+    Y[i * ldy + w] = w == (rel >> 6) ? 1ull << (rel & 63) : 0ull;
 }
 
 // Step 5, the permutation and rank: the right block's P and Q entries
@@ -435,6 +482,8 @@ struct Ctx {
     int psplit;           // Strassen's split of the fp4 products (product_plan)
     uint64_t *plan_ws;    // the plan's sums
     size_t plan_bytes;
+    uint64_t *tinv;       // the solve's diagonal-block inverses
+    size_t tinv_bytes;
 };
 
 // the left block's columns of a split of n columns
@@ -528,7 +577,8 @@ hipError_t trsm128(Ctx &c, uint64_t *A, int64_t j0, int nb, int64_t xw0, int64_t
     const int64_t blocks = (xw1 - xw0 + 3) / 4;
     if (blocks <= 0 || nb <= 0) return hipSuccess;
     ProfScope ps(KID_TRSM, c.s);
-    hipLaunchKernelGGL(k_trsm128, dim3((unsigned)blocks), dim3(256), 0, c.s, A, c.ldw, j0, nb, j0 >> 6, xw0, xw1);
+    hipLaunchKernelGGL(k_trsm128, dim3((unsigned)blocks), dim3(256), 0, c.s, A, c.ldw, A, c.ldw, j0, nb, xw0, xw1,
+                       (int64_t)0, (int64_t)0);
     return hipGetLastError();
 }
 
@@ -554,8 +604,8 @@ hipError_t trsm_sweep(Ctx &c, uint64_t *A, int64_t j0, int nb, int64_t rb, int64
         }
     }
     ProfScope ps(KID_TRSM, c.s);
-    hipLaunchKernelGGL(k_trsm_pair, dim3((unsigned)(nt * nchunks)), dim3(1024), 0, c.s, A, c.ldw, j0, nb, j0 >> 6, rb,
-                       re, xw0, xw1, nt, nchunks);
+    hipLaunchKernelGGL(k_trsm_pair, dim3((unsigned)(nt * nchunks)), dim3(1024), 0, c.s, A, c.ldw, A, c.ldw, j0, nb, rb,
+                       re, xw0, xw1, nt, nchunks, (int64_t)0, (int64_t)0);
     return hipGetLastError();
 }
 
@@ -573,21 +623,77 @@ hipError_t trsm_diag(Ctx &c, uint64_t *A, int64_t d0, int64_t d1, int64_t xw0, i
     return hipSuccess;
 }
 
-// With fp4 products, diagonal blocks of this many rows: each is solved by
-// the sweeps above, then removed from every row below it by one product
-// (inner size TRSM_BLOCK) instead of TRSM_BLOCK / 128 sweeps.  (The int8
-// product is too slow at this inner size to gain from it.)
+// With fp4 products, diagonal blocks of this many rows, each removed from
+// every row below it by one product (inner size TRSM_BLOCK) instead of
+// TRSM_BLOCK / 128 sweeps.  (The int8 product is too slow at this inner size
+// to gain from it.)
 constexpr int64_t TRSM_BLOCK = 4096;
+
+// The inverses of the diagonal blocks L_dd of L (rows [0, r), blocks of
+// TRSM_BLOCK rows, d0 a multiple of it) into Y (row i: row i - d0 of L_dd^-1,
+// TRSM_BLOCK / 64 words), all blocks at once: Y = I, then the blocked forward
+// substitution of each block on its own identity, 128-row steps in order,
+// each step one launch of the substitution and one of the sweep for every
+// block.  Row i of L_dd^-1 has no bit past column i - d0, so a step's
+// launches cover only the words up to its rows' columns.
+hipError_t invert_diag_blocks(Ctx &c, const uint64_t *A, int64_t r, uint64_t *Y) {
+    constexpr int64_t ldy = TRSM_BLOCK / 64;
+    const int64_t nblk = (r + TRSM_BLOCK - 1) / TRSM_BLOCK;
+    ProfScope ps(KID_TRSM, c.s);
+    hipLaunchKernelGGL(k_block_ident, dim3((unsigned)((r * ldy + 255) / 256)), dim3(256), 0, c.s, Y, ldy, r,
+                       TRSM_BLOCK, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t slots = device_cu_count();
+    for (int64_t b = 0; b < TRSM_BLOCK && b < r; b += 128) {
+        const int64_t xw = (b + 128) / 64 < ldy ? (b + 128) / 64 : ldy;
+        hipLaunchKernelGGL(k_trsm128, dim3((unsigned)((xw + 3) / 4), (unsigned)nblk), dim3(256), 0, c.s, A, c.ldw,
+                           Y, ldy, b, 128, (int64_t)0, xw, TRSM_BLOCK, r);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int64_t rows = TRSM_BLOCK - b - 128;  // below the step, in a whole block
+        if (rows <= 0) continue;
+        const int nt = (int)((xw + TP_TW - 1) / TP_TW);
+        int64_t nc = (rows + 255) / 256;
+        // about one round of the CUs over all blocks
+        const int64_t cap = (slots + nt * nblk - 1) / (nt * nblk);
+        if (nc > cap) nc = cap;
+        if (nc < 1) nc = 1;
+        hipLaunchKernelGGL(k_trsm_pair, dim3((unsigned)(nt * nc), (unsigned)nblk), dim3(1024), 0, c.s, A, c.ldw, Y,
+                           ldy, b, 128, b + 128, (int64_t)0, (int64_t)0, xw, nt, (int)nc, TRSM_BLOCK, r);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 // rows [0, r) of X = A[.][xw0, xw1) <- L^-1 X, with L the unit lower
 // triangle of A[0 .. r)[0 .. r)
 hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1, int64_t N) {
-    if (!c.mfma || c.fmt != 0) return trsm_diag(c, A, 0, r, xw0, xw1);
+    if (!c.mfma || c.fmt != 0 || r <= TRSM_BLOCK) return trsm_diag(c, A, 0, r, xw0, xw1);
+    // With fp4 products and several diagonal blocks: their inverses at once
+    // (Y, on identities TRSM_BLOCK / 64 words wide instead of the right
+    // block's width), then for each block in order X_d <- L_dd^-1 X_d as a
+    // product, X_d += (L_dd^-1 + I) X_d (the product reads X_d through its
+    // bit transpose, so it may add into X_d), and the rows below lose X_d.
+    constexpr int64_t ldy = TRSM_BLOCK / 64;
+    if ((size_t)r * ldy * 8 > c.tinv_bytes) return hipErrorInvalidValue;
+    uint64_t *Y = c.tinv;
     hipError_t e;
+    if ((e = invert_diag_blocks(c, A, r, Y)) != hipSuccess) return e;
+    {
+        ProfScope ps(KID_TRSM, c.s);
+        hipLaunchKernelGGL(k_block_ident, dim3((unsigned)((r + 255) / 256)), dim3(256), 0, c.s, Y, ldy, r, TRSM_BLOCK,
+                           1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int64_t Np = 64 * (xw1 - xw0);  // whole words of columns (Bt is zero past N)
     for (int64_t d0 = 0; d0 < r; d0 += TRSM_BLOCK) {
-        const int64_t d1 = r - d0 < TRSM_BLOCK ? r : d0 + TRSM_BLOCK;
-        if ((e = trsm_diag(c, A, d0, d1, xw0, xw1)) != hipSuccess) return e;
-        if (d1 < r && (e = product(c, A, d1, r - d1, d0 >> 6, d1 - d0, d0, xw0, xw1, N)) != hipSuccess) return e;
+        const int64_t d1 = r - d0 < TRSM_BLOCK ? r : d0 + TRSM_BLOCK, K = d1 - d0;
+        const int64_t ldbt = words_for(K);
+        if ((size_t)words_for(N) * 64 * (size_t)ldbt * 8 > c.bt_bytes) return hipErrorInvalidValue;
+        if ((e = launch_transpose_bits(A + d0 * c.ldw + xw0, c.ldw, K, N, c.bt, ldbt, c.s)) != hipSuccess) return e;
+        if ((e = run_plan(c, A + d0 * c.ldw + xw0, c.ldw, Y + d0 * ldy, ldy, c.bt, ldbt, K, K, Np)) != hipSuccess)
+            return e;
+        if (d1 < r && (e = product(c, A, d1, r - d1, d0 >> 6, K, d0, xw0, xw1, N)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -652,12 +758,20 @@ size_t plan_bytes_for(int64_t m, int64_t n, int levels, bool mfma, int64_t split
     const int64_t k = m < n1 ? m : n1;
     return al((size_t)product_plan_ws_bound(m, k, n - n1) * 8);
 }
+// the solve's diagonal-block inverses: a row of TRSM_BLOCK bits per row of
+// the largest solve (the first split's rank, at most min(m, n1))
+size_t tinv_bytes_for(int64_t m, int64_t n, int levels, bool mfma, int64_t split) {
+    if (!(mfma && levels > 0 && n > 64 && !(split > 0 && n <= split))) return 0;
+    const int64_t n1 = split_cols(n, split);
+    const int64_t k = m < n1 ? m : n1;
+    return al((size_t)k * (TRSM_BLOCK / 64) * 8);
+}
 }  // namespace
 
 size_t alg3_extra_bytes(int64_t m, int64_t n, int64_t ldw, int levels, bool mfma, int64_t split, int psplit) {
     (void)ldw;
     return al((size_t)MAX_DEPTH * 8) + bt_bytes_for(m, n, levels, mfma, split) +
-           plan_bytes_for(m, n, levels, mfma, split, psplit);
+           plan_bytes_for(m, n, levels, mfma, split, psplit) + tinv_bytes_for(m, n, levels, mfma, split);
 }
 
 hipError_t ple_alg3(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, int64_t *Q, int64_t *rank, void *ws,
@@ -678,6 +792,8 @@ hipError_t ple_alg3(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t *P, 
     c.psplit = products == 1 ? psplit : -1;
     c.plan_ws = (uint64_t *)((char *)c.bt + c.bt_bytes);
     c.plan_bytes = plan_bytes_for(m, n, levels, mfma, split, c.psplit);
+    c.tinv = (uint64_t *)((char *)c.plan_ws + c.plan_bytes);
+    c.tinv_bytes = tinv_bytes_for(m, n, levels, mfma, split);
     return ple_rec(c, A, m, n, P, Q, rank, levels, 0, 0);
 }
 
