@@ -903,20 +903,30 @@ def main():
         abytes = (alg_bytes_m4rm(m, split, Qh[:r1], r1, kinds_l) +
                   alg_bytes_m4rm(m - r1, N, Qh[r1:r] - split, r - r1, kinds_r))
         kinds = kinds_l + kinds_r
-        # the solve as the library runs it with fp4 products: diagonal blocks
-        # of TRSM_BLOCK rows, each swept in 128-row blocks and then removed
-        # from the rows below by one product
+        # the solve as the library runs it with fp4 products: with one
+        # diagonal block of at most TRSM_BLOCK rows, 128-row blocks swept
+        # over the right block's width; with several, the blocks' inverses
+        # at once (128-row steps over identities TRSM_BLOCK / 64 words wide,
+        # each step's words up to its rows' columns), then per block the
+        # product by its inverse and the product that removes it from the
+        # rows below.  Sweep bytes: 16 per row word below each 128-row step.
         nwr = (N + 63) // 64
         trsm_bytes = 0
         # each product's 2 M K N operations, and those the matrix cores run
         # by the library's plan for it (seven half-size products when it
         # takes Strassen's split)
         prod_list = [(m - r1, r1)]
-        for d0 in range(0, r1, TRSM_BLOCK):
-            d1 = min(r1, d0 + TRSM_BLOCK)
-            trsm_bytes += sum(16 * (d1 - b - 128) * nwr for b in range(d0, d1, 128) if b + 128 < d1)
-            if d1 < r1:
-                prod_list.append((r1 - d1, d1 - d0))
+        if r1 <= TRSM_BLOCK:
+            trsm_bytes = sum(16 * (r1 - b - 128) * nwr for b in range(0, r1, 128) if b + 128 < r1)
+        else:
+            for d0 in range(0, r1, TRSM_BLOCK):
+                d1 = min(r1, d0 + TRSM_BLOCK)
+                for b in range(0, d1 - d0, 128):
+                    if d0 + b + 128 < d1:
+                        trsm_bytes += 16 * (d1 - d0 - b - 128) * min(TRSM_BLOCK // 64, (b + 128) // 64)
+                prod_list.append((d1 - d0, d1 - d0))
+                if d1 < r1:
+                    prod_list.append((r1 - d1, d1 - d0))
         prod_flops = sum(2 * M * K * N for M, K in prod_list)
         prod_mfma_flops = 0
         for M, K in prod_list:
@@ -961,7 +971,8 @@ def main():
                 sec = kp["total_ms"] / args.steps * 1e-3  # every product of a step
                 tf = prod_mfma_flops / sec / 1e12
                 roofline_product = {"kernel": "k_mfma_gf2_fp4 (the Schur product, %d x %d x %d, and the solve's "
-                                              "products between its diagonal blocks)" % (m - r1, r1, n - split),
+                                              "products: each diagonal block by its inverse, then removed from "
+                                              "the rows below)" % (m - r1, r1, n - split),
                                     "bound": "mfma", "achieved": round(tf, 1), "peak": FP4_PEAK_TFLOPS,
                                     "unit": "TFLOP/s", "frac": round(tf / FP4_PEAK_TFLOPS, 4),
                                     "launches_per_step": kp["launches"] / args.steps,
@@ -971,8 +982,9 @@ def main():
                                     "ms_per_step": round(kp["total_ms"] / args.steps, 3)}
             if kt and kt["total_ms"] > 0:
                 gb = trsm_bytes / (kt["total_ms"] / args.steps * 1e-3) / 1e9
-                roofline_trsm = {"kernel": "k_trsm_pair sweeps inside the diagonal blocks, with the k_trsm128 "
-                                           "block solves", "bound": "hbm",
+                roofline_trsm = {"kernel": "k_trsm_pair sweeps and k_trsm128 block substitutions of the "
+                                           "diagonal blocks' inversion (all blocks in each launch), with the "
+                                           "identities' set-up", "bound": "hbm",
                                  "achieved": round(gb, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                                  "frac": round(gb / HBM_PEAK_GBPS, 4), "alg_bytes_per_step": trsm_bytes,
                                  "ms_per_step": round(kt["total_ms"] / args.steps, 3)}
