@@ -908,8 +908,9 @@ def main():
         # over the right block's width; with several, the blocks' inverses
         # at once (128-row steps over identities TRSM_BLOCK / 64 words wide,
         # each step's words up to its rows' columns), then per block the
-        # product by its inverse and the product that removes it from the
-        # rows below.  Sweep bytes: 16 per row word below each 128-row step.
+        # product that removes the solved blocks above it (inner size d0)
+        # and the product by its inverse.  Sweep bytes: 16 per row word
+        # below each 128-row step.
         nwr = (N + 63) // 64
         trsm_bytes = 0
         # each product's 2 M K N operations, and those the matrix cores run
@@ -924,9 +925,9 @@ def main():
                 for b in range(0, d1 - d0, 128):
                     if d0 + b + 128 < d1:
                         trsm_bytes += 16 * (d1 - d0 - b - 128) * min(TRSM_BLOCK // 64, (b + 128) // 64)
+                if d0 > 0:
+                    prod_list.append((d1 - d0, d0))
                 prod_list.append((d1 - d0, d1 - d0))
-                if d1 < r1:
-                    prod_list.append((r1 - d1, d1 - d0))
         prod_flops = sum(2 * M * K * N for M, K in prod_list)
         prod_mfma_flops = 0
         for M, K in prod_list:
@@ -971,8 +972,8 @@ def main():
                 sec = kp["total_ms"] / args.steps * 1e-3  # every product of a step
                 tf = prod_mfma_flops / sec / 1e12
                 roofline_product = {"kernel": "k_mfma_gf2_fp4 (the Schur product, %d x %d x %d, and the solve's "
-                                              "products: each diagonal block by its inverse, then removed from "
-                                              "the rows below)" % (m - r1, r1, n - split),
+                                              "products: each diagonal block loses the solved blocks above it, "
+                                              "then is multiplied by its inverse)" % (m - r1, r1, n - split),
                                     "bound": "mfma", "achieved": round(tf, 1), "peak": FP4_PEAK_TFLOPS,
                                     "unit": "TFLOP/s", "frac": round(tf / FP4_PEAK_TFLOPS, 4),
                                     "launches_per_step": kp["launches"] / args.steps,

@@ -671,12 +671,18 @@ hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1, int64_
     if (!c.mfma || c.fmt != 0 || r <= TRSM_BLOCK) return trsm_diag(c, A, 0, r, xw0, xw1);
     // With fp4 products and several diagonal blocks: their inverses at once
     // (Y, on identities TRSM_BLOCK / 64 words wide instead of the right
-    // block's width), then for each block in order X_d <- L_dd^-1 X_d as a
-    // product, X_d += (L_dd^-1 + I) X_d (the product reads X_d through its
-    // bit transpose, so it may add into X_d), and the rows below lose X_d.
+    // block's width), then for each block in order: X_d loses the solved
+    // blocks above it, X_d^ = X_d + L[d][0, d0) X[0, d0), as one product with
+    // inner size d0 (the solved blocks' bit transposes kept side by side in
+    // Bs, one product's operand for every later block); then X_d <- L_dd^-1
+    // X_d as X_d += (L_dd^-1 + I) X_d (the product reads X_d through its bit
+    // transpose Bd, so it may add into X_d); then X_d's transpose joins Bs.
     constexpr int64_t ldy = TRSM_BLOCK / 64;
-    if ((size_t)r * ldy * 8 > c.tinv_bytes) return hipErrorInvalidValue;
-    uint64_t *Y = c.tinv;
+    const int64_t Np = 64 * (xw1 - xw0);  // whole words of columns (Bt is zero past N)
+    const int64_t ldbs = words_for(r);
+    if (((size_t)r + (size_t)Np) * ldy * 8 > c.tinv_bytes || (size_t)Np * ldbs * 8 > c.bt_bytes)
+        return hipErrorInvalidValue;
+    uint64_t *Y = c.tinv, *Bd = c.tinv + r * ldy, *Bs = c.bt;
     hipError_t e;
     if ((e = invert_diag_blocks(c, A, r, Y)) != hipSuccess) return e;
     {
@@ -685,15 +691,13 @@ hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1, int64_
                            1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    const int64_t Np = 64 * (xw1 - xw0);  // whole words of columns (Bt is zero past N)
     for (int64_t d0 = 0; d0 < r; d0 += TRSM_BLOCK) {
         const int64_t d1 = r - d0 < TRSM_BLOCK ? r : d0 + TRSM_BLOCK, K = d1 - d0;
-        const int64_t ldbt = words_for(K);
-        if ((size_t)words_for(N) * 64 * (size_t)ldbt * 8 > c.bt_bytes) return hipErrorInvalidValue;
-        if ((e = launch_transpose_bits(A + d0 * c.ldw + xw0, c.ldw, K, N, c.bt, ldbt, c.s)) != hipSuccess) return e;
-        if ((e = run_plan(c, A + d0 * c.ldw + xw0, c.ldw, Y + d0 * ldy, ldy, c.bt, ldbt, K, K, Np)) != hipSuccess)
-            return e;
-        if (d1 < r && (e = product(c, A, d1, r - d1, d0 >> 6, K, d0, xw0, xw1, N)) != hipSuccess) return e;
+        uint64_t *Xd = A + d0 * c.ldw + xw0;
+        if (d0 > 0 && (e = run_plan(c, Xd, c.ldw, A + d0 * c.ldw, c.ldw, Bs, ldbs, K, d0, Np)) != hipSuccess) return e;
+        if ((e = launch_transpose_bits(Xd, c.ldw, K, N, Bd, ldy, c.s)) != hipSuccess) return e;
+        if ((e = run_plan(c, Xd, c.ldw, Y + d0 * ldy, ldy, Bd, ldy, K, K, Np)) != hipSuccess) return e;
+        if (d1 < r && (e = launch_transpose_bits(Xd, c.ldw, K, N, Bs + (d0 >> 6), ldbs, c.s)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -758,13 +762,14 @@ size_t plan_bytes_for(int64_t m, int64_t n, int levels, bool mfma, int64_t split
     const int64_t k = m < n1 ? m : n1;
     return al((size_t)product_plan_ws_bound(m, k, n - n1) * 8);
 }
-// the solve's diagonal-block inverses: a row of TRSM_BLOCK bits per row of
-// the largest solve (the first split's rank, at most min(m, n1))
+// the solve's diagonal-block inverses, a row of TRSM_BLOCK bits per row of
+// the largest solve (the first split's rank, at most min(m, n1)), then one
+// block's bit transpose (a row of TRSM_BLOCK bits per column, n - n1 at most)
 size_t tinv_bytes_for(int64_t m, int64_t n, int levels, bool mfma, int64_t split) {
     if (!(mfma && levels > 0 && n > 64 && !(split > 0 && n <= split))) return 0;
     const int64_t n1 = split_cols(n, split);
     const int64_t k = m < n1 ? m : n1;
-    return al((size_t)k * (TRSM_BLOCK / 64) * 8);
+    return al(((size_t)k + (size_t)words_for(n - n1) * 64) * (TRSM_BLOCK / 64) * 8);
 }
 }  // namespace
 
