@@ -172,40 +172,47 @@ def _trsm_blocked_words(W, r, xw0, xw1):
     word lw then word lw + 1's bits below the lane), then the rows below the
     block take the block's rows selected by their words lw, lw + 1."""
     W = W.copy()
-    one = np.uint64(1)
     for b in range(0, r, 128):
-        nb = min(128, r - b)
-        lw = b // 64
-        for w in range(xw0, xw1):
-            x0 = [W[b + l, w] if l < nb else np.uint64(0) for l in range(64)]
-            x1 = [W[b + 64 + l, w] if 64 + l < nb else np.uint64(0) for l in range(64)]
-            below = [np.uint64(0) if l == 0 else np.uint64((1 << l) - 1) for l in range(64)]
-            l0 = [W[b + l, lw] & below[l] if l < nb else np.uint64(0) for l in range(64)]
-            l1a = [W[b + 64 + l, lw] if 64 + l < nb else np.uint64(0) for l in range(64)]
-            l1b = [W[b + 64 + l, lw + 1] & below[l] if 64 + l < nb else np.uint64(0) for l in range(64)]
-            for j in range(min(nb, 64)):
-                xj = x0[j]
-                for l in range(64):
-                    if (l0[l] >> np.uint64(j)) & one:
-                        x0[l] ^= xj
-                    if (l1a[l] >> np.uint64(j)) & one:
-                        x1[l] ^= xj
-            for j in range(max(0, nb - 64 - 1)):
-                xj = x1[j]
-                for l in range(64):
-                    if (l1b[l] >> np.uint64(j)) & one:
-                        x1[l] ^= xj
-            for l in range(64):
-                if l < nb:
-                    W[b + l, w] = x0[l]
-                if 64 + l < nb:
-                    W[b + 64 + l, w] = x1[l]
-        for i in range(b + nb, r):
-            c = [W[i, lw], W[i, lw + 1]]
-            for j in range(nb):
-                if (c[j >> 6] >> np.uint64(j & 63)) & one:
-                    W[i, xw0:xw1] ^= W[b + j, xw0:xw1]
+        _trsm_step_words(W, b, r, xw0, xw1)
     return W
+
+
+def _trsm_step_words(W, b, r, xw0, xw1):
+    """One 128-row step of the blocked solve, in place: rows b .. b + 127
+    (up to r) by forward substitution, then rows b + 128 .. r - 1 lose them,
+    on words [xw0, xw1)."""
+    one = np.uint64(1)
+    nb = min(128, r - b)
+    lw = b // 64
+    for w in range(xw0, xw1):
+        x0 = [W[b + l, w] if l < nb else np.uint64(0) for l in range(64)]
+        x1 = [W[b + 64 + l, w] if 64 + l < nb else np.uint64(0) for l in range(64)]
+        below = [np.uint64(0) if l == 0 else np.uint64((1 << l) - 1) for l in range(64)]
+        l0 = [W[b + l, lw] & below[l] if l < nb else np.uint64(0) for l in range(64)]
+        l1a = [W[b + 64 + l, lw] if 64 + l < nb else np.uint64(0) for l in range(64)]
+        l1b = [W[b + 64 + l, lw + 1] & below[l] if 64 + l < nb else np.uint64(0) for l in range(64)]
+        for j in range(min(nb, 64)):
+            xj = x0[j]
+            for l in range(64):
+                if (l0[l] >> np.uint64(j)) & one:
+                    x0[l] ^= xj
+                if (l1a[l] >> np.uint64(j)) & one:
+                    x1[l] ^= xj
+        for j in range(max(0, nb - 64 - 1)):
+            xj = x1[j]
+            for l in range(64):
+                if (l1b[l] >> np.uint64(j)) & one:
+                    x1[l] ^= xj
+        for l in range(64):
+            if l < nb:
+                W[b + l, w] = x0[l]
+            if 64 + l < nb:
+                W[b + 64 + l, w] = x1[l]
+    for i in range(b + nb, r):
+        c = [W[i, lw], W[i, lw + 1]]
+        for j in range(nb):
+            if (c[j >> 6] >> np.uint64(j & 63)) & one:
+                W[i, xw0:xw1] ^= W[b + j, xw0:xw1]
 
 
 @pytest.mark.parametrize("r,ncols,seed", [(300, 200, 1), (128, 70, 2), (129, 64, 3), (256, 130, 4), (64, 64, 5),
@@ -227,6 +234,79 @@ def test_blocked_trsm_words_equal_forward_substitution(r, ncols, seed):
     W = H.pack(M)
     xw0 = nl // 64
     got = H.unpack(_trsm_blocked_words(W, r, xw0, W.shape[1]), nl + ncols)[:, nl:]
+    X = Xb.astype(np.int64)
+    for i in range(r):
+        X[i] = (X[i] + Lb[i, :i].astype(np.int64) @ X[:i]) & 1
+    assert np.array_equal(got, X.astype(np.uint8))
+
+
+def _solve_by_inverses_words(W, r, xw0, blk):
+    """The solve as the library runs it with fp4 products and a rank above
+    one diagonal block: the inverses of the diagonal blocks L_dd (blk rows)
+    by the blocked forward substitution (_trsm_blocked_words) of each block
+    on its own identity, every 128-row step covering only the words up to
+    its rows' columns (an inverse's row has no bit past its own column);
+    then per block, left-looking, X_d += L[d][0, d0) X[0, d0) and
+    X_d += (L_dd^-1 + I) X_d, both as plain products mod 2."""
+    W = W.copy()
+    bw = blk // 64
+    nblk = (r + blk - 1) // blk
+    # Y: row i = row i - d0 of L_dd^-1, bw words, columns relative to d0
+    Y = np.zeros((r, bw), dtype=np.uint64)
+    for i in range(r):
+        rel = i % blk
+        Y[i, rel // 64] = np.uint64(1) << np.uint64(rel % 64)
+    for d in range(nblk):
+        d0, d1 = d * blk, min(r, (d + 1) * blk)
+        K = d1 - d0
+        # the block's L bits in its own columns (words d0 / 64 ..) next to Y
+        Lblk = H.unpack(W[d0:d1, :], W.shape[1] * 64)[:, d0:d1]
+        M = np.zeros((K, (K + 63) // 64 * 64 + blk), dtype=np.uint8)
+        M[:, :K] = Lblk
+        M[:, (K + 63) // 64 * 64:] = H.unpack(Y[d0:d1], blk)
+        Mw = H.pack(M)
+        xo = (K + 63) // 64
+        for b in range(0, K, 128):
+            # one 128-row step on the words up to its rows' columns only
+            _trsm_step_words(Mw, b, K, xo, xo + min(bw, (b + 128) // 64))
+        Y[d0:d1] = Mw[:, xo:xo + bw]
+    # N = Y + I
+    for i in range(r):
+        rel = i % blk
+        Y[i, rel // 64] ^= np.uint64(1) << np.uint64(rel % 64)
+    nx = W.shape[1] - xw0
+    X = H.unpack(W[:, xw0:], nx * 64).astype(np.int64)
+    Lbits = H.unpack(W, W.shape[1] * 64)[:, :r].astype(np.int64)
+    for d in range(nblk):
+        d0, d1 = d * blk, min(r, (d + 1) * blk)
+        if d0 > 0:
+            X[d0:d1] = (X[d0:d1] + Lbits[d0:d1, :d0] @ X[:d0]) & 1
+        N = H.unpack(Y[d0:d1], blk).astype(np.int64)[:, :d1 - d0]
+        X[d0:d1] = (X[d0:d1] + N @ X[d0:d1]) & 1
+    W[:, xw0:] = H.pack(X.astype(np.uint8), nx)
+    return W
+
+
+@pytest.mark.parametrize("r,ncols,blk,seed", [(300, 200, 128, 1), (520, 70, 256, 2), (1000, 130, 256, 3),
+                                              (384, 64, 128, 4), (257, 100, 128, 5)])
+def test_solve_by_block_inverses_equals_forward_substitution(r, ncols, blk, seed):
+    """The solve by the diagonal blocks' inverses, left-looking between the
+    blocks (X_d loses the solved blocks above it, then X_d += (L_dd^-1 + I)
+    X_d), equals plain forward substitution X <- L^-1 X for a random unit
+    lower triangular L, with random bits on and right of the diagonal of the
+    L part (the E part of those rows), which the solve must not read."""
+    rng = np.random.default_rng(seed)
+    nl = (r + 63) // 64 * 64
+    Lb = np.tril(rng.integers(0, 2, (r, r), dtype=np.uint8), -1)
+    Eb = np.triu(rng.integers(0, 2, (r, nl), dtype=np.uint8))
+    Xb = rng.integers(0, 2, (r, ncols), dtype=np.uint8)
+    M = np.zeros((r, nl + ncols), np.uint8)
+    M[:, :nl] = Eb
+    M[:, :r] |= Lb
+    M[:, nl:] = Xb
+    W = H.pack(M)
+    xw0 = nl // 64
+    got = H.unpack(_solve_by_inverses_words(W, r, xw0, blk), nl + ncols)[:, nl:]
     X = Xb.astype(np.int64)
     for i in range(r):
         X[i] = (X[i] + Lb[i, :i].astype(np.int64) @ X[:i]) & 1
