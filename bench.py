@@ -39,7 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 FP4_PEAK_TFLOPS = 10100.0
-TRSM_BLOCK = 4096  # Algorithm 3's diagonal blocks of the solve with fp4 products (csrc/alg3.hip)
+TRSM_BLOCK = 2048  # Algorithm 3's diagonal blocks of the solve with fp4 products (csrc/alg3.hip)
 KW = 64
 # HBM bytes per trailing-update launch on the 65536^2 seed-5 workload (the
 # default timed path: Algorithm 3 with one split at column 24576):

@@ -9,8 +9,10 @@
 //   2. A01 <- L00^-1 A01 on the first r1 rows of A1 (triangular solve, in
 //      blocks of 128 rows: each block's own forward substitution, then one
 //      Four-Russians sweep that removes the block from every row below it;
-//      with fp4 products, in diagonal blocks of 4096 rows solved that way,
-//      each removed from the rows below by one product);
+//      with fp4 products and a rank above one diagonal block of TRSM_BLOCK
+//      rows, the inverses of all diagonal blocks are computed that way at
+//      once, then each block, in order, loses the solved blocks above it
+//      and is multiplied by its inverse, both as products);
 //   3. A11 <- A11 + L10 A01 (the product that Algorithm 3 hands to matrix
 //      multiplication);
 //   4. PLE of A11 (rows r1.., columns n1..), again moving whole rows, so the
@@ -627,7 +629,7 @@ hipError_t trsm_diag(Ctx &c, uint64_t *A, int64_t d0, int64_t d1, int64_t xw0, i
 // every row below it by one product (inner size TRSM_BLOCK) instead of
 // TRSM_BLOCK / 128 sweeps.  (The int8 product is too slow at this inner size
 // to gain from it.)
-constexpr int64_t TRSM_BLOCK = 4096;
+constexpr int64_t TRSM_BLOCK = 2048;
 
 // The inverses of the diagonal blocks L_dd of L (rows [0, r), blocks of
 // TRSM_BLOCK rows, d0 a multiple of it) into Y (row i: row i - d0 of L_dd^-1,
