@@ -789,8 +789,8 @@ def run_helpers(m, n, A, Qh, r, log_fn):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--cpu-cols", type=int, default=4096,
