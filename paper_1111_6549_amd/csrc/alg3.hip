@@ -550,14 +550,16 @@ hipError_t run_plan(Ctx &c, uint64_t *C, int64_t ldc, const uint64_t *Aop, int64
     return hipSuccess;
 }
 
+// bt_ready: c.bt already holds the right operand's bit transpose (words_for(K)
+// words per row), as the solve leaves it.
 hipError_t product(Ctx &c, uint64_t *A, int64_t crow0, int64_t M, int64_t kw0, int64_t K, int64_t brow0, int64_t xw0,
-                   int64_t xw1, int64_t N) {
+                   int64_t xw1, int64_t N, bool bt_ready = false) {
     if (M <= 0 || K <= 0 || N <= 0) return hipSuccess;
     const int64_t ldw = c.ldw;
     if (c.mfma && K >= MFMA_MIN_K) {
         const int64_t ldbt = words_for(K);
         if ((size_t)words_for(N) * 64 * (size_t)ldbt * 8 > c.bt_bytes) return hipErrorInvalidValue;
-        hipError_t e = launch_transpose_bits(A + brow0 * ldw + xw0, ldw, K, N, c.bt, ldbt, c.s);
+        hipError_t e = bt_ready ? hipSuccess : launch_transpose_bits(A + brow0 * ldw + xw0, ldw, K, N, c.bt, ldbt, c.s);
         if (e != hipSuccess) return e;
         // (the plan takes whole words of columns: Bt's rows past N are zero)
         if (c.fmt == 0)
@@ -670,7 +672,10 @@ hipError_t invert_diag_blocks(Ctx &c, const uint64_t *A, int64_t r, uint64_t *Y)
 
 // rows [0, r) of X = A[.][xw0, xw1) <- L^-1 X, with L the unit lower
 // triangle of A[0 .. r)[0 .. r)
-hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1, int64_t N) {
+// *bt_x: set when c.bt holds X's bit transpose afterwards (words_for(r) words
+// per column of X), the right operand of the Schur product.
+hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1, int64_t N, bool *bt_x) {
+    *bt_x = false;
     if (!c.mfma || c.fmt != 0 || r <= TRSM_BLOCK) return trsm_diag(c, A, 0, r, xw0, xw1);
     // With fp4 products and several diagonal blocks: their inverses at once
     // (Y, on identities TRSM_BLOCK / 64 words wide instead of the right
@@ -679,7 +684,8 @@ hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1, int64_
     // inner size d0 (the solved blocks' bit transposes kept side by side in
     // Bs, one product's operand for every later block); then X_d <- L_dd^-1
     // X_d as X_d += (L_dd^-1 + I) X_d (the product reads X_d through its bit
-    // transpose Bd, so it may add into X_d); then X_d's transpose joins Bs.
+    // transpose Bd, so it may add into X_d); then X_d's transpose joins Bs,
+    // which in the end is X's, the Schur product's right operand.
     constexpr int64_t ldy = TRSM_BLOCK / 64;
     const int64_t Np = 64 * (xw1 - xw0);  // whole words of columns (Bt is zero past N)
     const int64_t ldbs = words_for(r);
@@ -700,8 +706,9 @@ hipError_t trsm(Ctx &c, uint64_t *A, int64_t r, int64_t xw0, int64_t xw1, int64_
         if (d0 > 0 && (e = run_plan(c, Xd, c.ldw, A + d0 * c.ldw, c.ldw, Bs, ldbs, K, d0, Np)) != hipSuccess) return e;
         if ((e = launch_transpose_bits(Xd, c.ldw, K, N, Bd, ldy, c.s)) != hipSuccess) return e;
         if ((e = run_plan(c, Xd, c.ldw, Y + d0 * ldy, ldy, Bd, ldy, K, K, Np)) != hipSuccess) return e;
-        if (d1 < r && (e = launch_transpose_bits(Xd, c.ldw, K, N, Bs + (d0 >> 6), ldbs, c.s)) != hipSuccess) return e;
+        if ((e = launch_transpose_bits(Xd, c.ldw, K, N, Bs + (d0 >> 6), ldbs, c.s)) != hipSuccess) return e;
     }
+    *bt_x = true;
     return hipSuccess;
 }
 
@@ -719,8 +726,9 @@ hipError_t ple_rec(Ctx &c, uint64_t *A, int64_t m, int64_t n, int64_t *P, int64_
     if ((e = hipStreamSynchronize(c.s)) != hipSuccess) return e;
     const int64_t xw0 = n1 >> 6, xw1 = words_for(n), N = n - n1;
     if (r1 > 0) {
-        if ((e = trsm(c, A, r1, xw0, xw1, N)) != hipSuccess) return e;
-        if ((e = product(c, A, r1, m - r1, 0, r1, 0, xw0, xw1, N)) != hipSuccess) return e;
+        bool bt_x = false;
+        if ((e = trsm(c, A, r1, xw0, xw1, N, &bt_x)) != hipSuccess) return e;
+        if ((e = product(c, A, r1, m - r1, 0, r1, 0, xw0, xw1, N, bt_x)) != hipSuccess) return e;
     }
     if (m <= r1) return hipSuccess;  // then min(m, n) = r1: P and Q are complete
     int64_t *r2 = c.rank_slots + depth;
