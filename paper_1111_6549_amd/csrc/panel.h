@@ -105,24 +105,384 @@ struct PairPanel {
     int32_t *gsid = nullptr;
 };
 
+// Slow search bookkeeping: a row with a zero stripe word sits at position
+// npiv and goes to position `found` (the pivot's).  Lane d of dzp/dzi holds
+// the d-th such row: where it is now and where it started (-1: none).  A row
+// moved before moves on; at most one new row per pivot.
+__device__ __forceinline__ void move_zero_row(int &dzp, int &dzi, const int npiv, const int found, const int lane) {
+    if (__ballot(dzp == npiv)) {
+        dzp = dzp == npiv ? found : dzp;
+    } else {
+        const int nd = __popcll(__ballot(dzp >= 0));
+        if (lane == nd) {
+            dzp = found;
+            dzi = npiv;
+        }
+    }
+}
+
+// The special-row list of a slow search, finished by one wave: entries
+// [npiv, nsp) already hold the kept rows that moved, in any order.  Adds the
+// pivots in order at [0, npiv) and the zero-word rows that moved, then ranks
+// the displaced rows (at most npiv) by position.  Returns the list's length.
+template <int SR>
+__device__ __forceinline__ int finish_special(PanelLdsT<SR> &L, const int64_t r, const int npiv, int nsp,
+                                              const int my_id, const int dzp, const int dzi, const int lane) {
+    const uint64_t lt = (1ull << lane) - 1ull;
+    if (lane < npiv) {
+        L.dst[lane] = r + lane;
+        L.src[lane] = r + my_id;
+    }
+    {
+        const uint64_t msk = __ballot(dzp >= 0);
+        if (dzp >= 0) {
+            const int idx = nsp + __popcll(msk & lt);
+            L.dst[idx] = r + dzp;
+            L.src[idx] = r + dzi;
+        }
+        nsp += __popcll(msk);
+    }
+    const int nspec = uni(nsp);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int nd = nspec - npiv;  // <= npiv <= 64
+    int64_t dd = 0, ds = 0;
+    if (lane < nd) {
+        dd = L.dst[npiv + lane];
+        ds = L.src[npiv + lane];
+    }
+    const int dpos = (int)(dd - r);
+    int rank = 0;
+    for (int k = 0; k < nd; k++) rank += readlane32(dpos, k) < dpos ? 1 : 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane < nd) {
+        L.dst[npiv + rank] = dd;
+        L.src[npiv + rank] = ds;
+    }
+    return nspec;
+}
+
+// ---- the slow search on every wave of the block ----------------------------
+// When the panel has a block of NW waves, its slow search runs on all of
+// them.  The scan over the remaining rows is split into rounds of NW * 64 * 4
+// rows, one part per wave, and the kept rows (non-zero stripe word, in row
+// order) are staged in LDS, then taken into registers: slot k lives in
+// register k / (64 NW) of wave (k / 64) % NW, lane k % 64, so each wave's
+// slots ascend with its register and lane.  A column then costs one barrier:
+// every wave posts its first active slot and its first active slot with the
+// column's bit, every wave reads the NW posts and takes the smallest, and
+// all apply the same move and the same elimination to the slots they hold.
+// The slot rules are those of the one-wave search below (a slot keeps its
+// position, a swap exchanges word and first position, a pivot that takes a
+// zero row's place retires); the elimination is eager: each pivot leaves
+// every active slot that has its bit at once.
+constexpr int MW_SLOTS = 8192;  // kept rows held in registers, over all waves
+
+// Minimum and sum over lanes 0..15 (one DPP row), in each of those lanes:
+// exchanges within pairs, within quads, across the two quads of each half
+// and across the two halves.
+__device__ __forceinline__ int row16_min(int v) {
+    int o = __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    v = o < v ? o : v;
+    o = __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    v = o < v ? o : v;
+    o = __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    v = o < v ? o : v;
+    o = __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    return o < v ? o : v;
+}
+__device__ __forceinline__ int row16_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);
+    return v + __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false);
+}
+
+// LDS exchange of the multi-wave search.
+template <int NW>
+struct MwX {
+    struct Post {
+        uint64_t word;
+        int32_t slot, pos, id, pad;
+    };
+    Post fm[2][NW], fa[2][NW];  // per column, alternating: first slot with the bit, first active slot
+    int32_t cnt[2][NW];         // per scan round, alternating: kept rows of each wave
+    uint64_t orv[NW];
+    int32_t lcount, flag;
+};
+
+// Where the multi-wave search stages the kept rows (LDS, cap entries) and
+// keeps its exchange (an MwX<NW>), and the one-wave search's LDS arrays
+// (word, position, first position), to which it hands few kept rows.
+struct MwCtx {
+    void *x = nullptr;
+    uint64_t *stv = nullptr;
+    int32_t *stp = nullptr;
+    int cap = 0;
+    uint64_t *hv = nullptr;
+    int32_t *hp = nullptr, *hi = nullptr;
+};
+
+// Up to this many kept rows the one-wave search (a barrier-free step per
+// column) takes over from the multi-wave one after the shared scan.
+constexpr int MW_HANDOFF = 512;
+enum MwResult { MW_FALLBACK = 0, MW_HANDED = 1, MW_DONE = 2 };
+
+// The column search of the multi-wave slow search over the first RR of the
+// R registers of slots (the others are empty).  One barrier per column with
+// a possible pivot: every wave posts its first active slot and its first
+// active slot with the column's bit, then reads all NW posts at once (lane w
+// takes wave w's) and picks the smallest from its lanes.
+template <int NW, int RR, int R>
+__device__ __forceinline__ void mw_columns(MwX<NW> &X, uint64_t (&wd)[R], int (&cpos)[R], int (&cid)[R],
+                                           const int lane, const int wave, const uint64_t orv, const int kp,
+                                           const int64_t rows, int &npiv, int &my_q, uint64_t &my_fin, int &my_p,
+                                           int &my_id, int &dzp, int &dzi) {
+    using Post = typename MwX<NW>::Post;
+    uint64_t or_pe = 0;
+    int par = 0;
+    for (int j = 0; j < kp && npiv < rows; j++) {
+        if (!(((orv | or_pe) >> j) & 1ull)) continue;  // no row can have a 1 here
+        // this wave's first active slot (register qa, lane la) and first
+        // active slot with bit j (qm, lm); each lane keeps its own entry of
+        // the register they are in.  Empty slots are never active.
+        int qa = RR, qm = RR, la = 0, lm = 0;
+        uint64_t wa = 0, wm = 0;
+        int pa = 0, ia = 0, pm = 0, im = 0;
+#pragma unroll
+        for (int q = 0; q < RR; q++) {
+            if (qm == RR) {
+                const bool act = cpos[q] >= npiv;
+                const uint64_t am = __ballot(act);
+                const uint64_t cm = __ballot(act && ((wd[q] >> j) & 1ull));
+                if (qa == RR && am) {
+                    qa = q;
+                    la = (int)__builtin_ctzll(am);
+                    wa = wd[q];
+                    pa = cpos[q];
+                    ia = cid[q];
+                }
+                if (cm) {
+                    qm = q;
+                    lm = (int)__builtin_ctzll(cm);
+                    wm = wd[q];
+                    pm = cpos[q];
+                    im = cid[q];
+                }
+            }
+        }
+        // the lanes that hold them post them (lane 0 posts "none")
+        if (lane == la) X.fa[par][wave] = Post{wa, qa == RR ? INT32_MAX : (qa * NW + wave) * 64 + la, pa, ia, 0};
+        if (lane == lm) X.fm[par][wave] = Post{wm, qm == RR ? INT32_MAX : (qm * NW + wave) * 64 + lm, pm, im, 0};
+        __syncthreads();
+        Post ea, em;
+        ea.slot = em.slot = INT32_MAX;
+        if (lane < NW) {
+            ea = X.fa[par][lane];
+            em = X.fm[par][lane];
+        }
+        par ^= 1;  // the next column posts to the other half: no second barrier
+        // the smallest posts (slot numbers are distinct)
+        const int h = uni(row16_min(ea.slot)), kf = uni(row16_min(em.slot));
+        if (kf == INT32_MAX) continue;  // column j has no pivot
+        const int wh = (int)__builtin_ctzll(__ballot(ea.slot == h));
+        const int wf = (int)__builtin_ctzll(__ballot(em.slot == kf));
+        const uint64_t pv = readlane64(em.word, wf), vh = readlane64(ea.word, wh);
+        const int found = readlane32(em.pos, wf), pid = readlane32(em.id, wf);
+        const int ph = readlane32(ea.pos, wh), idh = readlane32(ea.id, wh);
+        // owners: the slot's lane in this wave (-1: another wave's) and register
+        const int lf = (kf >> 6) % NW == wave ? (kf & 63) : -1, rf = (kf >> 6) / NW;
+        const int lh = (h >> 6) % NW == wave ? (h & 63) : -1, rh = (h >> 6) / NW;
+        if (ph == npiv) {
+            // the row at npiv is slot h: h now holds the pivot and kf that row
+            // (kf == h: the pivot is in place)
+            if (kf != h) {
+#pragma unroll
+                for (int q = 0; q < RR; q++) {
+                    const bool th = q == rh && lane == lh;
+                    const bool tf = q == rf && lane == lf;
+                    wd[q] = th ? pv : (tf ? vh : wd[q]);
+                    cid[q] = th ? pid : (tf ? idh : cid[q]);
+                }
+            }
+        } else {
+            // a row with a zero stripe word is at npiv: it takes the pivot's
+            // place, and the pivot's slot retires
+#pragma unroll
+            for (int q = 0; q < RR; q++)
+                if (q == rf && lane == lf) cpos[q] = -1;
+            move_zero_row(dzp, dzi, npiv, found, lane);
+        }
+        // every later active slot with bit j leaves it
+        const uint64_t pe = pv & above(j);
+#pragma unroll
+        for (int q = 0; q < RR; q++) {
+            const bool e = cpos[q] > npiv && ((wd[q] >> j) & 1ull);
+            wd[q] = e ? wd[q] ^ pe : wd[q];
+        }
+        my_q = writelane32(my_q, j, npiv);
+        my_fin = writelane64(my_fin, pv, npiv);
+        my_p = writelane32(my_p, found, npiv);
+        my_id = writelane32(my_id, pid, npiv);
+        or_pe |= pe;
+        npiv++;
+    }
+}
+
+// Run by every wave of the block (wave = its index, uniform); the result is
+// the same on every wave.  MW_FALLBACK: the kept rows exceed what the
+// registers or the staging hold (nothing was written but the exchange and
+// the staging).  MW_HANDED: at most MW_HANDOFF kept rows, now in the one-wave
+// search's arrays (nc_out, orv_out: their count and union).  MW_DONE: wave 0
+// holds the pivots (lane l: column, reduced stripe word, position found) and
+// L the special rows.
+template <int NW, int SR>
+__device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int64_t ldw, const int64_t sw,
+                                                   const int64_t r, const int64_t rows, const uint64_t kmask,
+                                                   const int kp, const int lane, const int wave, const MwCtx &mc,
+                                                   PanelLdsT<SR> &L, int &npiv_out, int &my_q, uint64_t &my_fin,
+                                                   int &my_p, int &nspec_out, int &nc_out, uint64_t &orv_out) {
+    constexpr int R = MW_SLOTS / (NW * 64);  // slots per lane
+    constexpr int SB = 4;                    // row loads in flight per lane
+    static_assert(R * NW * 64 == MW_SLOTS, "slots per lane");
+    static_assert(NW <= 16, "the waves' posts fit one DPP row");
+    MwX<NW> &X = *(MwX<NW> *)mc.x;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int cap = mc.cap < MW_SLOTS ? mc.cap : MW_SLOTS;
+    if (wave == 0 && lane == 0) X.lcount = 0;
+
+    // ---- scan: every wave takes 64 * SB rows of each round ----
+    int nc = 0, par = 0;
+    uint64_t orv = 0;
+    for (int64_t b0 = 0; b0 < rows; b0 += (int64_t)NW * 64 * SB) {
+        const int64_t wb = b0 + (int64_t)wave * 64 * SB;
+        uint64_t v[SB];
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+            const int64_t pos = wb + 64 * u + lane;
+            v[u] = ld_stripe(A + (r + (pos < rows ? pos : rows - 1)) * ldw + sw);
+        }
+        int cw = 0;
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+            v[u] = wb + 64 * u + lane < rows ? v[u] & kmask : 0ull;
+            cw += __popcll(__ballot(v[u] != 0));
+            orv |= v[u];
+        }
+        if (lane == 0) X.cnt[par][wave] = cw;
+        __syncthreads();
+        // this wave's first slot: the rows the waves before it keep
+        const int cl = lane < NW ? X.cnt[par][lane] : 0;
+        const int total = uni(row16_sum(cl));
+        int k0 = nc + uni(row16_sum(lane < wave ? cl : 0));
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+            const uint64_t msk = __ballot(v[u] != 0);
+            const int k = k0 + __popcll(msk & lt);
+            if (v[u] && k < cap) {
+                mc.stv[k] = v[u];
+                mc.stp[k] = (int32_t)(wb + 64 * u + lane);
+            }
+            k0 += __popcll(msk);
+        }
+        nc += total;
+        par ^= 1;
+    }
+    orv = wave_or64(orv);
+    if (lane == 0) X.orv[wave] = orv;
+    __syncthreads();  // also completes the staging
+    orv = wave_or64(lane < NW ? X.orv[lane] : 0ull);
+    if (nc > cap) return MW_FALLBACK;
+    if (nc <= MW_HANDOFF) {
+        for (int k = wave * 64 + lane; k < nc; k += NW * 64) {
+            if (mc.hv != mc.stv) mc.hv[k] = mc.stv[k];
+            const int32_t p = mc.stp[k];
+            mc.hp[k] = p;
+            mc.hi[k] = p;
+        }
+        __syncthreads();
+        nc_out = nc;
+        orv_out = orv;
+        return MW_HANDED;
+    }
+
+    // ---- the kept rows into registers ----
+    uint64_t wd[R];
+    int cpos[R], cid[R];  // position now (-1: retired or empty), first position
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const int k = (q * NW + wave) * 64 + lane;
+        const bool in = k < nc;
+        wd[q] = in ? mc.stv[k] : 0ull;
+        cpos[q] = in ? mc.stp[k] : -1;
+        cid[q] = cpos[q];
+    }
+
+    // ---- column search, on the registers in use ----
+    my_q = 0;
+    my_fin = 0;
+    my_p = 0;
+    int npiv = 0, dzp = -1, dzi = 0, my_id = 0;
+    static_assert(R == 8, "register counts 1, 2, 4, 8");
+    const int rr = (nc + NW * 64 - 1) / (NW * 64);
+    if (rr <= 1)
+        mw_columns<NW, 1, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+    else if (rr <= 2)
+        mw_columns<NW, 2, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+    else if (rr <= 4)
+        mw_columns<NW, 4, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+    else
+        mw_columns<NW, 8, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+
+    // ---- kept rows that moved: listed after the pivots, in any order ----
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const bool f = cpos[q] >= npiv && cpos[q] != cid[q];
+        const uint64_t msk = __ballot(f);
+        if (msk) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&X.lcount, (int)__popcll(msk));
+            base = uni(base);
+            if (f) {
+                const int idx = npiv + base + __popcll(msk & lt);
+                L.dst[idx] = r + cpos[q];
+                L.src[idx] = r + cid[q];
+            }
+        }
+    }
+    __syncthreads();
+    npiv_out = npiv;
+    if (wave != 0) return MW_DONE;
+    nspec_out = finish_special(L, r, npiv, npiv + uni(X.lcount), my_id, dzp, dzi, lane);
+    return MW_DONE;
+}
+
 // One wave (lane = threadIdx.x & 63) computes the panel of the stripe at
 // column c.  `prev` is the previous pass's record (its r + rbar is this
 // pass's r; it is read before `rec` is written, so the two may be the same
 // record), `rec` receives this pass.  Writes P[r..r+rbar), Q[r..r+rbar)
-// and *rank_out = r + rbar.
-template <int WQ, int SR, bool KEPT = true>
+// and *rank_out = r + rbar.  With NW > 1 every wave of the block calls it
+// (`wave` = its index): wave 0 runs the panel, and the others join it for
+// the slow search (mc: its LDS).
+template <int WQ, int SR, bool KEPT = true, int NW = 1>
 __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c,
                                            const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
                                            int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelLdsT<SR> &L,
-                                           const int lane, PanelFix fix = PanelFix()) {
+                                           const int lane, PanelFix fix = PanelFix(), const int wave = 0,
+                                           const MwCtx &mc = MwCtx()) {
+    static_assert(NW == 1 || (WQ == 2 && KEPT && SR >= MW_HANDOFF), "the multi-wave slow search follows the "
+                                                                     "two-register window");
 #ifdef GF2_PANEL_TIMING
     uint64_t *dbg = gsv + (c >> 6) * 8;
     uint64_t *dbg2 = gsv + 2048 + (c >> 6) * 8;  // phase sums of the kept-row search
 #define PANEL_STAMP(k) \
-    if (lane == 0) dbg[k] = wall_clock64();
+    if (lane == 0 && wave == 0) dbg[k] = wall_clock64();
 #define PANEL_T0(t) const uint64_t t = wall_clock64();
 #define PANEL_ACC(k, t) \
-    if (lane == 0) dbg2[k] += wall_clock64() - t;
+    if (lane == 0 && wave == 0) dbg2[k] += wall_clock64() - t;
 #else
 #define PANEL_STAMP(k)
 #define PANEL_T0(t)
@@ -135,9 +495,9 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
     // other paths read rows back from A, so the fix completes first
     const bool patch = WQ == 2 && fix.mode != 0 && r < m && c < n;
     auto run_fix = [&](const bool wait) -> FixOut { return fix_from_record(A, ldw, c >> 6, prev, lane, wait); };
-    if (fix.mode != 0 && c < n && !patch) run_fix(true);
+    if (fix.mode != 0 && c < n && !patch && wave == 0) run_fix(true);
     if (r >= m || c >= n) {
-        if (lane == 0) {
+        if (lane == 0 && wave == 0) {
             rec->r = r;
             rec->rbar = 0;
             rec->nspec = 0;
@@ -151,6 +511,15 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
     const uint64_t kmask = kp == 64 ? ~0ull : ((1ull << kp) - 1);
     const int64_t sw = c >> 6;
     const int64_t rows = m - r;
+    // The other waves stay for the slow search only when the previous pass
+    // needed one (sparse stripes come in runs); otherwise wave 0 goes on alone
+    // and no barrier is taken.  (With prev == rec, wave 0 may rewrite the
+    // flag before another wave reads it: then always alone.)
+    bool mw = false;
+    if constexpr (NW > 1) {
+        mw = prev != rec && prev->slow != 0;
+        if (!mw && wave != 0) return;
+    }
 
     // lane l keeps pivot l: stripe column, reduced stripe word, window position
     int my_q = 0;
@@ -161,318 +530,323 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
     bool slow = false;
 
     // ---- search over a register window ---------------------------------------
-    if constexpr (WQ == 2) {
-        // Two registers (128 rows), loaded at once, kept as 32-bit halves:
-        // lane l holds positions l (x0) and 64 + l (x1).  Per column the
-        // candidate masks are ballots of one half, the pivot is their first
-        // set bit, and every move is a select on a scalar lane mask: the
-        // rows with the bit (but the pivot) get the pivot's part above the
-        // column, the row at npiv moves to the pivot's place and the pivot
-        // row to npiv.  Positions below npiv are never written again, so at
-        // the end they hold the pivot rows as found.  No branch but the exit.
-        const int nmax = (int)(rows < 128 ? rows : 128);
-        uint32_t x0l, x0h, x1l, x1h;
-        {
-            const int64_t row0 = r + (lane < rows ? lane : rows - 1);
-            const int64_t row1 = r + (64 + lane < rows ? 64 + lane : rows - 1);
-            // the fix's record entries load first (every entry, masked once
-            // the header is in), so waiting for them never waits for the
-            // stripe words behind them
-            FixOut fo;
-            int fa = 0, fnr = 0;
-            if (patch) {
-                fa = prev->active;
-                fnr = prev->nspec;
-                fo.d0 = prev->spec_dst[lane];
-                fo.d1 = prev->spec_dst[64 + lane];
-                fo.n0 = prev->spec_next[lane];
-                fo.n1 = prev->spec_next[64 + lane];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            uint64_t t0 = ld_stripe(A + row0 * ldw + sw);
-            uint64_t t1 = ld_stripe(A + row1 * ldw + sw);
-            __builtin_amdgcn_sched_barrier(0);
-            if (patch) {
-                // the previous pass(es)' special rows in the window: their
-                // loaded words are stale, the fix's new words replace them
-                // (LDS scratch of this wave: its LDS accesses execute in
-                // program order, and the compiler barriers keep that order)
-                const int fn = fa ? fnr : 0;
-                if (lane >= fn) fo.d0 = -1;
-                if (64 + lane >= fn) fo.d1 = -1;
-                if (fo.d0 >= 0) A[fo.d0 * ldw + sw] = fo.n0;
-                if (fo.d1 >= 0) A[fo.d1 * ldw + sw] = fo.n1;
-                int64_t *pf = L.src;
-                uint64_t *pw = (uint64_t *)L.dst;
-                pf[lane] = -1;
-                pf[64 + lane] = -1;
-                lds_order();
-                if (fo.d0 >= r && fo.d0 < r + 128) {
-                    pw[fo.d0 - r] = fo.n0;
-                    pf[fo.d0 - r] = 1;
+    // (wave 0 alone when the block has several)
+    if (NW == 1 || wave == 0) {
+        if constexpr (WQ == 2) {
+            // Two registers (128 rows), loaded at once, kept as 32-bit halves:
+            // lane l holds positions l (x0) and 64 + l (x1).  Per column the
+            // candidate masks are ballots of one half, the pivot is their first
+            // set bit, and every move is a select on a scalar lane mask: the
+            // rows with the bit (but the pivot) get the pivot's part above the
+            // column, the row at npiv moves to the pivot's place and the pivot
+            // row to npiv.  Positions below npiv are never written again, so at
+            // the end they hold the pivot rows as found.  No branch but the exit.
+            const int nmax = (int)(rows < 128 ? rows : 128);
+            uint32_t x0l, x0h, x1l, x1h;
+            {
+                const int64_t row0 = r + (lane < rows ? lane : rows - 1);
+                const int64_t row1 = r + (64 + lane < rows ? 64 + lane : rows - 1);
+                // the fix's record entries load first (every entry, masked once
+                // the header is in), so waiting for them never waits for the
+                // stripe words behind them
+                FixOut fo;
+                int fa = 0, fnr = 0;
+                if (patch) {
+                    fa = prev->active;
+                    fnr = prev->nspec;
+                    fo.d0 = prev->spec_dst[lane];
+                    fo.d1 = prev->spec_dst[64 + lane];
+                    fo.n0 = prev->spec_next[lane];
+                    fo.n1 = prev->spec_next[64 + lane];
                 }
-                if (fo.d1 >= r && fo.d1 < r + 128) {
-                    pw[fo.d1 - r] = fo.n1;
-                    pf[fo.d1 - r] = 1;
+                __builtin_amdgcn_sched_barrier(0);
+                uint64_t t0 = ld_stripe(A + row0 * ldw + sw);
+                uint64_t t1 = ld_stripe(A + row1 * ldw + sw);
+                __builtin_amdgcn_sched_barrier(0);
+                if (patch) {
+                    // the previous pass(es)' special rows in the window: their
+                    // loaded words are stale, the fix's new words replace them
+                    // (LDS scratch of this wave: its LDS accesses execute in
+                    // program order, and the compiler barriers keep that order)
+                    const int fn = fa ? fnr : 0;
+                    if (lane >= fn) fo.d0 = -1;
+                    if (64 + lane >= fn) fo.d1 = -1;
+                    if (fo.d0 >= 0) A[fo.d0 * ldw + sw] = fo.n0;
+                    if (fo.d1 >= 0) A[fo.d1 * ldw + sw] = fo.n1;
+                    int64_t *pf = L.src;
+                    uint64_t *pw = (uint64_t *)L.dst;
+                    pf[lane] = -1;
+                    pf[64 + lane] = -1;
+                    lds_order();
+                    if (fo.d0 >= r && fo.d0 < r + 128) {
+                        pw[fo.d0 - r] = fo.n0;
+                        pf[fo.d0 - r] = 1;
+                    }
+                    if (fo.d1 >= r && fo.d1 < r + 128) {
+                        pw[fo.d1 - r] = fo.n1;
+                        pf[fo.d1 - r] = 1;
+                    }
+                    lds_order();
+                    if (pf[lane] >= 0) t0 = pw[lane];
+                    if (pf[64 + lane] >= 0) t1 = pw[64 + lane];
+                    lds_order();
                 }
-                lds_order();
-                if (pf[lane] >= 0) t0 = pw[lane];
-                if (pf[64 + lane] >= 0) t1 = pw[64 + lane];
-                lds_order();
+                const uint64_t v0 = lane < nmax ? (t0 & kmask) : 0ull;
+                const uint64_t v1 = 64 + lane < nmax ? (t1 & kmask) : 0ull;
+                x0l = (uint32_t)v0;
+                x0h = (uint32_t)(v0 >> 32);
+                x1l = (uint32_t)v1;
+                x1h = (uint32_t)(v1 >> 32);
             }
-            const uint64_t v0 = lane < nmax ? (t0 & kmask) : 0ull;
-            const uint64_t v1 = 64 + lane < nmax ? (t1 & kmask) : 0ull;
-            x0l = (uint32_t)v0;
-            x0h = (uint32_t)(v0 >> 32);
-            x1l = (uint32_t)v1;
-            x1h = (uint32_t)(v1 >> 32);
-        }
-        PANEL_STAMP(1)
-        int id0 = lane, id1 = 64 + lane;  // original position of the row each lane holds
-        uint64_t act0 = nmax >= 64 ? ~0ull : ((1ull << nmax) - 1ull);
-        uint64_t act1 = nmax >= 128 ? ~0ull : (nmax <= 64 ? 0ull : ((1ull << (nmax - 64)) - 1ull));
-        int my_qp = 0;  // pivot column | (window position where it was found) << 8
-        // Columns [jb, je) of one half (HI: the high half holds their bits).
-        // The inner loop takes the usual column, whose pivot is in register
-        // 0, without a branch; a column with no candidate in register 0
-        // leaves it for the general step (pivot in register 1, no pivot, or
-        // rows past the window).  Once every row is a pivot, the candidate
-        // masks are empty and the remaining columns cost a ballot each.
-        bool go = true;
-        auto run = [&](const int jb, const int je, const bool HI) {
-            int j = jb;
-            while (j < je && go) {
-                // one exit: m0 is empty when column j has no candidate in
-                // register 0 or j reaches je
-                uint64_t m0 = __ballot(((HI ? x0h : x0l) & (1u << (j & 31))) != 0) & act0;
-                while (m0) {
+            PANEL_STAMP(1)
+            int id0 = lane, id1 = 64 + lane;  // original position of the row each lane holds
+            uint64_t act0 = nmax >= 64 ? ~0ull : ((1ull << nmax) - 1ull);
+            uint64_t act1 = nmax >= 128 ? ~0ull : (nmax <= 64 ? 0ull : ((1ull << (nmax - 64)) - 1ull));
+            int my_qp = 0;  // pivot column | (window position where it was found) << 8
+            // Columns [jb, je) of one half (HI: the high half holds their bits).
+            // The inner loop takes the usual column, whose pivot is in register
+            // 0, without a branch; a column with no candidate in register 0
+            // leaves it for the general step (pivot in register 1, no pivot, or
+            // rows past the window).  Once every row is a pivot, the candidate
+            // masks are empty and the remaining columns cost a ballot each.
+            bool go = true;
+            auto run = [&](const int jb, const int je, const bool HI) {
+                int j = jb;
+                while (j < je && go) {
+                    // one exit: m0 is empty when column j has no candidate in
+                    // register 0 or j reaches je
+                    uint64_t m0 = __ballot(((HI ? x0h : x0l) & (1u << (j & 31))) != 0) & act0;
+                    while (m0) {
+                        const uint32_t bj = 1u << (j & 31);
+                        const uint64_t m1 = __ballot(((HI ? x1h : x1l) & bj) != 0) & act1;
+                        const int lf = (int)__builtin_ctzll(m0);
+                        const uint32_t pvl = (uint32_t)readlane32((int)x0l, lf);
+                        const uint32_t pvh = (uint32_t)readlane32((int)x0h, lf);
+                        const int idp = readlane32(id0, lf);
+                        const uint32_t vrl = (uint32_t)readlane32((int)x0l, npiv);
+                        const uint32_t vrh = (uint32_t)readlane32((int)x0h, npiv);
+                        const int idr = readlane32(id0, npiv);
+                        // the pivot's part strictly above column j leaves the other
+                        // rows that have the bit
+                        const uint32_t pel = HI ? 0u : (j == 31 ? 0u : pvl & (~0u << (j + 1)));
+                        const uint32_t peh = HI ? (j == 63 ? 0u : pvh & (~0u << ((j & 31) + 1))) : pvh;
+                        const uint64_t lbit = 1ull << lf, nbit = 1ull << npiv;
+                        // lane masks as all-ones/zero words, opaque to the compiler,
+                        // so that each update below is one three-input logic
+                        // instruction with the scalar operand (a select on a scalar
+                        // mask would first copy the scalar into a vector register)
+                        uint32_t e0 = __builtin_amdgcn_inverse_ballot_w64(m0 & ~lbit) ? ~0u : 0u;
+                        uint32_t e1 = __builtin_amdgcn_inverse_ballot_w64(m1) ? ~0u : 0u;
+                        uint32_t s0 = __builtin_amdgcn_inverse_ballot_w64(lbit) ? ~0u : 0u;
+                        uint32_t sn = __builtin_amdgcn_inverse_ballot_w64(nbit) ? ~0u : 0u;
+                        __asm__ volatile("" : "+v"(e0), "+v"(e1), "+v"(s0), "+v"(sn));
+                        if (!HI) {
+                            x0l ^= pel & e0;
+                            x1l ^= pel & e1;
+                        }
+                        x0h ^= peh & e0;
+                        x1h ^= peh & e1;
+                        // the row at npiv to the pivot's place, the pivot to npiv
+                        x0l = (x0l & ~s0) | (vrl & s0);
+                        x0h = (x0h & ~s0) | (vrh & s0);
+                        id0 = (int)(((uint32_t)id0 & ~s0) | ((uint32_t)idr & s0));
+                        x0l = (x0l & ~sn) | (pvl & sn);
+                        x0h = (x0h & ~sn) | (pvh & sn);
+                        id0 = (int)(((uint32_t)id0 & ~sn) | ((uint32_t)idp & sn));
+                        my_qp = (int)(((uint32_t)my_qp & ~sn) | ((uint32_t)(j | (lf << 8)) & sn));
+                        act0 &= ~nbit;
+                        npiv++;
+                        j++;
+                        const uint64_t nx = __ballot(((HI ? x0h : x0l) & (1u << (j & 31))) != 0) & act0;
+                        m0 = j < je ? nx : 0ull;
+                    }
+                    if (j >= je) return;
+                    // general step for column j: no candidate in register 0
                     const uint32_t bj = 1u << (j & 31);
                     const uint64_t m1 = __ballot(((HI ? x1h : x1l) & bj) != 0) & act1;
-                    const int lf = (int)__builtin_ctzll(m0);
-                    const uint32_t pvl = (uint32_t)readlane32((int)x0l, lf), pvh = (uint32_t)readlane32((int)x0h, lf);
-                    const int idp = readlane32(id0, lf);
+                    if (!m1) {
+                        if (nmax < rows) {  // a row outside the window may hold the pivot
+                            slow = true;
+                            go = false;
+                            return;
+                        }
+                        j++;  // column j has no pivot
+                        continue;
+                    }
+                    const int lf = (int)__builtin_ctzll(m1);
+                    const uint32_t pvl = (uint32_t)readlane32((int)x1l, lf), pvh = (uint32_t)readlane32((int)x1h, lf);
+                    const int idp = readlane32(id1, lf);
                     const uint32_t vrl = (uint32_t)readlane32((int)x0l, npiv);
                     const uint32_t vrh = (uint32_t)readlane32((int)x0h, npiv);
                     const int idr = readlane32(id0, npiv);
-                    // the pivot's part strictly above column j leaves the other
-                    // rows that have the bit
                     const uint32_t pel = HI ? 0u : (j == 31 ? 0u : pvl & (~0u << (j + 1)));
                     const uint32_t peh = HI ? (j == 63 ? 0u : pvh & (~0u << ((j & 31) + 1))) : pvh;
                     const uint64_t lbit = 1ull << lf, nbit = 1ull << npiv;
-                    // lane masks as all-ones/zero words, opaque to the compiler,
-                    // so that each update below is one three-input logic
-                    // instruction with the scalar operand (a select on a scalar
-                    // mask would first copy the scalar into a vector register)
-                    uint32_t e0 = __builtin_amdgcn_inverse_ballot_w64(m0 & ~lbit) ? ~0u : 0u;
-                    uint32_t e1 = __builtin_amdgcn_inverse_ballot_w64(m1) ? ~0u : 0u;
-                    uint32_t s0 = __builtin_amdgcn_inverse_ballot_w64(lbit) ? ~0u : 0u;
-                    uint32_t sn = __builtin_amdgcn_inverse_ballot_w64(nbit) ? ~0u : 0u;
-                    __asm__ volatile("" : "+v"(e0), "+v"(e1), "+v"(s0), "+v"(sn));
-                    if (!HI) {
-                        x0l ^= pel & e0;
-                        x1l ^= pel & e1;
-                    }
-                    x0h ^= peh & e0;
-                    x1h ^= peh & e1;
-                    // the row at npiv to the pivot's place, the pivot to npiv
-                    x0l = (x0l & ~s0) | (vrl & s0);
-                    x0h = (x0h & ~s0) | (vrh & s0);
-                    id0 = (int)(((uint32_t)id0 & ~s0) | ((uint32_t)idr & s0));
-                    x0l = (x0l & ~sn) | (pvl & sn);
-                    x0h = (x0h & ~sn) | (pvh & sn);
-                    id0 = (int)(((uint32_t)id0 & ~sn) | ((uint32_t)idp & sn));
-                    my_qp = (int)(((uint32_t)my_qp & ~sn) | ((uint32_t)(j | (lf << 8)) & sn));
+                    const bool e1 = __builtin_amdgcn_inverse_ballot_w64(m1 & ~lbit);
+                    if (!HI) x1l = e1 ? x1l ^ pel : x1l;
+                    x1h = e1 ? x1h ^ peh : x1h;
+                    const bool s1 = __builtin_amdgcn_inverse_ballot_w64(lbit);
+                    x1l = s1 ? vrl : x1l;
+                    x1h = s1 ? vrh : x1h;
+                    id1 = s1 ? idr : id1;
+                    const bool sn = __builtin_amdgcn_inverse_ballot_w64(nbit);
+                    x0l = sn ? pvl : x0l;
+                    x0h = sn ? pvh : x0h;
+                    id0 = sn ? idp : id0;
+                    my_qp = sn ? (j | ((64 + lf) << 8)) : my_qp;
                     act0 &= ~nbit;
                     npiv++;
                     j++;
-                    const uint64_t nx = __ballot(((HI ? x0h : x0l) & (1u << (j & 31))) != 0) & act0;
-                    m0 = j < je ? nx : 0ull;
                 }
-                if (j >= je) return;
-                // general step for column j: no candidate in register 0
-                const uint32_t bj = 1u << (j & 31);
-                const uint64_t m1 = __ballot(((HI ? x1h : x1l) & bj) != 0) & act1;
-                if (!m1) {
-                    if (nmax < rows) {  // a row outside the window may hold the pivot
-                        slow = true;
-                        go = false;
-                        return;
-                    }
-                    j++;  // column j has no pivot
-                    continue;
-                }
-                const int lf = (int)__builtin_ctzll(m1);
-                const uint32_t pvl = (uint32_t)readlane32((int)x1l, lf), pvh = (uint32_t)readlane32((int)x1h, lf);
-                const int idp = readlane32(id1, lf);
-                const uint32_t vrl = (uint32_t)readlane32((int)x0l, npiv);
-                const uint32_t vrh = (uint32_t)readlane32((int)x0h, npiv);
-                const int idr = readlane32(id0, npiv);
-                const uint32_t pel = HI ? 0u : (j == 31 ? 0u : pvl & (~0u << (j + 1)));
-                const uint32_t peh = HI ? (j == 63 ? 0u : pvh & (~0u << ((j & 31) + 1))) : pvh;
-                const uint64_t lbit = 1ull << lf, nbit = 1ull << npiv;
-                const bool e1 = __builtin_amdgcn_inverse_ballot_w64(m1 & ~lbit);
-                if (!HI) x1l = e1 ? x1l ^ pel : x1l;
-                x1h = e1 ? x1h ^ peh : x1h;
-                const bool s1 = __builtin_amdgcn_inverse_ballot_w64(lbit);
-                x1l = s1 ? vrl : x1l;
-                x1h = s1 ? vrh : x1h;
-                id1 = s1 ? idr : id1;
-                const bool sn = __builtin_amdgcn_inverse_ballot_w64(nbit);
-                x0l = sn ? pvl : x0l;
-                x0h = sn ? pvh : x0h;
-                id0 = sn ? idp : id0;
-                my_qp = sn ? (j | ((64 + lf) << 8)) : my_qp;
-                act0 &= ~nbit;
-                npiv++;
-                j++;
-            }
-        };
-        run(0, kp < 32 ? kp : 32, false);
-        if (go && kp > 32) run(32, kp, true);
-        my_fin = lane < npiv ? (((uint64_t)x0h << 32) | x0l) : 0ull;
-        my_q = my_qp & 255;
-        my_p = my_qp >> 8;
-        npiv = uni(npiv);
-        PANEL_STAMP(2)
-        if (!slow) {
-            int base = 0;
+            };
+            run(0, kp < 32 ? kp : 32, false);
+            if (go && kp > 32) run(32, kp, true);
+            my_fin = lane < npiv ? (((uint64_t)x0h << 32) | x0l) : 0ull;
+            my_q = my_qp & 255;
+            my_p = my_qp >> 8;
+            npiv = uni(npiv);
+            PANEL_STAMP(2)
+            if (!slow) {
+                int base = 0;
 #pragma unroll
-            for (int q = 0; q < 2; q++) {
-                const int pos = 64 * q + lane;
-                const int idq = q ? id1 : id0;
-                const bool f = pos < nmax && (pos < npiv || idq != pos);
-                const uint64_t msk = __ballot(f);
-                const int idx = base + __popcll(msk & ((1ull << lane) - 1ull));
-                if (f) {
-                    L.dst[idx] = r + pos;
-                    L.src[idx] = r + idq;
-                }
-                base += __popcll(msk);
-            }
-            nspec = uni(base);
-        }
-    } else {
-
-        uint64_t val[WQ];
-        int id[WQ];
-#pragma unroll
-        for (int q = 0; q < WQ; q++) {
-            val[q] = 0;
-            id[q] = 64 * q + lane;
-        }
-        const int nmax = (int)(rows < 64 * WQ ? rows : 64 * WQ);
-        const int nregmax = (nmax + 63) >> 6;
-        int nreg = 0;
-        // fetch registers [nreg, want) and reduce them by the pivots so far
-        auto extend = [&](int want) {
-            uint64_t tmp[WQ];
-#pragma unroll
-            for (int q = 0; q < WQ; q++) {
-                if (q >= nreg && q < want) {
+                for (int q = 0; q < 2; q++) {
                     const int pos = 64 * q + lane;
-                    const int64_t row = r + (pos < rows ? pos : rows - 1);
-                    tmp[q] = ld_stripe(A + row * ldw + sw);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < WQ; q++) {
-                if (q >= nreg && q < want) val[q] = (64 * q + lane) < nmax ? (tmp[q] & kmask) : 0ull;
-            }
-            for (int l = 0; l < npiv; l++) {
-                const int ql = uni(readlane32(my_q, l));
-                const uint64_t fl = readlane64(my_fin, l) & above(ql);
-#pragma unroll
-                for (int q = 0; q < WQ; q++) {
-                    if (q >= nreg && q < want && ((val[q] >> ql) & 1ull)) val[q] ^= fl;
-                }
-            }
-            nreg = want;
-        };
-        extend(nregmax < 2 ? nregmax : 2);
-        PANEL_STAMP(1)
-
-        // act[q]: lanes of register q that are candidates (loaded, position
-        // >= npiv, row < m); kept as scalar masks and updated as npiv grows
-        uint64_t act[WQ];
-#pragma unroll
-        for (int q = 0; q < WQ; q++) act[q] = __ballot(q < nreg && 64 * q + lane < nmax);
-        for (int j = 0; j < kp; j++) {
-            uint64_t msk[WQ];
-            int found = -1;
-            for (;;) {
-#pragma unroll
-                for (int q = 0; q < WQ; q++) msk[q] = __ballot(((val[q] >> j) & 1ull) != 0) & act[q];
-                found = -1;
-#pragma unroll
-                for (int q = WQ - 1; q >= 0; q--)
-                    if (msk[q]) found = 64 * q + (int)__builtin_ctzll(msk[q]);
-                found = uni(found);
-                if (found >= 0 || nreg >= nregmax) break;
-                extend(uni(nreg + 1));
-#pragma unroll
-                for (int q = 0; q < WQ; q++) act[q] = __ballot(q < nreg && 64 * q + lane < nmax && 64 * q + lane >= npiv);
-            }
-            if (found < 0) {
-                if (nmax < rows) {  // a row outside the window may hold the pivot
-                    slow = true;
-                    break;
-                }
-                continue;  // column j has no pivot
-            }
-            const int qf = found >> 6, lf = found & 63;
-            // the pivot row (at `found`) and the row at npiv (register 0, npiv < 64)
-            uint64_t pv = 0;
-            int idp = 0;
-#pragma unroll
-            for (int q = 0; q < WQ; q++) {
-                const uint64_t t = readlane64(val[q], lf);
-                const int ti = readlane32(id[q], lf);
-                pv = q == qf ? t : pv;
-                idp = q == qf ? ti : idp;
-            }
-            const uint64_t vr = readlane64(val[0], npiv);
-            const int idr = readlane32(id[0], npiv);
-            // swap the two rows, then eliminate column j from the later rows
-            // that have it (the row now at `found` never has it)
-            const uint64_t pe = pv & above(j);
-#pragma unroll
-            for (int q = 0; q < WQ; q++) {
-                uint64_t e = msk[q];
-                if (q == 0) e &= ~(1ull << npiv);
-                if (q == qf) e &= ~(1ull << lf);
-                const bool at_found = (q == qf) && lane == lf;
-                const bool at_npiv = (q == 0) && lane == npiv;
-                uint64_t v = at_found ? vr : val[q];
-                v = at_npiv ? pv : v;
-                id[q] = at_npiv ? idp : (at_found ? idr : id[q]);
-                val[q] = v ^ (pe & (0ull - ((e >> lane) & 1ull)));
-            }
-            act[0] &= ~(1ull << npiv);
-            const bool me = lane == npiv;
-            my_q = me ? j : my_q;
-            my_fin = me ? pv : my_fin;
-            my_p = me ? found : my_p;
-            npiv = uni(npiv + 1);
-            if (npiv == rows) break;
-        }
-        PANEL_STAMP(2)
-        if (!slow) {
-            int base = 0;
-#pragma unroll
-            for (int q = 0; q < WQ; q++) {
-                if (q < nreg) {
-                    const int pos = 64 * q + lane;
-                    const bool f = pos < nmax && (pos < npiv || id[q] != pos);
+                    const int idq = q ? id1 : id0;
+                    const bool f = pos < nmax && (pos < npiv || idq != pos);
                     const uint64_t msk = __ballot(f);
                     const int idx = base + __popcll(msk & ((1ull << lane) - 1ull));
                     if (f) {
                         L.dst[idx] = r + pos;
-                        L.src[idx] = r + id[q];
+                        L.src[idx] = r + idq;
                     }
                     base += __popcll(msk);
                 }
+                nspec = uni(base);
             }
-            nspec = uni(base);
+        } else {
+
+            uint64_t val[WQ];
+            int id[WQ];
+#pragma unroll
+            for (int q = 0; q < WQ; q++) {
+                val[q] = 0;
+                id[q] = 64 * q + lane;
+            }
+            const int nmax = (int)(rows < 64 * WQ ? rows : 64 * WQ);
+            const int nregmax = (nmax + 63) >> 6;
+            int nreg = 0;
+            // fetch registers [nreg, want) and reduce them by the pivots so far
+            auto extend = [&](int want) {
+                uint64_t tmp[WQ];
+#pragma unroll
+                for (int q = 0; q < WQ; q++) {
+                    if (q >= nreg && q < want) {
+                        const int pos = 64 * q + lane;
+                        const int64_t row = r + (pos < rows ? pos : rows - 1);
+                        tmp[q] = ld_stripe(A + row * ldw + sw);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < WQ; q++) {
+                    if (q >= nreg && q < want) val[q] = (64 * q + lane) < nmax ? (tmp[q] & kmask) : 0ull;
+                }
+                for (int l = 0; l < npiv; l++) {
+                    const int ql = uni(readlane32(my_q, l));
+                    const uint64_t fl = readlane64(my_fin, l) & above(ql);
+#pragma unroll
+                    for (int q = 0; q < WQ; q++) {
+                        if (q >= nreg && q < want && ((val[q] >> ql) & 1ull)) val[q] ^= fl;
+                    }
+                }
+                nreg = want;
+            };
+            extend(nregmax < 2 ? nregmax : 2);
+            PANEL_STAMP(1)
+
+            // act[q]: lanes of register q that are candidates (loaded, position
+            // >= npiv, row < m); kept as scalar masks and updated as npiv grows
+            uint64_t act[WQ];
+#pragma unroll
+            for (int q = 0; q < WQ; q++) act[q] = __ballot(q < nreg && 64 * q + lane < nmax);
+            for (int j = 0; j < kp; j++) {
+                uint64_t msk[WQ];
+                int found = -1;
+                for (;;) {
+#pragma unroll
+                    for (int q = 0; q < WQ; q++) msk[q] = __ballot(((val[q] >> j) & 1ull) != 0) & act[q];
+                    found = -1;
+#pragma unroll
+                    for (int q = WQ - 1; q >= 0; q--)
+                        if (msk[q]) found = 64 * q + (int)__builtin_ctzll(msk[q]);
+                    found = uni(found);
+                    if (found >= 0 || nreg >= nregmax) break;
+                    extend(uni(nreg + 1));
+#pragma unroll
+                    for (int q = 0; q < WQ; q++)
+                        act[q] = __ballot(q < nreg && 64 * q + lane < nmax && 64 * q + lane >= npiv);
+                }
+                if (found < 0) {
+                    if (nmax < rows) {  // a row outside the window may hold the pivot
+                        slow = true;
+                        break;
+                    }
+                    continue;  // column j has no pivot
+                }
+                const int qf = found >> 6, lf = found & 63;
+                // the pivot row (at `found`) and the row at npiv (register 0, npiv < 64)
+                uint64_t pv = 0;
+                int idp = 0;
+#pragma unroll
+                for (int q = 0; q < WQ; q++) {
+                    const uint64_t t = readlane64(val[q], lf);
+                    const int ti = readlane32(id[q], lf);
+                    pv = q == qf ? t : pv;
+                    idp = q == qf ? ti : idp;
+                }
+                const uint64_t vr = readlane64(val[0], npiv);
+                const int idr = readlane32(id[0], npiv);
+                // swap the two rows, then eliminate column j from the later rows
+                // that have it (the row now at `found` never has it)
+                const uint64_t pe = pv & above(j);
+#pragma unroll
+                for (int q = 0; q < WQ; q++) {
+                    uint64_t e = msk[q];
+                    if (q == 0) e &= ~(1ull << npiv);
+                    if (q == qf) e &= ~(1ull << lf);
+                    const bool at_found = (q == qf) && lane == lf;
+                    const bool at_npiv = (q == 0) && lane == npiv;
+                    uint64_t v = at_found ? vr : val[q];
+                    v = at_npiv ? pv : v;
+                    id[q] = at_npiv ? idp : (at_found ? idr : id[q]);
+                    val[q] = v ^ (pe & (0ull - ((e >> lane) & 1ull)));
+                }
+                act[0] &= ~(1ull << npiv);
+                const bool me = lane == npiv;
+                my_q = me ? j : my_q;
+                my_fin = me ? pv : my_fin;
+                my_p = me ? found : my_p;
+                npiv = uni(npiv + 1);
+                if (npiv == rows) break;
+            }
+            PANEL_STAMP(2)
+            if (!slow) {
+                int base = 0;
+#pragma unroll
+                for (int q = 0; q < WQ; q++) {
+                    if (q < nreg) {
+                        const int pos = 64 * q + lane;
+                        const bool f = pos < nmax && (pos < npiv || id[q] != pos);
+                        const uint64_t msk = __ballot(f);
+                        const int idx = base + __popcll(msk & ((1ull << lane) - 1ull));
+                        if (f) {
+                            L.dst[idx] = r + pos;
+                            L.src[idx] = r + id[q];
+                        }
+                        base += __popcll(msk);
+                    }
+                }
+                nspec = uni(base);
+            }
         }
     }
 
@@ -483,8 +857,30 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
     // elimination changes it; only its position can change, when a pivot is
     // swapped into its place.  The search then runs on the kept rows alone,
     // in LDS or workspace.  The batched kernels' panels (KEPT = false) search
-    // every row in place.
-    if (slow) {
+    // every row in place.  A block of several waves first tries the
+    // multi-wave search above, with the one-wave search as its fallback.
+    bool slow_done = false, handed = false;
+    int h_nc = 0;
+    uint64_t h_orv = 0;
+    if constexpr (NW > 1) {
+        if (mw) {
+            MwX<NW> &X = *(MwX<NW> *)mc.x;
+            if (wave == 0) {
+                if (slow && patch) fix_wait();  // the fix's stores, before the other waves read rows back
+                if (lane == 0) X.flag = slow ? 1 : 0;
+            }
+            __syncthreads();
+            slow = X.flag != 0;
+            if (slow) {
+                const MwResult res = slow_search_mw<NW>(A, ldw, sw, r, rows, kmask, kp, lane, wave, mc, L, npiv,
+                                                        my_q, my_fin, my_p, nspec, h_nc, h_orv);
+                slow_done = res == MW_DONE;
+                handed = res == MW_HANDED;
+            }
+            if (wave != 0) return;
+        }
+    }
+    if (slow && !slow_done) {
         if (patch) fix_wait();  // the fix's stores, before every row is read back
         npiv = 0;
         my_q = 0;
@@ -616,30 +1012,22 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             };
-            keep(SR > 0 ? SR : INT32_MAX);
-            if (SR > 0 && nc > SR) {  // more kept rows than the LDS holds
-                cv = gsv;
-                ci = gsid;
-                cp = gsid + m;
-                rg = gsid + 2 * m;
-                keep(INT32_MAX);
+            if (handed) {  // the multi-wave scan's rows, already in LDS
+                nc = h_nc;
+                orv = h_orv;
+            } else {
+                keep(SR > 0 ? SR : INT32_MAX);
+                if (SR > 0 && nc > SR) {  // more kept rows than the LDS holds
+                    cv = gsv;
+                    ci = gsid;
+                    cp = gsid + m;
+                    rg = gsid + 2 * m;
+                    keep(INT32_MAX);
+                }
             }
             // lane d: a row with a zero stripe word moved to position dzp (it
             // started at dzi); -1 = none.  At most one per pivot.
             int dzp = -1, dzi = 0;
-            // the row at position npiv, if it has a zero stripe word, goes to
-            // position found
-            auto move_zero_row = [&](const int found) {
-                if (__ballot(dzp == npiv)) {
-                    dzp = dzp == npiv ? found : dzp;
-                } else {
-                    const int nd = __popcll(__ballot(dzp >= 0));
-                    if (lane == nd) {
-                        dzp = found;
-                        dzi = npiv;
-                    }
-                }
-            };
             int my_id = 0;
             int nsp = 0;  // special rows listed
             // The kept rows are searched in row order and reduced lazily.
@@ -719,7 +1107,7 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                 } else {
                     // a row with a zero stripe word is at npiv: it takes the
                     // pivot's place, and the pivot's slot retires
-                    move_zero_row(found);
+                    move_zero_row(dzp, dzi, npiv, found, lane);
                     if (lane == 0) cp[kf] = -1;
                     if (kf == h) head = h + 1;
                 }
@@ -750,40 +1138,8 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                 nsp += __popcll(msk);
             }
             // special rows: the pivots in order, then the displaced rows by
-            // position (listed above in any order, ranked here)
-            if (lane < npiv) {
-                L.dst[lane] = r + lane;
-                L.src[lane] = r + my_id;
-            }
-            {
-                const uint64_t msk = __ballot(dzp >= 0);
-                if (dzp >= 0) {
-                    const int idx = nsp + __popcll(msk & lt);
-                    L.dst[idx] = r + dzp;
-                    L.src[idx] = r + dzi;
-                }
-                nsp += __popcll(msk);
-            }
-            nspec = uni(nsp);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            const int nd = nspec - npiv;  // <= npiv <= 64
-            int64_t dd = 0, ds = 0;
-            if (lane < nd) {
-                dd = L.dst[npiv + lane];
-                ds = L.src[npiv + lane];
-            }
-            const int dpos = (int)(dd - r);
-            int rank = 0;
-            for (int k = 0; k < nd; k++) rank += readlane32(dpos, k) < dpos ? 1 : 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            if (lane < nd) {
-                L.dst[npiv + rank] = dd;
-                L.src[npiv + rank] = ds;
-            }
+            // position (listed above in any order, ranked there)
+            nspec = finish_special(L, r, npiv, nsp, my_id, dzp, dzi, lane);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

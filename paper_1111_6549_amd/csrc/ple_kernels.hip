@@ -50,16 +50,36 @@ __global__ void k_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *r
 // ---------------------------------------------------------------------------
 // k_panel: one wave runs the panel of the stripe at column c.
 // ---------------------------------------------------------------------------
+// waves of a standalone panel's block (wave 0 runs the panel, all of them its
+// slow search)
+constexpr int PANEL_WAVES = 16;
+
 // SR: rows of the all-rows search kept in LDS.  The look-ahead panel runs
 // beside the update kernels on their CUs, so it uses SR = 0 (workspace) and
-// a raised wave priority.
-template <int WQ, int SR>
-__global__ __launch_bounds__(64) void k_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c,
-                                              const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
-                                              int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelFix fix) {
+// a raised wave priority.  NW > 1: a block of NW waves, all of which run the
+// slow search (staged in the LDS rows).
+template <int WQ, int SR, int NW = 1>
+__global__ __launch_bounds__(64 * NW) void k_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c,
+                                                   const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
+                                                   int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelFix fix) {
     __shared__ PanelLdsT<SR> L;
     if (SR == 0) __builtin_amdgcn_s_setprio(3);
-    panel_body<WQ, SR>(A, m, n, ldw, c, prev, rec, P, Q, rank_out, gsv, gsid, L, threadIdx.x, fix);
+    if constexpr (NW > 1) {
+        static_assert(SR >= MW_SLOTS, "the staging holds every slot");
+        __shared__ MwX<NW> X;
+        MwCtx mc;
+        mc.x = &X;
+        mc.stv = L.sv;
+        mc.stp = L.spos;
+        mc.cap = SR;
+        mc.hv = L.sv;
+        mc.hp = L.spos;
+        mc.hi = L.sid;
+        panel_body<WQ, SR, true, NW>(A, m, n, ldw, c, prev, rec, P, Q, rank_out, gsv, gsid, L, threadIdx.x & 63, fix,
+                                     uni(threadIdx.x >> 6), mc);
+    } else {
+        panel_body<WQ, SR>(A, m, n, ldw, c, prev, rec, P, Q, rank_out, gsv, gsid, L, threadIdx.x, fix);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -487,7 +507,23 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
         panel_body<2, PAIR_PANEL_ROWS>(C, m, pp.n, ldc, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank, pp.gsv, pp.gsid, PL, tid & 63, f);
     };
     if (own && panel_here) {
-        if (tid < 64) run_panel();
+        // a block of its own: every wave joins the slow search, which stages
+        // its kept rows where the tables would be
+        static_assert(MW_SLOTS * 12 + sizeof(MwX<NT / 64>) <= sizeof(T), "staging in the tables' LDS");
+        __builtin_amdgcn_s_setprio(3);
+        PanelFix f;
+        f.mode = 1;
+        MwCtx mc;
+        uint64_t *tb = &T[0][0][0];
+        mc.stv = tb;
+        mc.stp = (int32_t *)(tb + MW_SLOTS);
+        mc.x = (void *)(tb + MW_SLOTS + MW_SLOTS / 2);
+        mc.cap = MW_SLOTS;
+        mc.hv = PL.sv;
+        mc.hp = PL.spos;
+        mc.hi = PL.sid;
+        panel_body<2, PAIR_PANEL_ROWS, true, NT / 64>(C, m, pp.n, ldc, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank,
+                                                     pp.gsv, pp.gsid, PL, tid & 63, f, uni(tid >> 6), mc);
         return;
     }
     const int at = rect->active, au = recu->active;
@@ -900,8 +936,11 @@ hipError_t launch_panel(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t 
     hipExtLaunchKernelGGL((k_panel<WQ, SR>), dim3(1), dim3(64), 0, s, nullptr, done, 0, A, m, n, ldw, c, prev, rec, P, \
                           Q, rank, gsv, gsid, fix)
     if (panel_regs == 0 || panel_regs == 2) {
+        // the default panel: a block of PANEL_WAVES waves for the slow search
         if (beside) PANEL_LAUNCH(2, 0);
-        else PANEL_LAUNCH(2, SLOW_LDS_ROWS);
+        else
+            hipExtLaunchKernelGGL((k_panel<2, SLOW_LDS_ROWS, PANEL_WAVES>), dim3(1), dim3(64 * PANEL_WAVES), 0, s,
+                                  nullptr, done, 0, A, m, n, ldw, c, prev, rec, P, Q, rank, gsv, gsid, fix);
     } else if (panel_regs == 4) {
         if (beside) PANEL_LAUNCH(4, 0);
         else PANEL_LAUNCH(4, SLOW_LDS_ROWS);
