@@ -212,6 +212,9 @@ struct MwX {
     int32_t cnt[2][NW];         // per scan round, alternating: kept rows of each wave
     uint64_t orv[NW];
     int32_t lcount, flag;
+#ifdef GF2_PANEL_TIMING
+    uint64_t tph[4];  // wave 0's clock: start, scan done, columns done, end
+#endif
 };
 
 // Where the multi-wave search stages the kept rows (LDS, cap entries) and
@@ -353,6 +356,13 @@ __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int6
     const uint64_t lt = (1ull << lane) - 1ull;
     const int cap = mc.cap < MW_SLOTS ? mc.cap : MW_SLOTS;
     if (wave == 0 && lane == 0) X.lcount = 0;
+#ifdef GF2_PANEL_TIMING
+    if (wave == 0 && lane == 0) X.tph[0] = wall_clock64();
+#define MW_STAMP(k) \
+    if (wave == 0 && lane == 0) X.tph[k] = wall_clock64();
+#else
+#define MW_STAMP(k)
+#endif
 
     // ---- scan: every wave takes 64 * SB rows of each round ----
     int nc = 0, par = 0;
@@ -395,6 +405,7 @@ __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int6
     if (lane == 0) X.orv[wave] = orv;
     __syncthreads();  // also completes the staging
     orv = wave_or64(lane < NW ? X.orv[lane] : 0ull);
+    MW_STAMP(1)
     if (nc > cap) return MW_FALLBACK;
     if (nc <= MW_HANDOFF) {
         for (int k = wave * 64 + lane; k < nc; k += NW * 64) {
@@ -436,6 +447,7 @@ __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int6
         mw_columns<NW, 4, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
     else
         mw_columns<NW, 8, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+    MW_STAMP(2)
 
     // ---- kept rows that moved: listed after the pivots, in any order ----
 #pragma unroll
@@ -457,6 +469,8 @@ __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int6
     npiv_out = npiv;
     if (wave != 0) return MW_DONE;
     nspec_out = finish_special(L, r, npiv, npiv + uni(X.lcount), my_id, dzp, dzi, lane);
+    MW_STAMP(3)
+#undef MW_STAMP
     return MW_DONE;
 }
 
@@ -876,6 +890,16 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
                                                         my_q, my_fin, my_p, nspec, h_nc, h_orv);
                 slow_done = res == MW_DONE;
                 handed = res == MW_HANDED;
+#ifdef GF2_PANEL_TIMING
+                if (wave == 0 && lane == 0) {
+                    dbg2[3] += X.tph[1] - X.tph[0];
+                    if (slow_done) {
+                        dbg2[4] += X.tph[2] - X.tph[1];
+                        dbg2[5] += X.tph[3] - X.tph[2];
+                    }
+                    dbg2[6] += (uint64_t)res;
+                }
+#endif
             }
             if (wave != 0) return;
         }
