@@ -64,6 +64,21 @@ def test_parity_sparse_tall():
     assert_same_ple(gpu_ple(A, 1500), oracle_ple(A, 1500), "30000x1500 sparse")
 
 
+def test_parity_slow_search_forms():
+    """24000 x 3072 whose 256-column blocks cycle through 0.0003, 0.005 and
+    0.02 non-zero entries per bit: the slow searches of its stripes keep from
+    a few hundred rows (handed to the one-wave search) to a few thousand (the
+    multi-wave search) and beyond 8192 (its fall-back), in the standalone
+    panels and in the pair updates' panel blocks."""
+    m, n = 24000, 3072
+    say("parity slow-search forms", m, n)
+    dens = (0.0003, 0.005, 0.02)
+    A = np.ascontiguousarray(np.concatenate(
+        [inputs.bernoulli(m, 256, 40 + b, p=dens[b % 3]) for b in range(n // 256)], axis=1))
+    assert A.shape == (m, inputs.words(n))
+    assert_same_ple(gpu_ple(A, n), oracle_ple(A, n), "24000x3072 banded densities")
+
+
 @pytest.mark.parametrize("m,n,rho", [(600, 600, 300), (1000, 700, 650), (700, 1000, 700), (800, 800, 800),
                                      (3000, 300, 50), (8000, 300, 100), (256, 2048, 200)])
 def test_parity_known_rank(m, n, rho):
