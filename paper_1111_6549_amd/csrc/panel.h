@@ -437,7 +437,7 @@ __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int6
     my_fin = 0;
     my_p = 0;
     int npiv = 0, dzp = -1, dzi = 0, my_id = 0;
-    static_assert(R == 8, "register counts 1, 2, 4, 8");
+    static_assert(R == 8 || R == 16, "register counts 1, 2, 4, 8 (, 16)");
     const int rr = (nc + NW * 64 - 1) / (NW * 64);
     if (rr <= 1)
         mw_columns<NW, 1, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
@@ -445,8 +445,11 @@ __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int6
         mw_columns<NW, 2, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
     else if (rr <= 4)
         mw_columns<NW, 4, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
-    else
+    else if (R == 8 || rr <= 8)
         mw_columns<NW, 8, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+    else
+        mw_columns<NW, (R > 8 ? 16 : 8), R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p,
+                                             my_id, dzp, dzi);
     MW_STAMP(2)
 
     // ---- kept rows that moved: listed after the pivots, in any order ----

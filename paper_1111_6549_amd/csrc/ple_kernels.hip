@@ -51,8 +51,10 @@ __global__ void k_init(int64_t *P, int64_t m, int64_t *Q, int64_t mn, int64_t *r
 // k_panel: one wave runs the panel of the stripe at column c.
 // ---------------------------------------------------------------------------
 // waves of a standalone panel's block (wave 0 runs the panel, all of them its
-// slow search)
-constexpr int PANEL_WAVES = 16;
+// slow search).  Eight, two per SIMD, with 16 registers of kept rows per lane,
+// repeat less per-wave work per column than sixteen; four lengthen the scan
+// and the register loops more than they save.
+constexpr int PANEL_WAVES = 8;
 
 // SR: rows of the all-rows search kept in LDS.  The look-ahead panel runs
 // beside the update kernels on their CUs, so it uses SR = 0 (workspace) and
