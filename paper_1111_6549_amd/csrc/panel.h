@@ -219,7 +219,7 @@ struct MwX {
 
 // Where the multi-wave search stages the kept rows (LDS, cap entries) and
 // keeps its exchange (an MwX<NW>), and the one-wave search's LDS arrays
-// (word, position, first position), to which it hands few kept rows.
+// (word, position, first position), to which it may hand few kept rows.
 struct MwCtx {
     void *x = nullptr;
     uint64_t *stv = nullptr;
@@ -229,9 +229,9 @@ struct MwCtx {
     int32_t *hp = nullptr, *hi = nullptr;
 };
 
-// Up to this many kept rows the one-wave search (a barrier-free step per
-// column) takes over from the multi-wave one after the shared scan.
-constexpr int MW_HANDOFF = 512;
+// Up to this many kept rows wave 0 alone (no barrier per column) takes over
+// from the multi-wave search after the shared scan.
+constexpr int MW_ALONE = 512;
 enum MwResult { MW_FALLBACK = 0, MW_HANDED = 1, MW_DONE = 2 };
 
 // The column search of the multi-wave slow search over the first RR of the
@@ -280,7 +280,11 @@ __device__ __forceinline__ void mw_columns(MwX<NW> &X, uint64_t (&wd)[R], int (&
         // the lanes that hold them post them (lane 0 posts "none")
         if (lane == la) X.fa[par][wave] = Post{wa, qa == RR ? INT32_MAX : (qa * NW + wave) * 64 + la, pa, ia, 0};
         if (lane == lm) X.fm[par][wave] = Post{wm, qm == RR ? INT32_MAX : (qm * NW + wave) * 64 + lm, pm, im, 0};
-        __syncthreads();
+        if constexpr (NW > 1) {
+            __syncthreads();
+        } else {
+            lds_order();  // one wave: its own posts, in program order
+        }
         Post ea, em;
         ea.slot = em.slot = INT32_MAX;
         if (lane < NW) {
@@ -335,14 +339,69 @@ __device__ __forceinline__ void mw_columns(MwX<NW> &X, uint64_t (&wd)[R], int (&
     }
 }
 
+// Wave 0 alone, after the scan, on at most MW_ALONE kept rows: slot k in
+// register k / 64, lane k mod 64; the column loop of the multi-wave search
+// with one wave (its posts need no barrier), then the list.  Uses the LDS of
+// the exchange as an MwX<1> (the other waves read none of it any more).
+template <int NW, int SR>
+__device__ __forceinline__ void mw_alone(const MwCtx &mc, PanelLdsT<SR> &L, const int nc, const uint64_t orv,
+                                         const int64_t r, const int64_t rows, const int kp, const int lane,
+                                         int &npiv_out, int &my_q, uint64_t &my_fin, int &my_p, int &nspec_out) {
+    static_assert(sizeof(MwX<1>) <= sizeof(MwX<NW>) && offsetof(MwX<NW>, orv) >= sizeof(MwX<1>),
+                  "the one-wave exchange stays clear of what the others still read");
+    MwX<1> &X = *(MwX<1> *)mc.x;
+    constexpr int R = MW_ALONE / 64;
+    uint64_t wd[R];
+    int cpos[R], cid[R];  // position now (-1: retired or empty), first position
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const int k = q * 64 + lane;
+        const bool in = k < nc;
+        wd[q] = in ? mc.stv[k] : 0ull;
+        cpos[q] = in ? mc.stp[k] : -1;
+        cid[q] = cpos[q];
+    }
+    my_q = 0;
+    my_fin = 0;
+    my_p = 0;
+    int npiv = 0, dzp = -1, dzi = 0, my_id = 0;
+    const int rr = (nc + 63) / 64;
+    static_assert(R == 8, "register counts 1, 2, 4, 8");
+    if (rr <= 1)
+        mw_columns<1, 1, R>(X, wd, cpos, cid, lane, 0, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+    else if (rr <= 2)
+        mw_columns<1, 2, R>(X, wd, cpos, cid, lane, 0, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+    else if (rr <= 4)
+        mw_columns<1, 4, R>(X, wd, cpos, cid, lane, 0, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+    else
+        mw_columns<1, 8, R>(X, wd, cpos, cid, lane, 0, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+    // kept rows that moved: listed after the pivots, in any order
+    const uint64_t lt = (1ull << lane) - 1ull;
+    int nsp = npiv;
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const bool f = cpos[q] >= npiv && cpos[q] != cid[q];
+        const uint64_t msk = __ballot(f);
+        if (f) {
+            const int idx = nsp + __popcll(msk & lt);
+            L.dst[idx] = r + cpos[q];
+            L.src[idx] = r + cid[q];
+        }
+        nsp += __popcll(msk);
+    }
+    npiv_out = npiv;
+    nspec_out = finish_special(L, r, npiv, nsp, my_id, dzp, dzi, lane);
+}
+
 // Run by every wave of the block (wave = its index, uniform); the result is
-// the same on every wave.  MW_FALLBACK: the kept rows exceed what the
+// the same on every wave.  At most MW_ALONE kept rows: with ALONE, wave 0
+// searches them in its registers; otherwise they go to the one-wave search.  MW_FALLBACK: the kept rows exceed what the
 // registers or the staging hold (nothing was written but the exchange and
-// the staging).  MW_HANDED: at most MW_HANDOFF kept rows, now in the one-wave
+// the staging).  MW_HANDED: at most MW_ALONE kept rows, now in the one-wave
 // search's arrays (nc_out, orv_out: their count and union).  MW_DONE: wave 0
 // holds the pivots (lane l: column, reduced stripe word, position found) and
 // L the special rows.
-template <int NW, int SR>
+template <int NW, bool ALONE, int SR>
 __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int64_t ldw, const int64_t sw,
                                                    const int64_t r, const int64_t rows, const uint64_t kmask,
                                                    const int kp, const int lane, const int wave, const MwCtx &mc,
@@ -407,7 +466,13 @@ __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int6
     orv = wave_or64(lane < NW ? X.orv[lane] : 0ull);
     MW_STAMP(1)
     if (nc > cap) return MW_FALLBACK;
-    if (nc <= MW_HANDOFF) {
+    if (nc <= MW_ALONE) {
+        // few kept rows: wave 0 alone holds them, and its columns take no
+        // barrier (the others leave; nothing they read is written below)
+        if constexpr (ALONE) {
+            if (wave == 0) mw_alone<NW>(mc, L, nc, orv, r, rows, kp, lane, npiv_out, my_q, my_fin, my_p, nspec_out);
+            return MW_DONE;
+        }
         for (int k = wave * 64 + lane; k < nc; k += NW * 64) {
             if (mc.hv != mc.stv) mc.hv[k] = mc.stv[k];
             const int32_t p = mc.stp[k];
@@ -483,14 +548,16 @@ __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int6
 // record), `rec` receives this pass.  Writes P[r..r+rbar), Q[r..r+rbar)
 // and *rank_out = r + rbar.  With NW > 1 every wave of the block calls it
 // (`wave` = its index): wave 0 runs the panel, and the others join it for
-// the slow search (mc: its LDS).
-template <int WQ, int SR, bool KEPT = true, int NW = 1>
+// the slow search (mc: its LDS; ALONE: few kept rows in wave 0's registers
+// rather than the one-wave search's LDS arrays: faster on sparse stripes, but
+// in the standalone panel the larger kernel cost its dense launches time).
+template <int WQ, int SR, bool KEPT = true, int NW = 1, bool ALONE = false>
 __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, int64_t ldw, int64_t c,
                                            const PassRec *prev, PassRec *rec, int64_t *P, int64_t *Q,
                                            int64_t *rank_out, uint64_t *gsv, int32_t *gsid, PanelLdsT<SR> &L,
                                            const int lane, PanelFix fix = PanelFix(), const int wave = 0,
                                            const MwCtx &mc = MwCtx()) {
-    static_assert(NW == 1 || (WQ == 2 && KEPT && SR >= MW_HANDOFF), "the multi-wave slow search follows the "
+    static_assert(NW == 1 || (WQ == 2 && KEPT), "the multi-wave slow search follows the "
                                                                      "two-register window");
 #ifdef GF2_PANEL_TIMING
     uint64_t *dbg = gsv + (c >> 6) * 8;
@@ -889,7 +956,7 @@ __device__ __forceinline__ void panel_body(uint64_t *A, int64_t m, int64_t n, in
             __syncthreads();
             slow = X.flag != 0;
             if (slow) {
-                const MwResult res = slow_search_mw<NW>(A, ldw, sw, r, rows, kmask, kp, lane, wave, mc, L, npiv,
+                const MwResult res = slow_search_mw<NW, ALONE>(A, ldw, sw, r, rows, kmask, kp, lane, wave, mc, L, npiv,
                                                         my_q, my_fin, my_p, nspec, h_nc, h_orv);
                 slow_done = res == MW_DONE;
                 handed = res == MW_HANDED;

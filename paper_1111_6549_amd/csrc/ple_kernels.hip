@@ -524,7 +524,7 @@ __global__ __launch_bounds__(NT) void k_m4rm_pair(uint64_t *__restrict__ C, int6
         mc.hv = PL.sv;
         mc.hp = PL.spos;
         mc.hi = PL.sid;
-        panel_body<2, PAIR_PANEL_ROWS, true, NT / 64>(C, m, pp.n, ldc, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank,
+        panel_body<2, PAIR_PANEL_ROWS, true, NT / 64, true>(C, m, pp.n, ldc, pp.c, recu, pp.rec, pp.P, pp.Q, pp.rank,
                                                      pp.gsv, pp.gsid, PL, tid & 63, f, uni(tid >> 6), mc);
         return;
     }
