@@ -175,10 +175,11 @@ __device__ __forceinline__ int finish_special(PanelLdsT<SR> &L, const int64_t r,
 // every wave posts its first active slot and its first active slot with the
 // column's bit, every wave reads the NW posts and takes the smallest, and
 // all apply the same move and the same elimination to the slots they hold.
-// The slot rules are those of the one-wave search below (a slot keeps its
-// position, a swap exchanges word and first position, a pivot that takes a
-// zero row's place retires); the elimination is eager: each pivot leaves
-// every active slot that has its bit at once.
+// A slot keeps its position and a swap exchanges word and first position,
+// as in the one-wave search below; but where a pivot takes a zero row's
+// place, that row moves into the pivot's slot (as a word of 0) instead of
+// the slot retiring, so the active slots stay a range.  The elimination is
+// eager: each pivot leaves every active slot that has its bit at once.
 constexpr int MW_SLOTS = 8192;  // kept rows held in registers, over all waves
 
 // Minimum and sum over lanes 0..15 (one DPP row), in each of those lanes:
@@ -235,39 +236,33 @@ constexpr int MW_ALONE = 512;
 enum MwResult { MW_FALLBACK = 0, MW_HANDED = 1, MW_DONE = 2 };
 
 // The column search of the multi-wave slow search over the first RR of the
-// R registers of slots (the others are empty).  One barrier per column with
-// a possible pivot: every wave posts its first active slot and its first
-// active slot with the column's bit, then reads all NW posts at once (lane w
-// takes wave w's) and picks the smallest from its lanes.
+// R registers of slots (the others are empty).  No slot retires: when a row
+// with a zero stripe word sits at the rank position, it moves into the
+// pivot's slot as a word of 0.  Slot positions ascend with the slot and never
+// change, so the active slots are the range [kthr, nc) and the first active
+// slot is kthr.  One barrier per column with a possible pivot: every wave
+// posts its first active slot with the column's bit, and the owner of slot
+// kthr posts that slot's word, position and first position; then every wave
+// reads the posts (lane w takes wave w's) and picks the smallest slot.
 template <int NW, int RR, int R>
 __device__ __forceinline__ void mw_columns(MwX<NW> &X, uint64_t (&wd)[R], int (&cpos)[R], int (&cid)[R],
                                            const int lane, const int wave, const uint64_t orv, const int kp,
-                                           const int64_t rows, int &npiv, int &my_q, uint64_t &my_fin, int &my_p,
-                                           int &my_id, int &dzp, int &dzi) {
+                                           const int nc, const int64_t rows, int &npiv, int &kthr, int &my_q,
+                                           uint64_t &my_fin, int &my_p, int &my_id) {
     using Post = typename MwX<NW>::Post;
     uint64_t or_pe = 0;
     int par = 0;
     for (int j = 0; j < kp && npiv < rows; j++) {
         if (!(((orv | or_pe) >> j) & 1ull)) continue;  // no row can have a 1 here
-        // this wave's first active slot (register qa, lane la) and first
-        // active slot with bit j (qm, lm); each lane keeps its own entry of
-        // the register they are in.  Empty slots are never active.
-        int qa = RR, qm = RR, la = 0, lm = 0;
-        uint64_t wa = 0, wm = 0;
-        int pa = 0, ia = 0, pm = 0, im = 0;
+        // this wave's first active slot with bit j (register qm, lane lm);
+        // each lane keeps its own entry of that register
+        int qm = RR, lm = 0;
+        uint64_t wm = 0;
+        int pm = 0, im = 0;
 #pragma unroll
         for (int q = 0; q < RR; q++) {
             if (qm == RR) {
-                const bool act = cpos[q] >= npiv;
-                const uint64_t am = __ballot(act);
-                const uint64_t cm = __ballot(act && ((wd[q] >> j) & 1ull));
-                if (qa == RR && am) {
-                    qa = q;
-                    la = (int)__builtin_ctzll(am);
-                    wa = wd[q];
-                    pa = cpos[q];
-                    ia = cid[q];
-                }
+                const uint64_t cm = __ballot(cpos[q] >= npiv && ((wd[q] >> j) & 1ull));
                 if (cm) {
                     qm = q;
                     lm = (int)__builtin_ctzll(cm);
@@ -277,51 +272,70 @@ __device__ __forceinline__ void mw_columns(MwX<NW> &X, uint64_t (&wd)[R], int (&
                 }
             }
         }
-        // the lanes that hold them post them (lane 0 posts "none")
-        if (lane == la) X.fa[par][wave] = Post{wa, qa == RR ? INT32_MAX : (qa * NW + wave) * 64 + la, pa, ia, 0};
+        // slot h = kthr's owner: this wave or not, its register and lane
+        const int h = kthr;
+        const bool oh = h < nc && (h >> 6) % NW == wave;
+        const int rh = (h >> 6) / NW, lh = h & 63;
         if (lane == lm) X.fm[par][wave] = Post{wm, qm == RR ? INT32_MAX : (qm * NW + wave) * 64 + lm, pm, im, 0};
+        if (oh) {
+            uint64_t w_h = 0;
+            int p_h = 0, i_h = 0;
+#pragma unroll
+            for (int q = 0; q < RR; q++) {
+                if (q == rh) {
+                    w_h = wd[q];
+                    p_h = cpos[q];
+                    i_h = cid[q];
+                }
+            }
+            if (lane == lh) X.fa[par][0] = Post{w_h, h, p_h, i_h, 0};
+        }
         if constexpr (NW > 1) {
             __syncthreads();
         } else {
             lds_order();  // one wave: its own posts, in program order
         }
-        Post ea, em;
-        ea.slot = em.slot = INT32_MAX;
-        if (lane < NW) {
-            ea = X.fa[par][lane];
-            em = X.fm[par][lane];
-        }
+        Post em;
+        em.slot = INT32_MAX;
+        if (lane < NW) em = X.fm[par][lane];
+        const Post eh = X.fa[par][0];
         par ^= 1;  // the next column posts to the other half: no second barrier
-        // the smallest posts (slot numbers are distinct)
-        const int h = uni(row16_min(ea.slot)), kf = uni(row16_min(em.slot));
+        const int kf = uni(row16_min(em.slot));
         if (kf == INT32_MAX) continue;  // column j has no pivot
-        const int wh = (int)__builtin_ctzll(__ballot(ea.slot == h));
         const int wf = (int)__builtin_ctzll(__ballot(em.slot == kf));
-        const uint64_t pv = readlane64(em.word, wf), vh = readlane64(ea.word, wh);
+        const uint64_t pv = readlane64(em.word, wf);
         const int found = readlane32(em.pos, wf), pid = readlane32(em.id, wf);
-        const int ph = readlane32(ea.pos, wh), idh = readlane32(ea.id, wh);
-        // owners: the slot's lane in this wave (-1: another wave's) and register
-        const int lf = (kf >> 6) % NW == wave ? (kf & 63) : -1, rf = (kf >> 6) / NW;
-        const int lh = (h >> 6) % NW == wave ? (h & 63) : -1, rh = (h >> 6) / NW;
+        const uint64_t vh = readlane64(eh.word, 0);  // kf exists, so slot h does
+        const int ph = uni(eh.pos), idh = uni(eh.id);
+        const bool of = (kf >> 6) % NW == wave;
+        const int rf = (kf >> 6) / NW, lf = kf & 63;
         if (ph == npiv) {
-            // the row at npiv is slot h: h now holds the pivot and kf that row
-            // (kf == h: the pivot is in place)
+            // the row at npiv is slot h: h now holds the pivot (and leaves the
+            // range) and kf that row (kf == h: the pivot is in place)
             if (kf != h) {
 #pragma unroll
                 for (int q = 0; q < RR; q++) {
-                    const bool th = q == rh && lane == lh;
-                    const bool tf = q == rf && lane == lf;
-                    wd[q] = th ? pv : (tf ? vh : wd[q]);
-                    cid[q] = th ? pid : (tf ? idh : cid[q]);
+                    if (oh && q == rh) {
+                        wd[q] = lane == lh ? pv : wd[q];
+                        cid[q] = lane == lh ? pid : cid[q];
+                    }
+                    if (of && q == rf) {
+                        wd[q] = lane == lf ? vh : wd[q];
+                        cid[q] = lane == lf ? idh : cid[q];
+                    }
                 }
             }
+            kthr = h + 1;
         } else {
-            // a row with a zero stripe word is at npiv: it takes the pivot's
-            // place, and the pivot's slot retires
+            // a row with a zero stripe word is at npiv, where it has always
+            // been: it moves into the pivot's slot
 #pragma unroll
-            for (int q = 0; q < RR; q++)
-                if (q == rf && lane == lf) cpos[q] = -1;
-            move_zero_row(dzp, dzi, npiv, found, lane);
+            for (int q = 0; q < RR; q++) {
+                if (of && q == rf) {
+                    wd[q] = lane == lf ? 0ull : wd[q];
+                    cid[q] = lane == lf ? npiv : cid[q];
+                }
+            }
         }
         // every later active slot with bit j leaves it
         const uint64_t pe = pv & above(j);
@@ -364,17 +378,17 @@ __device__ __forceinline__ void mw_alone(const MwCtx &mc, PanelLdsT<SR> &L, cons
     my_q = 0;
     my_fin = 0;
     my_p = 0;
-    int npiv = 0, dzp = -1, dzi = 0, my_id = 0;
+    int npiv = 0, kthr = 0, my_id = 0;
     const int rr = (nc + 63) / 64;
     static_assert(R == 8, "register counts 1, 2, 4, 8");
     if (rr <= 1)
-        mw_columns<1, 1, R>(X, wd, cpos, cid, lane, 0, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+        mw_columns<1, 1, R>(X, wd, cpos, cid, lane, 0, orv, kp, nc, rows, npiv, kthr, my_q, my_fin, my_p, my_id);
     else if (rr <= 2)
-        mw_columns<1, 2, R>(X, wd, cpos, cid, lane, 0, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+        mw_columns<1, 2, R>(X, wd, cpos, cid, lane, 0, orv, kp, nc, rows, npiv, kthr, my_q, my_fin, my_p, my_id);
     else if (rr <= 4)
-        mw_columns<1, 4, R>(X, wd, cpos, cid, lane, 0, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+        mw_columns<1, 4, R>(X, wd, cpos, cid, lane, 0, orv, kp, nc, rows, npiv, kthr, my_q, my_fin, my_p, my_id);
     else
-        mw_columns<1, 8, R>(X, wd, cpos, cid, lane, 0, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+        mw_columns<1, 8, R>(X, wd, cpos, cid, lane, 0, orv, kp, nc, rows, npiv, kthr, my_q, my_fin, my_p, my_id);
     // kept rows that moved: listed after the pivots, in any order
     const uint64_t lt = (1ull << lane) - 1ull;
     int nsp = npiv;
@@ -390,7 +404,7 @@ __device__ __forceinline__ void mw_alone(const MwCtx &mc, PanelLdsT<SR> &L, cons
         nsp += __popcll(msk);
     }
     npiv_out = npiv;
-    nspec_out = finish_special(L, r, npiv, nsp, my_id, dzp, dzi, lane);
+    nspec_out = finish_special(L, r, npiv, nsp, my_id, -1, 0, lane);
 }
 
 // Run by every wave of the block (wave = its index, uniform); the result is
@@ -501,20 +515,24 @@ __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int6
     my_q = 0;
     my_fin = 0;
     my_p = 0;
-    int npiv = 0, dzp = -1, dzi = 0, my_id = 0;
+    int npiv = 0, kthr = 0, my_id = 0;
     static_assert(R == 8 || R == 16, "register counts 1, 2, 4, 8 (, 16)");
     const int rr = (nc + NW * 64 - 1) / (NW * 64);
     if (rr <= 1)
-        mw_columns<NW, 1, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+        mw_columns<NW, 1, R>(X, wd, cpos, cid, lane, wave, orv, kp, nc, rows, npiv, kthr, my_q, my_fin, my_p,
+                              my_id);
     else if (rr <= 2)
-        mw_columns<NW, 2, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+        mw_columns<NW, 2, R>(X, wd, cpos, cid, lane, wave, orv, kp, nc, rows, npiv, kthr, my_q, my_fin, my_p,
+                              my_id);
     else if (rr <= 4)
-        mw_columns<NW, 4, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+        mw_columns<NW, 4, R>(X, wd, cpos, cid, lane, wave, orv, kp, nc, rows, npiv, kthr, my_q, my_fin, my_p,
+                              my_id);
     else if (R == 8 || rr <= 8)
-        mw_columns<NW, 8, R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p, my_id, dzp, dzi);
+        mw_columns<NW, 8, R>(X, wd, cpos, cid, lane, wave, orv, kp, nc, rows, npiv, kthr, my_q, my_fin, my_p,
+                              my_id);
     else
-        mw_columns<NW, (R > 8 ? 16 : 8), R>(X, wd, cpos, cid, lane, wave, orv, kp, rows, npiv, my_q, my_fin, my_p,
-                                             my_id, dzp, dzi);
+        mw_columns<NW, (R > 8 ? 16 : 8), R>(X, wd, cpos, cid, lane, wave, orv, kp, nc, rows, npiv, kthr, my_q, my_fin,
+                                             my_p, my_id);
     MW_STAMP(2)
 
     // ---- kept rows that moved: listed after the pivots, in any order ----
@@ -536,7 +554,7 @@ __device__ __forceinline__ MwResult slow_search_mw(const uint64_t *A, const int6
     __syncthreads();
     npiv_out = npiv;
     if (wave != 0) return MW_DONE;
-    nspec_out = finish_special(L, r, npiv, npiv + uni(X.lcount), my_id, dzp, dzi, lane);
+    nspec_out = finish_special(L, r, npiv, npiv + uni(X.lcount), my_id, -1, 0, lane);
     MW_STAMP(3)
 #undef MW_STAMP
     return MW_DONE;

@@ -182,6 +182,81 @@ def kept_waves(vals, kp, nw, regs, order):
     return out
 
 
+def kept_waves_nz(vals, kp, nw, regs, order):
+    """The multi-wave form with no retirement: when a zero-word row sits at
+    the rank position, it moves into the pivot's slot as a word of 0 (its
+    first position is that rank position), so the active slots are always
+    the range [kthr, nc) and the first of them is kthr; only the first
+    active slot with the bit is posted per wave."""
+    kept = [(v, p) for p, v in enumerate(vals) if v]
+    nc = len(kept)
+    assert nc <= nw * regs * 64
+    wd = [v for v, _ in kept]
+    cid = [p for _, p in kept]
+    pos = [p for _, p in kept]  # never changes
+    by_wave = [[k for q in range(regs) for k in range((q * nw + w) * 64, (q * nw + w) * 64 + 64) if k < nc]
+               for w in range(nw)]
+    orv = 0
+    for v in wd:
+        orv |= v
+    out, pid_of = [], []
+    npiv, or_pe, kthr = 0, 0, 0
+    for j in range(kp):
+        if npiv >= len(vals):
+            break
+        if not ((orv | or_pe) >> j) & 1:
+            continue
+        posts = []
+        for w in range(nw):
+            m = [k for k in by_wave[w] if k >= kthr and (wd[k] >> j) & 1]
+            posts.append(m[0] if m else None)
+        cands = [k for k in posts if k is not None]
+        if not cands:
+            continue
+        kf = min(cands)
+        h = kthr
+        pv, found, pid = wd[kf], pos[kf], cid[kf]
+        if pos[h] == npiv:
+            if kf != h:
+                wd[h], cid[h], wd[kf], cid[kf] = pv, pid, wd[h], cid[h]
+            kthr += 1
+        else:
+            wd[kf], cid[kf] = 0, npiv
+        pe = pv & above(j)
+        for k in range(kthr, nc):
+            if (wd[k] >> j) & 1:
+                wd[k] ^= pe
+        out.append((j, found, pid, pv))
+        pid_of.append(pid)
+        or_pe |= pe
+        npiv += 1
+    order[:] = list(range(len(vals)))
+    for l, pid in enumerate(pid_of):
+        order[l] = pid
+    for k in range(kthr, nc):
+        if cid[k] != pos[k]:
+            order[pos[k]] = cid[k]
+    return out
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("nw,regs", [(16, 8), (8, 16), (1, 8)])
+def test_multi_wave_no_retire_matches_eager(seed, nw, regs):
+    rng = random.Random(200 + seed)
+    for _ in range(25):
+        n = rng.choice([1, 64, 65, 300, 700, 1500])
+        d = rng.choice([0.002, 0.01, 0.05, 0.3])
+        zero_heavy = rng.random() < 0.4
+        vals = [0 if (zero_heavy and rng.random() < 0.7) else
+                sum(1 << b for b in range(64) if rng.random() < d) for _ in range(n)]
+        if sum(1 for v in vals if v) > nw * regs * 64:
+            continue
+        kp = rng.choice([64, 64, 23])
+        o1, o2 = [], []
+        assert kept_waves_nz(vals, kp, nw, regs, o2) == eager(vals, kp, o1)
+        assert o2 == o1
+
+
 @pytest.mark.parametrize("seed", range(4))
 @pytest.mark.parametrize("nw,regs", [(16, 8), (8, 16), (1, 8)])
 def test_multi_wave_search_matches_eager(seed, nw, regs):
