@@ -252,8 +252,13 @@ __device__ __forceinline__ void mw_columns(MwX<NW> &X, uint64_t (&wd)[R], int (&
     using Post = typename MwX<NW>::Post;
     uint64_t or_pe = 0;
     int par = 0;
-    for (int j = 0; j < kp && npiv < rows; j++) {
-        if (!(((orv | or_pe) >> j) & 1ull)) continue;  // no row can have a 1 here
+    // one column; HI: j >= 32, whose bit and part above it lie in the high
+    // half of each word (one 32-bit test, one half to update)
+    auto column = [&](const int j, auto hi_c) {
+        constexpr bool HI = decltype(hi_c)::value;
+        const uint32_t bj = 1u << (j & 31);
+        auto half = [&](const uint64_t w) { return HI ? (uint32_t)(w >> 32) : (uint32_t)w; };
+        if (!(((orv | or_pe) >> j) & 1ull)) return;  // no row can have a 1 here
         // this wave's first active slot with bit j (register qm, lane lm);
         // each lane keeps its own entry of that register
         int qm = RR, lm = 0;
@@ -262,7 +267,7 @@ __device__ __forceinline__ void mw_columns(MwX<NW> &X, uint64_t (&wd)[R], int (&
 #pragma unroll
         for (int q = 0; q < RR; q++) {
             if (qm == RR) {
-                const uint64_t cm = __ballot(cpos[q] >= npiv && ((wd[q] >> j) & 1ull));
+                const uint64_t cm = __ballot(cpos[q] >= npiv && (half(wd[q]) & bj) != 0);
                 if (cm) {
                     qm = q;
                     lm = (int)__builtin_ctzll(cm);
@@ -301,7 +306,7 @@ __device__ __forceinline__ void mw_columns(MwX<NW> &X, uint64_t (&wd)[R], int (&
         const Post eh = X.fa[par][0];
         par ^= 1;  // the next column posts to the other half: no second barrier
         const int kf = uni(row16_min(em.slot));
-        if (kf == INT32_MAX) continue;  // column j has no pivot
+        if (kf == INT32_MAX) return;  // column j has no pivot
         const int wf = (int)__builtin_ctzll(__ballot(em.slot == kf));
         const uint64_t pv = readlane64(em.word, wf);
         const int found = readlane32(em.pos, wf), pid = readlane32(em.id, wf);
@@ -339,10 +344,14 @@ __device__ __forceinline__ void mw_columns(MwX<NW> &X, uint64_t (&wd)[R], int (&
         }
         // every later active slot with bit j leaves it
         const uint64_t pe = pv & above(j);
+        const uint32_t pel = (uint32_t)pe, peh = (uint32_t)(pe >> 32);
 #pragma unroll
         for (int q = 0; q < RR; q++) {
-            const bool e = cpos[q] > npiv && ((wd[q] >> j) & 1ull);
-            wd[q] = e ? wd[q] ^ pe : wd[q];
+            uint32_t lo = (uint32_t)wd[q], hi = (uint32_t)(wd[q] >> 32);
+            const bool e = cpos[q] > npiv && ((HI ? hi : lo) & bj) != 0;
+            if (!HI) lo = e ? lo ^ pel : lo;  // a high column's part above it has no low bits
+            hi = e ? hi ^ peh : hi;
+            wd[q] = ((uint64_t)hi << 32) | lo;
         }
         my_q = writelane32(my_q, j, npiv);
         my_fin = writelane64(my_fin, pv, npiv);
@@ -350,7 +359,10 @@ __device__ __forceinline__ void mw_columns(MwX<NW> &X, uint64_t (&wd)[R], int (&
         my_id = writelane32(my_id, pid, npiv);
         or_pe |= pe;
         npiv++;
-    }
+    };
+    const int k32 = kp < 32 ? kp : 32;
+    for (int j = 0; j < k32 && npiv < rows; j++) column(j, std::false_type());
+    for (int j = 32; j < kp && npiv < rows; j++) column(j, std::true_type());
 }
 
 // Wave 0 alone, after the scan, on at most MW_ALONE kept rows: slot k in
