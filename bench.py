@@ -48,7 +48,7 @@ KW = 64
 # copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Reported only for that
 # configuration and while the kernel sources hash to the value the counters
 # were taken on.
-TRAFFIC = {"source": "0aa0c8103a01a31d", "n": 65536, "seed": 5, "split": 24576, "bytes_per_launch": 158714998}
+TRAFFIC = {"source": "54742199ad7df76a", "n": 65536, "seed": 5, "split": 24576, "bytes_per_launch": 158715144}
 
 
 def log(*a):
